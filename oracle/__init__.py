@@ -1,0 +1,196 @@
+"""Oracle: plain CPU evaluation of BGPs over a triple set, for testing only.
+
+TEST INFRASTRUCTURE.  Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU
+baseline leg of ``bench.py`` may import this package.  The product path (the
+GPU library and its Python binding) never does, and shares no code with it.
+
+Contents:
+  * ``liboracle.so`` (built from ``oracle.cpp`` with g++): set semantics,
+    per-pattern relations, hash/Cartesian joins, sorted output, fingerprint,
+    and the per-predicate compressed matrices of the storage scheme.
+  * ``brute_force``: enumeration of every assignment of the variables (tiny
+    inputs only), the definition of BGP matching written out.
+  * ``plan_order``: the planner's ordering rule, "connected minimal upper
+    bound" (paper Sec. 6.2.1 and its Algorithm "Query Plan Generated"), read as
+    its prose states it (see the reading notes in ``plan_order``).
+"""
+from __future__ import annotations
+
+import ctypes
+import itertools
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+_SRC = os.path.join(_HERE, "oracle.cpp")
+
+
+def build(force: bool = True) -> str:
+    if force or not os.path.exists(_SO):
+        tmp = _SO + ".tmp"
+        subprocess.check_call(["g++", "-O2", "-std=c++17", "-shared", "-fPIC", _SRC, "-o", tmp])
+        os.replace(tmp, _SO)
+    return _SO
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            build(force=False)
+        L = ctypes.CDLL(_SO)
+        i64, i32, vp = ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p
+        L.oracle_dedupe.restype = i64
+        L.oracle_dedupe.argtypes = [vp, vp, vp, i64, vp, vp, vp]
+        L.oracle_csr.restype = i64
+        L.oracle_csr.argtypes = [vp, vp, vp, i64, i32, i32, vp, vp, vp, vp]
+        L.oracle_join.restype = vp
+        L.oracle_join.argtypes = [vp, vp, vp, i64, vp, i32, i32, i64]
+        L.oracle_result_rows.restype = i64
+        L.oracle_result_rows.argtypes = [vp]
+        L.oracle_result_nvars.restype = i32
+        L.oracle_result_nvars.argtypes = [vp]
+        L.oracle_result_copy.argtypes = [vp, vp]
+        L.oracle_result_fingerprint.argtypes = [vp, vp]
+        L.oracle_result_free.argtypes = [vp]
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def dedupe(s, p, o):
+    """Sorted distinct (s, p, o) triples (the dataset as a set, Sec. 3.1)."""
+    s, p, o = _i32(s), _i32(p), _i32(o)
+    n = len(s)
+    so, po, oo = (np.empty(n, np.int32) for _ in range(3))
+    m = lib().oracle_dedupe(_p(s), _p(p), _p(o), n, _p(so), _p(po), _p(oo))
+    return so[:m], po[:m], oo[:m]
+
+
+def csr(s, p, o, pred, orient):
+    """(keys, ptr, nbr) of predicate `pred`: orient 0 by subject, 1 by object."""
+    s, p, o = _i32(s), _i32(p), _i32(o)
+    nr = ctypes.c_int64(0)
+    nnz = lib().oracle_csr(_p(s), _p(p), _p(o), len(s), pred, orient, ctypes.byref(nr),
+                           None, None, None)
+    keys = np.empty(nr.value, np.int32)
+    ptr = np.empty(nr.value + 1, np.int32)
+    nbr = np.empty(nnz, np.int32)
+    lib().oracle_csr(_p(s), _p(p), _p(o), len(s), pred, orient, ctypes.byref(nr), _p(keys),
+                     _p(ptr), _p(nbr))
+    return keys, ptr, nbr
+
+
+def join(s, p, o, tps, n_vars, cap_rows=-1, fingerprint=False):
+    """Sorted result rows (rows x n_vars int32) of the BGP `tps` ((n,3) int32).
+
+    With fingerprint=True returns (rows, h1 sum, h2 sum) instead.
+    """
+    s, p, o = _i32(s), _i32(p), _i32(o)
+    t = _i32(np.asarray(tps).reshape(-1, 3))
+    h = lib().oracle_join(_p(s), _p(p), _p(o), len(s), _p(t), len(t), n_vars, cap_rows)
+    if not h:
+        raise ValueError("oracle_join rejected the input (invalid BGP or row cap exceeded)")
+    try:
+        if fingerprint:
+            out = np.zeros(3, np.uint64)
+            lib().oracle_result_fingerprint(h, _p(out))
+            return tuple(int(x) for x in out)
+        rows = lib().oracle_result_rows(h)
+        out = np.empty((rows, n_vars), np.int32)
+        if rows and n_vars:
+            lib().oracle_result_copy(h, _p(out))
+        return out
+    finally:
+        lib().oracle_result_free(h)
+
+
+def brute_force(s, p, o, tps, n_vars, V):
+    """Every assignment mu in [0,V)^n_vars with (mu(s_i), p_i, mu(o_i)) in D for
+    all patterns; sorted.  Tiny inputs only (V**n_vars small)."""
+    D = set(zip(np.asarray(s).tolist(), np.asarray(p).tolist(), np.asarray(o).tolist()))
+    tps = [tuple(int(v) for v in t) for t in np.asarray(tps).reshape(-1, 3)]
+
+    def val(term, mu):
+        return term if term >= 0 else mu[-term - 1]
+
+    out = []
+    for mu in itertools.product(range(V), repeat=n_vars):
+        if all((val(a, mu), b, val(c, mu)) in D for a, b, c in tps):
+            out.append(mu)
+    return np.array(out, dtype=np.int32).reshape(len(out), n_vars)
+
+
+def plan_order(tps, stat):
+    """Order of the triple patterns under the paper's planner (Sec. 6.2.1).
+
+    Steps as the prose gives them: (1) sort all edges by their statistic;
+    (2) take the smallest edge first and put its nodes in N; (3) repeatedly take,
+    in sorted order, the first remaining edge with at least one node in N, add
+    its nodes to N and remove it; (4) until no edge remains.
+
+    Readings where the text is silent or its listing disagrees with the prose:
+      * ties in the sort keep the original pattern order (stable sort);
+      * "a node in N" means a shared *variable*: constants do not connect
+        patterns (the prose speaks of common join variables);
+      * when no remaining edge shares a variable (a disconnected BGP) the first
+        remaining edge in sorted order is taken (a Cartesian step).
+    """
+    tps = [tuple(int(v) for v in t) for t in np.asarray(tps).reshape(-1, 3)]
+    n = len(tps)
+    L = sorted(range(n), key=lambda i: (stat[i], i))
+    order = [L.pop(0)]
+    N = {x for x in (tps[order[0]][0], tps[order[0]][2]) if x < 0}
+    while L:
+        pick = None
+        for j, e in enumerate(L):
+            if any(x < 0 and x in N for x in (tps[e][0], tps[e][2])):
+                pick = j
+                break
+        if pick is None:
+            pick = 0
+        e = L.pop(pick)
+        order.append(e)
+        N |= {x for x in (tps[e][0], tps[e][2]) if x < 0}
+    return order
+
+
+def fingerprint_rows(rows: np.ndarray):
+    """The same fingerprint as the C oracle's, over rows given as an array.
+
+    Used by the tests to fingerprint rows fetched from the GPU library."""
+    rows = np.asarray(rows)
+    M = np.uint64(0xFFFFFFFFFFFFFFFF)
+
+    def mix(z):
+        z = z ^ (z >> np.uint64(30))
+        z = z * np.uint64(0xbf58476d1ce4e5b9)
+        z = z ^ (z >> np.uint64(27))
+        z = z * np.uint64(0x94d049bb133111eb)
+        z = z ^ (z >> np.uint64(31))
+        return z
+
+    with np.errstate(over="ignore"):
+        x = np.full(len(rows), 0x1234567, np.uint64)
+        y = np.full(len(rows), 0x89abcdef, np.uint64)
+        for c in range(rows.shape[1] if rows.ndim == 2 else 0):
+            v = rows[:, c].astype(np.int64).astype(np.uint64) & np.uint64(0xFFFFFFFF)
+            x = mix(x ^ v)
+            y = mix(y ^ v)
+        a = int(np.sum(x, dtype=np.uint64)) if len(rows) else 0
+        b = int(np.sum(y, dtype=np.uint64)) if len(rows) else 0
+    del M
+    return (len(rows), a, b)

@@ -1,0 +1,273 @@
+// Oracle: a plain, slow, obviously correct CPU evaluation of basic graph
+// patterns (BGPs) over an RDF triple set.
+//
+// TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or
+// call this file; only the tests, the smoke check and the benchmark's CPU
+// baseline leg use it.  It shares no code, header or table with the GPU
+// library.
+//
+// What it computes (paper Sec. 3.1, Sec. 6 "procedure of SM-based BGP query
+// evaluation", Sec. 6.1 last paragraphs):
+//   * The dataset D is a SET of (s, p, o) triples (Sec. 3.1), so duplicates in
+//     the input are removed first.
+//   * Each triple pattern (TP) t_i is initialised as the relation R_i of the
+//     variable bindings it matches on its own (Sec. 6, step "Initializing").
+//   * Relations are joined pairwise on their common variables, the schema of a
+//     join being the distinct union of the two schemas (Sec. 6, step
+//     "Joining"); the join keeps every matching pair (no accumulation of a
+//     value column: the boolean reading of the sparse-matrix product in
+//     Sec. 6.1).
+//   * The final relation over all variables is returned (step "Returning"),
+//     here as rows in variable-number order, sorted lexicographically.
+//
+// Join order: query order repaired for connectivity (start with TP 0, then
+// repeatedly the lowest-numbered remaining TP that shares a variable with the
+// bound set, else the lowest-numbered remaining TP).  This deliberately
+// ignores the paper's statistics-based plan; the result does not depend on
+// the order.  Each join is a hash join keyed on the shared variables, or a
+// nested-loop Cartesian product when none is shared.
+//
+// Pattern encoding: endpoint >= 0 is a vertex constant; endpoint < 0 is the
+// variable -(x+1).  The predicate is always a constant (Sec. 6.3 assumes a
+// known predicate).
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <unordered_map>
+#include <vector>
+
+namespace {
+
+struct Triple {
+  int32_t s, p, o;
+  bool operator<(const Triple& b) const {
+    if (s != b.s) return s < b.s;
+    if (p != b.p) return p < b.p;
+    return o < b.o;
+  }
+  bool operator==(const Triple& b) const { return s == b.s && p == b.p && o == b.o; }
+};
+
+// A relation: schema (variable numbers) and row-major values.
+struct Relation {
+  std::vector<int32_t> vars;
+  std::vector<int32_t> vals;
+  int64_t rows = 0;
+};
+
+std::vector<Triple> dedupe(const int32_t* s, const int32_t* p, const int32_t* o, int64_t n) {
+  std::vector<Triple> d(n);
+  for (int64_t i = 0; i < n; ++i) d[i] = Triple{s[i], p[i], o[i]};
+  std::sort(d.begin(), d.end());
+  d.erase(std::unique(d.begin(), d.end()), d.end());
+  return d;
+}
+
+// R_i: the bindings of the TP's variables for which the instantiated TP is in D.
+Relation tp_relation(const std::vector<Triple>& D, int32_t ts, int32_t tp, int32_t to) {
+  Relation r;
+  bool sv = ts < 0, ov = to < 0;
+  int32_t xs = sv ? -ts - 1 : -1, xo = ov ? -to - 1 : -1;
+  if (sv) r.vars.push_back(xs);
+  if (ov && !(sv && xo == xs)) r.vars.push_back(xo);
+  for (const Triple& t : D) {
+    if (t.p != tp) continue;
+    if (!sv && t.s != ts) continue;
+    if (!ov && t.o != to) continue;
+    if (sv && ov && xs == xo && t.s != t.o) continue;
+    if (sv) r.vals.push_back(t.s);
+    if (ov && !(sv && xo == xs)) r.vals.push_back(t.o);
+    ++r.rows;
+  }
+  return r;
+}
+
+uint64_t pack_key(const int32_t* row, const std::vector<int>& cols) {
+  uint64_t k = 0;
+  for (int c : cols) k = (k << 32) | (uint32_t)row[c];
+  return k;
+}
+
+// Natural join of a (current) and b (a TP relation with at most 2 variables).
+Relation join(const Relation& a, const Relation& b) {
+  std::vector<int> a_shared, b_shared, b_new;
+  for (size_t j = 0; j < b.vars.size(); ++j) {
+    auto it = std::find(a.vars.begin(), a.vars.end(), b.vars[j]);
+    if (it != a.vars.end()) {
+      a_shared.push_back((int)(it - a.vars.begin()));
+      b_shared.push_back((int)j);
+    } else {
+      b_new.push_back((int)j);
+    }
+  }
+  Relation out;
+  out.vars = a.vars;
+  for (int j : b_new) out.vars.push_back(b.vars[j]);
+  const size_t wa = a.vars.size(), wb = b.vars.size();
+  if (b_shared.empty()) {  // Cartesian product
+    for (int64_t i = 0; i < a.rows; ++i)
+      for (int64_t j = 0; j < b.rows; ++j) {
+        for (size_t c = 0; c < wa; ++c) out.vals.push_back(a.vals[i * wa + c]);
+        for (int c : b_new) out.vals.push_back(b.vals[j * wb + c]);
+        ++out.rows;
+      }
+    return out;
+  }
+  std::unordered_multimap<uint64_t, int64_t> h;
+  h.reserve((size_t)b.rows * 2 + 1);
+  for (int64_t j = 0; j < b.rows; ++j) h.emplace(pack_key(&b.vals[j * wb], b_shared), j);
+  for (int64_t i = 0; i < a.rows; ++i) {
+    auto range = h.equal_range(pack_key(&a.vals[i * wa], a_shared));
+    for (auto it = range.first; it != range.second; ++it) {
+      int64_t j = it->second;
+      for (size_t c = 0; c < wa; ++c) out.vals.push_back(a.vals[i * wa + c]);
+      for (int c : b_new) out.vals.push_back(b.vals[j * wb + c]);
+      ++out.rows;
+    }
+  }
+  return out;
+}
+
+std::vector<int> join_order(const int32_t* tps, int32_t ntp, int32_t nvars) {
+  std::vector<int> order;
+  std::vector<char> used(ntp, 0), bound(nvars > 0 ? nvars : 1, 0);
+  for (int step = 0; step < ntp; ++step) {
+    int pick = -1;
+    for (int t = 0; t < ntp && pick < 0; ++t) {
+      if (used[t]) continue;
+      int32_t s = tps[3 * t], o = tps[3 * t + 2];
+      if ((s < 0 && bound[-s - 1]) || (o < 0 && bound[-o - 1])) pick = t;
+    }
+    for (int t = 0; t < ntp && pick < 0; ++t)
+      if (!used[t]) pick = t;
+    used[pick] = 1;
+    order.push_back(pick);
+    if (tps[3 * pick] < 0) bound[-tps[3 * pick] - 1] = 1;
+    if (tps[3 * pick + 2] < 0) bound[-tps[3 * pick + 2] - 1] = 1;
+  }
+  return order;
+}
+
+struct Result {
+  int32_t nvars = 0;
+  int64_t rows = 0;
+  std::vector<int32_t> vals;  // sorted, row-major, variable order
+};
+
+inline uint64_t mix64(uint64_t z) {
+  z ^= z >> 30; z *= 0xbf58476d1ce4e5b9ULL;
+  z ^= z >> 27; z *= 0x94d049bb133111ebULL;
+  z ^= z >> 31;
+  return z;
+}
+
+}  // namespace
+
+extern "C" {
+
+// Sorted distinct triples of the input; returns their number.  Output arrays
+// (may be null to query the count) must hold n entries.
+int64_t oracle_dedupe(const int32_t* s, const int32_t* p, const int32_t* o, int64_t n,
+                      int32_t* s_out, int32_t* p_out, int32_t* o_out) {
+  std::vector<Triple> d = dedupe(s, p, o, n);
+  if (s_out)
+    for (size_t i = 0; i < d.size(); ++i) { s_out[i] = d[i].s; p_out[i] = d[i].p; o_out[i] = d[i].o; }
+  return (int64_t)d.size();
+}
+
+// The h-index sparse matrix of predicate `pred` (Sec. 5.3) in compressed form:
+// orient 0 groups the (s, o) pairs by subject (rows = subjects, members =
+// objects), orient 1 by object.  keys: distinct row ids ascending (the "Row"
+// array of Sec. 6.3), ptr: nr+1 offsets (the "Rpos" array, 0-based; "Num" is
+// the difference), nbr: members ascending within each row.  Returns nnz; with
+// null outputs, only nnz and *nr are computed.
+int64_t oracle_csr(const int32_t* s, const int32_t* p, const int32_t* o, int64_t n, int32_t pred,
+                   int32_t orient, int64_t* nr, int32_t* keys, int32_t* ptr, int32_t* nbr) {
+  std::vector<Triple> d = dedupe(s, p, o, n);
+  std::vector<std::pair<int32_t, int32_t>> pairs;
+  for (const Triple& t : d)
+    if (t.p == pred) pairs.emplace_back(orient == 0 ? t.s : t.o, orient == 0 ? t.o : t.s);
+  std::sort(pairs.begin(), pairs.end());
+  int64_t r = 0;
+  for (size_t i = 0; i < pairs.size(); ++i) {
+    bool head = i == 0 || pairs[i].first != pairs[i - 1].first;
+    if (head) {
+      if (keys) { keys[r] = pairs[i].first; ptr[r] = (int32_t)i; }
+      ++r;
+    }
+    if (nbr) nbr[i] = pairs[i].second;
+  }
+  if (ptr) ptr[r] = (int32_t)pairs.size();
+  *nr = r;
+  return (int64_t)pairs.size();
+}
+
+// Evaluates the BGP.  Returns an opaque result handle (null on invalid input).
+// Rows beyond cap_rows (if cap_rows >= 0) make the call return null.
+void* oracle_join(const int32_t* s, const int32_t* p, const int32_t* o, int64_t n,
+                  const int32_t* tps, int32_t ntp, int32_t nvars, int64_t cap_rows) {
+  if (ntp < 0 || nvars < 0) return nullptr;
+  std::vector<Triple> D = dedupe(s, p, o, n);
+  std::vector<int> order = join_order(tps, ntp, nvars);
+  Relation cur;  // the unit relation: one row, no columns
+  cur.rows = 1;
+  for (int t : order) {
+    Relation r = tp_relation(D, tps[3 * t], tps[3 * t + 1], tps[3 * t + 2]);
+    cur = join(cur, r);
+    if (cap_rows >= 0 && cur.rows > cap_rows) return nullptr;
+  }
+  // variables that appear in no TP cannot be bound: the BGP defines them only
+  // through its patterns, so such inputs are rejected
+  if ((int32_t)cur.vars.size() != nvars) return nullptr;
+  Result* res = new Result;
+  res->nvars = nvars;
+  res->rows = cur.rows;
+  std::vector<int> col_of(nvars);
+  for (int c = 0; c < nvars; ++c) col_of[cur.vars[c]] = c;
+  std::vector<int32_t> perm((size_t)cur.rows * nvars);
+  for (int64_t i = 0; i < cur.rows; ++i)
+    for (int x = 0; x < nvars; ++x) perm[i * nvars + x] = cur.vals[i * nvars + col_of[x]];
+  std::vector<int64_t> idx(cur.rows);
+  for (int64_t i = 0; i < cur.rows; ++i) idx[i] = i;
+  std::sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) {
+    return std::lexicographical_compare(&perm[a * nvars], &perm[a * nvars] + nvars,
+                                        &perm[b * nvars], &perm[b * nvars] + nvars);
+  });
+  res->vals.resize((size_t)cur.rows * nvars);
+  for (int64_t i = 0; i < cur.rows; ++i)
+    for (int x = 0; x < nvars; ++x) res->vals[i * nvars + x] = perm[idx[i] * nvars + x];
+  return res;
+}
+
+int64_t oracle_result_rows(void* h) { return static_cast<Result*>(h)->rows; }
+int32_t oracle_result_nvars(void* h) { return static_cast<Result*>(h)->nvars; }
+
+void oracle_result_copy(void* h, int32_t* out) {
+  Result* r = static_cast<Result*>(h);
+  if (!r->vals.empty()) std::memcpy(out, r->vals.data(), r->vals.size() * sizeof(int32_t));
+}
+
+// Order-independent fingerprint of the row multiset: (rows, sum of h1, sum of
+// h2) modulo 2^64, with h_k a SplitMix64 chain over the row's values in
+// variable order started from seed k.
+void oracle_result_fingerprint(void* h, uint64_t* out3) {
+  Result* r = static_cast<Result*>(h);
+  uint64_t a = 0, b = 0;
+  for (int64_t i = 0; i < r->rows; ++i) {
+    uint64_t x = 0x1234567ULL, y = 0x89abcdefULL;
+    for (int c = 0; c < r->nvars; ++c) {
+      uint32_t v = (uint32_t)r->vals[i * r->nvars + c];
+      x = mix64(x ^ v);
+      y = mix64(y ^ v);
+    }
+    a += x;
+    b += y;
+  }
+  out3[0] = (uint64_t)r->rows;
+  out3[1] = a;
+  out3[2] = b;
+}
+
+void oracle_result_free(void* h) { delete static_cast<Result*>(h); }
+
+}  // extern "C"
