@@ -1,0 +1,226 @@
+/*
+ * gsmat: sparse-matrix BGP join on MI355X (gfx950) -- C ABI.
+ *
+ * Method (gSMat, arXiv 1807.07691):
+ *   - An RDF dataset is a SET of (subject, predicate, object) triples
+ *     (Sec. 3.1).  Vertices are caller-encoded int32 ids in [0, n_vertices),
+ *     predicates int32 ids in [0, n_predicates) (the integer codes of the
+ *     RDF cube, Sec. 5.1-5.2).
+ *   - Each predicate h owns a boolean sparse matrix M_h of (s, o) pairs
+ *     (Sec. 5.3), reached through a predicate-indexed table.  The library keeps
+ *     every M_h twice: row-compressed by subject and column-compressed by
+ *     object, each with the non-empty row ids, row offsets and member lists of
+ *     the auxiliary arrays Row/Num/Rpos (Sec. 6.3).
+ *   - A basic graph pattern (BGP) is a set of triple patterns (TPs) with a
+ *     constant predicate (Sec. 3.2, Sec. 6.3).  Its answer is the final
+ *     relation over all its variables obtained by joining the TP relations
+ *     (Sec. 6, "Initializing / Joining / Returning"); with set semantics it is
+ *     the set of assignments mu with (mu(s_i), p_i, mu(o_i)) in D for every i.
+ *   - The plan orders TPs by statistics, keeping every new TP connected to the
+ *     bound variables (Sec. 6.2, "connected minimal upper bound").
+ *   - Every join step counts its output per input row, prefix-sums the counts
+ *     and writes each row's output at its offset (Sec. 7.2.2, Algorithm
+ *     "Pre-allocating result matrix space").
+ *
+ * Conventions for every entry point:
+ *   - Return value: a gsmat_status; GSMAT_OK on success.  On error nothing is
+ *     returned through output pointers and gsmat_last_error() describes the
+ *     failure (thread-local).  No entry point throws or aborts.
+ *   - Argument validation happens before any device work.
+ *   - Handles (store, plan, result) are owned by the caller and released with
+ *     the matching *_free.  A plan or result must not outlive its store.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *     device work of a call is enqueued on that stream; calls return after
+ *     the work they need on the host side has completed.
+ *   - Device memory comes from the library's stream-ordered pool unless an
+ *     allocator is given to gsmat_load_triples.
+ *   - The store is immutable after gsmat_build_index; concurrent gsmat_join
+ *     calls on different streams (and different results) are allowed.
+ */
+#ifndef GSMAT_H
+#define GSMAT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t gsmat_status;
+enum {
+  GSMAT_OK = 0,
+  GSMAT_EINVAL = 1,       /* bad pointer, size or id; malformed BGP */
+  GSMAT_ENOMEM = 2,       /* device allocation failed, or budget below one row */
+  GSMAT_EHIP = 3,         /* HIP runtime error (no device, launch failure, ...) */
+  GSMAT_ESTATE = 4,       /* call out of order (e.g. join before build_index) */
+  GSMAT_EUNSUPPORTED = 5, /* variable predicate, or ids too wide to pack */
+  GSMAT_ETOOBIG = 6       /* result rows exceed the caller's max_rows */
+};
+
+typedef struct gsmat_store gsmat_store;   /* device CSR/CSC of every predicate */
+typedef struct gsmat_query_plan gsmat_query_plan; /* host-only ordered step list */
+typedef struct gsmat_result gsmat_result; /* device binding table, possibly in segments */
+
+/* Optional device allocator.  alloc returns NULL on failure.  free receives
+ * the pointer and size that alloc returned.  Both are called on the host
+ * thread of the gsmat call, with the stream the memory is used on. */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* stream, void* ctx);
+  void (*free)(void* ptr, size_t bytes, void* stream, void* ctx);
+  void* ctx;
+} gsmat_allocator;
+
+/* One triple pattern.  s and o: >= 0 is a vertex constant, < 0 is the
+ * variable number -(x+1).  p: a predicate constant (>= 0); a negative p
+ * (a variable predicate) is GSMAT_EUNSUPPORTED (Sec. 6.3 assumes it is known).
+ * The variables of a BGP must be numbered densely 0..n_vars-1. */
+typedef struct {
+  int32_t s, p, o;
+} gsmat_pattern;
+
+/* Step kinds reported by gsmat_plan_info. */
+enum {
+  GSMAT_STEP_SCAN = 0,      /* materialise one TP's relation (first step) */
+  GSMAT_STEP_INTERSECT = 1, /* star centre: intersect row/column id lists */
+  GSMAT_STEP_EXPAND = 2,    /* one endpoint bound: append the other's neighbours */
+  GSMAT_STEP_FILTER = 3,    /* both endpoints bound/constant: membership test */
+  GSMAT_STEP_CARTESIAN = 4  /* no shared variable: cross product */
+};
+
+/* Plan modes. */
+enum {
+  GSMAT_PLAN_PAPER = 0,   /* statistic = pair count of the predicate; pure
+                             connected-minimal-upper-bound order (Sec. 6.2.1) */
+  GSMAT_PLAN_DEFAULT = 1  /* statistic = triples the TP matches on its own;
+                             constant-only TPs first; star centre intersection
+                             as first step; filters before expansions */
+};
+
+typedef struct {
+  int32_t kind;        /* GSMAT_STEP_* */
+  int32_t tp;          /* the TP this step evaluates (INTERSECT: first member) */
+  int32_t orient;      /* EXPAND: 0 = from bound subject (row-compressed),
+                          1 = from bound object (column-compressed); else -1 */
+  int32_t var;         /* variable this step binds (INTERSECT: the centre; SCAN:
+                          the subject variable or the object variable if the
+                          subject is constant); -1 if none */
+  uint32_t members;    /* INTERSECT: bit i set if TP i is in the star */
+  int32_t pad;
+  int64_t est_rows;    /* upper bound on the rows after this step (saturated) */
+} gsmat_step_info;
+
+/* ---- storage (Sec. 5) ---------------------------------------------------- */
+
+/* Copies n host triples (s[i], p[i], o[i]) to the device.  Duplicates are
+ * allowed and removed by gsmat_build_index (D is a set).  EINVAL if any id is
+ * out of range, n < 0, or a pointer is NULL while n > 0; EUNSUPPORTED if
+ * bits(n_predicates-1) + 2*bits(n_vertices-1) > 64.  `alloc` may be NULL. */
+gsmat_status gsmat_load_triples(const int32_t* s, const int32_t* p, const int32_t* o, int64_t n,
+                                int32_t n_vertices, int32_t n_predicates,
+                                const gsmat_allocator* alloc, void* stream, gsmat_store** out);
+
+/* Builds, on the device, the per-predicate matrices: sort, deduplicate, split
+ * by predicate, compress by subject and by object, and record statistics
+ * (pair count, non-empty rows, non-empty columns) -- Sec. 5.3.  Predicates
+ * whose non-empty rows reach n_vertices/dense_div also get a dense row
+ * pointer (dense_div <= 0: default 32).  Idempotent. */
+gsmat_status gsmat_build_index(gsmat_store* st, int32_t dense_div, void* stream);
+
+/* Whole-store statistics: distinct triples, predicate count, device bytes
+ * held by the index.  ESTATE before build. */
+gsmat_status gsmat_store_stats(const gsmat_store* st, int64_t* n_triples, int32_t* n_predicates,
+                               int64_t* device_bytes);
+
+/* Statistics of one predicate: pairs, distinct subjects, distinct objects. */
+gsmat_status gsmat_pred_stats(const gsmat_store* st, int32_t pred, int64_t* nnz, int64_t* n_rows,
+                              int64_t* n_cols);
+
+/* Copies one predicate's compressed matrix to host buffers: orient 0 = by
+ * subject, 1 = by object.  keys[n_rows] (non-empty row ids ascending),
+ * ptr[n_rows+1] (0-based offsets; ptr[0] = 0), nbr[nnz] (members ascending
+ * within a row).  Sizes from gsmat_pred_stats (n_cols rows for orient 1). */
+gsmat_status gsmat_export_matrix(const gsmat_store* st, int32_t pred, int32_t orient,
+                                 int32_t* keys, int32_t* ptr, int32_t* nbr, void* stream);
+
+void gsmat_store_free(gsmat_store* st);
+
+/* ---- planning (Sec. 6.2) ------------------------------------------------- */
+
+/* Orders the n_pats TPs and classifies each step.  Statistics come from the
+ * store (mode GSMAT_PLAN_DEFAULT looks up the degrees of constants on the
+ * device).  EINVAL on malformed patterns or non-dense variable numbers,
+ * EUNSUPPORTED on a variable predicate or n_pats > 32. */
+gsmat_status gsmat_plan(const gsmat_store* st, const gsmat_pattern* pats, int32_t n_pats,
+                        int32_t mode, void* stream, gsmat_query_plan** out);
+
+/* Host-only planning from caller-supplied per-TP statistics (the sort keys,
+ * stat[i] >= 0) and per-TP "list sizes" for star intersection estimates
+ * (may be NULL: stat is used).  Same rules as gsmat_plan. */
+gsmat_status gsmat_plan_from_stats(const gsmat_pattern* pats, int32_t n_pats, int32_t mode,
+                                   const int64_t* stat, gsmat_query_plan** out);
+
+/* Number of steps and variables; steps[] receives up to `cap` entries. */
+gsmat_status gsmat_plan_info(const gsmat_query_plan* pl, int32_t* n_steps, int32_t* n_vars,
+                             gsmat_step_info* steps, int32_t cap);
+
+void gsmat_plan_free(gsmat_query_plan* pl);
+
+/* ---- execution (Sec. 6.3, Sec. 7.2) --------------------------------------- */
+
+/* Evaluates the plan on the device.  budget_bytes bounds each step's output
+ * buffer; a larger step is cut into output ranges that are carried through
+ * the remaining steps one at a time (chunked expansion, Sec. 7.3 "block
+ * transmission"); budget_bytes <= 0 means no limit.  max_rows < 0 means no
+ * limit; otherwise a result with more rows fails with ETOOBIG.  ENOMEM when an
+ * allocation fails or the budget cannot hold a single output row. */
+gsmat_status gsmat_join(gsmat_store* st, const gsmat_query_plan* pl, int64_t budget_bytes,
+                        int64_t max_rows, void* stream, gsmat_result** out);
+
+/* Result shape; per-step rows in/out (arrays of n_steps entries, may be NULL)
+ * are summed over chunks. */
+gsmat_status gsmat_result_info(const gsmat_result* r, int64_t* n_rows, int32_t* n_vars,
+                               int32_t* n_steps, int64_t* step_rows_in, int64_t* step_rows_out);
+
+/* Copies rows [row_offset, row_offset + max_rows) (clipped to the result) to
+ * host_rows, row-major [rows][n_vars], column j = variable j.  Row order is
+ * unspecified but fixed for a given result.  *n_written = rows copied. */
+gsmat_status gsmat_fetch_bindings(const gsmat_result* r, int64_t row_offset, int64_t max_rows,
+                                  int32_t* host_rows, int64_t* n_written, void* stream);
+
+void gsmat_result_free(gsmat_result* r);
+
+/* Thread-local message for the last non-OK status of this thread. */
+const char* gsmat_last_error(void);
+
+/* Waits for the device and returns the unused memory cached by the library's
+ * device pools to the driver (the pools stay usable).  Meant for process
+ * shutdown after every handle is freed, and for callers that need the memory
+ * back for other allocators. */
+gsmat_status gsmat_release_pools(void);
+
+/* ---- instrumentation ----------------------------------------------------- */
+
+/* Kernel classes timed when profiling is on. */
+enum {
+  GSMAT_K_COUNT = 0,    /* per-row output counts (+ tile sums) */
+  GSMAT_K_SCAN = 1,     /* prefix sums */
+  GSMAT_K_WRITE = 2,    /* expansion write (merge-path) */
+  GSMAT_K_COMPACT = 3,  /* ordered compaction for filters / intersections */
+  GSMAT_K_OTHER = 4,
+  GSMAT_K_NCLASS = 5
+};
+
+/* on != 0: record HIP events around kernels of every class on their stream
+ * (adds host overhead); on == 0: stop.  Resets the counters. */
+void gsmat_prof_enable(int32_t on);
+
+/* Per class: launches, summed kernel milliseconds, algorithmic bytes.  Waits
+ * for the recorded events.  Arrays of GSMAT_K_NCLASS entries. */
+gsmat_status gsmat_prof_read(int64_t* launches, double* ms, double* bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GSMAT_H */

@@ -1,0 +1,363 @@
+"""Python binding of libgsmat (sparse-matrix BGP join on MI355X).
+
+Argument marshalling only: every step of storage building, planning and the
+join runs inside the C-ABI library (HIP kernels for gfx950).  The function
+names are those of the C-ABI (include/gsmat.h).  The library is loaded from
+this directory; if it has not been built, importing the binding fails loudly.
+
+Streams: functions take an optional `stream` (an int hipStream_t handle).  By
+default torch's current stream on the current device is used when torch has a
+GPU, else the null stream.
+"""
+from __future__ import annotations
+
+import atexit
+import ctypes
+import os
+import weakref
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "libgsmat.so")
+
+GSMAT_OK, GSMAT_EINVAL, GSMAT_ENOMEM, GSMAT_EHIP, GSMAT_ESTATE, GSMAT_EUNSUPPORTED, GSMAT_ETOOBIG = range(7)
+STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EHIP", 4: "ESTATE", 5: "EUNSUPPORTED",
+                6: "ETOOBIG"}
+STEP_SCAN, STEP_INTERSECT, STEP_EXPAND, STEP_FILTER, STEP_CARTESIAN = range(5)
+STEP_NAMES = {0: "SCAN", 1: "INTERSECT", 2: "EXPAND", 3: "FILTER", 4: "CARTESIAN"}
+PLAN_PAPER, PLAN_DEFAULT = 0, 1
+K_COUNT, K_SCAN, K_WRITE, K_COMPACT, K_OTHER = range(5)
+K_NAMES = ["count", "scan", "write", "compact", "other"]
+EXPORTED = [
+    "gsmat_load_triples", "gsmat_build_index", "gsmat_store_stats", "gsmat_pred_stats",
+    "gsmat_export_matrix", "gsmat_store_free", "gsmat_plan", "gsmat_plan_from_stats",
+    "gsmat_plan_info", "gsmat_plan_free", "gsmat_join", "gsmat_result_info",
+    "gsmat_fetch_bindings", "gsmat_result_free", "gsmat_last_error", "gsmat_prof_enable",
+    "gsmat_prof_read", "gsmat_release_pools",
+]
+
+
+class GsmatError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class _Pattern(ctypes.Structure):
+    _fields_ = [("s", ctypes.c_int32), ("p", ctypes.c_int32), ("o", ctypes.c_int32)]
+
+
+class _StepInfo(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("tp", ctypes.c_int32), ("orient", ctypes.c_int32),
+                ("var", ctypes.c_int32), ("members", ctypes.c_uint32), ("pad", ctypes.c_int32),
+                ("est_rows", ctypes.c_int64)]
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class _Allocator(ctypes.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", ctypes.c_void_p)]
+
+
+def _load():
+    if not os.path.exists(_SO):
+        raise ImportError(
+            f"{_SO} is missing: build the HIP library first (python __graft_entry__.py build)")
+    L = ctypes.CDLL(_SO)
+    i32, i64, vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
+    pp = ctypes.POINTER(ctypes.c_void_p)
+    L.gsmat_load_triples.restype = i32
+    L.gsmat_load_triples.argtypes = [vp, vp, vp, i64, i32, i32, vp, vp, pp]
+    L.gsmat_build_index.restype = i32
+    L.gsmat_build_index.argtypes = [vp, i32, vp]
+    L.gsmat_store_stats.restype = i32
+    L.gsmat_store_stats.argtypes = [vp, vp, vp, vp]
+    L.gsmat_pred_stats.restype = i32
+    L.gsmat_pred_stats.argtypes = [vp, i32, vp, vp, vp]
+    L.gsmat_export_matrix.restype = i32
+    L.gsmat_export_matrix.argtypes = [vp, i32, i32, vp, vp, vp, vp]
+    L.gsmat_store_free.restype = None
+    L.gsmat_store_free.argtypes = [vp]
+    L.gsmat_plan.restype = i32
+    L.gsmat_plan.argtypes = [vp, vp, i32, i32, vp, pp]
+    L.gsmat_plan_from_stats.restype = i32
+    L.gsmat_plan_from_stats.argtypes = [vp, i32, i32, vp, pp]
+    L.gsmat_plan_info.restype = i32
+    L.gsmat_plan_info.argtypes = [vp, vp, vp, vp, i32]
+    L.gsmat_plan_free.restype = None
+    L.gsmat_plan_free.argtypes = [vp]
+    L.gsmat_join.restype = i32
+    L.gsmat_join.argtypes = [vp, vp, i64, i64, vp, pp]
+    L.gsmat_result_info.restype = i32
+    L.gsmat_result_info.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.gsmat_fetch_bindings.restype = i32
+    L.gsmat_fetch_bindings.argtypes = [vp, i64, i64, vp, vp, vp]
+    L.gsmat_result_free.restype = None
+    L.gsmat_result_free.argtypes = [vp]
+    L.gsmat_last_error.restype = ctypes.c_char_p
+    L.gsmat_last_error.argtypes = []
+    L.gsmat_prof_enable.restype = None
+    L.gsmat_prof_enable.argtypes = [i32]
+    L.gsmat_prof_read.restype = i32
+    L.gsmat_prof_read.argtypes = [vp, vp, vp]
+    L.gsmat_release_pools.restype = i32
+    L.gsmat_release_pools.argtypes = []
+    return L
+
+
+_lib = _load()
+
+
+def lib():
+    return _lib
+
+
+def library_path() -> str:
+    return _SO
+
+
+def _check(st):
+    if st != GSMAT_OK:
+        raise GsmatError(st, _lib.gsmat_last_error().decode(errors="replace"))
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def default_stream():
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return int(torch.cuda.current_stream().cuda_stream)
+    except Exception:  # torch absent or without a GPU: the null stream
+        pass
+    return 0
+
+
+def _stream(s):
+    return ctypes.c_void_p(default_stream() if s is None else int(s))
+
+
+# Live handles, closed in dependency order at interpreter exit (results and
+# plans before their stores) while the HIP runtime and torch are still up.
+_live_results = weakref.WeakSet()
+_live_plans = weakref.WeakSet()
+_live_stores = weakref.WeakSet()
+_used_device = [False]
+
+
+@atexit.register
+def _shutdown():
+    for group in (_live_results, _live_plans, _live_stores):
+        for obj in list(group):
+            try:
+                obj.close()
+            except Exception:
+                pass
+    if _used_device[0]:
+        _lib.gsmat_release_pools()
+
+
+class Store:
+    def __init__(self, handle, n_vertices, n_predicates):
+        self.h = handle
+        self.n_vertices = n_vertices
+        self.n_predicates = n_predicates
+        self._alloc_keep = None
+        _live_stores.add(self)
+        _used_device[0] = True
+
+    def close(self):
+        if self.h:
+            _lib.gsmat_store_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+
+class Plan:
+    def __init__(self, handle):
+        self.h = handle
+        _live_plans.add(self)
+
+    def close(self):
+        if self.h:
+            _lib.gsmat_plan_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+
+class Result:
+    def __init__(self, handle, store):
+        self.h = handle
+        self.store = store  # keeps the store alive while the result lives
+        _live_results.add(self)
+
+    def close(self):
+        if self.h:
+            _lib.gsmat_result_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+
+def _patterns(tps):
+    t = np.ascontiguousarray(np.asarray(tps, dtype=np.int32).reshape(-1, 3))
+    arr = (_Pattern * len(t))()
+    for i, (s, p, o) in enumerate(t.tolist()):
+        arr[i] = _Pattern(s, p, o)
+    return arr, len(t)
+
+
+def make_allocator(alloc_fn, free_fn):
+    """Wraps Python callables alloc(bytes, stream)->int and free(ptr, bytes, stream)
+    into a gsmat_allocator (kept alive by the returned object)."""
+    a = ALLOC_FN(lambda b, s, c: alloc_fn(b, s) or None)
+    f = FREE_FN(lambda ptr, b, s, c: free_fn(ptr, b, s))
+    return _Allocator(a, f, None), (a, f)
+
+
+def gsmat_load_triples(s, p, o, n_vertices, n_predicates, stream=None, allocator=None):
+    s = np.ascontiguousarray(s, np.int32)
+    p = np.ascontiguousarray(p, np.int32)
+    o = np.ascontiguousarray(o, np.int32)
+    if not (len(s) == len(p) == len(o)):
+        raise ValueError("s, p, o must have the same length")
+    h = ctypes.c_void_p()
+    aptr = None
+    keep = None
+    if allocator is not None:
+        struct, keep = allocator
+        aptr = ctypes.cast(ctypes.pointer(struct), ctypes.c_void_p)
+        keep = (keep, struct)
+    _check(_lib.gsmat_load_triples(_p(s), _p(p), _p(o), len(s), n_vertices, n_predicates, aptr,
+                                   _stream(stream), ctypes.byref(h)))
+    st = Store(h, n_vertices, n_predicates)
+    st._alloc_keep = keep
+    return st
+
+
+def gsmat_build_index(store, dense_div=0, stream=None):
+    _check(_lib.gsmat_build_index(store.h, dense_div, _stream(stream)))
+
+
+def gsmat_store_stats(store):
+    t, pr, b = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int64()
+    _check(_lib.gsmat_store_stats(store.h, ctypes.byref(t), ctypes.byref(pr), ctypes.byref(b)))
+    return {"n_triples": t.value, "n_predicates": pr.value, "device_bytes": b.value}
+
+
+def gsmat_pred_stats(store, pred):
+    a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(_lib.gsmat_pred_stats(store.h, pred, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    return a.value, b.value, c.value
+
+
+def gsmat_export_matrix(store, pred, orient, stream=None):
+    nnz, nr, nc = gsmat_pred_stats(store, pred)
+    rows = nr if orient == 0 else nc
+    keys = np.empty(rows, np.int32)
+    ptr = np.empty(rows + 1, np.int32)
+    nbr = np.empty(nnz, np.int32)
+    _check(_lib.gsmat_export_matrix(store.h, pred, orient, _p(keys), _p(ptr), _p(nbr),
+                                    _stream(stream)))
+    return keys, ptr, nbr
+
+
+def gsmat_plan(store, tps, mode=PLAN_DEFAULT, stream=None):
+    arr, n = _patterns(tps)
+    h = ctypes.c_void_p()
+    _check(_lib.gsmat_plan(store.h, arr, n, mode, _stream(stream), ctypes.byref(h)))
+    return Plan(h)
+
+
+def gsmat_plan_from_stats(tps, mode, stats):
+    arr, n = _patterns(tps)
+    st = np.ascontiguousarray(stats, np.int64)
+    h = ctypes.c_void_p()
+    _check(_lib.gsmat_plan_from_stats(arr, n, mode, _p(st), ctypes.byref(h)))
+    return Plan(h)
+
+
+def gsmat_plan_info(plan):
+    ns, nv = ctypes.c_int32(), ctypes.c_int32()
+    _check(_lib.gsmat_plan_info(plan.h, ctypes.byref(ns), ctypes.byref(nv), None, 0))
+    steps = (_StepInfo * max(ns.value, 1))()
+    _check(_lib.gsmat_plan_info(plan.h, ctypes.byref(ns), ctypes.byref(nv), steps, ns.value))
+    out = []
+    for i in range(ns.value):
+        s = steps[i]
+        out.append({"kind": STEP_NAMES[s.kind], "tp": s.tp, "orient": s.orient, "var": s.var,
+                    "members": [b for b in range(32) if s.members >> b & 1],
+                    "est_rows": s.est_rows})
+    return nv.value, out
+
+
+def gsmat_join(store, plan, budget_bytes=0, max_rows=-1, stream=None):
+    h = ctypes.c_void_p()
+    _check(_lib.gsmat_join(store.h, plan.h, budget_bytes, max_rows, _stream(stream),
+                           ctypes.byref(h)))
+    return Result(h, store)
+
+
+def gsmat_result_info(result):
+    rows, nv, ns = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
+    _check(_lib.gsmat_result_info(result.h, ctypes.byref(rows), ctypes.byref(nv),
+                                  ctypes.byref(ns), None, None))
+    si = np.zeros(max(ns.value, 1), np.int64)
+    so = np.zeros(max(ns.value, 1), np.int64)
+    _check(_lib.gsmat_result_info(result.h, None, None, None, _p(si), _p(so)))
+    return {"rows": rows.value, "n_vars": nv.value, "step_rows_in": si[:ns.value].tolist(),
+            "step_rows_out": so[:ns.value].tolist()}
+
+
+def gsmat_fetch_bindings(result, row_offset=0, max_rows=None, stream=None):
+    info = gsmat_result_info(result)
+    rows, nv = info["rows"], info["n_vars"]
+    if max_rows is None:
+        max_rows = rows
+    n = max(0, min(rows - min(row_offset, rows), max_rows))
+    out = np.empty((n, nv), np.int32)
+    written = ctypes.c_int64()
+    _check(_lib.gsmat_fetch_bindings(result.h, row_offset, max_rows,
+                                     _p(out) if out.size else None, ctypes.byref(written),
+                                     _stream(stream)))
+    return out[:written.value]
+
+
+def gsmat_release_pools():
+    _check(_lib.gsmat_release_pools())
+
+
+def gsmat_prof_enable(on=True):
+    _lib.gsmat_prof_enable(1 if on else 0)
+
+
+def gsmat_prof_read():
+    la = np.zeros(5, np.int64)
+    ms = np.zeros(5, np.float64)
+    by = np.zeros(5, np.float64)
+    _check(_lib.gsmat_prof_read(_p(la), _p(ms), _p(by)))
+    return {K_NAMES[i]: {"launches": int(la[i]), "ms": float(ms[i]), "bytes": float(by[i])}
+            for i in range(5)}
+
+
+def evaluate(store, tps, mode=PLAN_DEFAULT, budget_bytes=0, max_rows=-1, stream=None):
+    """Plan + join + fetch: all rows of the BGP as an (rows, n_vars) int32 array."""
+    pl = gsmat_plan(store, tps, mode, stream)
+    try:
+        r = gsmat_join(store, pl, budget_bytes, max_rows, stream)
+        try:
+            return gsmat_fetch_bindings(r, stream=stream)
+        finally:
+            r.close()
+    finally:
+        pl.close()

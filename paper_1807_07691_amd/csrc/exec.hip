@@ -1,0 +1,652 @@
+// Query execution (paper Sec. 6.3 and Sec. 7.2): runs a plan's steps over
+// device-resident binding tables.
+//
+// A binding table is columnar int32 (one array per bound variable).  Each
+// step follows the preallocation scheme of Algorithm "Pre-allocating result
+// matrix space": per input row, count the output rows (N_i); exclusive prefix
+// sum (P_i, int64); allocate exactly P_n rows; write every input row's
+// outputs at its offset.  Expansions write through a merge path over
+// (row ends, output indices) so hub rows are split across workgroups; filters
+// and star-centre intersections write through a stable ballot compaction.
+// When a step's output exceeds the byte budget it is cut into output ranges,
+// each carried through the remaining steps before the next one is produced
+// (chunked expansion); the final table may therefore consist of segments.
+#include <algorithm>
+#include <cstring>
+#include <memory>
+
+#include "store.hpp"
+
+using namespace gsmat;
+
+namespace gsmat {
+struct Segment {
+  int64_t rows = 0;
+  const int32_t* col[kMaxCols] = {};  // variable order
+  void* owned = nullptr;
+  size_t owned_bytes = 0;
+};
+}  // namespace gsmat
+
+struct gsmat_result {
+  gsmat_store* st = nullptr;
+  hipStream_t stream = nullptr;
+  int32_t n_vars = 0;
+  int64_t rows = 0;
+  std::vector<gsmat::Segment> segs;
+  std::vector<int64_t> step_in, step_out;
+  ~gsmat_result() {
+    for (auto& s : segs)
+      if (s.owned) st->mem->free(s.owned, s.owned_bytes, stream);
+  }
+};
+
+namespace {
+
+inline bool is_var(int32_t t) { return t < 0; }
+inline int var_of(int32_t t) { return -t - 1; }
+
+struct Table {
+  int64_t n = 0;
+  int k = 0;
+  const int32_t* col[kMaxCols] = {};
+  int var[kMaxCols] = {};
+  void* owned = nullptr;
+  size_t owned_bytes = 0;
+  bool unit() const { return n == 1 && k == 0; }
+  int col_of(int v) const {
+    for (int c = 0; c < k; ++c)
+      if (var[c] == v) return c;
+    return -1;
+  }
+};
+
+template <class T>
+struct Tmp {
+  DeviceMem* mem;
+  hipStream_t s;
+  T* p = nullptr;
+  size_t bytes = 0;
+  Tmp(DeviceMem* m, int64_t n, hipStream_t st) : mem(m), s(st) {
+    bytes = sizeof(T) * (size_t)std::max<int64_t>(n, 1);
+    p = (T*)mem->alloc(bytes, s);
+    if (!p) throw OomFail{bytes};
+  }
+  ~Tmp() {
+    if (p) mem->free(p, bytes, s);
+  }
+  Tmp(const Tmp&) = delete;
+  Tmp& operator=(const Tmp&) = delete;
+};
+
+int64_t* pinned_slot() {
+  thread_local int64_t* slot = nullptr;
+  if (!slot) GS_HIP(hipHostMalloc((void**)&slot, 64, hipHostMallocDefault));
+  return slot;
+}
+
+int64_t read_total(const int64_t* d, hipStream_t s) {
+  int64_t* h = pinned_slot();
+  GS_HIP(hipMemcpyAsync(h, d, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  GS_HIP(hipStreamSynchronize(s));
+  return h[0];
+}
+
+struct Exec {
+  gsmat_store* st;
+  const gsmat_query_plan* pl;
+  hipStream_t s;
+  int64_t budget;
+  int64_t max_rows;
+  gsmat_result* res;
+
+  // table allocations not yet released or handed to the result
+  std::vector<std::pair<void*, size_t>> live;
+
+  DeviceMem* mem() { return st->mem.get(); }
+
+  void forget(void* p) {
+    for (size_t i = 0; i < live.size(); ++i)
+      if (live[i].first == p) {
+        live[i] = live.back();
+        live.pop_back();
+        return;
+      }
+  }
+
+  void release(Table& t) {
+    if (t.owned) {
+      forget(t.owned);
+      mem()->free(t.owned, t.owned_bytes, s);
+    }
+    t.owned = nullptr;
+  }
+
+  // frees every table still alive (error paths)
+  void release_all() {
+    for (auto& a : live) mem()->free(a.first, a.second, s);
+    live.clear();
+  }
+
+  // Allocates a table of n rows for the given variables (columns in order).
+  Table alloc_table(int64_t n, const int* vars, int k) {
+    Table t;
+    t.n = n;
+    t.k = k;
+    const size_t bytes = sizeof(int32_t) * (size_t)std::max<int64_t>(n, 1) * (size_t)std::max(k, 1);
+    if (k > 0) {
+      t.owned = mem()->alloc(bytes, s);
+      if (!t.owned) throw OomFail{bytes};
+      t.owned_bytes = bytes;
+      live.push_back({t.owned, bytes});
+    }
+    for (int c = 0; c < k; ++c) {
+      t.var[c] = vars[c];
+      t.col[c] = (int32_t*)t.owned + (size_t)c * (size_t)n;
+    }
+    return t;
+  }
+
+  LookupRes lookup(int orient, int32_t p, int32_t v, int32_t member) {
+    Tmp<LookupReq> req(mem(), 1, s);
+    Tmp<LookupRes> out(mem(), 1, s);
+    LookupReq q{orient, p, v, member};
+    GS_HIP(hipMemcpyAsync(req.p, &q, sizeof(q), hipMemcpyHostToDevice, s));
+    launch_lookup(req.p, 1, st->out.d_desc, st->in.d_desc, st->out.keys, st->out.ptr, st->out.nbr,
+                  st->out.dense, st->in.keys, st->in.ptr, st->in.nbr, st->in.dense, out.p, s);
+    LookupRes r;
+    GS_HIP(hipMemcpyAsync(&r, out.p, sizeof(r), hipMemcpyDeviceToHost, s));
+    GS_HIP(hipStreamSynchronize(s));
+    return r;
+  }
+
+  void emit(Table& t) {
+    const int nv = pl->n_vars;
+    Segment seg;
+    seg.rows = t.n;
+    for (int v = 0; v < nv; ++v) {
+      const int c = t.col_of(v);
+      if (c < 0) throw StatusFail{GSMAT_EHIP, "internal: unbound variable at the end of the plan"};
+      seg.col[v] = t.col[c];
+    }
+    seg.owned = t.owned;
+    seg.owned_bytes = t.owned_bytes;
+    if (t.owned) forget(t.owned);
+    t.owned = nullptr;
+    res->rows += seg.rows;
+    res->segs.push_back(seg);
+    if (max_rows >= 0 && res->rows > max_rows)
+      throw StatusFail{GSMAT_ETOOBIG, "result exceeds max_rows (" + std::to_string(max_rows) + ")"};
+  }
+
+  int64_t chunk_rows(int width) {
+    if (budget <= 0) return INT64_MAX;
+    const int64_t r = budget / (4 * (int64_t)std::max(width, 1));
+    if (r < 1) throw StatusFail{GSMAT_ENOMEM, "budget_bytes cannot hold one output row"};
+    return r;
+  }
+
+  // The relation of one TP on its own (views into the store where possible).
+  Table tp_relation(int tp) {
+    const gsmat_pattern& q = pl->pats[tp];
+    const int32_t p = q.p;
+    Table t;
+    if (is_var(q.s) && is_var(q.o)) {
+      const PredView pv = st->out.view(p);
+      if (q.s != q.o) {
+        t.n = pv.nnz;
+        t.k = 2;
+        t.col[0] = pv.src;
+        t.var[0] = var_of(q.s);
+        t.col[1] = pv.nbr;
+        t.var[1] = var_of(q.o);
+        return t;
+      }
+      // (?x p ?x): the diagonal
+      const int64_t n = pv.nnz;
+      const int64_t nt = ceil_div(std::max<int64_t>(n, 1), kTile);
+      Tmp<uint8_t> flags(mem(), n, s);
+      Tmp<int64_t> ts(mem(), nt + 1, s);
+      if (n > 0) launch_flag_diag(pv.src, pv.nbr, n, flags.p, ts.p, s);
+      launch_scan_tile_sums(ts.p, nt, ts.p + nt, s);
+      const int64_t m = n > 0 ? read_total(ts.p + nt, s) : 0;
+      int v = var_of(q.s);
+      Table o = alloc_table(m, &v, 1);
+      if (m > 0) {
+        ColSet in{};
+        in.c[0] = pv.src;
+        OutSet out{};
+        out.c[0] = const_cast<int32_t*>(o.col[0]);
+        launch_compact_cols(in, 1, flags.p, n, ts.p, out, s);
+      }
+      return o;
+    }
+    if (!is_var(q.s) && is_var(q.o)) {
+      const LookupRes r = lookup(0, p, q.s, -1);
+      const PredView pv = st->out.view(p);
+      t.n = r.len;
+      t.k = 1;
+      t.col[0] = pv.nbr + r.start;
+      t.var[0] = var_of(q.o);
+      return t;
+    }
+    if (is_var(q.s) && !is_var(q.o)) {
+      const LookupRes r = lookup(1, p, q.o, -1);
+      const PredView pv = st->in.view(p);
+      t.n = r.len;
+      t.k = 1;
+      t.col[0] = pv.nbr + r.start;
+      t.var[0] = var_of(q.s);
+      return t;
+    }
+    const LookupRes r = lookup(0, p, q.s, q.o);
+    t.n = r.found ? 1 : 0;
+    t.k = 0;
+    return t;
+  }
+
+  void run(int si, Table& t) {
+    if (t.n == 0) {
+      release(t);
+      return;
+    }
+    if (si == (int)pl->steps.size()) {
+      emit(t);
+      return;
+    }
+    const gsmat_step_info& sp = pl->steps[si];
+    res->step_in[si] += t.n;
+    switch (sp.kind) {
+      case GSMAT_STEP_SCAN:
+      case GSMAT_STEP_CARTESIAN: {
+        Table r = tp_relation(sp.tp);
+        combine(si, t, r);
+        break;
+      }
+      case GSMAT_STEP_INTERSECT: {
+        Table r = intersect(sp);
+        combine(si, t, r);
+        break;
+      }
+      case GSMAT_STEP_FILTER:
+        filter(si, t);
+        break;
+      case GSMAT_STEP_EXPAND:
+        expand(si, t);
+        break;
+      default:
+        throw StatusFail{GSMAT_EINVAL, "unknown step kind"};
+    }
+  }
+
+  // t x r: r alone when t is the unit table, else the Cartesian product.
+  void combine(int si, Table& t, Table& r) {
+    if (t.unit()) {
+      res->step_out[si] += r.n;
+      release(t);
+      run(si + 1, r);
+      return;
+    }
+    if (r.n == 0) {
+      release(t);
+      release(r);
+      return;
+    }
+    if (t.k + r.k > kMaxCols) throw StatusFail{GSMAT_EUNSUPPORTED, "too many columns"};
+    if (r.n > 0 && t.n > INT64_MAX / r.n) throw StatusFail{GSMAT_ETOOBIG, "Cartesian product overflows"};
+    const int64_t m = t.n * r.n;
+    res->step_out[si] += m;
+    int vars[kMaxCols];
+    for (int c = 0; c < t.k; ++c) vars[c] = t.var[c];
+    for (int c = 0; c < r.k; ++c) vars[t.k + c] = r.var[c];
+    const int k = t.k + r.k;
+    const int64_t rpc = chunk_rows(k);
+    ColSet a{}, b{};
+    for (int c = 0; c < t.k; ++c) a.c[c] = t.col[c];
+    for (int c = 0; c < r.k; ++c) b.c[c] = r.col[c];
+    for (int64_t J0 = 0; J0 < m; J0 += rpc) {
+      const int64_t J1 = std::min(m, J0 + rpc);
+      Table o = alloc_table(J1 - J0, vars, k);
+      OutSet out{};
+      for (int c = 0; c < k; ++c) out.c[c] = const_cast<int32_t*>(o.col[c]);
+      if (k > 0) launch_cartesian(a, t.k, t.n, b, r.k, r.n, J0, J1, out, s);
+      run(si + 1, o);
+    }
+    release(t);
+    release(r);
+  }
+
+  Table intersect(const gsmat_step_info& sp) {
+    const int32_t cterm = -(sp.var + 1);
+    struct L {
+      ListRef ref;
+      const int32_t* ids;  // the list as an array (row ids or segment)
+    };
+    std::vector<L> lists;
+    for (int tp = 0; tp < (int)pl->pats.size(); ++tp) {
+      if (!(sp.members >> tp & 1)) continue;
+      const gsmat_pattern& q = pl->pats[tp];
+      L l{};
+      if (q.s == cterm && is_var(q.o)) {
+        l.ref.pv = st->out.view(q.p);
+        l.ref.is_keys = 1;
+        l.ref.len = l.ref.pv.nr;
+        l.ids = l.ref.pv.keys;
+      } else if (q.o == cterm && is_var(q.s)) {
+        l.ref.pv = st->in.view(q.p);
+        l.ref.is_keys = 1;
+        l.ref.len = l.ref.pv.nr;
+        l.ids = l.ref.pv.keys;
+      } else if (q.s == cterm) {  // (v p c): v among the subjects of object c
+        const LookupRes r = lookup(1, q.p, q.o, -1);
+        l.ref.seg = st->in.view(q.p).nbr + r.start;
+        l.ref.len = r.len;
+        l.ids = l.ref.seg;
+      } else {  // (c p v): v among the objects of subject c
+        const LookupRes r = lookup(0, q.p, q.s, -1);
+        l.ref.seg = st->out.view(q.p).nbr + r.start;
+        l.ref.len = r.len;
+        l.ids = l.ref.seg;
+      }
+      lists.push_back(l);
+    }
+    Table t;
+    t.k = 1;
+    t.var[0] = sp.var;
+    size_t d = 0;
+    for (size_t i = 1; i < lists.size(); ++i)
+      if (lists[i].ref.len < lists[d].ref.len) d = i;
+    const int64_t n = lists[d].ref.len;
+    if (n == 0) {
+      t.n = 0;
+      return t;
+    }
+    ListSet ls{};
+    for (size_t i = 0; i < lists.size(); ++i)
+      if (i != d) ls.l[ls.n++] = lists[i].ref;
+    const int64_t nt = ceil_div(n, kTile);
+    Tmp<uint8_t> flags(mem(), n, s);
+    Tmp<int64_t> ts(mem(), nt + 1, s);
+    launch_flag_intersect(lists[d].ids, n, ls, flags.p, ts.p, s);
+    launch_scan_tile_sums(ts.p, nt, ts.p + nt, s);
+    const int64_t m = read_total(ts.p + nt, s);
+    if (m == n) {  // every driver id survives: the driver list itself
+      t.n = n;
+      t.col[0] = lists[d].ids;
+      return t;
+    }
+    int v = sp.var;
+    Table o = alloc_table(m, &v, 1);
+    if (m > 0) {
+      ColSet in{};
+      in.c[0] = lists[d].ids;
+      OutSet out{};
+      out.c[0] = const_cast<int32_t*>(o.col[0]);
+      launch_compact_cols(in, 1, flags.p, n, ts.p, out, s);
+    }
+    return o;
+  }
+
+  void filter(int si, Table& t) {
+    const gsmat_pattern& q = pl->pats[pl->steps[si].tp];
+    if (!is_var(q.s) && !is_var(q.o)) {
+      const LookupRes r = lookup(0, q.p, q.s, q.o);
+      if (r.found) {
+        res->step_out[si] += t.n;
+        run(si + 1, t);
+      } else {
+        release(t);
+      }
+      return;
+    }
+    ProbeArgs pa{};
+    if (is_var(q.s)) pa.s_col = t.col[t.col_of(var_of(q.s))];
+    else pa.s_const = q.s;
+    if (is_var(q.o)) pa.o_col = t.col[t.col_of(var_of(q.o))];
+    else pa.o_const = q.o;
+    const PredView pv = st->out.view(q.p);
+    const int64_t n = t.n;
+    const int64_t nt = ceil_div(n, kTile);
+    Tmp<uint8_t> flags(mem(), n, s);
+    Tmp<int64_t> ts(mem(), nt + 1, s);
+    launch_flag_filter(pa, n, pv, flags.p, ts.p, s);
+    launch_scan_tile_sums(ts.p, nt, ts.p + nt, s);
+    const int64_t m = read_total(ts.p + nt, s);
+    res->step_out[si] += m;
+    if (m == n) {  // nothing removed: pass the table on unchanged
+      run(si + 1, t);
+      return;
+    }
+    if (m == 0) {
+      release(t);
+      return;
+    }
+    Table o = alloc_table(m, t.var, t.k);
+    ColSet in{};
+    OutSet out{};
+    for (int c = 0; c < t.k; ++c) {
+      in.c[c] = t.col[c];
+      out.c[c] = const_cast<int32_t*>(o.col[c]);
+    }
+    launch_compact_cols(in, t.k, flags.p, n, ts.p, out, s);
+    release(t);
+    run(si + 1, o);
+  }
+
+  void expand(int si, Table& t) {
+    const gsmat_step_info& sp = pl->steps[si];
+    const gsmat_pattern& q = pl->pats[sp.tp];
+    const int bound_var = sp.orient == 0 ? var_of(q.s) : var_of(q.o);
+    const int new_var = sp.orient == 0 ? var_of(q.o) : var_of(q.s);
+    const int bc = t.col_of(bound_var);
+    if (bc < 0) throw StatusFail{GSMAT_EHIP, "internal: expansion from an unbound variable"};
+    if (t.k + 1 > kMaxCols) throw StatusFail{GSMAT_EUNSUPPORTED, "too many columns"};
+    const PredView pv = sp.orient == 0 ? st->out.view(q.p) : st->in.view(q.p);
+    const int64_t n = t.n;
+    const int64_t nt = ceil_div(n, kTile);
+    Tmp<int32_t> N(mem(), n, s), start(mem(), n, s);
+    Tmp<int64_t> ts(mem(), nt + 1, s), P(mem(), n + 1, s);
+    launch_count_expand(t.col[bc], n, pv, N.p, start.p, ts.p, s);
+    launch_scan_tile_sums(ts.p, nt, ts.p + nt, s);
+    const int64_t m = read_total(ts.p + nt, s);
+    res->step_out[si] += m;
+    if (m == 0) {
+      release(t);
+      return;
+    }
+    launch_scan_add_i32(N.p, n, ts.p, P.p, s);
+    int vars[kMaxCols];
+    for (int c = 0; c < t.k; ++c) vars[c] = t.var[c];
+    vars[t.k] = new_var;
+    const int k = t.k;
+    const int64_t rpc = chunk_rows(k + 1);
+    ColSet in{};
+    for (int c = 0; c < k; ++c) in.c[c] = t.col[c];
+    for (int64_t J0 = 0; J0 < m; J0 += rpc) {
+      const int64_t J1 = std::min(m, J0 + rpc);
+      const int64_t ntiles = ceil_div(n + (J1 - J0), kTile);
+      Tmp<int64_t> split(mem(), ntiles + 1, s);
+      launch_mp_partition(P.p, n, J0, J1, split.p, ntiles, s);
+      Table o = alloc_table(J1 - J0, vars, k + 1);
+      OutSet out{};
+      for (int c = 0; c <= k; ++c) out.c[c] = const_cast<int32_t*>(o.col[c]);
+      const double parents = (double)n * (double)(J1 - J0) / (double)m;
+      const double bytes = 4.0 * (double)(J1 - J0) * (k + 2) + parents * (4.0 * k + 12.0);
+      launch_write_expand(in, k, P.p, start.p, n, pv.nbr, J0, J1, split.p, ntiles, out, bytes, s);
+      run(si + 1, o);
+    }
+    release(t);
+  }
+};
+
+// Statistics of each pattern for the planner.
+std::vector<TpStat> pattern_stats(const gsmat_store* st, const gsmat_pattern* pats, int n,
+                                  int mode, hipStream_t s) {
+  std::vector<TpStat> out(n);
+  std::vector<LookupReq> reqs;
+  std::vector<int> req_of(n, -1);
+  for (int i = 0; i < n; ++i) {
+    const gsmat_pattern& q = pats[i];
+    TpStat& t = out[i];
+    if (q.p < 0 || q.p >= st->P) continue;  // absent predicate: empty relation
+    const PredDesc& dout = st->out.desc[q.p];
+    const PredDesc& din = st->in.desc[q.p];
+    t.stat = dout.nnz;
+    t.rows_s = dout.nr;
+    t.rows_o = din.nr;
+    if (mode != GSMAT_PLAN_DEFAULT) continue;
+    const bool sc = !is_var(q.s), oc = !is_var(q.o);
+    if ((sc && q.s >= st->V) || (oc && q.o >= st->V)) {
+      t.stat = t.rows_s = t.rows_o = 0;
+      continue;
+    }
+    if (sc && oc) {
+      req_of[i] = (int)reqs.size();
+      reqs.push_back({0, q.p, q.s, q.o});
+    } else if (sc) {
+      req_of[i] = (int)reqs.size();
+      reqs.push_back({0, q.p, q.s, -1});
+    } else if (oc) {
+      req_of[i] = (int)reqs.size();
+      reqs.push_back({1, q.p, q.o, -1});
+    }
+  }
+  if (!reqs.empty()) {
+    DeviceMem* mem = st->mem.get();
+    Tmp<LookupReq> dreq(mem, (int64_t)reqs.size(), s);
+    Tmp<LookupRes> dres(mem, (int64_t)reqs.size(), s);
+    std::vector<LookupRes> res(reqs.size());
+    GS_HIP(hipMemcpyAsync(dreq.p, reqs.data(), sizeof(LookupReq) * reqs.size(), hipMemcpyHostToDevice, s));
+    launch_lookup(dreq.p, (int)reqs.size(), st->out.d_desc, st->in.d_desc, st->out.keys,
+                  st->out.ptr, st->out.nbr, st->out.dense, st->in.keys, st->in.ptr, st->in.nbr,
+                  st->in.dense, dres.p, s);
+    GS_HIP(hipMemcpyAsync(res.data(), dres.p, sizeof(LookupRes) * reqs.size(), hipMemcpyDeviceToHost, s));
+    GS_HIP(hipStreamSynchronize(s));
+    for (int i = 0; i < n; ++i) {
+      if (req_of[i] < 0) continue;
+      const LookupRes& r = res[req_of[i]];
+      const gsmat_pattern& q = pats[i];
+      const bool sc = !is_var(q.s), oc = !is_var(q.o);
+      const int64_t v = (sc && oc) ? r.found : r.len;
+      out[i].stat = v;
+      out[i].rows_s = v;
+      out[i].rows_o = v;
+    }
+  }
+  return out;
+}
+
+}  // namespace
+
+extern "C" gsmat_status gsmat_plan(const gsmat_store* st, const gsmat_pattern* pats,
+                                   int32_t n_pats, int32_t mode, void* stream, gsmat_query_plan** out) {
+  return guarded([&]() -> gsmat_status {
+    if (!out) throw StatusFail{GSMAT_EINVAL, "out is NULL"};
+    *out = nullptr;
+    if (!st) throw StatusFail{GSMAT_EINVAL, "store is NULL"};
+    std::string err;
+    int32_t nv = 0;
+    gsmat_status rc = validate_patterns(pats, n_pats, &nv, &err);
+    if (rc != GSMAT_OK) throw StatusFail{rc, err};
+    if (!st->built) throw StatusFail{GSMAT_ESTATE, "index not built"};
+    std::vector<TpStat> ts = pattern_stats(st, pats, n_pats, mode, (hipStream_t)stream);
+    std::unique_ptr<gsmat_query_plan> pl(new gsmat_query_plan);
+    rc = build_plan(pats, n_pats, mode, ts, pl.get(), &err);
+    if (rc != GSMAT_OK) throw StatusFail{rc, err};
+    *out = pl.release();
+    return GSMAT_OK;
+  });
+}
+
+extern "C" gsmat_status gsmat_join(gsmat_store* st, const gsmat_query_plan* pl, int64_t budget_bytes,
+                                   int64_t max_rows, void* stream, gsmat_result** out) {
+  return guarded([&]() -> gsmat_status {
+    if (!out) throw StatusFail{GSMAT_EINVAL, "out is NULL"};
+    *out = nullptr;
+    if (!st || !pl) throw StatusFail{GSMAT_EINVAL, "store or plan is NULL"};
+    if (!st->built) throw StatusFail{GSMAT_ESTATE, "index not built"};
+    hipStream_t s = (hipStream_t)stream;
+    std::unique_ptr<gsmat_result> res(new gsmat_result);
+    res->st = st;
+    res->stream = s;
+    res->n_vars = pl->n_vars;
+    res->step_in.assign(pl->steps.size(), 0);
+    res->step_out.assign(pl->steps.size(), 0);
+    // a pattern over an absent predicate or vertex matches nothing
+    bool empty = false;
+    for (const gsmat_pattern& q : pl->pats) {
+      if (q.p >= st->P) empty = true;
+      if (!is_var(q.s) && q.s >= st->V) empty = true;
+      if (!is_var(q.o) && q.o >= st->V) empty = true;
+    }
+    if (!empty) {
+      Exec ex{st, pl, s, budget_bytes, max_rows, res.get(), {}};
+      Table unit;
+      unit.n = 1;
+      unit.k = 0;
+      try {
+        ex.run(0, unit);
+      } catch (...) {
+        ex.release_all();
+        throw;
+      }
+      GS_HIP(hipStreamSynchronize(s));
+    }
+    *out = res.release();
+    return GSMAT_OK;
+  });
+}
+
+extern "C" gsmat_status gsmat_result_info(const gsmat_result* r, int64_t* n_rows, int32_t* n_vars,
+                                          int32_t* n_steps, int64_t* step_rows_in,
+                                          int64_t* step_rows_out) {
+  return guarded([&]() -> gsmat_status {
+    if (!r) throw StatusFail{GSMAT_EINVAL, "result is NULL"};
+    if (n_rows) *n_rows = r->rows;
+    if (n_vars) *n_vars = r->n_vars;
+    if (n_steps) *n_steps = (int32_t)r->step_in.size();
+    if (step_rows_in) std::copy(r->step_in.begin(), r->step_in.end(), step_rows_in);
+    if (step_rows_out) std::copy(r->step_out.begin(), r->step_out.end(), step_rows_out);
+    return GSMAT_OK;
+  });
+}
+
+extern "C" gsmat_status gsmat_fetch_bindings(const gsmat_result* r, int64_t row_offset,
+                                             int64_t max_rows, int32_t* host_rows,
+                                             int64_t* n_written, void* stream) {
+  return guarded([&]() -> gsmat_status {
+    if (!r) throw StatusFail{GSMAT_EINVAL, "result is NULL"};
+    if (row_offset < 0 || max_rows < 0) throw StatusFail{GSMAT_EINVAL, "negative offset or count"};
+    const int64_t lo = std::min(row_offset, r->rows);
+    const int64_t hi = std::min(r->rows, lo + max_rows);
+    if (n_written) *n_written = hi - lo;
+    const int nv = r->n_vars;
+    if (hi <= lo || nv == 0) return GSMAT_OK;
+    if (!host_rows) throw StatusFail{GSMAT_EINVAL, "host_rows is NULL"};
+    hipStream_t s = (hipStream_t)stream;
+    DeviceMem* mem = r->st->mem.get();
+    const int64_t stage_rows = std::min<int64_t>(hi - lo, (int64_t)1 << 24);
+    Tmp<int32_t> stage(mem, stage_rows * nv, s);
+    int64_t seg_lo = 0;
+    int64_t written = 0;
+    for (const Segment& seg : r->segs) {
+      const int64_t seg_hi = seg_lo + seg.rows;
+      int64_t a = std::max(lo, seg_lo), b = std::min(hi, seg_hi);
+      while (a < b) {
+        const int64_t c = std::min(b - a, stage_rows);
+        ColSet cs{};
+        for (int v = 0; v < nv; ++v) cs.c[v] = seg.col[v];
+        launch_pack_rows(cs, nv, a - seg_lo, c, stage.p, s);
+        GS_HIP(hipMemcpyAsync(host_rows + written * nv, stage.p, sizeof(int32_t) * c * nv,
+                              hipMemcpyDeviceToHost, s));
+        GS_HIP(hipStreamSynchronize(s));
+        written += c;
+        a += c;
+      }
+      seg_lo = seg_hi;
+    }
+    return GSMAT_OK;
+  });
+}
+
+extern "C" void gsmat_result_free(gsmat_result* r) { delete r; }

@@ -1,0 +1,851 @@
+// Device kernels of the gsmat library (CDNA4 / gfx950, wave64).
+//
+// All per-row work uses the same tiling: a workgroup of kBlock threads owns a
+// tile of kTile consecutive items and thread t touches items t, t+kBlock, ...,
+// so every global access of a tile is coalesced.  Kernels that feed a prefix
+// sum also write one partial sum per tile; the offsets are then produced by a
+// small single-workgroup scan over the tile sums and an add pass.  Ordered
+// (stable) compaction ranks the kept items of a tile with wave ballots and
+// mbcnt, so output order equals input order.
+#include <hip/hip_runtime.h>
+
+#include "common.hpp"
+
+namespace gsmat {
+
+namespace {
+
+__device__ inline int lane_id() { return threadIdx.x & 63; }
+__device__ inline int wave_id() { return threadIdx.x >> 6; }
+constexpr int kWaves = kBlock / 64;
+
+__device__ inline uint32_t mbcnt(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__device__ inline int64_t wave_incl_scan(int64_t v) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    int64_t t = __shfl_up(v, d, 64);
+    if (lane >= d) v += t;
+  }
+  return v;
+}
+
+__device__ inline int64_t wave_sum(int64_t v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+  return v;
+}
+
+// Exclusive scan of one value per thread over the workgroup.  Contains
+// barriers: every thread of the block must call it.
+__device__ inline int64_t block_excl_scan(int64_t v, int64_t* total) {
+  __shared__ int64_t ws[kWaves];
+  const int64_t inc = wave_incl_scan(v);
+  if (lane_id() == 63) ws[wave_id()] = inc;
+  __syncthreads();
+  int64_t off = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < kWaves; ++i) {
+    if (i < wave_id()) off += ws[i];
+    tot += ws[i];
+  }
+  __syncthreads();
+  *total = tot;
+  return off + inc - v;
+}
+
+__device__ inline int64_t block_sum(int64_t v) {
+  __shared__ int64_t ws[kWaves];
+  v = wave_sum(v);
+  if (lane_id() == 0) ws[wave_id()] = v;
+  __syncthreads();
+  int64_t tot = 0;
+#pragma unroll
+  for (int i = 0; i < kWaves; ++i) tot += ws[i];
+  __syncthreads();
+  return tot;
+}
+
+__device__ inline int32_t lower_bound_i32(const int32_t* __restrict__ a, int32_t n, int32_t v) {
+  int32_t lo = 0, len = n;
+  while (len > 0) {
+    int32_t half = len >> 1;
+    if (a[lo + half] < v) {
+      lo += half + 1;
+      len -= half + 1;
+    } else {
+      len = half;
+    }
+  }
+  return lo;
+}
+
+// Row of vertex v in one predicate's compressed matrix: (start, len), len 0
+// when v has no entry.
+__device__ inline void row_lookup(const PredView& pv, int32_t v, int32_t& start, int32_t& len) {
+  if (pv.dense) {
+    start = pv.dense[v];
+    len = pv.dense[v + 1] - start;
+    return;
+  }
+  const int32_t r = lower_bound_i32(pv.keys, pv.nr, v);
+  if (r < pv.nr && pv.keys[r] == v) {
+    start = pv.ptr[r];
+    len = pv.ptr[r + 1] - start;
+  } else {
+    start = 0;
+    len = 0;
+  }
+}
+
+__device__ inline bool seg_contains(const int32_t* __restrict__ a, int32_t n, int32_t v) {
+  const int32_t r = lower_bound_i32(a, n, v);
+  return r < n && a[r] == v;
+}
+
+// Stable compaction of one tile: emit(i, pos) for each kept item i, pos
+// counted from base.  Barriers inside: all threads must call.
+template <class Keep, class Emit>
+__device__ inline void compact_tile(int64_t n, int64_t base, Keep keep, Emit emit) {
+  __shared__ uint32_t wtot[kWaves];
+  const int64_t tile0 = (int64_t)blockIdx.x * kTile;
+  int64_t running = base;
+  for (int j = 0; j < kItems; ++j) {
+    const int64_t i = tile0 + (int64_t)j * kBlock + threadIdx.x;
+    const bool f = (i < n) && keep(i);
+    const uint64_t m = __ballot(f);
+    const uint32_t rank = mbcnt(m);
+    if (lane_id() == 0) wtot[wave_id()] = (uint32_t)__popcll(m);
+    __syncthreads();
+    uint32_t wp = 0, tot = 0;
+#pragma unroll
+    for (int q = 0; q < kWaves; ++q) {
+      const uint32_t c = wtot[q];
+      if (q < wave_id()) wp += c;
+      tot += c;
+    }
+    if (f) emit(i, running + wp + rank);
+    running += tot;
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- prefix sums
+__global__ __launch_bounds__(kBlock) void k_scan_tile_sums(int64_t* ts, int64_t nt,
+                                                           int64_t* total) {
+  int64_t carry = 0;
+  for (int64_t c0 = 0; c0 < nt; c0 += kTile) {
+    int64_t v[kItems];
+    int64_t loc = 0;
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+      const int64_t i = c0 + (int64_t)threadIdx.x * kItems + j;
+      v[j] = i < nt ? ts[i] : 0;
+      loc += v[j];
+    }
+    int64_t tot;
+    int64_t ex = block_excl_scan(loc, &tot) + carry;
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+      const int64_t i = c0 + (int64_t)threadIdx.x * kItems + j;
+      if (i < nt) ts[i] = ex;
+      ex += v[j];
+    }
+    carry += tot;
+  }
+  if (threadIdx.x == 0) total[0] = carry;
+}
+
+template <class Tin, class Tout>
+__global__ __launch_bounds__(kBlock) void k_scan_add(const Tin* __restrict__ x, int64_t n,
+                                                     const int64_t* __restrict__ tile_off,
+                                                     Tout* __restrict__ out, int write_total) {
+  __shared__ int64_t s[kTile];
+  const int64_t tile0 = (int64_t)blockIdx.x * kTile;
+#pragma unroll
+  for (int j = 0; j < kItems; ++j) {
+    const int64_t i = tile0 + (int64_t)j * kBlock + threadIdx.x;
+    s[j * kBlock + threadIdx.x] = i < n ? (int64_t)x[i] : 0;
+  }
+  __syncthreads();
+  int64_t loc = 0;
+#pragma unroll
+  for (int j = 0; j < kItems; ++j) loc += s[threadIdx.x * kItems + j];
+  int64_t tot;
+  int64_t ex = block_excl_scan(loc, &tot) + tile_off[blockIdx.x];
+#pragma unroll
+  for (int j = 0; j < kItems; ++j) {
+    const int64_t v = s[threadIdx.x * kItems + j];
+    s[threadIdx.x * kItems + j] = ex;
+    ex += v;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kItems; ++j) {
+    const int64_t i = tile0 + (int64_t)j * kBlock + threadIdx.x;
+    if (i < n) out[i] = (Tout)s[j * kBlock + threadIdx.x];
+  }
+  if (write_total && threadIdx.x == 0 && blockIdx.x == gridDim.x - 1)
+    out[n] = (Tout)(tile_off[blockIdx.x] + tot);
+}
+
+__global__ __launch_bounds__(kBlock) void k_tile_reduce_u32(const uint32_t* __restrict__ x,
+                                                            int64_t n, int64_t* ts) {
+  const int64_t tile0 = (int64_t)blockIdx.x * kTile;
+  int64_t loc = 0;
+#pragma unroll
+  for (int j = 0; j < kItems; ++j) {
+    const int64_t i = tile0 + (int64_t)j * kBlock + threadIdx.x;
+    if (i < n) loc += x[i];
+  }
+  const int64_t t = block_sum(loc);
+  if (threadIdx.x == 0) ts[blockIdx.x] = t;
+}
+
+// ---------------------------------------------------------------- radix sort
+__global__ __launch_bounds__(kBlock) void k_rs_hist(const uint64_t* __restrict__ keys, int64_t n,
+                                                    int shift, uint32_t* __restrict__ hist,
+                                                    int64_t nb) {
+  __shared__ uint32_t h[kWaves][256];
+  for (int i = threadIdx.x; i < kWaves * 256; i += kBlock) (&h[0][0])[i] = 0;
+  __syncthreads();
+  const int64_t tile0 = (int64_t)blockIdx.x * kTile;
+#pragma unroll
+  for (int j = 0; j < kItems; ++j) {
+    const int64_t i = tile0 + (int64_t)j * kBlock + threadIdx.x;
+    if (i < n) atomicAdd(&h[wave_id()][(keys[i] >> shift) & 255], 1u);
+  }
+  __syncthreads();
+  uint32_t c = 0;
+#pragma unroll
+  for (int w = 0; w < kWaves; ++w) c += h[w][threadIdx.x];
+  hist[(int64_t)threadIdx.x * nb + blockIdx.x] = c;
+}
+
+__global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint64_t* __restrict__ in,
+                                                       uint64_t* __restrict__ out, int64_t n,
+                                                       int shift,
+                                                       const uint32_t* __restrict__ offs,
+                                                       int64_t nb) {
+  __shared__ uint32_t base[256];
+  __shared__ uint32_t wcnt[kWaves][256];
+  base[threadIdx.x] = offs[(int64_t)threadIdx.x * nb + blockIdx.x];
+#pragma unroll
+  for (int w = 0; w < kWaves; ++w) wcnt[w][threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t tile0 = (int64_t)blockIdx.x * kTile;
+  const uint64_t lt = __lanemask_lt();
+  for (int j = 0; j < kItems; ++j) {
+    const int64_t i = tile0 + (int64_t)j * kBlock + threadIdx.x;
+    const bool valid = i < n;
+    const uint64_t k = valid ? in[i] : 0;
+    const uint32_t d = (uint32_t)(k >> shift) & 255u;
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const uint64_t m = __ballot(bit);
+      peers &= bit ? m : ~m;
+    }
+    const uint32_t rank = (uint32_t)__popcll(peers & lt);
+    if (valid && (peers & lt) == 0) wcnt[wave_id()][d] = (uint32_t)__popcll(peers);
+    __syncthreads();
+    if (valid) {
+      uint32_t pos = base[d] + rank;
+      for (int w = 0; w < wave_id(); ++w) pos += wcnt[w][d];
+      out[pos] = k;
+    }
+    __syncthreads();
+    uint32_t add = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+      add += wcnt[w][threadIdx.x];
+      wcnt[w][threadIdx.x] = 0;
+    }
+    base[threadIdx.x] += add;
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- index build
+__global__ void k_pack_keys(const int32_t* __restrict__ s, const int32_t* __restrict__ p,
+                            const int32_t* __restrict__ o, int64_t n, int vb,
+                            uint64_t* __restrict__ ks, uint64_t* __restrict__ ko) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t pp = (uint64_t)(uint32_t)p[i] << (2 * vb);
+    const uint64_t ss = (uint32_t)s[i], oo = (uint32_t)o[i];
+    ks[i] = pp | (ss << vb) | oo;
+    ko[i] = pp | (oo << vb) | ss;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_flag_adjacent(const uint64_t* __restrict__ k,
+                                                          int64_t n, int sh,
+                                                          uint8_t* __restrict__ flags,
+                                                          int64_t* __restrict__ ts) {
+  const int64_t tile0 = (int64_t)blockIdx.x * kTile;
+  int64_t loc = 0;
+#pragma unroll
+  for (int j = 0; j < kItems; ++j) {
+    const int64_t i = tile0 + (int64_t)j * kBlock + threadIdx.x;
+    if (i < n) {
+      const uint8_t f = (i == 0 || (k[i] >> sh) != (k[i - 1] >> sh)) ? 1 : 0;
+      flags[i] = f;
+      loc += f;
+    }
+  }
+  const int64_t t = block_sum(loc);
+  if (threadIdx.x == 0) ts[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(kBlock) void k_compact_u64(const uint64_t* __restrict__ in,
+                                                        const uint8_t* __restrict__ flags,
+                                                        int64_t n,
+                                                        const int64_t* __restrict__ tile_off,
+                                                        uint64_t* __restrict__ out) {
+  compact_tile(
+      n, tile_off[blockIdx.x], [&](int64_t i) { return flags[i] != 0; },
+      [&](int64_t i, int64_t pos) { out[pos] = in[i]; });
+}
+
+__global__ __launch_bounds__(kBlock) void k_compact_index(const uint8_t* __restrict__ flags,
+                                                          int64_t n,
+                                                          const int64_t* __restrict__ tile_off,
+                                                          int64_t* __restrict__ out) {
+  compact_tile(
+      n, tile_off[blockIdx.x], [&](int64_t i) { return flags[i] != 0; },
+      [&](int64_t i, int64_t pos) { out[pos] = i; });
+}
+
+__global__ void k_split_members(const uint64_t* __restrict__ k, int64_t n, int vb,
+                                int32_t* __restrict__ nbr, int32_t* __restrict__ src) {
+  const uint64_t vmask = (vb >= 64) ? ~0ull : ((1ull << vb) - 1);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t x = k[i];
+    nbr[i] = (int32_t)(x & vmask);
+    if (src) src[i] = (int32_t)((x >> vb) & vmask);
+  }
+}
+
+__global__ void k_pred_heads(const uint64_t* __restrict__ k, const int64_t* __restrict__ row_pos,
+                             int64_t R, int vb, int64_t* __restrict__ pfe,
+                             int64_t* __restrict__ pfr) {
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < R;
+       r += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = row_pos[r];
+    const uint64_t p = k[i] >> (2 * vb);
+    if (r == 0 || p != (k[row_pos[r - 1]] >> (2 * vb))) {
+      pfe[p] = i;
+      pfr[p] = r;
+    }
+  }
+}
+
+__global__ void k_fill_rows(const uint64_t* __restrict__ k, const int64_t* __restrict__ row_pos,
+                            int64_t R, int vb, const int64_t* __restrict__ pfe,
+                            int32_t* __restrict__ keys, int32_t* __restrict__ ptr) {
+  const uint64_t vmask = (1ull << vb) - 1;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < R;
+       r += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = row_pos[r];
+    const uint64_t x = k[i];
+    const int64_t p = (int64_t)(x >> (2 * vb));
+    keys[r] = (int32_t)((x >> vb) & vmask);
+    ptr[r + p] = (int32_t)(i - pfe[p]);
+  }
+}
+
+__global__ void k_fill_i64(int64_t* p, int64_t n, int64_t v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void k_dense_ptr(PredView pv, int64_t V, int32_t* __restrict__ dense) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v <= V;
+       v += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t r = (v >= (int64_t)INT32_MAX) ? pv.nr : lower_bound_i32(pv.keys, pv.nr, (int32_t)v);
+    dense[v] = pv.ptr[r];
+  }
+}
+
+__global__ void k_ptr_sentinels(const PredDesc* __restrict__ d, int32_t P, int32_t* __restrict__ ptr) {
+  const int32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < P) ptr[d[p].ptr_base + d[p].nr] = (int32_t)d[p].nnz;
+}
+
+__device__ inline PredView view_of(const PredDesc& d, const int32_t* keys, const int32_t* ptr,
+                                   const int32_t* nbr, const int32_t* dense) {
+  PredView pv;
+  pv.keys = keys + d.row_base;
+  pv.ptr = ptr + d.ptr_base;
+  pv.nbr = nbr + d.nbr_base;
+  pv.src = nullptr;
+  pv.dense = d.dense_base >= 0 ? dense + d.dense_base : nullptr;
+  pv.nr = (int32_t)d.nr;
+  pv.nnz = (int32_t)d.nnz;
+  return pv;
+}
+
+__global__ void k_lookup(const LookupReq* __restrict__ req, int n, const PredDesc* dout,
+                         const PredDesc* din, const int32_t* keys_out, const int32_t* ptr_out,
+                         const int32_t* nbr_out, const int32_t* dense_out,
+                         const int32_t* keys_in, const int32_t* ptr_in, const int32_t* nbr_in,
+                         const int32_t* dense_in, LookupRes* __restrict__ res) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const LookupReq q = req[i];
+  const PredView pv = q.orient == 0
+                          ? view_of(dout[q.pred], keys_out, ptr_out, nbr_out, dense_out)
+                          : view_of(din[q.pred], keys_in, ptr_in, nbr_in, dense_in);
+  LookupRes r;
+  row_lookup(pv, q.v, r.start, r.len);
+  r.found = (q.member >= 0 && r.len > 0) ? (seg_contains(pv.nbr + r.start, r.len, q.member) ? 1 : 0)
+                                         : 0;
+  r.pad = 0;
+  res[i] = r;
+}
+
+// ---------------------------------------------------------------- join steps
+__global__ __launch_bounds__(kBlock) void k_count_expand(const int32_t* __restrict__ col,
+                                                         int64_t n, PredView pv,
+                                                         int32_t* __restrict__ N,
+                                                         int32_t* __restrict__ start,
+                                                         int64_t* __restrict__ ts) {
+  const int64_t tile0 = (int64_t)blockIdx.x * kTile;
+  int64_t loc = 0;
+#pragma unroll
+  for (int j = 0; j < kItems; ++j) {
+    const int64_t i = tile0 + (int64_t)j * kBlock + threadIdx.x;
+    if (i < n) {
+      int32_t st, len;
+      row_lookup(pv, col[i], st, len);
+      N[i] = len;
+      start[i] = st;
+      loc += len;
+    }
+  }
+  const int64_t t = block_sum(loc);
+  if (threadIdx.x == 0) ts[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(kBlock) void k_flag_filter(ProbeArgs pa, int64_t n, PredView pv,
+                                                        uint8_t* __restrict__ flags,
+                                                        int64_t* __restrict__ ts) {
+  const int64_t tile0 = (int64_t)blockIdx.x * kTile;
+  int64_t loc = 0;
+#pragma unroll
+  for (int j = 0; j < kItems; ++j) {
+    const int64_t i = tile0 + (int64_t)j * kBlock + threadIdx.x;
+    if (i < n) {
+      const int32_t sv = pa.s_col ? pa.s_col[i] : pa.s_const;
+      const int32_t ov = pa.o_col ? pa.o_col[i] : pa.o_const;
+      int32_t st, len;
+      row_lookup(pv, sv, st, len);
+      const uint8_t f = (len > 0 && seg_contains(pv.nbr + st, len, ov)) ? 1 : 0;
+      flags[i] = f;
+      loc += f;
+    }
+  }
+  const int64_t t = block_sum(loc);
+  if (threadIdx.x == 0) ts[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(kBlock) void k_flag_diag(const int32_t* __restrict__ a,
+                                                      const int32_t* __restrict__ b, int64_t n,
+                                                      uint8_t* __restrict__ flags,
+                                                      int64_t* __restrict__ ts) {
+  const int64_t tile0 = (int64_t)blockIdx.x * kTile;
+  int64_t loc = 0;
+#pragma unroll
+  for (int j = 0; j < kItems; ++j) {
+    const int64_t i = tile0 + (int64_t)j * kBlock + threadIdx.x;
+    if (i < n) {
+      const uint8_t f = a[i] == b[i] ? 1 : 0;
+      flags[i] = f;
+      loc += f;
+    }
+  }
+  const int64_t t = block_sum(loc);
+  if (threadIdx.x == 0) ts[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(kBlock) void k_flag_intersect(const int32_t* __restrict__ driver,
+                                                           int64_t n, ListSet ls,
+                                                           uint8_t* __restrict__ flags,
+                                                           int64_t* __restrict__ ts) {
+  const int64_t tile0 = (int64_t)blockIdx.x * kTile;
+  int64_t loc = 0;
+#pragma unroll
+  for (int j = 0; j < kItems; ++j) {
+    const int64_t i = tile0 + (int64_t)j * kBlock + threadIdx.x;
+    if (i < n) {
+      const int32_t x = driver[i];
+      bool keep = true;
+      for (int l = 0; l < ls.n && keep; ++l) {
+        const ListRef& L = ls.l[l];
+        if (L.is_keys) {
+          int32_t st, len;
+          row_lookup(L.pv, x, st, len);
+          keep = len > 0;
+        } else {
+          keep = seg_contains(L.seg, (int32_t)L.len, x);
+        }
+      }
+      flags[i] = keep ? 1 : 0;
+      loc += keep ? 1 : 0;
+    }
+  }
+  const int64_t t = block_sum(loc);
+  if (threadIdx.x == 0) ts[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(kBlock) void k_compact_cols(ColSet in, int k,
+                                                         const uint8_t* __restrict__ flags,
+                                                         int64_t n,
+                                                         const int64_t* __restrict__ tile_off,
+                                                         OutSet out) {
+  compact_tile(
+      n, tile_off[blockIdx.x], [&](int64_t i) { return flags[i] != 0; },
+      [&](int64_t i, int64_t pos) {
+        for (int c = 0; c < k; ++c) out.c[c][pos] = in.c[c][i];
+      });
+}
+
+// Merge path over A = row ends E[i] = P[i+1] (i < n) and B = output indices
+// J0..J1-1, rows before outputs on ties.  split[t] = rows consumed before path
+// position t*kTile.
+__global__ void k_mp_partition(const int64_t* __restrict__ P, int64_t n, int64_t J0, int64_t J1,
+                               int64_t* __restrict__ split, int64_t ntiles) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t > ntiles) return;
+  const int64_t nb = J1 - J0;
+  const int64_t d = min(t * (int64_t)kTile, n + nb);
+  int64_t lo = max((int64_t)0, d - nb), hi = min(d, n);
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (P[mid + 1] <= J0 + (d - 1 - mid)) lo = mid + 1;
+    else hi = mid;
+  }
+  split[t] = lo;
+}
+
+// Expansion write: output j in [P_i, P_{i+1}) copies the parent row i and
+// appends the (j - P_i)-th member of row i's segment (start_i) in nbr.
+__global__ __launch_bounds__(kBlock) void k_write_expand(ColSet in, int k,
+                                                         const int64_t* __restrict__ P,
+                                                         const int32_t* __restrict__ start,
+                                                         int64_t n,
+                                                         const int32_t* __restrict__ nbr,
+                                                         int64_t J0, int64_t J1,
+                                                         const int64_t* __restrict__ split,
+                                                         OutSet out) {
+  __shared__ int64_t sP[kTile + 2];
+  __shared__ int32_t sStart[kTile + 1];
+  __shared__ uint16_t sRow[kTile];
+  const int64_t t = blockIdx.x;
+  const int64_t nb = J1 - J0;
+  const int64_t total = n + nb;
+  const int64_t d0 = t * (int64_t)kTile;
+  const int64_t d1 = min(d0 + (int64_t)kTile, total);
+  const int64_t a0 = split[t], a1 = split[t + 1];
+  const int64_t b0 = d0 - a0, b1 = d1 - a1;
+  const int nat = (int)(a1 - a0), nbt = (int)(b1 - b0);
+  if (nbt <= 0) return;  // block-uniform
+  const int64_t rl = min(a1, n - 1);
+  const int nr = (int)(rl - a0 + 1);
+  for (int i = threadIdx.x; i <= nr; i += kBlock) sP[i] = P[a0 + i];
+  for (int i = threadIdx.x; i < nr; i += kBlock) sStart[i] = start[a0 + i];
+  __syncthreads();
+  const int64_t jb = J0 + b0;
+  const int dl = min((int)threadIdx.x * kItems, nat + nbt);
+  const int de = min((int)threadIdx.x * kItems + kItems, nat + nbt);
+  int lo = max(0, dl - nbt), hi = min(dl, nat);
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (sP[mid + 1] <= jb + (dl - 1 - mid)) lo = mid + 1;
+    else hi = mid;
+  }
+  int a = lo, b = dl - lo;
+  for (int step = dl; step < de; ++step) {
+    const bool takeA = (a < nat) && (b >= nbt || sP[a + 1] <= jb + b);
+    if (takeA) {
+      ++a;
+    } else {
+      sRow[b] = (uint16_t)a;
+      ++b;
+    }
+  }
+  __syncthreads();
+  for (int o = threadIdx.x; o < nbt; o += kBlock) {
+    const int r = sRow[o];
+    const int64_t j = jb + o;
+    const int32_t rank = (int32_t)(j - sP[r]);
+    const int32_t v = nbr[sStart[r] + rank];
+    const int64_t row = a0 + r;
+    const int64_t oj = j - J0;
+    for (int c = 0; c < k; ++c) __builtin_nontemporal_store(in.c[c][row], &out.c[c][oj]);
+    __builtin_nontemporal_store(v, &out.c[k][oj]);
+  }
+}
+
+__global__ void k_cartesian(ColSet a, int ka, ColSet b, int kb, int64_t nb, int64_t J0,
+                            int64_t J1, OutSet out) {
+  for (int64_t j = J0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < J1;
+       j += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t ia = j / nb, ib = j - ia * nb;
+    const int64_t oj = j - J0;
+    for (int c = 0; c < ka; ++c) out.c[c][oj] = a.c[c][ia];
+    for (int c = 0; c < kb; ++c) out.c[ka + c][oj] = b.c[c][ib];
+  }
+}
+
+__global__ void k_pack_rows(ColSet cols, int k, int64_t row0, int64_t rows,
+                            int32_t* __restrict__ out) {
+  const int64_t total = rows * k;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e / k;
+    const int c = (int)(e - r * k);
+    out[e] = cols.c[c][row0 + r];
+  }
+}
+
+inline unsigned grid_for(int64_t n, int block = kBlock, int64_t cap = 65536) {
+  int64_t g = ceil_div(n > 0 ? n : 1, block);
+  if (g > cap) g = cap;
+  return (unsigned)g;
+}
+inline unsigned tiles_for(int64_t n) { return (unsigned)ceil_div(n > 0 ? n : 1, kTile); }
+
+}  // namespace
+
+// ---------------------------------------------------------------- launchers
+#define GS_LAUNCH(cls, bytes, ...)        \
+  do {                                    \
+    if (prof_on()) prof_begin(s, cls);    \
+    __VA_ARGS__;                          \
+    GS_HIP(hipGetLastError());            \
+    if (prof_on()) prof_end(s, cls, bytes); \
+  } while (0)
+
+void launch_scan_tile_sums(int64_t* tile_sum, int64_t nt, int64_t* total, hipStream_t s) {
+  GS_LAUNCH(GSMAT_K_SCAN, 16.0 * nt,
+            hipLaunchKernelGGL(k_scan_tile_sums, dim3(1), dim3(kBlock), 0, s, tile_sum, nt, total));
+}
+
+void launch_scan_add_i32(const int32_t* N, int64_t n, const int64_t* tile_off, int64_t* P,
+                         hipStream_t s) {
+  GS_LAUNCH(GSMAT_K_SCAN, 12.0 * n,
+            hipLaunchKernelGGL((k_scan_add<int32_t, int64_t>), dim3(tiles_for(n)), dim3(kBlock),
+                               0, s, N, n, tile_off, P, 1));
+}
+
+void launch_tile_reduce_u32(const uint32_t* x, int64_t n, int64_t* tile_sum, hipStream_t s) {
+  GS_LAUNCH(GSMAT_K_OTHER, 4.0 * n,
+            hipLaunchKernelGGL(k_tile_reduce_u32, dim3(tiles_for(n)), dim3(kBlock), 0, s, x, n,
+                               tile_sum));
+}
+
+void launch_scan_add_u32(const uint32_t* x, int64_t n, const int64_t* tile_off, uint32_t* out,
+                         hipStream_t s) {
+  GS_LAUNCH(GSMAT_K_OTHER, 8.0 * n,
+            hipLaunchKernelGGL((k_scan_add<uint32_t, uint32_t>), dim3(tiles_for(n)),
+                               dim3(kBlock), 0, s, x, n, tile_off, out, 0));
+}
+
+void radix_sort_u64(uint64_t* keys, uint64_t* tmp, int64_t n, int nbits, DeviceMem& mem,
+                    hipStream_t s) {
+  if (n <= 1) return;
+  const int64_t nb = ceil_div(n, kTile);
+  const int64_t hn = 256 * nb;
+  const int64_t ht = ceil_div(hn, kTile);
+  uint32_t* hist = (uint32_t*)mem.alloc(sizeof(uint32_t) * hn, s);
+  uint32_t* offs = (uint32_t*)mem.alloc(sizeof(uint32_t) * hn, s);
+  int64_t* ts = (int64_t*)mem.alloc(sizeof(int64_t) * (ht + 1), s);
+  if (!hist || !offs || !ts) {
+    if (hist) mem.free(hist, sizeof(uint32_t) * hn, s);
+    if (offs) mem.free(offs, sizeof(uint32_t) * hn, s);
+    if (ts) mem.free(ts, sizeof(int64_t) * (ht + 1), s);
+    throw OomFail{sizeof(uint32_t) * (size_t)hn};
+  }
+  uint64_t* src = keys;
+  uint64_t* dst = tmp;
+  const int passes = (nbits + 7) / 8;
+  for (int pass = 0; pass < passes; ++pass) {
+    const int shift = 8 * pass;
+    GS_LAUNCH(GSMAT_K_OTHER, 8.0 * n,
+              hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)nb), dim3(kBlock), 0, s, src, n, shift,
+                                 hist, nb));
+    launch_tile_reduce_u32(hist, hn, ts, s);
+    launch_scan_tile_sums(ts, ht, ts + ht, s);
+    launch_scan_add_u32(hist, hn, ts, offs, s);
+    GS_LAUNCH(GSMAT_K_OTHER, 16.0 * n,
+              hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)nb), dim3(kBlock), 0, s, src, dst,
+                                 n, shift, offs, nb));
+    std::swap(src, dst);
+  }
+  if (src != keys) GS_HIP(hipMemcpyAsync(keys, src, sizeof(uint64_t) * n, hipMemcpyDeviceToDevice, s));
+  mem.free(hist, sizeof(uint32_t) * hn, s);
+  mem.free(offs, sizeof(uint32_t) * hn, s);
+  mem.free(ts, sizeof(int64_t) * (ht + 1), s);
+}
+
+void launch_pack_keys(const int32_t* sv, const int32_t* p, const int32_t* o, int64_t n, int vb,
+                      uint64_t* k_by_s, uint64_t* k_by_o, hipStream_t s) {
+  GS_LAUNCH(GSMAT_K_OTHER, 28.0 * n,
+            hipLaunchKernelGGL(k_pack_keys, dim3(grid_for(n)), dim3(kBlock), 0, s, sv, p, o, n,
+                               vb, k_by_s, k_by_o));
+}
+
+void launch_flag_unique(const uint64_t* k, int64_t n, uint8_t* flags, int64_t* tile_sum,
+                        hipStream_t s) {
+  GS_LAUNCH(GSMAT_K_OTHER, 9.0 * n,
+            hipLaunchKernelGGL(k_flag_adjacent, dim3(tiles_for(n)), dim3(kBlock), 0, s, k, n, 0,
+                               flags, tile_sum));
+}
+
+void launch_flag_row_heads(const uint64_t* k, int64_t n, int vb, uint8_t* flags,
+                           int64_t* tile_sum, hipStream_t s) {
+  GS_LAUNCH(GSMAT_K_OTHER, 9.0 * n,
+            hipLaunchKernelGGL(k_flag_adjacent, dim3(tiles_for(n)), dim3(kBlock), 0, s, k, n, vb,
+                               flags, tile_sum));
+}
+
+void launch_compact_u64(const uint64_t* in, const uint8_t* flags, int64_t n,
+                        const int64_t* tile_off, uint64_t* out, hipStream_t s) {
+  GS_LAUNCH(GSMAT_K_COMPACT, 17.0 * n,
+            hipLaunchKernelGGL(k_compact_u64, dim3(tiles_for(n)), dim3(kBlock), 0, s, in, flags,
+                               n, tile_off, out));
+}
+
+void launch_compact_index(const uint8_t* flags, int64_t n, const int64_t* tile_off,
+                          int64_t* out_idx, hipStream_t s) {
+  GS_LAUNCH(GSMAT_K_COMPACT, 9.0 * n,
+            hipLaunchKernelGGL(k_compact_index, dim3(tiles_for(n)), dim3(kBlock), 0, s, flags, n,
+                               tile_off, out_idx));
+}
+
+void launch_split_members(const uint64_t* k, int64_t n, int vb, int32_t* nbr, int32_t* src,
+                          hipStream_t s) {
+  GS_LAUNCH(GSMAT_K_OTHER, 16.0 * n,
+            hipLaunchKernelGGL(k_split_members, dim3(grid_for(n)), dim3(kBlock), 0, s, k, n, vb,
+                               nbr, src));
+}
+
+void launch_pred_heads(const uint64_t* k, const int64_t* row_pos, int64_t R, int vb,
+                       int64_t* pfe, int64_t* pfr, hipStream_t s) {
+  GS_LAUNCH(GSMAT_K_OTHER, 24.0 * R,
+            hipLaunchKernelGGL(k_pred_heads, dim3(grid_for(R)), dim3(kBlock), 0, s, k, row_pos,
+                               R, vb, pfe, pfr));
+}
+
+void launch_fill_rows(const uint64_t* k, const int64_t* row_pos, int64_t R, int vb,
+                      const int64_t* pfe, int32_t* keys, int32_t* ptr, hipStream_t s) {
+  GS_LAUNCH(GSMAT_K_OTHER, 24.0 * R,
+            hipLaunchKernelGGL(k_fill_rows, dim3(grid_for(R)), dim3(kBlock), 0, s, k, row_pos, R,
+                               vb, pfe, keys, ptr));
+}
+
+void launch_fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t s) {
+  if (n <= 0) return;
+  GS_LAUNCH(GSMAT_K_OTHER, 8.0 * n,
+            hipLaunchKernelGGL(k_fill_i64, dim3(grid_for(n)), dim3(kBlock), 0, s, p, n, v));
+}
+
+void launch_dense_ptr(PredView pv, int64_t V, int32_t* dense, hipStream_t s) {
+  GS_LAUNCH(GSMAT_K_OTHER, 4.0 * (V + 1),
+            hipLaunchKernelGGL(k_dense_ptr, dim3(grid_for(V + 1)), dim3(kBlock), 0, s, pv, V,
+                               dense));
+}
+
+void launch_ptr_sentinels(const PredDesc* d, int32_t P, int32_t* ptr, hipStream_t s) {
+  if (P <= 0) return;
+  GS_LAUNCH(GSMAT_K_OTHER, 0.0,
+            hipLaunchKernelGGL(k_ptr_sentinels, dim3((unsigned)ceil_div(P, kBlock)), dim3(kBlock), 0,
+                               s, d, P, ptr));
+}
+
+void launch_lookup(const LookupReq* req, int n, const PredDesc* desc_out, const PredDesc* desc_in,
+                   const int32_t* keys_out, const int32_t* ptr_out, const int32_t* nbr_out,
+                   const int32_t* dense_out, const int32_t* keys_in, const int32_t* ptr_in,
+                   const int32_t* nbr_in, const int32_t* dense_in, LookupRes* res,
+                   hipStream_t s) {
+  if (n <= 0) return;
+  GS_LAUNCH(GSMAT_K_OTHER, 32.0 * n,
+            hipLaunchKernelGGL(k_lookup, dim3((unsigned)ceil_div(n, 64)), dim3(64), 0, s, req, n,
+                               desc_out, desc_in, keys_out, ptr_out, nbr_out, dense_out, keys_in,
+                               ptr_in, nbr_in, dense_in, res));
+}
+
+void launch_count_expand(const int32_t* col, int64_t n, PredView pv, int32_t* N, int32_t* start,
+                         int64_t* tile_sum, hipStream_t s) {
+  GS_LAUNCH(GSMAT_K_COUNT, 20.0 * n,
+            hipLaunchKernelGGL(k_count_expand, dim3(tiles_for(n)), dim3(kBlock), 0, s, col, n, pv,
+                               N, start, tile_sum));
+}
+
+void launch_flag_filter(ProbeArgs pa, int64_t n, PredView pv, uint8_t* flags, int64_t* tile_sum,
+                        hipStream_t s) {
+  GS_LAUNCH(GSMAT_K_COUNT, 21.0 * n,
+            hipLaunchKernelGGL(k_flag_filter, dim3(tiles_for(n)), dim3(kBlock), 0, s, pa, n, pv,
+                               flags, tile_sum));
+}
+
+void launch_flag_diag(const int32_t* a, const int32_t* b, int64_t n, uint8_t* flags,
+                      int64_t* tile_sum, hipStream_t s) {
+  GS_LAUNCH(GSMAT_K_COUNT, 9.0 * n,
+            hipLaunchKernelGGL(k_flag_diag, dim3(tiles_for(n)), dim3(kBlock), 0, s, a, b, n, flags,
+                               tile_sum));
+}
+
+void launch_flag_intersect(const int32_t* driver, int64_t n, ListSet ls, uint8_t* flags,
+                           int64_t* tile_sum, hipStream_t s) {
+  GS_LAUNCH(GSMAT_K_COUNT, (4.0 + 4.0 * ls.n + 1.0) * n,
+            hipLaunchKernelGGL(k_flag_intersect, dim3(tiles_for(n)), dim3(kBlock), 0, s, driver, n,
+                               ls, flags, tile_sum));
+}
+
+void launch_compact_cols(ColSet in, int k, const uint8_t* flags, int64_t n,
+                         const int64_t* tile_off, OutSet out, hipStream_t s) {
+  GS_LAUNCH(GSMAT_K_COMPACT, (1.0 + 4.0 * k) * n,
+            hipLaunchKernelGGL(k_compact_cols, dim3(tiles_for(n)), dim3(kBlock), 0, s, in, k, flags,
+                               n, tile_off, out));
+}
+
+void launch_mp_partition(const int64_t* P, int64_t n, int64_t J0, int64_t J1, int64_t* split,
+                         int64_t ntiles, hipStream_t s) {
+  GS_LAUNCH(GSMAT_K_OTHER, 8.0 * (ntiles + 1),
+            hipLaunchKernelGGL(k_mp_partition, dim3((unsigned)ceil_div(ntiles + 1, kBlock)),
+                               dim3(kBlock), 0, s, P, n, J0, J1, split, ntiles));
+}
+
+void launch_write_expand(ColSet in, int k, const int64_t* P, const int32_t* start, int64_t n,
+                         const int32_t* nbr, int64_t J0, int64_t J1, const int64_t* split,
+                         int64_t ntiles, OutSet out, double alg_bytes, hipStream_t s) {
+  GS_LAUNCH(GSMAT_K_WRITE, alg_bytes,
+            hipLaunchKernelGGL(k_write_expand, dim3((unsigned)ntiles), dim3(kBlock), 0, s, in, k,
+                               P, start, n, nbr, J0, J1, split, out));
+}
+
+void launch_cartesian(ColSet a, int ka, int64_t na, ColSet b, int kb, int64_t nb, int64_t J0,
+                      int64_t J1, OutSet out, hipStream_t s) {
+  (void)na;
+  GS_LAUNCH(GSMAT_K_OTHER, 4.0 * (ka + kb) * 2.0 * (J1 - J0),
+            hipLaunchKernelGGL(k_cartesian, dim3(grid_for(J1 - J0)), dim3(kBlock), 0, s, a, ka, b,
+                               kb, nb, J0, J1, out));
+}
+
+void launch_pack_rows(ColSet cols, int k, int64_t row0, int64_t rows, int32_t* out,
+                      hipStream_t s) {
+  GS_LAUNCH(GSMAT_K_OTHER, 8.0 * k * rows,
+            hipLaunchKernelGGL(k_pack_rows, dim3(grid_for(rows * k)), dim3(kBlock), 0, s, cols, k,
+                               row0, rows, out));
+}
+
+}  // namespace gsmat

@@ -1,0 +1,51 @@
+// Device-resident sparse-matrix store (one boolean matrix per predicate, kept
+// row-compressed by subject and column-compressed by object).
+#pragma once
+
+#include <memory>
+#include <vector>
+
+#include "common.hpp"
+
+namespace gsmat {
+
+// One orientation of every predicate matrix, in global arrays ordered by
+// (predicate, row, member).
+struct Orientation {
+  int32_t* nbr = nullptr;    // [T] members
+  int32_t* src = nullptr;    // [T] row id of each member (by-subject orientation only)
+  int32_t* keys = nullptr;   // [R] non-empty row ids per predicate
+  int32_t* ptr = nullptr;    // [R + P] row offsets per predicate, one sentinel each
+  int32_t* dense = nullptr;  // dense row pointers of heavy predicates
+  int64_t R = 0;
+  int64_t dense_len = 0;
+  std::vector<PredDesc> desc;   // [P]
+  PredDesc* d_desc = nullptr;   // device copy
+  PredView view(int32_t p) const;
+};
+
+struct Alloc {
+  void* p;
+  size_t bytes;
+};
+
+}  // namespace gsmat
+
+struct gsmat_store {
+  std::unique_ptr<gsmat::DeviceMem> mem;
+  int32_t V = 0, P = 0;
+  int vb = 1, pb = 1;
+  int64_t n_in = 0;
+  int32_t* d_s = nullptr;  // raw triples until the index is built
+  int32_t* d_p = nullptr;
+  int32_t* d_o = nullptr;
+  bool built = false;
+  int64_t T = 0;           // distinct triples
+  gsmat::Orientation out;  // by subject: rows = subjects, members = objects
+  gsmat::Orientation in;   // by object: rows = objects, members = subjects
+  std::vector<gsmat::Alloc> index_allocs;
+  int64_t device_bytes = 0;
+
+  void* dalloc(size_t bytes, hipStream_t s, bool index);
+  void dfree_index(hipStream_t s);
+};

@@ -1,0 +1,166 @@
+"""C-ABI checks that need no GPU: exported symbols, host-side validation and
+the host-only planner (paper mode pinned to the worked example's order)."""
+import ctypes
+import json
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gsmat.h")
+
+
+@pytest.fixture(scope="module")
+def G():
+    import paper_1807_07691_amd as G
+    return G
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(gsmat_[a-z_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol(G):
+    names = _declared()
+    assert "gsmat_join" in names and "gsmat_fetch_bindings" in names
+    lib = ctypes.CDLL(G.library_path())
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(G.EXPORTED) == names
+
+
+def test_binding_has_same_names(G):
+    for n in ["gsmat_load_triples", "gsmat_build_index", "gsmat_plan", "gsmat_join",
+              "gsmat_fetch_bindings"]:
+        assert callable(getattr(G, n))
+
+
+def test_load_validation_before_device_work(G):
+    z = np.zeros(1, np.int32)
+    with pytest.raises(G.GsmatError) as e:
+        G.gsmat_load_triples(z + 8, z, z, 8, 2)
+    assert e.value.status == G.GSMAT_EINVAL
+    with pytest.raises(G.GsmatError) as e:
+        G.gsmat_load_triples(z, z + 2, z, 8, 2)
+    assert e.value.status == G.GSMAT_EINVAL
+    with pytest.raises(G.GsmatError) as e:
+        G.gsmat_load_triples(z, z, z - 1, 8, 2)
+    assert e.value.status == G.GSMAT_EINVAL
+    with pytest.raises(G.GsmatError) as e:
+        G.gsmat_load_triples(z, z, z, 2**31 - 1, 2**20)  # 20 + 2*31 bits > 64
+    assert e.value.status == G.GSMAT_EUNSUPPORTED
+
+
+def test_allocator_failure_is_enomem(G):
+    calls = []
+
+    def alloc(nbytes, stream):
+        calls.append(nbytes)
+        return 0  # always fails
+
+    def free(ptr, nbytes, stream):
+        raise AssertionError("nothing was allocated")
+
+    a = G.make_allocator(alloc, free)
+    z = np.zeros(4, np.int32)
+    with pytest.raises(G.GsmatError) as e:
+        G.gsmat_load_triples(z, z, z, 8, 2, allocator=a)
+    assert e.value.status == G.GSMAT_ENOMEM
+    assert calls
+
+
+def test_plan_validation(G):
+    with pytest.raises(G.GsmatError) as e:
+        G.gsmat_plan_from_stats([[-1, -2, -2]], 0, [1])
+    assert e.value.status == G.GSMAT_EUNSUPPORTED
+    with pytest.raises(G.GsmatError) as e:
+        G.gsmat_plan_from_stats([[-1, 0, -3]], 0, [1])
+    assert e.value.status == G.GSMAT_EINVAL
+    with pytest.raises(G.GsmatError) as e:
+        G.gsmat_plan_from_stats([[-1, 0, -2]] * 33, 0, [1] * 33)
+    assert e.value.status == G.GSMAT_EUNSUPPORTED
+
+
+def test_paper_plan_reproduces_worked_example_order(G):
+    with open(os.path.join(ROOT, "tests", "golden", "worked_example.json")) as f:
+        g = json.load(f)
+    nnz = {int(h): len(v) for h, v in g["matrices"].items()}
+    stat = [nnz[t[1]] for t in g["query_tps"]]
+    pl = G.gsmat_plan_from_stats(g["query_tps"], G.PLAN_PAPER, stat)
+    nv, steps = G.gsmat_plan_info(pl)
+    assert nv == 4
+    assert [s["tp"] for s in steps] == g["paper_plan_order"]
+    assert [s["kind"] for s in steps] == ["SCAN", "EXPAND", "EXPAND", "FILTER"]
+
+
+def _random_bgp(rng, ntp, nv, P, V, cprob):
+    tps = []
+    for _ in range(ntp):
+        def term():
+            return int(rng.integers(0, V)) if rng.random() < cprob else -int(rng.integers(0, nv)) - 1
+        tps.append([term(), int(rng.integers(0, P)), term()])
+    used = sorted({-t - 1 for tp in tps for t in (tp[0], tp[2]) if t < 0})
+    remap = {x: i for i, x in enumerate(used)}
+    tps = [[(-remap[-a - 1] - 1) if a < 0 else a, b, (-remap[-c - 1] - 1) if c < 0 else c]
+           for a, b, c in tps]
+    return tps, len(used)
+
+
+@pytest.mark.parametrize("seed", range(30))
+def test_paper_plan_matches_oracle_order(G, seed):
+    rng = np.random.default_rng(seed)
+    tps, nv = _random_bgp(rng, int(rng.integers(1, 9)), int(rng.integers(1, 6)), 5, 20, 0.15)
+    stat = rng.integers(0, 5, len(tps)).tolist()
+    pl = G.gsmat_plan_from_stats(tps, G.PLAN_PAPER, stat)
+    _, steps = G.gsmat_plan_info(pl)
+    assert [s["tp"] for s in steps] == O.plan_order(tps, stat)
+
+
+@pytest.mark.parametrize("seed", range(30))
+def test_default_plan_is_valid(G, seed):
+    """Every pattern is evaluated exactly once (or consumed exactly by the
+    intersection), each step's kind matches the variables bound before it."""
+    rng = np.random.default_rng(100 + seed)
+    tps, nv = _random_bgp(rng, int(rng.integers(1, 9)), int(rng.integers(1, 6)), 5, 20, 0.15)
+    stat = rng.integers(0, 50, len(tps)).tolist()
+    pl = G.gsmat_plan_from_stats(tps, G.PLAN_DEFAULT, stat)
+    _, steps = G.gsmat_plan_info(pl)
+    bound = set()
+    done = set()
+    unit = True
+    for s in steps:
+        if s["kind"] == "INTERSECT":
+            assert unit and len(s["members"]) >= 2
+            c = -(s["var"] + 1)
+            for m in s["members"]:
+                a, _, b = tps[m]
+                assert (a == c) != (b == c)
+                other = b if a == c else a
+                if other >= 0:
+                    done.add(m)
+            bound.add(s["var"])
+            unit = False
+            continue
+        t = s["tp"]
+        assert t not in done
+        done.add(t)
+        a, _, b = tps[t]
+        vs = {x for x in (a, b) if x < 0}
+        if s["kind"] == "FILTER":
+            assert all(-x - 1 in bound for x in vs)
+        elif s["kind"] == "EXPAND":
+            src = a if s["orient"] == 0 else b
+            dst = b if s["orient"] == 0 else a
+            assert src < 0 and -src - 1 in bound and dst < 0 and -dst - 1 not in bound
+        elif s["kind"] in ("SCAN", "CARTESIAN"):
+            assert not any(-x - 1 in bound for x in vs)
+        bound |= {-x - 1 for x in vs}
+        unit = unit and not vs
+    assert done == set(range(len(tps)))
+    assert bound == set(range(nv))

@@ -97,7 +97,7 @@ class GraphSpec:
     out_cap: int
     in_cap: int
     out_exp: float = 2.2
-    in_alpha: float = 0.4
+    in_alpha: float = 0.3
     rho: float = -1.0
     seed: int = 0x18070769
 

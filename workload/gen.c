@@ -21,6 +21,13 @@
 #include <stdlib.h>
 #include <string.h>
 #include <omp.h>
+#include <stdio.h>
+
+static int wl_verbose(void) {
+  const char* e = getenv("WL_VERBOSE");
+  return e && e[0] == '1';
+}
+#define VLOG(...) do { if (wl_verbose()) { fprintf(stderr, __VA_ARGS__); fflush(stderr); } } while (0)
 
 /* ------------------------------------------------------------------ */
 /* counter-based random numbers                                        */
@@ -104,6 +111,39 @@ static void radix_sort_u64(uint64_t *a, uint64_t *tmp, int64_t n, int nbits) {
   free(hist);
 }
 
+/* Stable counting sort of (a, p, b)-packed keys (a<<(pb+vb) | p<<vb | b) by p,
+ * writing them repacked as (p, a, b) = p<<2vb | a<<vb | b.  Input sorted by
+ * (a, p, b) therefore comes out sorted by (p, a, b). */
+static void regroup_by_pred(const uint64_t *in, uint64_t *out, int64_t n, int32_t P, int pb, int vb) {
+  int nt = omp_get_max_threads();
+  int64_t *hist = (int64_t *)calloc((size_t)P * nt, sizeof(int64_t));
+  uint64_t vmask = ((uint64_t)1 << vb) - 1, pmask = ((uint64_t)1 << pb) - 1;
+#pragma omp parallel num_threads(nt)
+  {
+    int t = omp_get_thread_num();
+    int64_t lo = n * t / nt, hi = n * (t + 1) / nt;
+    int64_t *h = hist + (size_t)P * t;
+    for (int64_t i = lo; i < hi; ++i) h[(in[i] >> vb) & pmask]++;
+#pragma omp barrier
+#pragma omp single
+    {
+      int64_t run = 0;
+      for (int32_t p = 0; p < P; ++p)
+        for (int tt = 0; tt < nt; ++tt) {
+          int64_t c = hist[(size_t)P * tt + p];
+          hist[(size_t)P * tt + p] = run;
+          run += c;
+        }
+    }
+    for (int64_t i = lo; i < hi; ++i) {
+      uint64_t x = in[i];
+      uint64_t p = (x >> vb) & pmask, a = x >> (pb + vb), b = x & vmask;
+      out[h[p]++] = (p << (2 * vb)) | (a << vb) | b;
+    }
+  }
+  free(hist);
+}
+
 /* Deterministic sum of doubles: fixed chunks, fixed order. */
 #define DCHUNK 65536
 static double det_sum(const double *x, int64_t n) {
@@ -133,8 +173,8 @@ static double det_sum(const double *x, int64_t n) {
  * u'_v = u_v with probability rho (rank-correlated hubs) and fresh otherwise;
  * ym solved so the weights sum to the candidate edge count, so a weight is
  * the vertex's expected in-degree.  Each edge's object is drawn in proportion
- * to in-weight (preferential by expected in-degree); its predicate from
- * Zipf(zipf_s) over 0..P-1.
+ * to in-weight (preferential by expected in-degree, by inverse CDF); its
+ * predicate from Zipf(zipf_s) over 0..P-1.
  * Candidates are deduplicated as a set; a keyed bijective hash orders them, and
  * the first T distinct triples in hash order are kept (a uniform subset, in
  * random order).  If fewer than T are distinct, more candidates are drawn.
@@ -146,26 +186,55 @@ typedef struct {
   uint64_t seed;
 } wl_graph_params;
 
-static void build_alias(const double *w, int64_t n, double total, float *prob, int32_t *alias) {
-  /* Vose's alias method; sequential (deterministic). */
-  int32_t *small = (int32_t *)malloc(sizeof(int32_t) * n);
-  int32_t *large = (int32_t *)malloc(sizeof(int32_t) * n);
-  double *sc = (double *)malloc(sizeof(double) * n);
-  int64_t ns = 0, nl = 0;
-  for (int64_t i = 0; i < n; ++i) {
-    sc[i] = w[i] * (double)n / total;
-    if (sc[i] < 1.0) small[ns++] = (int32_t)i; else large[nl++] = (int32_t)i;
+/* Inverse-CDF sampling with a guide table (Chen and Asau's method): C is the
+ * inclusive prefix sum of the weights (computed over fixed chunks in a fixed
+ * order, so it does not depend on the thread count); guide[k] is the first
+ * index whose prefix exceeds k/G of the total.  A draw x in [0, total) then
+ * needs a binary search only inside one guide bucket. */
+#define GUIDE_BITS 22
+static void prefix_sum_det(const double *w, int64_t n, double *C) {
+  int64_t nc = (n + DCHUNK - 1) / DCHUNK;
+  double *part = (double *)calloc(nc > 0 ? nc : 1, sizeof(double));
+#pragma omp parallel for schedule(static)
+  for (int64_t c = 0; c < nc; ++c) {
+    double s = 0;
+    int64_t hi = (c + 1) * DCHUNK < n ? (c + 1) * DCHUNK : n;
+    for (int64_t i = c * DCHUNK; i < hi; ++i) s += w[i];
+    part[c] = s;
   }
-  while (ns > 0 && nl > 0) {
-    int32_t s = small[--ns], l = large[--nl];
-    prob[s] = (float)sc[s];
-    alias[s] = l;
-    sc[l] = (sc[l] + sc[s]) - 1.0;
-    if (sc[l] < 1.0) small[ns++] = l; else large[nl++] = l;
+  double run = 0;
+  for (int64_t c = 0; c < nc; ++c) { double t = part[c]; part[c] = run; run += t; }
+#pragma omp parallel for schedule(static)
+  for (int64_t c = 0; c < nc; ++c) {
+    double s = part[c];
+    int64_t hi = (c + 1) * DCHUNK < n ? (c + 1) * DCHUNK : n;
+    for (int64_t i = c * DCHUNK; i < hi; ++i) { s += w[i]; C[i] = s; }
   }
-  while (nl > 0) { int32_t l = large[--nl]; prob[l] = 1.0f; alias[l] = l; }
-  while (ns > 0) { int32_t s = small[--ns]; prob[s] = 1.0f; alias[s] = s; }
-  free(small); free(large); free(sc);
+  free(part);
+}
+static void build_guide(const double *C, int64_t n, int64_t *guide) {
+  const int64_t G = (int64_t)1 << GUIDE_BITS;
+  const double total = C[n - 1];
+#pragma omp parallel for schedule(static)
+  for (int64_t k = 0; k <= G; ++k) {
+    double x = total * (double)k / (double)G;
+    int64_t lo = 0, hi = n - 1;
+    while (lo < hi) { int64_t m = (lo + hi) / 2; if (C[m] > x) hi = m; else lo = m + 1; }
+    guide[k] = lo;
+  }
+}
+static inline int64_t sample_cdf(const double *C, int64_t n, const int64_t *guide, double u) {
+  const int64_t G = (int64_t)1 << GUIDE_BITS;
+  const double total = C[n - 1];
+  double x = u * total;
+  int64_t k = (int64_t)(u * (double)G);
+  if (k >= G) k = G - 1;
+  int64_t lo = guide[k], hi = guide[k + 1];
+  if (hi > n - 1) hi = n - 1;
+  while (lo < hi) { int64_t m = (lo + hi) / 2; if (C[m] > x) hi = m; else lo = m + 1; }
+  /* skip zero-weight entries that share the prefix value */
+  while (lo < n - 1 && C[lo] <= x) ++lo;
+  return lo;
 }
 
 /* Returns number of triples written (== T) or a negative error code. */
@@ -207,17 +276,18 @@ int64_t wl_gen_graph(int64_t V, int32_t P, int64_t T, double zipf_s, double out_
   int64_t *deg = (int64_t *)malloc(sizeof(int64_t) * V);
   int64_t *off = (int64_t *)malloc(sizeof(int64_t) * (V + 1));
   double *w = (double *)malloc(sizeof(double) * V);
-  float *aprob = (float *)malloc(sizeof(float) * V);
-  int32_t *alias = (int32_t *)malloc(sizeof(int32_t) * V);
+  double *C = (double *)malloc(sizeof(double) * V);
+  int64_t *guide = (int64_t *)malloc(sizeof(int64_t) * (((int64_t)1 << GUIDE_BITS) + 1));
   uint64_t hseed = mix64(seed ^ 0x5eed5eed5eedULL);
-  double over = 1.03;
+  double over = 1.10;
   int64_t result = -4;
   uint64_t *h = NULL, *tmp = NULL;
   for (int attempt = 0; attempt < 12; ++attempt) {
+    double t0 = omp_get_wtime();
     double want = over * (double)T;
     /* solve xm: total out-degree ~= want */
     double lo = 1e-9, hi = 1e9;
-    for (int it = 0; it < 100; ++it) {
+    for (int it = 0; it < 64; ++it) {
       double xm = sqrt(lo * hi);
       int64_t tot = 0;
 #pragma omp parallel for reduction(+ : tot) schedule(static)
@@ -228,6 +298,7 @@ int64_t wl_gen_graph(int64_t V, int32_t P, int64_t T, double zipf_s, double out_
       if ((double)tot > want) hi = xm; else lo = xm;
     }
     double xm = hi;
+    VLOG("[wl] attempt %d over=%.4f xm solve %.2fs\n", attempt, over, omp_get_wtime() - t0);
 #pragma omp parallel for schedule(static)
     for (int64_t v = 0; v < V; ++v) {
       double d = floor(xm * q[v]);
@@ -238,7 +309,7 @@ int64_t wl_gen_graph(int64_t V, int32_t P, int64_t T, double zipf_s, double out_
     int64_t E = off[V];
     /* solve ym: in-weights sum to E */
     double ylo = 1e-12, yhi = 1e12;
-    for (int it = 0; it < 100; ++it) {
+    for (int it = 0; it < 64; ++it) {
       double ym = sqrt(ylo * yhi);
 #pragma omp parallel for schedule(static)
       for (int64_t v = 0; v < V; ++v) {
@@ -252,8 +323,10 @@ int64_t wl_gen_graph(int64_t V, int32_t P, int64_t T, double zipf_s, double out_
       double x = yhi * r[v];
       w[v] = x > (double)in_cap ? (double)in_cap : x;
     }
-    double wsum = det_sum(w, V);
-    build_alias(w, V, wsum, aprob, alias);
+    VLOG("[wl] ym solve done %.2fs\n", omp_get_wtime() - t0);
+    prefix_sum_det(w, V, C);
+    build_guide(C, V, guide);
+    VLOG("[wl] cdf done %.2fs E=%lld\n", omp_get_wtime() - t0, (long long)E);
 
     free(h); free(tmp);
     h = (uint64_t *)malloc(sizeof(uint64_t) * (E > 0 ? E : 1));
@@ -265,18 +338,20 @@ int64_t wl_gen_graph(int64_t V, int32_t P, int64_t T, double zipf_s, double out_
         int32_t lo2 = 0, hi2 = P - 1;
         while (lo2 < hi2) { int32_t m = (lo2 + hi2) / 2; if (rp < thr[m]) hi2 = m; else lo2 = m + 1; }
         uint64_t rt = rng(seed, S_TGT, (uint64_t)e + (uint64_t)attempt * 0x100000000000ULL);
-        int64_t slot = (int64_t)((rt >> 32) * (uint64_t)V >> 32);
-        double coin = (double)(uint32_t)rt * (1.0 / 4294967296.0);
-        int64_t tgt = coin < (double)aprob[slot] ? slot : alias[slot];
+        int64_t tgt = sample_cdf(C, V, guide, u01(rt));
         uint64_t key = ((uint64_t)v << (pb + vb)) | ((uint64_t)lo2 << vb) | (uint64_t)tgt;
         h[e] = mix64(key ^ hseed);
       }
     }
+    VLOG("[wl] edges done %.2fs\n", omp_get_wtime() - t0);
     radix_sort_u64(h, tmp, E, 64);
+    VLOG("[wl] sort done %.2fs\n", omp_get_wtime() - t0);
     /* unique */
     int64_t u = 0;
     for (int64_t i = 0; i < E; ++i)
       if (i == 0 || h[i] != h[i - 1]) h[u++] = h[i];
+    VLOG("[wl] unique %lld of %lld (T=%lld) %.2fs\n", (long long)u, (long long)E, (long long)T,
+         omp_get_wtime() - t0);
     if (u >= T) {
       uint64_t vmask = ((uint64_t)1 << vb) - 1, pmask = ((uint64_t)1 << pb) - 1;
 #pragma omp parallel for schedule(static)
@@ -292,7 +367,7 @@ int64_t wl_gen_graph(int64_t V, int32_t P, int64_t T, double zipf_s, double out_
     over *= 1.02 * (double)T / (double)(u > 0 ? u : 1);
   }
   free(h); free(tmp); free(q); free(r); free(thr); free(deg); free(off); free(w);
-  free(aprob); free(alias);
+  free(C); free(guide);
   return result;
 }
 
@@ -364,46 +439,32 @@ void *wl_index_new(const int32_t *s, const int32_t *p, const int32_t *o, int64_t
   uint64_t vmask = ((uint64_t)1 << vb) - 1, pmask = ((uint64_t)1 << pb) - 1;
   uint64_t *k = (uint64_t *)malloc(sizeof(uint64_t) * (n > 0 ? n : 1));
   uint64_t *t = (uint64_t *)malloc(sizeof(uint64_t) * (n > 0 ? n : 1));
-  /* (s, p, o) */
+  for (int side = 0; side < 2; ++side) {
+    /* side 0: (s, p, o) -> out adjacency and per-predicate by-subject view;
+     * side 1: (o, p, s) -> in adjacency and per-predicate by-object view */
+    const int32_t *a1 = side == 0 ? s : o, *a2 = side == 0 ? o : s;
 #pragma omp parallel for schedule(static)
-  for (int64_t i = 0; i < n; ++i)
-    k[i] = ((uint64_t)s[i] << (pb + vb)) | ((uint64_t)p[i] << vb) | (uint64_t)o[i];
-  radix_sort_u64(k, t, n, nb);
-  ix->out_off = (int64_t *)malloc(sizeof(int64_t) * (V + 1));
-  build_grouped(k, n, V, pb + vb, vmask, ix->out_off);
-  ix->out_p = (int32_t *)malloc(sizeof(int32_t) * (n > 0 ? n : 1));
-  ix->out_o = (int32_t *)malloc(sizeof(int32_t) * (n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; ++i)
+      k[i] = ((uint64_t)a1[i] << (pb + vb)) | ((uint64_t)p[i] << vb) | (uint64_t)a2[i];
+    radix_sort_u64(k, t, n, nb);
+    int64_t *off = (int64_t *)malloc(sizeof(int64_t) * (V + 1));
+    build_grouped(k, n, V, pb + vb, vmask, off);
+    int32_t *pp = (int32_t *)malloc(sizeof(int32_t) * (n > 0 ? n : 1));
+    int32_t *mm = (int32_t *)malloc(sizeof(int32_t) * (n > 0 ? n : 1));
 #pragma omp parallel for schedule(static)
-  for (int64_t i = 0; i < n; ++i) {
-    ix->out_p[i] = (int32_t)((k[i] >> vb) & pmask);
-    ix->out_o[i] = (int32_t)(k[i] & vmask);
+    for (int64_t i = 0; i < n; ++i) {
+      pp[i] = (int32_t)((k[i] >> vb) & pmask);
+      mm[i] = (int32_t)(k[i] & vmask);
+    }
+    regroup_by_pred(k, t, n, P, pb, vb);
+    if (side == 0) {
+      ix->out_off = off; ix->out_p = pp; ix->out_o = mm;
+      build_pred_view(t, n, P, vb, &ix->ps_pred_row, &ix->ps_row, &ix->ps_off, &ix->ps_nbr);
+    } else {
+      ix->in_off = off; ix->in_p = pp; ix->in_s = mm;
+      build_pred_view(t, n, P, vb, &ix->po_pred_row, &ix->po_row, &ix->po_off, &ix->po_nbr);
+    }
   }
-  /* (o, p, s) */
-#pragma omp parallel for schedule(static)
-  for (int64_t i = 0; i < n; ++i)
-    k[i] = ((uint64_t)o[i] << (pb + vb)) | ((uint64_t)p[i] << vb) | (uint64_t)s[i];
-  radix_sort_u64(k, t, n, nb);
-  ix->in_off = (int64_t *)malloc(sizeof(int64_t) * (V + 1));
-  build_grouped(k, n, V, pb + vb, vmask, ix->in_off);
-  ix->in_p = (int32_t *)malloc(sizeof(int32_t) * (n > 0 ? n : 1));
-  ix->in_s = (int32_t *)malloc(sizeof(int32_t) * (n > 0 ? n : 1));
-#pragma omp parallel for schedule(static)
-  for (int64_t i = 0; i < n; ++i) {
-    ix->in_p[i] = (int32_t)((k[i] >> vb) & pmask);
-    ix->in_s[i] = (int32_t)(k[i] & vmask);
-  }
-  /* (p, s, o) */
-#pragma omp parallel for schedule(static)
-  for (int64_t i = 0; i < n; ++i)
-    k[i] = ((uint64_t)p[i] << (2 * vb)) | ((uint64_t)s[i] << vb) | (uint64_t)o[i];
-  radix_sort_u64(k, t, n, nb);
-  build_pred_view(k, n, P, vb, &ix->ps_pred_row, &ix->ps_row, &ix->ps_off, &ix->ps_nbr);
-  /* (p, o, s) */
-#pragma omp parallel for schedule(static)
-  for (int64_t i = 0; i < n; ++i)
-    k[i] = ((uint64_t)p[i] << (2 * vb)) | ((uint64_t)o[i] << vb) | (uint64_t)s[i];
-  radix_sort_u64(k, t, n, nb);
-  build_pred_view(k, n, P, vb, &ix->po_pred_row, &ix->po_row, &ix->po_off, &ix->po_nbr);
   free(k); free(t);
   ix->deg_total = (int64_t *)malloc(sizeof(int64_t) * V);
 #pragma omp parallel for schedule(static)
@@ -758,16 +819,19 @@ int32_t wl_walk_query(void *h, int32_t kind, int32_t n, int32_t const_mode, int3
       witness[nv++] = br[b];
       ++ti;
     }
-    /* split the remaining patterns over the two branches: as even as the
-     * branch vertices' distinct out-predicates allow, at least one each */
+    /* split the remaining patterns over the two branches, as even as the
+     * branch vertices' distinct out-predicates allow (at least one each);
+     * what does not fit becomes further leaves of the centre */
     int rest = n - 2;
     int64_t av0 = n_pred_runs(ix->out_p, ix->out_off[br[0]], ix->out_off[br[0] + 1]);
     int64_t av1 = n_pred_runs(ix->out_p, ix->out_off[br[1]], ix->out_off[br[1] + 1]);
-    int k0 = (rest + 1) / 2;
-    if (k0 > av0) k0 = (int)av0;
-    if (rest - k0 > av1) k0 = rest - (int)av1;
-    int k1 = rest - k0;
-    if (k0 < 1 || k1 < 1 || k0 > av0 || k1 > av1) return 0;
+    if (av0 < 1 || av1 < 1) return 0;
+    int k0 = (rest + 1) / 2, k1 = rest - k0;
+    if (k0 > av0) { k1 += k0 - (int)av0; k0 = (int)av0; }
+    if (k1 > av1) { int ex = k1 - (int)av1; k1 = (int)av1; int room = (int)av0 - k0; int mv = ex < room ? ex : room; k0 += mv; }
+    if (k1 < 1) { k1 = 1; k0 = rest - 1 < k0 ? rest - 1 : k0; }
+    int kc = rest - k0 - k1; /* extra centre leaves */
+    if (kc < 0) return 0;
     int ks[2] = {k0, k1};
     for (int b = 0; b < 2; ++b) {
       int32_t y = br[b];
@@ -780,6 +844,23 @@ int32_t wl_walk_query(void *h, int32_t kind, int32_t n, int32_t const_mode, int3
         witness[nv++] = ix->out_o[e];
         ++ti;
       }
+    }
+    if (kc > 0) {
+      /* further out-edges of the centre with predicates not used by the branches */
+      int64_t cpick[40];
+      if (!pick_distinct_preds(ix->out_p, ix->out_off[v0], ix->out_off[v0 + 1], 2 + kc, bias, seed,
+                               ctr * 7 + 5, cpick))
+        return 0;
+      int added = 0;
+      for (int i = 0; i < 2 + kc && added < kc; ++i) {
+        int64_t e = cpick[i];
+        if (ix->out_p[e] == tp3[1] || ix->out_p[e] == tp3[4]) continue;
+        tp3[3 * ti] = -1; tp3[3 * ti + 1] = ix->out_p[e]; tp3[3 * ti + 2] = -nv - 1;
+        witness[nv++] = ix->out_o[e];
+        ++ti;
+        ++added;
+      }
+      if (added < kc) return 0;
     }
   } else {
     return 0;
