@@ -32,8 +32,9 @@
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
  *     device work of a call is enqueued on that stream; calls return after
  *     the work they need on the host side has completed.
- *   - Device memory comes from the library's stream-ordered pool unless an
- *     allocator is given to gsmat_load_triples.
+ *   - Device memory comes from the library's caching block allocator (blocks
+ *     from hipMalloc, reused per stream, cross-stream reuse ordered by events)
+ *     unless an allocator is given to gsmat_load_triples.
  *   - The store is immutable after gsmat_build_index; concurrent gsmat_join
  *     calls on different streams (and different results) are allowed.
  */
@@ -92,9 +93,15 @@ enum {
 enum {
   GSMAT_PLAN_PAPER = 0,   /* statistic = pair count of the predicate; pure
                              connected-minimal-upper-bound order (Sec. 6.2.1) */
-  GSMAT_PLAN_DEFAULT = 1  /* statistic = triples the TP matches on its own;
-                             constant-only TPs first; star centre intersection
-                             as first step; filters before expansions */
+  GSMAT_PLAN_DEFAULT = 1,  /* statistic = triples the TP matches on its own;
+                              constant-only TPs first; star centre intersection
+                              as first step; filters before expansions */
+  GSMAT_PLAN_ADAPTIVE = 2  /* GSMAT_PLAN_DEFAULT's first steps; afterwards the
+                              join picks, at every step, a connected TP whose
+                              endpoints are bound (filter) if any, else the
+                              expansion with the smallest output estimated from
+                              a sample of the bound rows; gsmat_plan_info then
+                              reports the static order, not the executed one */
 };
 
 typedef struct {
@@ -193,8 +200,8 @@ void gsmat_result_free(gsmat_result* r);
 /* Thread-local message for the last non-OK status of this thread. */
 const char* gsmat_last_error(void);
 
-/* Waits for the device and returns the unused memory cached by the library's
- * device pools to the driver (the pools stay usable).  Meant for process
+/* Waits for the device and returns the unused blocks cached by the library's
+ * allocator to the driver (the allocator stays usable).  Meant for process
  * shutdown after every handle is freed, and for callers that need the memory
  * back for other allocators. */
 gsmat_status gsmat_release_pools(void);
@@ -211,13 +218,19 @@ enum {
   GSMAT_K_NCLASS = 5
 };
 
-/* on != 0: record HIP events around kernels of every class on their stream
- * (adds host overhead); on == 0: stop.  Resets the counters. */
-void gsmat_prof_enable(int32_t on);
+/* Bit c of class_mask set: record a HIP event pair around every launch of
+ * kernel class c, on the launch's stream (adds a little host work per launch);
+ * 0 stops recording.  Resets the counters. */
+void gsmat_prof_enable(int32_t class_mask);
 
 /* Per class: launches, summed kernel milliseconds, algorithmic bytes.  Waits
  * for the recorded events.  Arrays of GSMAT_K_NCLASS entries. */
 gsmat_status gsmat_prof_read(int64_t* launches, double* ms, double* bytes);
+
+/* Host-side counters since the last gsmat_prof_enable: out5[0] ms inside
+ * device allocations, [1] allocation count, [2] ms inside frees, [3] ms
+ * waiting for streams, [4] number of waits. */
+gsmat_status gsmat_prof_host(double* out5);
 
 #ifdef __cplusplus
 }

@@ -59,6 +59,11 @@ def lib():
         L.oracle_result_copy.argtypes = [vp, vp]
         L.oracle_result_fingerprint.argtypes = [vp, vp]
         L.oracle_result_free.argtypes = [vp]
+        L.oracle_dataset_new.restype = vp
+        L.oracle_dataset_new.argtypes = [vp, vp, vp, i64]
+        L.oracle_dataset_free.argtypes = [vp]
+        L.oracle_join_dataset.restype = vp
+        L.oracle_join_dataset.argtypes = [vp, vp, i32, i32, i64]
         _lib = L
     return _lib
 
@@ -94,14 +99,28 @@ def csr(s, p, o, pred, orient):
     return keys, ptr, nbr
 
 
-def join(s, p, o, tps, n_vars, cap_rows=-1, fingerprint=False):
-    """Sorted result rows (rows x n_vars int32) of the BGP `tps` ((n,3) int32).
+class Dataset:
+    """The deduplicated triple set, built once for repeated oracle joins."""
 
-    With fingerprint=True returns (rows, h1 sum, h2 sum) instead.
-    """
-    s, p, o = _i32(s), _i32(p), _i32(o)
-    t = _i32(np.asarray(tps).reshape(-1, 3))
-    h = lib().oracle_join(_p(s), _p(p), _p(o), len(s), _p(t), len(t), n_vars, cap_rows)
+    def __init__(self, s, p, o):
+        s, p, o = _i32(s), _i32(p), _i32(o)
+        self.h = lib().oracle_dataset_new(_p(s), _p(p), _p(o), len(s))
+
+    def close(self):
+        if self.h:
+            lib().oracle_dataset_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def join(self, tps, n_vars, cap_rows=-1, fingerprint=False):
+        t = _i32(np.asarray(tps).reshape(-1, 3))
+        h = lib().oracle_join_dataset(self.h, _p(t), len(t), n_vars, cap_rows)
+        return _collect(h, n_vars, fingerprint)
+
+
+def _collect(h, n_vars, fingerprint):
     if not h:
         raise ValueError("oracle_join rejected the input (invalid BGP or row cap exceeded)")
     try:
@@ -116,6 +135,17 @@ def join(s, p, o, tps, n_vars, cap_rows=-1, fingerprint=False):
         return out
     finally:
         lib().oracle_result_free(h)
+
+
+def join(s, p, o, tps, n_vars, cap_rows=-1, fingerprint=False):
+    """Sorted result rows (rows x n_vars int32) of the BGP `tps` ((n,3) int32).
+
+    With fingerprint=True returns (rows, h1 sum, h2 sum) instead.
+    """
+    s, p, o = _i32(s), _i32(p), _i32(o)
+    t = _i32(np.asarray(tps).reshape(-1, 3))
+    h = lib().oracle_join(_p(s), _p(p), _p(o), len(s), _p(t), len(t), n_vars, cap_rows)
+    return _collect(h, n_vars, fingerprint)
 
 
 def brute_force(s, p, o, tps, n_vars, V):

@@ -89,7 +89,8 @@ uint64_t pack_key(const int32_t* row, const std::vector<int>& cols) {
 }
 
 // Natural join of a (current) and b (a TP relation with at most 2 variables).
-Relation join(const Relation& a, const Relation& b) {
+// Stops (returning rows = cap + 1) once more than cap rows exist, cap >= 0.
+Relation join(const Relation& a, const Relation& b, int64_t cap) {
   std::vector<int> a_shared, b_shared, b_new;
   for (size_t j = 0; j < b.vars.size(); ++j) {
     auto it = std::find(a.vars.begin(), a.vars.end(), b.vars[j]);
@@ -109,7 +110,7 @@ Relation join(const Relation& a, const Relation& b) {
       for (int64_t j = 0; j < b.rows; ++j) {
         for (size_t c = 0; c < wa; ++c) out.vals.push_back(a.vals[i * wa + c]);
         for (int c : b_new) out.vals.push_back(b.vals[j * wb + c]);
-        ++out.rows;
+        if (++out.rows > cap && cap >= 0) return out;
       }
     return out;
   }
@@ -122,7 +123,7 @@ Relation join(const Relation& a, const Relation& b) {
       int64_t j = it->second;
       for (size_t c = 0; c < wa; ++c) out.vals.push_back(a.vals[i * wa + c]);
       for (int c : b_new) out.vals.push_back(b.vals[j * wb + c]);
-      ++out.rows;
+      if (++out.rows > cap && cap >= 0) return out;
     }
   }
   return out;
@@ -202,18 +203,39 @@ int64_t oracle_csr(const int32_t* s, const int32_t* p, const int32_t* o, int64_t
   return (int64_t)pairs.size();
 }
 
+// A dataset handle: the deduplicated triple set, built once and reused by
+// oracle_join_dataset (so repeated queries do not pay the set construction).
+void* oracle_dataset_new(const int32_t* s, const int32_t* p, const int32_t* o, int64_t n) {
+  return new std::vector<Triple>(dedupe(s, p, o, n));
+}
+void oracle_dataset_free(void* ds) { delete static_cast<std::vector<Triple>*>(ds); }
+
+static void* join_impl(const std::vector<Triple>& D, const int32_t* tps, int32_t ntp,
+                       int32_t nvars, int64_t cap_rows);
+
 // Evaluates the BGP.  Returns an opaque result handle (null on invalid input).
 // Rows beyond cap_rows (if cap_rows >= 0) make the call return null.
 void* oracle_join(const int32_t* s, const int32_t* p, const int32_t* o, int64_t n,
                   const int32_t* tps, int32_t ntp, int32_t nvars, int64_t cap_rows) {
   if (ntp < 0 || nvars < 0) return nullptr;
   std::vector<Triple> D = dedupe(s, p, o, n);
+  return join_impl(D, tps, ntp, nvars, cap_rows);
+}
+
+void* oracle_join_dataset(void* ds, const int32_t* tps, int32_t ntp, int32_t nvars,
+                          int64_t cap_rows) {
+  if (!ds || ntp < 0 || nvars < 0) return nullptr;
+  return join_impl(*static_cast<std::vector<Triple>*>(ds), tps, ntp, nvars, cap_rows);
+}
+
+static void* join_impl(const std::vector<Triple>& D, const int32_t* tps, int32_t ntp,
+                       int32_t nvars, int64_t cap_rows) {
   std::vector<int> order = join_order(tps, ntp, nvars);
   Relation cur;  // the unit relation: one row, no columns
   cur.rows = 1;
   for (int t : order) {
     Relation r = tp_relation(D, tps[3 * t], tps[3 * t + 1], tps[3 * t + 2]);
-    cur = join(cur, r);
+    cur = join(cur, r, cap_rows);
     if (cap_rows >= 0 && cur.rows > cap_rows) return nullptr;
   }
   // variables that appear in no TP cannot be bound: the BGP defines them only

@@ -26,7 +26,7 @@ STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EHIP", 4: "ESTATE", 5: "E
                 6: "ETOOBIG"}
 STEP_SCAN, STEP_INTERSECT, STEP_EXPAND, STEP_FILTER, STEP_CARTESIAN = range(5)
 STEP_NAMES = {0: "SCAN", 1: "INTERSECT", 2: "EXPAND", 3: "FILTER", 4: "CARTESIAN"}
-PLAN_PAPER, PLAN_DEFAULT = 0, 1
+PLAN_PAPER, PLAN_DEFAULT, PLAN_ADAPTIVE = 0, 1, 2
 K_COUNT, K_SCAN, K_WRITE, K_COMPACT, K_OTHER = range(5)
 K_NAMES = ["count", "scan", "write", "compact", "other"]
 EXPORTED = [
@@ -34,7 +34,7 @@ EXPORTED = [
     "gsmat_export_matrix", "gsmat_store_free", "gsmat_plan", "gsmat_plan_from_stats",
     "gsmat_plan_info", "gsmat_plan_free", "gsmat_join", "gsmat_result_info",
     "gsmat_fetch_bindings", "gsmat_result_free", "gsmat_last_error", "gsmat_prof_enable",
-    "gsmat_prof_read", "gsmat_release_pools",
+    "gsmat_prof_read", "gsmat_prof_host", "gsmat_release_pools",
 ]
 
 
@@ -103,6 +103,8 @@ def _load():
     L.gsmat_prof_enable.argtypes = [i32]
     L.gsmat_prof_read.restype = i32
     L.gsmat_prof_read.argtypes = [vp, vp, vp]
+    L.gsmat_prof_host.restype = i32
+    L.gsmat_prof_host.argtypes = [vp]
     L.gsmat_release_pools.restype = i32
     L.gsmat_release_pools.argtypes = []
     return L
@@ -337,8 +339,9 @@ def gsmat_release_pools():
     _check(_lib.gsmat_release_pools())
 
 
-def gsmat_prof_enable(on=True):
-    _lib.gsmat_prof_enable(1 if on else 0)
+def gsmat_prof_enable(class_mask=0x1F):
+    """class_mask: bit K_* set to time that kernel class (0 stops)."""
+    _lib.gsmat_prof_enable(int(class_mask))
 
 
 def gsmat_prof_read():
@@ -350,7 +353,14 @@ def gsmat_prof_read():
             for i in range(5)}
 
 
-def evaluate(store, tps, mode=PLAN_DEFAULT, budget_bytes=0, max_rows=-1, stream=None):
+def gsmat_prof_host():
+    out = np.zeros(5, np.float64)
+    _check(_lib.gsmat_prof_host(_p(out)))
+    return {"alloc_ms": float(out[0]), "allocs": int(out[1]), "free_ms": float(out[2]),
+            "sync_ms": float(out[3]), "syncs": int(out[4])}
+
+
+def evaluate(store, tps, mode=PLAN_ADAPTIVE, budget_bytes=0, max_rows=-1, stream=None):
     """Plan + join + fetch: all rows of the BGP as an (rows, n_vars) int32 array."""
     pl = gsmat_plan(store, tps, mode, stream)
     try:

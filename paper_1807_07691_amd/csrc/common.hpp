@@ -77,6 +77,15 @@ struct ProbeArgs {
   int32_t o_const;
 };
 
+// Candidate expansions whose fan-out is estimated on a strided sample of the
+// bound column (one workgroup per candidate).
+struct SampleSet {
+  const int32_t* col[kMaxPats];
+  PredView pv[kMaxPats];
+  int64_t n;
+  int32_t ncand;
+};
+
 struct LookupReq {
   int32_t orient;  // 0 by subject, 1 by object
   int32_t pred;
@@ -104,7 +113,7 @@ class DeviceMem {
  private:
   gsmat_allocator user_{};
   bool has_user_ = false;
-  hipMemPool_t pool_ = nullptr;
+  void* cache_ = nullptr;  // the device's block cache
   int dev_ = 0;
 };
 
@@ -157,8 +166,9 @@ gsmat_status guarded(F&& f) {
 // profiling of kernel classes
 // -------------------------------------------------------------------------
 void prof_begin(hipStream_t s, int cls);
+void host_sync(hipStream_t s);  // hipStreamSynchronize, timed for instrumentation
 void prof_end(hipStream_t s, int cls, double bytes);
-bool prof_on();
+bool prof_on(int cls);
 
 // -------------------------------------------------------------------------
 // kernel launchers (kernels.hip)
@@ -224,6 +234,7 @@ void launch_write_expand(ColSet in, int k, const int64_t* P, const int32_t* star
                          int64_t ntiles, OutSet out, double alg_bytes, hipStream_t s);
 void launch_cartesian(ColSet a, int ka, int64_t na, ColSet b, int kb, int64_t nb, int64_t J0,
                       int64_t J1, OutSet out, hipStream_t s);
+void launch_sample_fanout(const SampleSet& ss, int64_t* sums, hipStream_t s);
 void launch_pack_rows(ColSet cols, int k, int64_t row0, int64_t rows, int32_t* out,
                       hipStream_t s);
 

@@ -88,7 +88,7 @@ int64_t* pinned_slot() {
 int64_t read_total(const int64_t* d, hipStream_t s) {
   int64_t* h = pinned_slot();
   GS_HIP(hipMemcpyAsync(h, d, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  GS_HIP(hipStreamSynchronize(s));
+  host_sync(s);
   return h[0];
 }
 
@@ -99,6 +99,9 @@ struct Exec {
   int64_t budget;
   int64_t max_rows;
   gsmat_result* res;
+  bool adaptive;
+
+  void sync_stream() { host_sync(s); }
 
   // table allocations not yet released or handed to the result
   std::vector<std::pair<void*, size_t>> live;
@@ -156,7 +159,7 @@ struct Exec {
                   st->out.dense, st->in.keys, st->in.ptr, st->in.nbr, st->in.dense, out.p, s);
     LookupRes r;
     GS_HIP(hipMemcpyAsync(&r, out.p, sizeof(r), hipMemcpyDeviceToHost, s));
-    GS_HIP(hipStreamSynchronize(s));
+    host_sync(s);
     return r;
   }
 
@@ -245,46 +248,146 @@ struct Exec {
     return t;
   }
 
-  void run(int si, Table& t) {
+  // TPs a step completes: its own TP, or for a star-centre intersection the
+  // members whose other endpoint is a constant (their membership is exact).
+  uint32_t completes(const gsmat_step_info& sp) const {
+    if (sp.kind != GSMAT_STEP_INTERSECT) return 1u << sp.tp;
+    uint32_t m = 0;
+    const int32_t cterm = -(sp.var + 1);
+    for (int tp = 0; tp < (int)pl->pats.size(); ++tp) {
+      if (!(sp.members >> tp & 1)) continue;
+      const gsmat_pattern& q = pl->pats[tp];
+      const int32_t other = q.s == cterm ? q.o : q.s;
+      if (!is_var(other)) m |= 1u << tp;
+    }
+    return m;
+  }
+
+  // Adaptive choice of the next step on the bound table t: connected patterns
+  // whose endpoints are all bound go first (filters never add rows); then the
+  // expansion with the smallest output, estimated by looking up a strided
+  // sample of the bound column on the device; with nothing connected, a
+  // Cartesian step with the smallest remaining pattern.
+  gsmat_step_info choose(const Table& t, uint32_t rem) {
+    uint64_t bound = 0;
+    for (int c = 0; c < t.k; ++c) bound |= 1ull << t.var[c];
+    auto is_bound = [&](int32_t term) { return !is_var(term) || (bound >> var_of(term) & 1); };
+    gsmat_step_info sp;
+    std::memset(&sp, 0, sizeof(sp));
+    sp.orient = -1;
+    sp.var = -1;
+    const int np = (int)pl->pats.size();
+    for (int tp = 0; tp < np; ++tp) {
+      if (!(rem >> tp & 1)) continue;
+      const gsmat_pattern& q = pl->pats[tp];
+      const bool connected = (is_var(q.s) && (bound >> var_of(q.s) & 1)) ||
+                             (is_var(q.o) && (bound >> var_of(q.o) & 1));
+      const bool all_const = !is_var(q.s) && !is_var(q.o);
+      if ((connected || all_const) && is_bound(q.s) && is_bound(q.o)) {
+        sp.kind = GSMAT_STEP_FILTER;
+        sp.tp = tp;
+        return sp;
+      }
+    }
+    SampleSet ss{};
+    int cand_tp[kMaxPats], cand_or[kMaxPats];
+    int nc = 0;
+    for (int tp = 0; tp < np; ++tp) {
+      if (!(rem >> tp & 1)) continue;
+      const gsmat_pattern& q = pl->pats[tp];
+      const bool sb = is_var(q.s) && (bound >> var_of(q.s) & 1);
+      const bool ob = is_var(q.o) && (bound >> var_of(q.o) & 1);
+      if (sb == ob) continue;  // not connected (both bound were handled above)
+      const int orient = sb ? 0 : 1;
+      const int32_t free_term = sb ? q.o : q.s;
+      if (!is_var(free_term)) continue;
+      ss.col[nc] = t.col[t.col_of(var_of(sb ? q.s : q.o))];
+      ss.pv[nc] = orient == 0 ? st->out.view(q.p) : st->in.view(q.p);
+      cand_tp[nc] = tp;
+      cand_or[nc] = orient;
+      ++nc;
+    }
+    if (nc > 0) {
+      int best = 0;
+      if (nc > 1) {
+        ss.n = t.n;
+        ss.ncand = nc;
+        Tmp<int64_t> sums(mem(), nc, s);
+        launch_sample_fanout(ss, sums.p, s);
+        int64_t h[kMaxPats];
+        GS_HIP(hipMemcpyAsync(h, sums.p, sizeof(int64_t) * nc, hipMemcpyDeviceToHost, s));
+        sync_stream();
+        for (int i = 1; i < nc; ++i)
+          if (h[i] < h[best]) best = i;
+      }
+      const gsmat_pattern& q = pl->pats[cand_tp[best]];
+      sp.kind = GSMAT_STEP_EXPAND;
+      sp.tp = cand_tp[best];
+      sp.orient = cand_or[best];
+      sp.var = cand_or[best] == 0 ? var_of(q.o) : var_of(q.s);
+      return sp;
+    }
+    int pick = -1;
+    int64_t best_nnz = INT64_MAX;
+    for (int tp = 0; tp < np; ++tp) {
+      if (!(rem >> tp & 1)) continue;
+      const int64_t z = st->out.desc[pl->pats[tp].p].nnz;
+      if (z < best_nnz) {
+        best_nnz = z;
+        pick = tp;
+      }
+    }
+    sp.kind = GSMAT_STEP_CARTESIAN;
+    sp.tp = pick;
+    return sp;
+  }
+
+  void run(int si, Table& t, uint32_t rem) {
     if (t.n == 0) {
       release(t);
       return;
     }
-    if (si == (int)pl->steps.size()) {
+    if (rem == 0) {
       emit(t);
       return;
     }
-    const gsmat_step_info& sp = pl->steps[si];
-    res->step_in[si] += t.n;
+    const gsmat_step_info sp =
+        (adaptive && !t.unit()) ? choose(t, rem) : pl->steps[std::min<size_t>(si, pl->steps.size() - 1)];
+    const uint32_t next = rem & ~completes(sp);
+    if (si < (int)res->step_in.size()) res->step_in[si] += t.n;
     switch (sp.kind) {
       case GSMAT_STEP_SCAN:
       case GSMAT_STEP_CARTESIAN: {
         Table r = tp_relation(sp.tp);
-        combine(si, t, r);
+        combine(si, t, r, next);
         break;
       }
       case GSMAT_STEP_INTERSECT: {
         Table r = intersect(sp);
-        combine(si, t, r);
+        combine(si, t, r, next);
         break;
       }
       case GSMAT_STEP_FILTER:
-        filter(si, t);
+        filter(si, sp, t, next);
         break;
       case GSMAT_STEP_EXPAND:
-        expand(si, t);
+        expand(si, sp, t, next);
         break;
       default:
         throw StatusFail{GSMAT_EINVAL, "unknown step kind"};
     }
   }
 
+  void add_out(int si, int64_t m) {
+    if (si < (int)res->step_out.size()) res->step_out[si] += m;
+  }
+
   // t x r: r alone when t is the unit table, else the Cartesian product.
-  void combine(int si, Table& t, Table& r) {
+  void combine(int si, Table& t, Table& r, uint32_t next) {
     if (t.unit()) {
-      res->step_out[si] += r.n;
+      add_out(si, r.n);
       release(t);
-      run(si + 1, r);
+      run(si + 1, r, next);
       return;
     }
     if (r.n == 0) {
@@ -295,7 +398,7 @@ struct Exec {
     if (t.k + r.k > kMaxCols) throw StatusFail{GSMAT_EUNSUPPORTED, "too many columns"};
     if (r.n > 0 && t.n > INT64_MAX / r.n) throw StatusFail{GSMAT_ETOOBIG, "Cartesian product overflows"};
     const int64_t m = t.n * r.n;
-    res->step_out[si] += m;
+    add_out(si, m);
     int vars[kMaxCols];
     for (int c = 0; c < t.k; ++c) vars[c] = t.var[c];
     for (int c = 0; c < r.k; ++c) vars[t.k + c] = r.var[c];
@@ -310,7 +413,7 @@ struct Exec {
       OutSet out{};
       for (int c = 0; c < k; ++c) out.c[c] = const_cast<int32_t*>(o.col[c]);
       if (k > 0) launch_cartesian(a, t.k, t.n, b, r.k, r.n, J0, J1, out, s);
-      run(si + 1, o);
+      run(si + 1, o, next);
     }
     release(t);
     release(r);
@@ -387,13 +490,13 @@ struct Exec {
     return o;
   }
 
-  void filter(int si, Table& t) {
-    const gsmat_pattern& q = pl->pats[pl->steps[si].tp];
+  void filter(int si, const gsmat_step_info& sp, Table& t, uint32_t next) {
+    const gsmat_pattern& q = pl->pats[sp.tp];
     if (!is_var(q.s) && !is_var(q.o)) {
       const LookupRes r = lookup(0, q.p, q.s, q.o);
       if (r.found) {
-        res->step_out[si] += t.n;
-        run(si + 1, t);
+        add_out(si, t.n);
+        run(si + 1, t, next);
       } else {
         release(t);
       }
@@ -412,9 +515,9 @@ struct Exec {
     launch_flag_filter(pa, n, pv, flags.p, ts.p, s);
     launch_scan_tile_sums(ts.p, nt, ts.p + nt, s);
     const int64_t m = read_total(ts.p + nt, s);
-    res->step_out[si] += m;
+    add_out(si, m);
     if (m == n) {  // nothing removed: pass the table on unchanged
-      run(si + 1, t);
+      run(si + 1, t, next);
       return;
     }
     if (m == 0) {
@@ -430,11 +533,10 @@ struct Exec {
     }
     launch_compact_cols(in, t.k, flags.p, n, ts.p, out, s);
     release(t);
-    run(si + 1, o);
+    run(si + 1, o, next);
   }
 
-  void expand(int si, Table& t) {
-    const gsmat_step_info& sp = pl->steps[si];
+  void expand(int si, const gsmat_step_info& sp, Table& t, uint32_t next) {
     const gsmat_pattern& q = pl->pats[sp.tp];
     const int bound_var = sp.orient == 0 ? var_of(q.s) : var_of(q.o);
     const int new_var = sp.orient == 0 ? var_of(q.o) : var_of(q.s);
@@ -449,7 +551,7 @@ struct Exec {
     launch_count_expand(t.col[bc], n, pv, N.p, start.p, ts.p, s);
     launch_scan_tile_sums(ts.p, nt, ts.p + nt, s);
     const int64_t m = read_total(ts.p + nt, s);
-    res->step_out[si] += m;
+    add_out(si, m);
     if (m == 0) {
       release(t);
       return;
@@ -473,7 +575,7 @@ struct Exec {
       const double parents = (double)n * (double)(J1 - J0) / (double)m;
       const double bytes = 4.0 * (double)(J1 - J0) * (k + 2) + parents * (4.0 * k + 12.0);
       launch_write_expand(in, k, P.p, start.p, n, pv.nbr, J0, J1, split.p, ntiles, out, bytes, s);
-      run(si + 1, o);
+      run(si + 1, o, next);
     }
     release(t);
   }
@@ -494,7 +596,7 @@ std::vector<TpStat> pattern_stats(const gsmat_store* st, const gsmat_pattern* pa
     t.stat = dout.nnz;
     t.rows_s = dout.nr;
     t.rows_o = din.nr;
-    if (mode != GSMAT_PLAN_DEFAULT) continue;
+    if (mode == GSMAT_PLAN_PAPER) continue;
     const bool sc = !is_var(q.s), oc = !is_var(q.o);
     if ((sc && q.s >= st->V) || (oc && q.o >= st->V)) {
       t.stat = t.rows_s = t.rows_o = 0;
@@ -580,12 +682,13 @@ extern "C" gsmat_status gsmat_join(gsmat_store* st, const gsmat_query_plan* pl, 
       if (!is_var(q.o) && q.o >= st->V) empty = true;
     }
     if (!empty) {
-      Exec ex{st, pl, s, budget_bytes, max_rows, res.get(), {}};
+      Exec ex{st, pl, s, budget_bytes, max_rows, res.get(), pl->mode == GSMAT_PLAN_ADAPTIVE, {}};
       Table unit;
       unit.n = 1;
       unit.k = 0;
+      const uint32_t all = pl->pats.size() >= 32 ? 0xFFFFFFFFu : ((1u << pl->pats.size()) - 1);
       try {
-        ex.run(0, unit);
+        ex.run(0, unit, all);
       } catch (...) {
         ex.release_all();
         throw;

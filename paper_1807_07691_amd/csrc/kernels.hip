@@ -605,6 +605,25 @@ __global__ void k_cartesian(ColSet a, int ka, ColSet b, int kb, int64_t nb, int6
   }
 }
 
+constexpr int64_t kSampleRows = 16384;
+
+__global__ __launch_bounds__(kBlock) void k_sample_fanout(SampleSet ss, int64_t* __restrict__ sums) {
+  const int b = blockIdx.x;
+  const int64_t n = ss.n;
+  const int64_t S = n < kSampleRows ? n : kSampleRows;
+  const int64_t stride = S > 0 ? n / S : 1;
+  const int32_t* col = ss.col[b];
+  const PredView pv = ss.pv[b];
+  int64_t loc = 0;
+  for (int64_t j = threadIdx.x; j < S; j += kBlock) {
+    int32_t st, len;
+    row_lookup(pv, col[j * stride], st, len);
+    loc += len;
+  }
+  const int64_t t = block_sum(loc);
+  if (threadIdx.x == 0) sums[b] = t;
+}
+
 __global__ void k_pack_rows(ColSet cols, int k, int64_t row0, int64_t rows,
                             int32_t* __restrict__ out) {
   const int64_t total = rows * k;
@@ -626,12 +645,13 @@ inline unsigned tiles_for(int64_t n) { return (unsigned)ceil_div(n > 0 ? n : 1, 
 }  // namespace
 
 // ---------------------------------------------------------------- launchers
-#define GS_LAUNCH(cls, bytes, ...)        \
-  do {                                    \
-    if (prof_on()) prof_begin(s, cls);    \
-    __VA_ARGS__;                          \
-    GS_HIP(hipGetLastError());            \
-    if (prof_on()) prof_end(s, cls, bytes); \
+#define GS_LAUNCH(cls, bytes, ...)              \
+  do {                                          \
+    const bool _prof = prof_on(cls);            \
+    if (_prof) prof_begin(s, cls);              \
+    __VA_ARGS__;                                \
+    GS_HIP(hipGetLastError());                  \
+    if (_prof) prof_end(s, cls, bytes);         \
   } while (0)
 
 void launch_scan_tile_sums(int64_t* tile_sum, int64_t nt, int64_t* total, hipStream_t s) {
@@ -839,6 +859,12 @@ void launch_cartesian(ColSet a, int ka, int64_t na, ColSet b, int kb, int64_t nb
   GS_LAUNCH(GSMAT_K_OTHER, 4.0 * (ka + kb) * 2.0 * (J1 - J0),
             hipLaunchKernelGGL(k_cartesian, dim3(grid_for(J1 - J0)), dim3(kBlock), 0, s, a, ka, b,
                                kb, nb, J0, J1, out));
+}
+
+void launch_sample_fanout(const SampleSet& ss, int64_t* sums, hipStream_t s) {
+  GS_LAUNCH(GSMAT_K_OTHER, 0.0,
+            hipLaunchKernelGGL(k_sample_fanout, dim3((unsigned)ss.ncand), dim3(kBlock), 0, s, ss,
+                               sums));
 }
 
 void launch_pack_rows(ColSet cols, int k, int64_t row0, int64_t rows, int32_t* out,

@@ -82,7 +82,7 @@ gsmat_status build_plan(const gsmat_pattern* pats, int32_t n, int32_t mode,
   int32_t nv = 0;
   gsmat_status rc = validate_patterns(pats, n, &nv, err);
   if (rc != GSMAT_OK) return rc;
-  if (mode != GSMAT_PLAN_PAPER && mode != GSMAT_PLAN_DEFAULT) {
+  if (mode != GSMAT_PLAN_PAPER && mode != GSMAT_PLAN_DEFAULT && mode != GSMAT_PLAN_ADAPTIVE) {
     *err = "unknown plan mode";
     return GSMAT_EINVAL;
   }
@@ -90,6 +90,7 @@ gsmat_status build_plan(const gsmat_pattern* pats, int32_t n, int32_t mode,
   out->n_vars = nv;
   out->mode = mode;
   out->steps.clear();
+  if (mode == GSMAT_PLAN_ADAPTIVE) mode = GSMAT_PLAN_DEFAULT;  // same static order
 
   std::vector<int> order(n);
   std::iota(order.begin(), order.end(), 0);

@@ -106,7 +106,7 @@ def test_tiny_index_matches_oracle(G, O, tiny):
             assert all(np.array_equal(a, b) for a, b in zip(got, want)), (pred, orient)
 
 
-@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("mode", [0, 1, 2])
 @pytest.mark.parametrize("qi", range(8))
 def test_tiny_queries(G, O, tiny, mode, qi):
     spec, s, p, o, qs, st, st_dense = tiny
@@ -128,8 +128,9 @@ def test_tiny_chunked(G, O, tiny, qi):
     print(f"[gpu] tiny chunked query {qi}", flush=True)
     want = O.join(s, p, o, q.tps, q.n_vars)
     for budget in (4 * (q.n_vars + 1) * 997, 4 * (q.n_vars + 1) * 50_000):
-        got = _sorted(G.evaluate(st, q.tps, 1, budget_bytes=budget))
-        assert np.array_equal(got, want), budget
+        for mode in (1, 2):
+            got = _sorted(G.evaluate(st, q.tps, mode, budget_bytes=budget))
+            assert np.array_equal(got, want), (budget, mode)
 
 
 def test_tiny_plan_permutation_invariance(G, O, tiny):
@@ -139,7 +140,7 @@ def test_tiny_plan_permutation_invariance(G, O, tiny):
         want = O.join(s, p, o, q.tps, q.n_vars)
         for _ in range(3):
             perm = rng.permutation(len(q.tps))
-            got = _sorted(G.evaluate(st, q.tps[perm], 1))
+            got = _sorted(G.evaluate(st, q.tps[perm], 2))
             assert np.array_equal(got, want)
 
 
@@ -189,7 +190,7 @@ SHAPES = {
 
 
 @pytest.mark.parametrize("shape", sorted(SHAPES))
-@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("mode", [0, 1, 2])
 def test_shapes(G, O, shape, mode):
     tps, nv = SHAPES[shape]
     rng = np.random.default_rng(7)
@@ -228,7 +229,7 @@ def test_random_bgps(G, O, seed):
         tps = [[(-remap[-a - 1] - 1) if a < 0 else a, b, (-remap[-c - 1] - 1) if c < 0 else c]
                for a, b, c in tps]
         want = O.join(s, p, o, tps, len(used), cap_rows=2_000_000)
-        for mode in (0, 1):
+        for mode in (0, 1, 2):
             got = _sorted(G.evaluate(st, tps, mode))
             assert got.shape == want.shape and np.array_equal(got, want), (tps, mode)
 
