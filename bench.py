@@ -21,6 +21,25 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "write_expand_large_pmc.md")
+KERNELS_SRC = os.path.join(ROOT, "paper_1807_07691_amd", "csrc", "kernels.hip")
+
+
+def counter_traffic(workload):
+    """HBM bytes per k_write_expand launch from the committed counter summary,
+    only if it was taken on this workload with the current kernel source."""
+    import hashlib
+    if workload != "large" or not os.path.exists(PMC_SUMMARY):
+        return None
+    vals = {}
+    for line in open(PMC_SUMMARY):
+        if ":" in line and line.split(":", 1)[0] in ("traffic_bytes_per_launch", "kernels_hip_sha256"):
+            k, v = line.split(":", 1)
+            vals[k] = v.strip()
+    cur = hashlib.sha256(open(KERNELS_SRC, "rb").read()).hexdigest()
+    if vals.get("kernels_hip_sha256") != cur or "traffic_bytes_per_launch" not in vals:
+        return None
+    return int(vals["traffic_bytes_per_launch"])
 
 
 def log(msg):
@@ -61,6 +80,9 @@ def main():
     ap.add_argument("--max-queries", type=int, default=0, help="0 = all")
     ap.add_argument("--cpu-sample-s", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy-gib", type=float, default=0.0,
+                    help="after the run, copy a buffer of this size device-to-device 3 times "
+                         "(a plain copy kernel of known size for counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -188,7 +210,8 @@ def main():
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": None,
+        "traffic": counter_traffic(args.workload),
+        "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
         "kernel": "k_write_expand",
         "launches": wr["launches"],
         "avg_launch_ms": round(wr["ms"] / max(1, wr["launches"]), 4),
@@ -283,6 +306,15 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
+    if args.calib_copy_gib > 0:
+        n = int(args.calib_copy_gib * 2**30) // 4
+        a_ = torch.empty(n, dtype=torch.int32, device="cuda").fill_(1)
+        b_ = torch.empty_like(a_)
+        for _ in range(3):
+            b_.copy_(a_)
+        torch.cuda.synchronize()
+        out["calib_copy_bytes"] = n * 4
+        del a_, b_
     print(json.dumps(out), flush=True)
     st.close()
 
