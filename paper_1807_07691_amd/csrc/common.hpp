@@ -92,6 +92,11 @@ struct LookupReq {
   int32_t v;       // the row (vertex) to look up
   int32_t member;  // >= 0: also test membership of this value in the row
 };
+constexpr int kMaxLookups = 32;
+struct LookupBatch {
+  LookupReq req[kMaxLookups];
+  int32_t n;
+};
 struct LookupRes {
   int32_t start;   // local offset of the row (0 if absent)
   int32_t len;     // row length (0 if absent)
@@ -176,7 +181,10 @@ bool prof_on(int cls);
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 // prefix sums
-void launch_scan_tile_sums(int64_t* tile_sum, int64_t nt, int64_t* total, hipStream_t s);
+// scan of tile sums in place; the grand total goes to total[0] and, if given,
+// to host_total[0] (pinned host memory, valid after the stream synchronizes)
+void launch_scan_tile_sums(int64_t* tile_sum, int64_t nt, int64_t* total, hipStream_t s,
+                           int64_t* host_total);
 void launch_scan_add_i32(const int32_t* N, int64_t n, const int64_t* tile_off, int64_t* P,
                          hipStream_t s);
 void launch_tile_reduce_u32(const uint32_t* x, int64_t n, int64_t* tile_sum, hipStream_t s);
@@ -210,7 +218,7 @@ void launch_dense_ptr(PredView pv, int64_t V, int32_t* dense, hipStream_t s);
 void launch_ptr_sentinels(const PredDesc* d, int32_t P, int32_t* ptr, hipStream_t s);
 
 // lookups (planner statistics, constant scans)
-void launch_lookup(const LookupReq* req, int n, const PredDesc* desc_out, const PredDesc* desc_in,
+void launch_lookup(const LookupBatch& b, const PredDesc* desc_out, const PredDesc* desc_in,
                    const int32_t* keys_out, const int32_t* ptr_out, const int32_t* nbr_out,
                    const int32_t* dense_out, const int32_t* keys_in, const int32_t* ptr_in,
                    const int32_t* nbr_in, const int32_t* dense_in, LookupRes* res,
@@ -234,7 +242,9 @@ void launch_write_expand(ColSet in, int k, const int64_t* P, const int32_t* star
                          int64_t ntiles, OutSet out, double alg_bytes, hipStream_t s);
 void launch_cartesian(ColSet a, int ka, int64_t na, ColSet b, int kb, int64_t nb, int64_t J0,
                       int64_t J1, OutSet out, hipStream_t s);
-void launch_sample_fanout(const SampleSet& ss, int64_t* sums, hipStream_t s);
+constexpr int kSampleBlocks = 8;  // workgroups per candidate in launch_sample_fanout
+// writes kSampleBlocks partial sums per candidate to part[cand * kSampleBlocks + b]
+void launch_sample_fanout(const SampleSet& ss, int64_t* part, hipStream_t s);
 void launch_pack_rows(ColSet cols, int k, int64_t row0, int64_t rows, int32_t* out,
                       hipStream_t s);
 

@@ -79,17 +79,26 @@ struct Tmp {
   Tmp& operator=(const Tmp&) = delete;
 };
 
-int64_t* pinned_slot() {
-  thread_local int64_t* slot = nullptr;
-  if (!slot) GS_HIP(hipHostMalloc((void**)&slot, 64, hipHostMallocDefault));
-  return slot;
+// Per-thread pinned host area that kernels write small results into (sizes
+// of the next step, lookups, fan-out samples); read after the stream syncs.
+struct PinnedArea {
+  int64_t total[8];
+  LookupRes res[kMaxLookups];
+  int64_t part[kMaxPats * kSampleBlocks];
+};
+
+PinnedArea* pinned() {
+  thread_local PinnedArea* a = nullptr;
+  if (!a) GS_HIP(hipHostMalloc((void**)&a, sizeof(PinnedArea), hipHostMallocDefault));
+  return a;
 }
 
-int64_t read_total(const int64_t* d, hipStream_t s) {
-  int64_t* h = pinned_slot();
-  GS_HIP(hipMemcpyAsync(h, d, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+// Scans the tile sums in place and returns the grand total.
+int64_t scan_total(int64_t* ts, int64_t nt, hipStream_t s) {
+  PinnedArea* h = pinned();
+  launch_scan_tile_sums(ts, nt, ts + nt, s, &h->total[0]);
   host_sync(s);
-  return h[0];
+  return h->total[0];
 }
 
 struct Exec {
@@ -151,16 +160,14 @@ struct Exec {
   }
 
   LookupRes lookup(int orient, int32_t p, int32_t v, int32_t member) {
-    Tmp<LookupReq> req(mem(), 1, s);
-    Tmp<LookupRes> out(mem(), 1, s);
-    LookupReq q{orient, p, v, member};
-    GS_HIP(hipMemcpyAsync(req.p, &q, sizeof(q), hipMemcpyHostToDevice, s));
-    launch_lookup(req.p, 1, st->out.d_desc, st->in.d_desc, st->out.keys, st->out.ptr, st->out.nbr,
-                  st->out.dense, st->in.keys, st->in.ptr, st->in.nbr, st->in.dense, out.p, s);
-    LookupRes r;
-    GS_HIP(hipMemcpyAsync(&r, out.p, sizeof(r), hipMemcpyDeviceToHost, s));
+    LookupBatch b{};
+    b.req[0] = LookupReq{orient, p, v, member};
+    b.n = 1;
+    PinnedArea* h = pinned();
+    launch_lookup(b, st->out.d_desc, st->in.d_desc, st->out.keys, st->out.ptr, st->out.nbr,
+                  st->out.dense, st->in.keys, st->in.ptr, st->in.nbr, st->in.dense, h->res, s);
     host_sync(s);
-    return r;
+    return h->res[0];
   }
 
   void emit(Table& t) {
@@ -211,8 +218,7 @@ struct Exec {
       Tmp<uint8_t> flags(mem(), n, s);
       Tmp<int64_t> ts(mem(), nt + 1, s);
       if (n > 0) launch_flag_diag(pv.src, pv.nbr, n, flags.p, ts.p, s);
-      launch_scan_tile_sums(ts.p, nt, ts.p + nt, s);
-      const int64_t m = n > 0 ? read_total(ts.p + nt, s) : 0;
+      const int64_t m = n > 0 ? scan_total(ts.p, nt, s) : 0;
       int v = var_of(q.s);
       Table o = alloc_table(m, &v, 1);
       if (m > 0) {
@@ -312,13 +318,16 @@ struct Exec {
       if (nc > 1) {
         ss.n = t.n;
         ss.ncand = nc;
-        Tmp<int64_t> sums(mem(), nc, s);
-        launch_sample_fanout(ss, sums.p, s);
-        int64_t h[kMaxPats];
-        GS_HIP(hipMemcpyAsync(h, sums.p, sizeof(int64_t) * nc, hipMemcpyDeviceToHost, s));
+        PinnedArea* h = pinned();
+        launch_sample_fanout(ss, h->part, s);
         sync_stream();
+        int64_t sum[kMaxPats];
+        for (int i = 0; i < nc; ++i) {
+          sum[i] = 0;
+          for (int b = 0; b < kSampleBlocks; ++b) sum[i] += h->part[i * kSampleBlocks + b];
+        }
         for (int i = 1; i < nc; ++i)
-          if (h[i] < h[best]) best = i;
+          if (sum[i] < sum[best]) best = i;
       }
       const gsmat_pattern& q = pl->pats[cand_tp[best]];
       sp.kind = GSMAT_STEP_EXPAND;
@@ -471,8 +480,7 @@ struct Exec {
     Tmp<uint8_t> flags(mem(), n, s);
     Tmp<int64_t> ts(mem(), nt + 1, s);
     launch_flag_intersect(lists[d].ids, n, ls, flags.p, ts.p, s);
-    launch_scan_tile_sums(ts.p, nt, ts.p + nt, s);
-    const int64_t m = read_total(ts.p + nt, s);
+    const int64_t m = scan_total(ts.p, nt, s);
     if (m == n) {  // every driver id survives: the driver list itself
       t.n = n;
       t.col[0] = lists[d].ids;
@@ -513,8 +521,7 @@ struct Exec {
     Tmp<uint8_t> flags(mem(), n, s);
     Tmp<int64_t> ts(mem(), nt + 1, s);
     launch_flag_filter(pa, n, pv, flags.p, ts.p, s);
-    launch_scan_tile_sums(ts.p, nt, ts.p + nt, s);
-    const int64_t m = read_total(ts.p + nt, s);
+    const int64_t m = scan_total(ts.p, nt, s);
     add_out(si, m);
     if (m == n) {  // nothing removed: pass the table on unchanged
       run(si + 1, t, next);
@@ -549,8 +556,7 @@ struct Exec {
     Tmp<int32_t> N(mem(), n, s), start(mem(), n, s);
     Tmp<int64_t> ts(mem(), nt + 1, s), P(mem(), n + 1, s);
     launch_count_expand(t.col[bc], n, pv, N.p, start.p, ts.p, s);
-    launch_scan_tile_sums(ts.p, nt, ts.p + nt, s);
-    const int64_t m = read_total(ts.p + nt, s);
+    const int64_t m = scan_total(ts.p, nt, s);
     add_out(si, m);
     if (m == 0) {
       release(t);
@@ -614,16 +620,14 @@ std::vector<TpStat> pattern_stats(const gsmat_store* st, const gsmat_pattern* pa
     }
   }
   if (!reqs.empty()) {
-    DeviceMem* mem = st->mem.get();
-    Tmp<LookupReq> dreq(mem, (int64_t)reqs.size(), s);
-    Tmp<LookupRes> dres(mem, (int64_t)reqs.size(), s);
-    std::vector<LookupRes> res(reqs.size());
-    GS_HIP(hipMemcpyAsync(dreq.p, reqs.data(), sizeof(LookupReq) * reqs.size(), hipMemcpyHostToDevice, s));
-    launch_lookup(dreq.p, (int)reqs.size(), st->out.d_desc, st->in.d_desc, st->out.keys,
-                  st->out.ptr, st->out.nbr, st->out.dense, st->in.keys, st->in.ptr, st->in.nbr,
-                  st->in.dense, dres.p, s);
-    GS_HIP(hipMemcpyAsync(res.data(), dres.p, sizeof(LookupRes) * reqs.size(), hipMemcpyDeviceToHost, s));
-    GS_HIP(hipStreamSynchronize(s));
+    LookupBatch b{};
+    for (size_t i = 0; i < reqs.size(); ++i) b.req[i] = reqs[i];
+    b.n = (int32_t)reqs.size();
+    PinnedArea* h = pinned();
+    launch_lookup(b, st->out.d_desc, st->in.d_desc, st->out.keys, st->out.ptr, st->out.nbr,
+                  st->out.dense, st->in.keys, st->in.ptr, st->in.nbr, st->in.dense, h->res, s);
+    host_sync(s);
+    std::vector<LookupRes> res(h->res, h->res + reqs.size());
     for (int i = 0; i < n; ++i) {
       if (req_of[i] < 0) continue;
       const LookupRes& r = res[req_of[i]];

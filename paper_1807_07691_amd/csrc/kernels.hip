@@ -135,7 +135,7 @@ __device__ inline void compact_tile(int64_t n, int64_t base, Keep keep, Emit emi
 
 // ---------------------------------------------------------------- prefix sums
 __global__ __launch_bounds__(kBlock) void k_scan_tile_sums(int64_t* ts, int64_t nt,
-                                                           int64_t* total) {
+                                                           int64_t* total, int64_t* host_total) {
   int64_t carry = 0;
   for (int64_t c0 = 0; c0 < nt; c0 += kTile) {
     int64_t v[kItems];
@@ -156,7 +156,10 @@ __global__ __launch_bounds__(kBlock) void k_scan_tile_sums(int64_t* ts, int64_t 
     }
     carry += tot;
   }
-  if (threadIdx.x == 0) total[0] = carry;
+  if (threadIdx.x == 0) {
+    total[0] = carry;
+    if (host_total) host_total[0] = carry;  // pinned host memory: read after the stream syncs
+  }
 }
 
 template <class Tin, class Tout>
@@ -392,14 +395,13 @@ __device__ inline PredView view_of(const PredDesc& d, const int32_t* keys, const
   return pv;
 }
 
-__global__ void k_lookup(const LookupReq* __restrict__ req, int n, const PredDesc* dout,
-                         const PredDesc* din, const int32_t* keys_out, const int32_t* ptr_out,
-                         const int32_t* nbr_out, const int32_t* dense_out,
-                         const int32_t* keys_in, const int32_t* ptr_in, const int32_t* nbr_in,
-                         const int32_t* dense_in, LookupRes* __restrict__ res) {
+__global__ void k_lookup(LookupBatch b, const PredDesc* dout, const PredDesc* din,
+                         const int32_t* keys_out, const int32_t* ptr_out, const int32_t* nbr_out,
+                         const int32_t* dense_out, const int32_t* keys_in, const int32_t* ptr_in,
+                         const int32_t* nbr_in, const int32_t* dense_in, LookupRes* res) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const LookupReq q = req[i];
+  if (i >= b.n) return;
+  const LookupReq q = b.req[i];
   const PredView pv = q.orient == 0
                           ? view_of(dout[q.pred], keys_out, ptr_out, nbr_out, dense_out)
                           : view_of(din[q.pred], keys_in, ptr_in, nbr_in, dense_in);
@@ -505,7 +507,8 @@ __global__ __launch_bounds__(kBlock) void k_flag_intersect(const int32_t* __rest
   if (threadIdx.x == 0) ts[blockIdx.x] = t;
 }
 
-__global__ __launch_bounds__(kBlock) void k_compact_cols(ColSet in, int k,
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_compact_cols(ColSet in, int kdyn,
                                                          const uint8_t* __restrict__ flags,
                                                          int64_t n,
                                                          const int64_t* __restrict__ tile_off,
@@ -513,7 +516,15 @@ __global__ __launch_bounds__(kBlock) void k_compact_cols(ColSet in, int k,
   compact_tile(
       n, tile_off[blockIdx.x], [&](int64_t i) { return flags[i] != 0; },
       [&](int64_t i, int64_t pos) {
-        for (int c = 0; c < k; ++c) out.c[c][pos] = in.c[c][i];
+        if (K >= 0) {
+          int32_t x[K > 0 ? K : 1];
+#pragma unroll
+          for (int c = 0; c < K; ++c) x[c] = in.c[c][i];
+#pragma unroll
+          for (int c = 0; c < K; ++c) out.c[c][pos] = x[c];
+        } else {
+          for (int c = 0; c < kdyn; ++c) out.c[c][pos] = in.c[c][i];
+        }
       });
 }
 
@@ -537,7 +548,72 @@ __global__ void k_mp_partition(const int64_t* __restrict__ P, int64_t n, int64_t
 
 // Expansion write: output j in [P_i, P_{i+1}) copies the parent row i and
 // appends the (j - P_i)-th member of row i's segment (start_i) in nbr.
-__global__ __launch_bounds__(kBlock) void k_write_expand(ColSet in, int k,
+//
+// A tile is kTile consecutive items of the merge path over (row ends, output
+// indices); split[t] gives the rows consumed before it, so the tile covers
+// rows a0..a1 and outputs jb + [0, nbt).  Per row the tile keeps in LDS the
+// row end relative to jb (clamped to [-1, kTile + 1], which preserves every
+// comparison the walk makes) and rb = start_i + (jb - P_i), so that output o of
+// row r reads nbr[rb[r] + o]; both fit int32.  Each thread walks kItems path
+// items to label outputs with their row; then the tile's outputs are written
+// column by column with unit stride.  The column loops are unrolled for a
+// compile-time column count K so that a thread's parent loads are all in
+// flight before its stores.
+template <int K>
+__device__ inline void write_outputs(const ColSet& in, int kdyn, const int32_t* __restrict__ nbr,
+                                     const uint16_t* sRow, const int32_t* sRb, int64_t a0,
+                                     int64_t ob, int nbt, OutSet& out) {
+  const int k = K >= 0 ? K : kdyn;
+  int o = threadIdx.x;
+  // two outputs per iteration: their loads overlap
+  for (; o + kBlock < nbt; o += 2 * kBlock) {
+    const int o2 = o + kBlock;
+    const int r1 = sRow[o], r2 = sRow[o2];
+    const int32_t v1 = nbr[sRb[r1] + o], v2 = nbr[sRb[r2] + o2];
+    const int64_t row1 = a0 + r1, row2 = a0 + r2;
+    if (K >= 0) {
+      int32_t x1[K > 0 ? K : 1], x2[K > 0 ? K : 1];
+#pragma unroll
+      for (int c = 0; c < K; ++c) {
+        x1[c] = in.c[c][row1];
+        x2[c] = in.c[c][row2];
+      }
+#pragma unroll
+      for (int c = 0; c < K; ++c) {
+        __builtin_nontemporal_store(x1[c], &out.c[c][ob + o]);
+        __builtin_nontemporal_store(x2[c], &out.c[c][ob + o2]);
+      }
+    } else {
+      for (int c0 = 0; c0 < k; c0 += 4) {
+        int32_t x1[4], x2[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+          if (c0 + c < k) {
+            x1[c] = in.c[c0 + c][row1];
+            x2[c] = in.c[c0 + c][row2];
+          }
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+          if (c0 + c < k) {
+            __builtin_nontemporal_store(x1[c], &out.c[c0 + c][ob + o]);
+            __builtin_nontemporal_store(x2[c], &out.c[c0 + c][ob + o2]);
+          }
+      }
+    }
+    __builtin_nontemporal_store(v1, &out.c[k][ob + o]);
+    __builtin_nontemporal_store(v2, &out.c[k][ob + o2]);
+  }
+  if (o < nbt) {
+    const int r = sRow[o];
+    const int32_t v = nbr[sRb[r] + o];
+    const int64_t row = a0 + r;
+    for (int c = 0; c < k; ++c) __builtin_nontemporal_store(in.c[c][row], &out.c[c][ob + o]);
+    __builtin_nontemporal_store(v, &out.c[k][ob + o]);
+  }
+}
+
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_write_expand(ColSet in, int kdyn,
                                                          const int64_t* __restrict__ P,
                                                          const int32_t* __restrict__ start,
                                                          int64_t n,
@@ -545,8 +621,8 @@ __global__ __launch_bounds__(kBlock) void k_write_expand(ColSet in, int k,
                                                          int64_t J0, int64_t J1,
                                                          const int64_t* __restrict__ split,
                                                          OutSet out) {
-  __shared__ int64_t sP[kTile + 2];
-  __shared__ int32_t sStart[kTile + 1];
+  __shared__ int32_t sE[kTile + 1];
+  __shared__ int32_t sRb[kTile + 1];
   __shared__ uint16_t sRow[kTile];
   const int64_t t = blockIdx.x;
   const int64_t nb = J1 - J0;
@@ -557,23 +633,27 @@ __global__ __launch_bounds__(kBlock) void k_write_expand(ColSet in, int k,
   const int64_t b0 = d0 - a0, b1 = d1 - a1;
   const int nat = (int)(a1 - a0), nbt = (int)(b1 - b0);
   if (nbt <= 0) return;  // block-uniform
+  const int64_t jb = J0 + b0;
   const int64_t rl = min(a1, n - 1);
   const int nr = (int)(rl - a0 + 1);
-  for (int i = threadIdx.x; i <= nr; i += kBlock) sP[i] = P[a0 + i];
-  for (int i = threadIdx.x; i < nr; i += kBlock) sStart[i] = start[a0 + i];
+  for (int i = threadIdx.x; i < nr; i += kBlock) {
+    const int64_t pb = P[a0 + i], pe = P[a0 + i + 1];
+    const int64_t er = pe - jb;
+    sE[i] = er > (int64_t)kTile + 1 ? kTile + 1 : (er < -1 ? -1 : (int32_t)er);
+    sRb[i] = (int32_t)((int64_t)start[a0 + i] + (jb - pb));
+  }
   __syncthreads();
-  const int64_t jb = J0 + b0;
   const int dl = min((int)threadIdx.x * kItems, nat + nbt);
   const int de = min((int)threadIdx.x * kItems + kItems, nat + nbt);
   int lo = max(0, dl - nbt), hi = min(dl, nat);
   while (lo < hi) {
     const int mid = (lo + hi) >> 1;
-    if (sP[mid + 1] <= jb + (dl - 1 - mid)) lo = mid + 1;
+    if (sE[mid] <= dl - 1 - mid) lo = mid + 1;
     else hi = mid;
   }
   int a = lo, b = dl - lo;
   for (int step = dl; step < de; ++step) {
-    const bool takeA = (a < nat) && (b >= nbt || sP[a + 1] <= jb + b);
+    const bool takeA = (a < nat) && (b >= nbt || sE[a] <= b);
     if (takeA) {
       ++a;
     } else {
@@ -582,16 +662,7 @@ __global__ __launch_bounds__(kBlock) void k_write_expand(ColSet in, int k,
     }
   }
   __syncthreads();
-  for (int o = threadIdx.x; o < nbt; o += kBlock) {
-    const int r = sRow[o];
-    const int64_t j = jb + o;
-    const int32_t rank = (int32_t)(j - sP[r]);
-    const int32_t v = nbr[sStart[r] + rank];
-    const int64_t row = a0 + r;
-    const int64_t oj = j - J0;
-    for (int c = 0; c < k; ++c) __builtin_nontemporal_store(in.c[c][row], &out.c[c][oj]);
-    __builtin_nontemporal_store(v, &out.c[k][oj]);
-  }
+  write_outputs<K>(in, kdyn, nbr, sRow, sRb, a0, jb - J0, nbt, out);
 }
 
 __global__ void k_cartesian(ColSet a, int ka, ColSet b, int kb, int64_t nb, int64_t J0,
@@ -607,21 +678,24 @@ __global__ void k_cartesian(ColSet a, int ka, ColSet b, int kb, int64_t nb, int6
 
 constexpr int64_t kSampleRows = 16384;
 
-__global__ __launch_bounds__(kBlock) void k_sample_fanout(SampleSet ss, int64_t* __restrict__ sums) {
-  const int b = blockIdx.x;
+// Sum of row lengths over a strided sample of the bound column; blockIdx.y
+// selects the candidate, blockIdx.x one of kSampleBlocks slices of the sample.
+__global__ __launch_bounds__(kBlock) void k_sample_fanout(SampleSet ss, int64_t* __restrict__ part) {
+  const int cand = blockIdx.y;
   const int64_t n = ss.n;
   const int64_t S = n < kSampleRows ? n : kSampleRows;
   const int64_t stride = S > 0 ? n / S : 1;
-  const int32_t* col = ss.col[b];
-  const PredView pv = ss.pv[b];
+  const int32_t* col = ss.col[cand];
+  const PredView pv = ss.pv[cand];
   int64_t loc = 0;
-  for (int64_t j = threadIdx.x; j < S; j += kBlock) {
+  for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < S;
+       j += (int64_t)kSampleBlocks * kBlock) {
     int32_t st, len;
     row_lookup(pv, col[j * stride], st, len);
     loc += len;
   }
   const int64_t t = block_sum(loc);
-  if (threadIdx.x == 0) sums[b] = t;
+  if (threadIdx.x == 0) part[cand * kSampleBlocks + blockIdx.x] = t;
 }
 
 __global__ void k_pack_rows(ColSet cols, int k, int64_t row0, int64_t rows,
@@ -654,9 +728,11 @@ inline unsigned tiles_for(int64_t n) { return (unsigned)ceil_div(n > 0 ? n : 1, 
     if (_prof) prof_end(s, cls, bytes);         \
   } while (0)
 
-void launch_scan_tile_sums(int64_t* tile_sum, int64_t nt, int64_t* total, hipStream_t s) {
+void launch_scan_tile_sums(int64_t* tile_sum, int64_t nt, int64_t* total, hipStream_t s,
+                           int64_t* host_total) {
   GS_LAUNCH(GSMAT_K_SCAN, 16.0 * nt,
-            hipLaunchKernelGGL(k_scan_tile_sums, dim3(1), dim3(kBlock), 0, s, tile_sum, nt, total));
+            hipLaunchKernelGGL(k_scan_tile_sums, dim3(1), dim3(kBlock), 0, s, tile_sum, nt, total,
+                               host_total));
 }
 
 void launch_scan_add_i32(const int32_t* N, int64_t n, const int64_t* tile_off, int64_t* P,
@@ -703,7 +779,7 @@ void radix_sort_u64(uint64_t* keys, uint64_t* tmp, int64_t n, int nbits, DeviceM
               hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)nb), dim3(kBlock), 0, s, src, n, shift,
                                  hist, nb));
     launch_tile_reduce_u32(hist, hn, ts, s);
-    launch_scan_tile_sums(ts, ht, ts + ht, s);
+    launch_scan_tile_sums(ts, ht, ts + ht, s, nullptr);
     launch_scan_add_u32(hist, hn, ts, offs, s);
     GS_LAUNCH(GSMAT_K_OTHER, 16.0 * n,
               hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)nb), dim3(kBlock), 0, s, src, dst,
@@ -791,16 +867,16 @@ void launch_ptr_sentinels(const PredDesc* d, int32_t P, int32_t* ptr, hipStream_
                                s, d, P, ptr));
 }
 
-void launch_lookup(const LookupReq* req, int n, const PredDesc* desc_out, const PredDesc* desc_in,
+void launch_lookup(const LookupBatch& b, const PredDesc* desc_out, const PredDesc* desc_in,
                    const int32_t* keys_out, const int32_t* ptr_out, const int32_t* nbr_out,
                    const int32_t* dense_out, const int32_t* keys_in, const int32_t* ptr_in,
                    const int32_t* nbr_in, const int32_t* dense_in, LookupRes* res,
                    hipStream_t s) {
-  if (n <= 0) return;
-  GS_LAUNCH(GSMAT_K_OTHER, 32.0 * n,
-            hipLaunchKernelGGL(k_lookup, dim3((unsigned)ceil_div(n, 64)), dim3(64), 0, s, req, n,
-                               desc_out, desc_in, keys_out, ptr_out, nbr_out, dense_out, keys_in,
-                               ptr_in, nbr_in, dense_in, res));
+  if (b.n <= 0) return;
+  GS_LAUNCH(GSMAT_K_OTHER, 32.0 * b.n,
+            hipLaunchKernelGGL(k_lookup, dim3(1), dim3(64), 0, s, b, desc_out, desc_in, keys_out,
+                               ptr_out, nbr_out, dense_out, keys_in, ptr_in, nbr_in, dense_in,
+                               res));
 }
 
 void launch_count_expand(const int32_t* col, int64_t n, PredView pv, int32_t* N, int32_t* start,
@@ -833,9 +909,25 @@ void launch_flag_intersect(const int32_t* driver, int64_t n, ListSet ls, uint8_t
 
 void launch_compact_cols(ColSet in, int k, const uint8_t* flags, int64_t n,
                          const int64_t* tile_off, OutSet out, hipStream_t s) {
-  GS_LAUNCH(GSMAT_K_COMPACT, (1.0 + 4.0 * k) * n,
-            hipLaunchKernelGGL(k_compact_cols, dim3(tiles_for(n)), dim3(kBlock), 0, s, in, k, flags,
-                               n, tile_off, out));
+#define GS_COMPACT_CASE(KK)                                                                    \
+  case KK:                                                                                   \
+    hipLaunchKernelGGL(k_compact_cols<KK>, dim3(tiles_for(n)), dim3(kBlock), 0, s, in, k, flags, \
+                       n, tile_off, out);                                                    \
+    break;
+  GS_LAUNCH(GSMAT_K_COMPACT, (1.0 + 4.0 * k) * n, switch (k) {
+    GS_COMPACT_CASE(1)
+    GS_COMPACT_CASE(2)
+    GS_COMPACT_CASE(3)
+    GS_COMPACT_CASE(4)
+    GS_COMPACT_CASE(5)
+    GS_COMPACT_CASE(6)
+    GS_COMPACT_CASE(7)
+    GS_COMPACT_CASE(8)
+    default:
+      hipLaunchKernelGGL(k_compact_cols<-1>, dim3(tiles_for(n)), dim3(kBlock), 0, s, in, k, flags, n,
+                         tile_off, out);
+  });
+#undef GS_COMPACT_CASE
 }
 
 void launch_mp_partition(const int64_t* P, int64_t n, int64_t J0, int64_t J1, int64_t* split,
@@ -848,9 +940,29 @@ void launch_mp_partition(const int64_t* P, int64_t n, int64_t J0, int64_t J1, in
 void launch_write_expand(ColSet in, int k, const int64_t* P, const int32_t* start, int64_t n,
                          const int32_t* nbr, int64_t J0, int64_t J1, const int64_t* split,
                          int64_t ntiles, OutSet out, double alg_bytes, hipStream_t s) {
-  GS_LAUNCH(GSMAT_K_WRITE, alg_bytes,
-            hipLaunchKernelGGL(k_write_expand, dim3((unsigned)ntiles), dim3(kBlock), 0, s, in, k,
-                               P, start, n, nbr, J0, J1, split, out));
+#define GS_WRITE_CASE(KK)                                                                        \
+  case KK:                                                                                     \
+    hipLaunchKernelGGL(k_write_expand<KK>, dim3((unsigned)ntiles), dim3(kBlock), 0, s, in, k, P, \
+                       start, n, nbr, J0, J1, split, out);                                      \
+    break;
+  GS_LAUNCH(GSMAT_K_WRITE, alg_bytes, switch (k) {
+    GS_WRITE_CASE(0)
+    GS_WRITE_CASE(1)
+    GS_WRITE_CASE(2)
+    GS_WRITE_CASE(3)
+    GS_WRITE_CASE(4)
+    GS_WRITE_CASE(5)
+    GS_WRITE_CASE(6)
+    GS_WRITE_CASE(7)
+    GS_WRITE_CASE(8)
+    GS_WRITE_CASE(9)
+    GS_WRITE_CASE(10)
+    GS_WRITE_CASE(11)
+    default:
+      hipLaunchKernelGGL(k_write_expand<-1>, dim3((unsigned)ntiles), dim3(kBlock), 0, s, in, k, P,
+                         start, n, nbr, J0, J1, split, out);
+  });
+#undef GS_WRITE_CASE
 }
 
 void launch_cartesian(ColSet a, int ka, int64_t na, ColSet b, int kb, int64_t nb, int64_t J0,
@@ -861,10 +973,10 @@ void launch_cartesian(ColSet a, int ka, int64_t na, ColSet b, int kb, int64_t nb
                                kb, nb, J0, J1, out));
 }
 
-void launch_sample_fanout(const SampleSet& ss, int64_t* sums, hipStream_t s) {
+void launch_sample_fanout(const SampleSet& ss, int64_t* part, hipStream_t s) {
   GS_LAUNCH(GSMAT_K_OTHER, 0.0,
-            hipLaunchKernelGGL(k_sample_fanout, dim3((unsigned)ss.ncand), dim3(kBlock), 0, s, ss,
-                               sums));
+            hipLaunchKernelGGL(k_sample_fanout, dim3(kSampleBlocks, (unsigned)ss.ncand),
+                               dim3(kBlock), 0, s, ss, part));
 }
 
 void launch_pack_rows(ColSet cols, int k, int64_t row0, int64_t rows, int32_t* out,

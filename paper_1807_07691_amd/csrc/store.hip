@@ -102,7 +102,7 @@ void build_orientation(gsmat_store* st, const uint64_t* keys, int64_t U, Orienta
     Tmp<int64_t> ts(mem, nt + 1, s);
     if (U > 0) {
       launch_flag_row_heads(keys, U, st->vb, flags.p, ts.p, s);
-      launch_scan_tile_sums(ts.p, nt, ts.p + nt, s);
+      launch_scan_tile_sums(ts.p, nt, ts.p + nt, s, nullptr);
       R = read_i64(ts.p + nt, s);
       launch_compact_index(flags.p, U, ts.p, row_pos.p, s);
     }
@@ -182,7 +182,7 @@ int64_t sort_unique(gsmat_store* st, uint64_t* keys, int64_t n, uint64_t* tmp, h
   Tmp<uint8_t> flags(mem, n, s);
   Tmp<int64_t> ts(mem, nt + 1, s);
   launch_flag_unique(keys, n, flags.p, ts.p, s);
-  launch_scan_tile_sums(ts.p, nt, ts.p + nt, s);
+  launch_scan_tile_sums(ts.p, nt, ts.p + nt, s, nullptr);
   const int64_t U = read_i64(ts.p + nt, s);
   launch_compact_u64(keys, flags.p, n, ts.p, tmp, s);
   GS_HIP(hipMemcpyAsync(keys, tmp, sizeof(uint64_t) * (size_t)U, hipMemcpyDeviceToDevice, s));
