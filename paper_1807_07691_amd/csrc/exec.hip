@@ -141,11 +141,14 @@ struct Exec {
   }
 
   // Allocates a table of n rows for the given variables (columns in order).
+  // Columns start on 256-byte boundaries (stride rounded up to 64 values) so
+  // that a wave's 64 stores of one column cover whole cache lines.
   Table alloc_table(int64_t n, const int* vars, int k) {
     Table t;
     t.n = n;
     t.k = k;
-    const size_t bytes = sizeof(int32_t) * (size_t)std::max<int64_t>(n, 1) * (size_t)std::max(k, 1);
+    const int64_t stride = (std::max<int64_t>(n, 1) + 63) / 64 * 64;
+    const size_t bytes = sizeof(int32_t) * (size_t)stride * (size_t)std::max(k, 1);
     if (k > 0) {
       t.owned = mem()->alloc(bytes, s);
       if (!t.owned) throw OomFail{bytes};
@@ -154,7 +157,7 @@ struct Exec {
     }
     for (int c = 0; c < k; ++c) {
       t.var[c] = vars[c];
-      t.col[c] = (int32_t*)t.owned + (size_t)c * (size_t)n;
+      t.col[c] = (int32_t*)t.owned + (size_t)c * (size_t)stride;
     }
     return t;
   }

@@ -556,59 +556,60 @@ __global__ void k_mp_partition(const int64_t* __restrict__ P, int64_t n, int64_t
 // comparison the walk makes) and rb = start_i + (jb - P_i), so that output o of
 // row r reads nbr[rb[r] + o]; both fit int32.  Each thread walks kItems path
 // items to label outputs with their row; then the tile's outputs are written
-// column by column with unit stride.  The column loops are unrolled for a
-// compile-time column count K so that a thread's parent loads are all in
-// flight before its stores.
+// column by column with unit stride.
+//
+// The write loop is laid out for the memory system: output columns start on
+// 256-byte boundaries and the loop is shifted by the tile's offset modulo 64,
+// so every wave store covers whole 128-byte lines (unaligned tile starts
+// halved the store bandwidth); each thread handles two outputs per iteration
+// and issues all their loads (neighbour ids, K parent values) before any
+// store.  K is a compile-time column count (-1: any count, in groups of 4).
 template <int K>
 __device__ inline void write_outputs(const ColSet& in, int kdyn, const int32_t* __restrict__ nbr,
                                      const uint16_t* sRow, const int32_t* sRb, int64_t a0,
                                      int64_t ob, int nbt, OutSet& out) {
   const int k = K >= 0 ? K : kdyn;
-  int o = threadIdx.x;
-  // two outputs per iteration: their loads overlap
-  for (; o + kBlock < nbt; o += 2 * kBlock) {
-    const int o2 = o + kBlock;
-    const int r1 = sRow[o], r2 = sRow[o2];
-    const int32_t v1 = nbr[sRb[r1] + o], v2 = nbr[sRb[r2] + o2];
+  const int al = (int)(ob & 63);
+  const int span = nbt + al;
+  for (int q = threadIdx.x; q < span; q += 2 * kBlock) {
+    const int o1 = q - al, o2 = q + kBlock - al;
+    const bool ok1 = o1 >= 0 && o1 < nbt, ok2 = o2 >= 0 && o2 < nbt;
+    const int r1 = ok1 ? sRow[o1] : 0, r2 = ok2 ? sRow[o2] : 0;
+    const int32_t v1 = ok1 ? nbr[sRb[r1] + o1] : 0;
+    const int32_t v2 = ok2 ? nbr[sRb[r2] + o2] : 0;
     const int64_t row1 = a0 + r1, row2 = a0 + r2;
     if (K >= 0) {
       int32_t x1[K > 0 ? K : 1], x2[K > 0 ? K : 1];
 #pragma unroll
       for (int c = 0; c < K; ++c) {
-        x1[c] = in.c[c][row1];
-        x2[c] = in.c[c][row2];
+        x1[c] = ok1 ? in.c[c][row1] : 0;
+        x2[c] = ok2 ? in.c[c][row2] : 0;
       }
+      if (ok1) {
 #pragma unroll
-      for (int c = 0; c < K; ++c) {
-        __builtin_nontemporal_store(x1[c], &out.c[c][ob + o]);
-        __builtin_nontemporal_store(x2[c], &out.c[c][ob + o2]);
+        for (int c = 0; c < K; ++c) __builtin_nontemporal_store(x1[c], &out.c[c][ob + o1]);
+      }
+      if (ok2) {
+#pragma unroll
+        for (int c = 0; c < K; ++c) __builtin_nontemporal_store(x2[c], &out.c[c][ob + o2]);
       }
     } else {
       for (int c0 = 0; c0 < k; c0 += 4) {
         int32_t x1[4], x2[4];
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
-          if (c0 + c < k) {
-            x1[c] = in.c[c0 + c][row1];
-            x2[c] = in.c[c0 + c][row2];
-          }
+        for (int c = 0; c < 4; ++c) {
+          x1[c] = (ok1 && c0 + c < k) ? in.c[c0 + c][row1] : 0;
+          x2[c] = (ok2 && c0 + c < k) ? in.c[c0 + c][row2] : 0;
+        }
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
-          if (c0 + c < k) {
-            __builtin_nontemporal_store(x1[c], &out.c[c0 + c][ob + o]);
-            __builtin_nontemporal_store(x2[c], &out.c[c0 + c][ob + o2]);
-          }
+        for (int c = 0; c < 4; ++c) {
+          if (ok1 && c0 + c < k) __builtin_nontemporal_store(x1[c], &out.c[c0 + c][ob + o1]);
+          if (ok2 && c0 + c < k) __builtin_nontemporal_store(x2[c], &out.c[c0 + c][ob + o2]);
+        }
       }
     }
-    __builtin_nontemporal_store(v1, &out.c[k][ob + o]);
-    __builtin_nontemporal_store(v2, &out.c[k][ob + o2]);
-  }
-  if (o < nbt) {
-    const int r = sRow[o];
-    const int32_t v = nbr[sRb[r] + o];
-    const int64_t row = a0 + r;
-    for (int c = 0; c < k; ++c) __builtin_nontemporal_store(in.c[c][row], &out.c[c][ob + o]);
-    __builtin_nontemporal_store(v, &out.c[k][ob + o]);
+    if (ok1) __builtin_nontemporal_store(v1, &out.c[k][ob + o1]);
+    if (ok2) __builtin_nontemporal_store(v2, &out.c[k][ob + o2]);
   }
 }
 
