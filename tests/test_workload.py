@@ -78,3 +78,29 @@ def test_tree_count_small_brute_force():
                     ([[-1, 1, 3], [-1, 0, -2]], 2), ([[-1, 0, -2], [-3, 1, -4]], 4)]:
         assert gi.count(np.array(tps), nv) == len(O.brute_force(s, p, o, tps, nv, V))
     assert gi.count(np.array([[-1, 0, -2], [-2, 1, -1]]), 2) == -1  # cycle: not a tree
+
+
+def test_tree_count_push_and_pull_paths_match_oracle():
+    """Random tree BGPs with constant leaves (small child supports take the
+    generator's push path, free leaves the pull path) against the oracle."""
+    import oracle as O
+    spec, qs = W.CONFIGS["tiny"]
+    s, p, o = W.gen_graph(spec)
+    gi = W.GraphIndex(s, p, o, spec.V, spec.P)
+    seed = 12345
+    checked = 0
+    for ctr in range(1, 400):
+        kind = ctr % 4
+        n = 2 + ctr % 3 if kind != W.KIND_SNOW else 4
+        w = gi.walk(kind, n, ctr % 3, -1, seed, ctr, W.SHAPE_BIAS[kind])
+        if w is None:
+            continue
+        tp, wit, nv = w
+        c = gi.count(tp, nv)
+        if c > 200_000:
+            continue
+        assert c == len(O.join(s, p, o, tp, nv)), tp.tolist()
+        checked += 1
+        if checked >= 40:
+            break
+    assert checked >= 30

@@ -26,6 +26,7 @@ import os
 import subprocess
 from dataclasses import dataclass, field
 
+import math
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -63,6 +64,8 @@ def lib():
         L.wl_index_free.argtypes = [vp]
         L.wl_count_tree.restype = i64
         L.wl_count_tree.argtypes = [vp, vp, i32, i32]
+        L.wl_count_many.restype = None
+        L.wl_count_many.argtypes = [vp, vp, vp, vp, vp, i32, vp]
         L.wl_walk_query.restype = i32
         L.wl_walk_query.argtypes = [vp, i32, i32, i32, i32, dbl, u64, u64, vp, vp]
         L.wl_out_degree.restype = i64
@@ -170,6 +173,20 @@ class GraphIndex:
         t = np.ascontiguousarray(tps, np.int32).reshape(-1, 3)
         return int(lib().wl_count_tree(self.h, _ptr(t), len(t), n_vars))
 
+    def count_many(self, queries):
+        """Exact counts of several (tps, n_vars) queries, computed concurrently."""
+        if not queries:
+            return []
+        tps = np.ascontiguousarray(np.concatenate([np.asarray(t, np.int32).reshape(-1, 3)
+                                                   for t, _ in queries]), np.int32)
+        ntp = np.array([len(np.asarray(t).reshape(-1, 3)) for t, _ in queries], np.int32)
+        nv = np.array([v for _, v in queries], np.int32)
+        off = np.concatenate([[0], np.cumsum(ntp)[:-1]]).astype(np.int64)
+        out = np.empty(len(queries), np.int64)
+        lib().wl_count_many(self.h, _ptr(tps), _ptr(ntp), _ptr(nv), _ptr(off), len(queries),
+                            _ptr(out))
+        return out.tolist()
+
     def degree_le_fraction(self, d: int) -> float:
         return lib().wl_count_degree_le(self.h, d) / self.V
 
@@ -270,6 +287,84 @@ def gen_queries(gi: GraphIndex, spec: GraphSpec, qs: QuerySpec, escalate_every=4
             raise RuntimeError(f"could not draw query {qi} kind={kind} n={n}")
         out.append(got)
     return out
+
+
+# Batched workload: the large graph with many small-to-medium BGPs whose result
+# sizes spread log-uniformly over [1, 1e6] (one decade per query slot, cycling).
+BATCH = QuerySpec(4096, 1, 6, 10**6, seed_offset=7)
+
+
+def gen_batch_queries(gi: GraphIndex, spec: GraphSpec, qs: QuerySpec = BATCH, n_queries=None,
+                      round_size=512, max_rounds=200):
+    """n_queries BGPs whose exact counts fill the six decades [10^d, 10^(d+1))
+    of [1, count_cap] equally (the last decade includes count_cap), in a
+    seeded order.  Candidates are drawn in rounds of `round_size`; each is
+    steered at the open decade with the most places left (more bound leaves
+    for smaller decades), counted exactly, and accepted in candidate order if
+    its decade still has room.  The outcome depends only on the seed."""
+    seed = (spec.seed + qs.seed_offset) & (2**64 - 1)
+    nq = qs.n_queries if n_queries is None else n_queries
+    kinds = [KIND_CHAIN, KIND_SSTAR, KIND_OSTAR, KIND_SNOW]
+    cum = np.cumsum([25, 30, 30, 15])
+    room = [nq // 6 + (1 if d < nq % 6 else 0) for d in range(6)]
+    bins = [[] for _ in range(6)]
+    steer = [0] * 6          # per decade: +1 after a candidate above it, -1 below
+
+    def decade(c):
+        return 5 if c >= 10**5 else int(math.floor(math.log10(c)))
+
+    def candidate(j, d):
+        ctr = j + 1
+        r = _rng_u64(seed, 3 * ctr)
+        kind = kinds[int(np.searchsorted(cum, int(r % int(cum[-1])), side="right"))]
+        r2 = _rng_u64(seed, 3 * ctr + 1)
+        n = int((4 + r2 % 3) if kind == KIND_SNOW else (1 + r2 % 6))
+        if n == 1:
+            kind = KIND_CHAIN
+        # bound leaves: many for the small decades, none for the largest,
+        # moved by that decade's previous misses, plus a jitter of -1..1
+        cmax = min(n, 3) if n > 1 else 1
+        jit = int(_rng_u64(seed, 3 * ctr + 2) % 3) - 1
+        cm = min(cmax, max(0, round(cmax * (5 - d) / 5) + steer[d] + jit))
+        w = gi.walk(kind, n, cm, -1, seed, ctr, SHAPE_BIAS[kind])
+        if w is None or w[2] < 1:
+            return None
+        return kind, cm, w
+
+    j = 0
+    for _ in range(max_rounds):
+        if not any(room):
+            break
+        # target decades for this round, in proportion to the places left
+        left = sum(room)
+        plan = []
+        for d in range(6):
+            plan += [d] * max(1 if room[d] else 0, round(round_size * room[d] / left))
+        pend = []
+        for d in plan:
+            c = candidate(j, d)
+            j += 1
+            if c is not None:
+                pend.append((d, c))
+        counts = gi.count_many([(c[2][0], c[2][2]) for _, c in pend])
+        for (d, (kind, cm, (tp, wit, nv))), cnt in zip(pend, counts):
+            if cnt < 1:
+                continue
+            if cnt > qs.count_cap:
+                steer[d] = min(3, steer[d] + 1)
+                continue
+            e = decade(cnt)
+            if e != d:
+                steer[d] = max(-3, min(3, steer[d] + (1 if e > d else -1)))
+            if room[e]:
+                bins[e].append(Query(tp, nv, wit, int(cnt), kind, cm))
+                room[e] -= 1
+    if any(room):
+        raise RuntimeError("could not draw the batch workload")
+    # interleave the decades in a seeded order
+    out = [q for b in bins for q in b]
+    perm = np.argsort([_rng_u64(seed ^ 0x5bd1e995, i) for i in range(len(out))], kind="stable")
+    return [out[i] for i in perm]
 
 
 def make_workload(name: str):

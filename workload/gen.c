@@ -543,6 +543,11 @@ static inline uint64_t smul(uint64_t a, uint64_t b) {
   return c > SAT ? SAT : (uint64_t)c;
 }
 
+int cmp32(const void *a, const void *b) {
+  int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+  return (x > y) - (x < y);
+}
+
 static int64_t find_row(const int32_t *rows, int64_t lo, int64_t hi, int32_t v) {
   while (lo < hi) { int64_t m = (lo + hi) / 2; if (rows[m] < v) lo = m + 1; else hi = m; }
   return lo;
@@ -575,6 +580,37 @@ static sparsef msg_of(wl_index *ix, int32_t p, int x_is_subject, int other_is_co
     return m;
   }
   int64_t r0 = pred_row[p], r1 = pred_row[p + 1];
+  if (!child->one && child->n * 8 < r1 - r0) {
+    /* push: the child's support is small, so sum its values into the
+     * neighbours on x's side through the other view (sparse accumulation) */
+    int64_t *pr2 = x_is_subject ? ix->po_pred_row : ix->ps_pred_row;
+    int32_t *rw2 = x_is_subject ? ix->po_row : ix->ps_row;
+    int64_t *of2 = x_is_subject ? ix->po_off : ix->ps_off;
+    int32_t *nb2 = x_is_subject ? ix->po_nbr : ix->ps_nbr;
+    int64_t cap = 1024, cnt = 0;
+    int32_t *touched = (int32_t *)malloc(sizeof(int32_t) * cap);
+    for (int64_t i = 0; i < child->n; ++i) {
+      int32_t u = child->id[i];
+      int64_t r = find_row(rw2, pr2[p], pr2[p + 1], u);
+      if (r >= pr2[p + 1] || rw2[r] != u) continue;
+      for (int64_t e = of2[r]; e < of2[r + 1]; ++e) {
+        int32_t v = nb2[e];
+        if (scratch[v] == 0) {
+          if (cnt == cap) { cap *= 2; touched = (int32_t *)realloc(touched, sizeof(int32_t) * cap); }
+          touched[cnt++] = v;
+        }
+        scratch[v] = sadd(scratch[v], child->val[i]);
+      }
+    }
+    /* sort touched ids (radix over 32 bits would do; small lists: insertion via qsort) */
+    qsort(touched, (size_t)cnt, sizeof(int32_t), cmp32);
+    m.n = cnt;
+    m.id = (int32_t *)malloc(sizeof(int32_t) * (cnt > 0 ? cnt : 1));
+    m.val = (uint64_t *)malloc(sizeof(uint64_t) * (cnt > 0 ? cnt : 1));
+    for (int64_t i = 0; i < cnt; ++i) { m.id[i] = touched[i]; m.val[i] = scratch[touched[i]]; scratch[touched[i]] = 0; }
+    free(touched);
+    return m;
+  }
   m.n = r1 - r0;
   m.id = (int32_t *)malloc(sizeof(int32_t) * (m.n > 0 ? m.n : 1));
   m.val = (uint64_t *)malloc(sizeof(uint64_t) * (m.n > 0 ? m.n : 1));
@@ -645,8 +681,59 @@ static sparsef eval_var(wl_index *ix, const wl_tp *tps, int ntp, int32_t x, int 
   return f;
 }
 
+static int64_t count_tree_impl(wl_index *ix, const int32_t *tp3, int32_t ntp, int32_t nvars,
+                               uint64_t *scratch);
+
 int64_t wl_count_tree(void *h, const int32_t *tp3, int32_t ntp, int32_t nvars) {
   wl_index *ix = (wl_index *)h;
+  return count_tree_impl(ix, tp3, ntp, nvars, ix->scratch);
+}
+
+/* Counts nq queries concurrently (one thread per query, private scratch;
+ * the per-query loops then run single-threaded).  Query q has ntp[q]
+ * patterns starting at tp3 + 3 * off[q]. */
+void wl_count_many(void *h, const int32_t *tp3, const int32_t *ntp, const int32_t *nvars,
+                   const int64_t *off, int32_t nq, int64_t *out) {
+  wl_index *ix = (wl_index *)h;
+  int nt = omp_get_max_threads();
+  uint64_t **scr = (uint64_t **)calloc(nt, sizeof(uint64_t *));
+  /* longest first (cost ~ the predicates' sizes), so no long count is left
+   * for the end of the loop */
+  int64_t *key = (int64_t *)malloc(sizeof(int64_t) * (nq > 0 ? nq : 1));
+  int32_t *ord = (int32_t *)malloc(sizeof(int32_t) * (nq > 0 ? nq : 1));
+  for (int32_t q = 0; q < nq; ++q) {
+    int64_t c = 0;
+    for (int32_t t = 0; t < ntp[q]; ++t) {
+      int32_t p = tp3[3 * (off[q] + t) + 1];
+      if (p >= 0 && p < ix->P) c += ix->ps_off[ix->ps_pred_row[p + 1]] - ix->ps_off[ix->ps_pred_row[p]];
+    }
+    key[q] = c;
+    ord[q] = q;
+  }
+  for (int32_t i = 1; i < nq; ++i) {  /* insertion sort by descending cost */
+    int32_t v = ord[i]; int32_t k = i;
+    while (k > 0 && key[ord[k - 1]] < key[v]) { ord[k] = ord[k - 1]; --k; }
+    ord[k] = v;
+  }
+  int lev = omp_get_max_active_levels();
+  omp_set_max_active_levels(1);
+#pragma omp parallel num_threads(nt)
+  {
+    int t = omp_get_thread_num();
+#pragma omp for schedule(dynamic, 1)
+    for (int32_t i = 0; i < nq; ++i) {
+      int32_t q = ord[i];
+      if (!scr[t]) scr[t] = (uint64_t *)calloc(ix->V, sizeof(uint64_t));
+      out[q] = count_tree_impl(ix, tp3 + 3 * off[q], ntp[q], nvars[q], scr[t]);
+    }
+  }
+  omp_set_max_active_levels(lev);
+  for (int t = 0; t < nt; ++t) free(scr[t]);
+  free(scr); free(key); free(ord);
+}
+
+static int64_t count_tree_impl(wl_index *ix, const int32_t *tp3, int32_t ntp, int32_t nvars,
+                               uint64_t *scratch) {
   const wl_tp *tps = (const wl_tp *)tp3;
   /* validate forest: union-find over variables */
   int32_t *par = (int32_t *)malloc(sizeof(int32_t) * (nvars > 0 ? nvars : 1));
@@ -665,7 +752,6 @@ int64_t wl_count_tree(void *h, const int32_t *tp3, int32_t ntp, int32_t nvars) {
     }
   }
   if (!ok) { free(par); return -1; }
-  uint64_t *scratch = ix->scratch;
   /* all-constant patterns: membership */
   for (int t = 0; t < ntp; ++t) {
     if (tps[t].s >= 0 && tps[t].o >= 0) {
