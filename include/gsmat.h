@@ -173,6 +173,18 @@ gsmat_status gsmat_plan_info(const gsmat_query_plan* pl, int32_t* n_steps, int32
 
 void gsmat_plan_free(gsmat_query_plan* pl);
 
+/* Plans n_queries BGPs at once: query i has the n_pats[i] patterns that
+ * follow those of queries 0..i-1 in pats.  Same plans as gsmat_plan per
+ * query; the device lookups of every query's constants go out as one batch
+ * (one stream synchronisation for the whole call).  out[i] receives query
+ * i's plan, or NULL when its patterns are rejected; status[i] (may be NULL)
+ * its status.  Returns OK when every query was planned, else the status of
+ * the first failed query (the other plans are still returned and must be
+ * freed). */
+gsmat_status gsmat_plan_batch(const gsmat_store* st, const gsmat_pattern* pats,
+                              const int32_t* n_pats, int32_t n_queries, int32_t mode,
+                              void* stream, gsmat_query_plan** out, gsmat_status* status);
+
 /* ---- execution (Sec. 6.3, Sec. 7.2) --------------------------------------- */
 
 /* Evaluates the plan on the device.  budget_bytes bounds each step's output
@@ -183,6 +195,22 @@ void gsmat_plan_free(gsmat_query_plan* pl);
  * allocation fails or the budget cannot hold a single output row. */
 gsmat_status gsmat_join(gsmat_store* st, const gsmat_query_plan* pl, int64_t budget_bytes,
                         int64_t max_rows, void* stream, gsmat_result** out);
+
+/* Evaluates n_plans plans together (Sec. 7.2's count, prefix sum, exact
+ * allocation and write, run as one launch per phase for every query in the
+ * batch).  Each query takes the same steps as under gsmat_join and yields
+ * the same rows in the same order.  A query whose next step would need a
+ * Cartesian product, a (?x p ?x) pattern, or a step output above
+ * budget_bytes (or the batch's outputs of one step above budget_bytes in
+ * total) is finished alone, as gsmat_join would.  budget_bytes and
+ * max_rows apply per query as in gsmat_join.  out[i] receives query i's
+ * result, or NULL if it failed; status[i] (may be NULL) its status.  Returns
+ * OK when every query succeeded, else the status of the first failed query
+ * (the other results are still returned and must be freed); a failure of
+ * the batch itself (HIP error, device allocation) returns no results. */
+gsmat_status gsmat_join_batch(gsmat_store* st, const gsmat_query_plan* const* plans,
+                              int32_t n_plans, int64_t budget_bytes, int64_t max_rows,
+                              void* stream, gsmat_result** out, gsmat_status* status);
 
 /* Result shape; per-step rows in/out (arrays of n_steps entries, may be NULL)
  * are summed over chunks. */

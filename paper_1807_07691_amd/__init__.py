@@ -34,7 +34,8 @@ EXPORTED = [
     "gsmat_export_matrix", "gsmat_store_free", "gsmat_plan", "gsmat_plan_from_stats",
     "gsmat_plan_info", "gsmat_plan_free", "gsmat_join", "gsmat_result_info",
     "gsmat_fetch_bindings", "gsmat_result_free", "gsmat_last_error", "gsmat_prof_enable",
-    "gsmat_prof_read", "gsmat_prof_host", "gsmat_release_pools",
+    "gsmat_prof_read", "gsmat_prof_host", "gsmat_release_pools", "gsmat_plan_batch",
+    "gsmat_join_batch",
 ]
 
 
@@ -107,6 +108,10 @@ def _load():
     L.gsmat_prof_host.argtypes = [vp]
     L.gsmat_release_pools.restype = i32
     L.gsmat_release_pools.argtypes = []
+    L.gsmat_plan_batch.restype = i32
+    L.gsmat_plan_batch.argtypes = [vp, vp, vp, i32, i32, vp, vp, vp]
+    L.gsmat_join_batch.restype = i32
+    L.gsmat_join_batch.argtypes = [vp, vp, i32, i64, i64, vp, vp, vp]
     return L
 
 
@@ -310,6 +315,49 @@ def gsmat_join(store, plan, budget_bytes=0, max_rows=-1, stream=None):
     return Result(h, store)
 
 
+def gsmat_plan_batch(store, queries, mode=PLAN_DEFAULT, stream=None, raise_on_error=True):
+    """Plans of several BGPs (a list of (n, 3) pattern arrays) with one device
+    round trip.  Returns (plans, statuses); a rejected query's plan is None.
+    With raise_on_error, the first failure raises after freeing the rest."""
+    nq = len(queries)
+    ts = [np.asarray(t, dtype=np.int32).reshape(-1, 3) for t in queries]
+    n_pats = np.array([len(t) for t in ts], np.int32)
+    flat = np.ascontiguousarray(np.concatenate(ts) if nq else np.zeros((0, 3), np.int32))
+    hs = (ctypes.c_void_p * max(nq, 1))()
+    st = np.zeros(max(nq, 1), np.int32)
+    rc = _lib.gsmat_plan_batch(store.h, _p(flat), _p(n_pats), nq, mode, _stream(stream), hs,
+                               _p(st))
+    msg = _lib.gsmat_last_error().decode(errors="replace") if rc != GSMAT_OK else ""
+    plans = [Plan(ctypes.c_void_p(hs[i])) if hs[i] else None for i in range(nq)]
+    if rc != GSMAT_OK and raise_on_error:
+        for pl in plans:
+            if pl is not None:
+                pl.close()
+        raise GsmatError(rc, msg)
+    return plans, [int(x) for x in st[:nq]]
+
+
+def gsmat_join_batch(store, plans, budget_bytes=0, max_rows=-1, stream=None,
+                     raise_on_error=True):
+    """Evaluates several plans together.  Returns (results, statuses); a failed
+    query's result is None.  With raise_on_error, the first failure raises
+    after freeing the rest."""
+    nq = len(plans)
+    ph = (ctypes.c_void_p * max(nq, 1))(*[pl.h for pl in plans])
+    hs = (ctypes.c_void_p * max(nq, 1))()
+    st = np.zeros(max(nq, 1), np.int32)
+    rc = _lib.gsmat_join_batch(store.h, ph, nq, budget_bytes, max_rows, _stream(stream), hs,
+                               _p(st))
+    msg = _lib.gsmat_last_error().decode(errors="replace") if rc != GSMAT_OK else ""
+    results = [Result(ctypes.c_void_p(hs[i]), store) if hs[i] else None for i in range(nq)]
+    if rc != GSMAT_OK and raise_on_error:
+        for r in results:
+            if r is not None:
+                r.close()
+        raise GsmatError(rc, msg)
+    return results, [int(x) for x in st[:nq]]
+
+
 def gsmat_result_info(result):
     rows, nv, ns = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
     _check(_lib.gsmat_result_info(result.h, ctypes.byref(rows), ctypes.byref(nv),
@@ -358,6 +406,22 @@ def gsmat_prof_host():
     _check(_lib.gsmat_prof_host(_p(out)))
     return {"alloc_ms": float(out[0]), "allocs": int(out[1]), "free_ms": float(out[2]),
             "sync_ms": float(out[3]), "syncs": int(out[4])}
+
+
+def evaluate_batch(store, queries, mode=PLAN_ADAPTIVE, budget_bytes=0, max_rows=-1,
+                   stream=None):
+    """Batched plan + join + fetch: one (rows, n_vars) int32 array per BGP."""
+    plans, _ = gsmat_plan_batch(store, queries, mode, stream)
+    try:
+        results, _ = gsmat_join_batch(store, plans, budget_bytes, max_rows, stream)
+        try:
+            return [gsmat_fetch_bindings(r, stream=stream) for r in results]
+        finally:
+            for r in results:
+                r.close()
+    finally:
+        for pl in plans:
+            pl.close()
 
 
 def evaluate(store, tps, mode=PLAN_ADAPTIVE, budget_bytes=0, max_rows=-1, stream=None):

@@ -1,0 +1,1046 @@
+// Batched join: many BGP plans evaluated together, one step of every query
+// per round (paper Sec. 7.2 evaluates one plan step as count, prefix sum,
+// exact allocation and write; here each of those phases is one launch for the
+// whole batch).
+//
+// A round takes the next step of every unfinished query: expansions, filters
+// and star-centre intersections become tasks of one count/flag launch whose
+// tiles are the concatenation of every task's tiles; one scan of all tile
+// sums and one per-task reduction give every task's output size, read back
+// with a single stream synchronisation.  The host then allocates one arena
+// for all outputs of the round and issues one prefix-sum launch, one
+// merge-path partition launch, and one write (expansions) or compaction
+// (filters, intersections) launch per column count.  Steps needing no kernel
+// (pattern scans, which are views into the store) are applied on the host.
+// The adaptive step choice samples every query's candidate expansions in one
+// launch per round.  A query whose next step would be a Cartesian product, a
+// (?x p ?x) scan, or an output above the byte budget leaves the batch and is
+// run on its own by the single-query executor, which handles those cases.
+//
+// Each query takes exactly the steps it takes alone (same plan, same choice
+// rule on the same tables), so its result rows come out in the same order.
+#include <algorithm>
+#include <cstring>
+#include <memory>
+
+#include "device.hpp"
+#include "exec.hpp"
+
+using namespace gsmat;
+
+namespace {
+
+using namespace gsmat::dev;
+
+enum : int32_t { kTaskExpand = 0, kTaskFilter = 1, kTaskIntersect = 2 };
+
+// Count-phase task: one step of one query.
+struct CTask {
+  int64_t n;           // input rows (intersection: driver list length)
+  int32_t kind;
+  int32_t l0, nl;      // intersection: lists[l0, l0 + nl)
+  int32_t pad;
+  PredView pv;         // expansion: view of the bound orientation; filter: by subject
+  ProbeArgs pa;        // filter
+  const int32_t* col;  // expansion: bound column; intersection: driver list
+  int32_t* N;          // expansion: output count per row
+  int32_t* start;      // expansion: row offset per row
+  uint8_t* flags;      // filter, intersection: keep flags
+};
+
+// Write-phase task.
+struct WTask {
+  int64_t n, m;        // input rows, output rows
+  int64_t t0;          // first tile of the task in the count launch
+  ColSet in;           // input columns
+  int32_t* out0;       // output column c at out0 + c * ostride
+  int64_t ostride;
+  int32_t k;           // input columns
+  int32_t pad;
+  const int32_t* nbr;  // expansion: members of the predicate view
+  const int32_t* N;
+  const int32_t* start;
+  int64_t* P;          // expansion: row offsets (n + 1)
+  int64_t* split;      // expansion: merge-path splits (path tiles + 1)
+  const uint8_t* flags;
+};
+
+// One task inside a launch: its tiles start at w0 of the launch's tiles.
+struct GItem {
+  int64_t w0;
+  int32_t task;
+  int32_t pad;
+};
+
+// Candidate expansion whose fan-out is sampled.
+struct SCand {
+  const int32_t* col;
+  PredView pv;
+  int64_t n;
+};
+
+// Index of the item owning tile b: the last item with w0 <= b.
+__device__ inline int find_item(const GItem* __restrict__ g, int n, int64_t b) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (g[mid].w0 <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ void k_lookup_many(const LookupReq* __restrict__ req, int32_t n, const PredDesc* dout,
+                              const PredDesc* din, const int32_t* keys_out, const int32_t* ptr_out,
+                              const int32_t* nbr_out, const int32_t* dense_out,
+                              const int32_t* keys_in, const int32_t* ptr_in, const int32_t* nbr_in,
+                              const int32_t* dense_in, LookupRes* res) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  res[i] = lookup_one(req[i], dout, din, keys_out, ptr_out, nbr_out, dense_out, keys_in, ptr_in,
+                      nbr_in, dense_in);
+}
+
+__global__ __launch_bounds__(kBlock) void k_b_sample(const SCand* __restrict__ c,
+                                                     int64_t* __restrict__ part) {
+  const int cand = blockIdx.x / kSampleBlocks;
+  const int slice = blockIdx.x % kSampleBlocks;
+  const SCand& sc = c[cand];
+  const int64_t t = sample_fanout_slice(slice, sc.col, sc.n, sc.pv);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// Count / flag tiles of every task; tile sums to ts.
+__global__ __launch_bounds__(kBlock) void k_b_count(const CTask* __restrict__ tasks,
+                                                    const GItem* __restrict__ items, int nitems,
+                                                    const ListRef* __restrict__ lists,
+                                                    int64_t* __restrict__ ts) {
+  const GItem& it = items[find_item(items, nitems, blockIdx.x)];
+  const CTask& T = tasks[it.task];
+  const int64_t tile = (int64_t)blockIdx.x - it.w0;
+  int64_t sum;
+  if (T.kind == kTaskExpand) {
+    const PredView pv = T.pv;
+    sum = count_expand_tile(tile, T.col, T.n, pv, T.N, T.start);
+  } else if (T.kind == kTaskFilter) {
+    const PredView pv = T.pv;
+    const ProbeArgs pa = T.pa;
+    sum = flag_filter_tile(tile, pa, T.n, pv, T.flags);
+  } else {
+    sum = flag_intersect_tile(tile, T.col, T.n, lists + T.l0, T.nl, T.flags);
+  }
+  if (threadIdx.x == 0) ts[blockIdx.x] = sum;
+}
+
+// Output size of every task from the scanned tile sums (exclusive, with the
+// grand total at ts[ntiles]); written to pinned host memory.
+__global__ void k_b_totals(const GItem* __restrict__ items, int nitems, const int64_t* ts,
+                           int64_t ntiles, int64_t* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nitems) return;
+  const int64_t a = items[i].w0;
+  const int64_t b = i + 1 < nitems ? items[i + 1].w0 : ntiles;
+  out[items[i].task] = ts[b] - ts[a];
+}
+
+// Expansion row offsets P (relative to the task) from the tile offsets.
+__global__ __launch_bounds__(kBlock) void k_b_scan_add(const WTask* __restrict__ tasks,
+                                                       const GItem* __restrict__ items,
+                                                       int nitems, const int64_t* __restrict__ ts) {
+  const GItem& it = items[find_item(items, nitems, blockIdx.x)];
+  const WTask& T = tasks[it.task];
+  const int64_t tile = (int64_t)blockIdx.x - it.w0;
+  const int64_t base = ts[T.t0 + tile] - ts[T.t0];
+  const int64_t tot = scan_add_tile<int32_t, int64_t>(tile, T.N, T.n, base, T.P);
+  if (threadIdx.x == 0 && (tile + 1) * kTile >= T.n) T.P[T.n] = base + tot;
+}
+
+// Merge-path splits of every expansion: one thread per split entry.
+__global__ void k_b_partition(const WTask* __restrict__ tasks, const GItem* __restrict__ items,
+                              int nitems, int64_t total) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= total) return;
+  const GItem& it = items[find_item(items, nitems, g)];
+  const WTask& T = tasks[it.task];
+  const int64_t t = g - it.w0;
+  T.split[t] = mp_split(T.P, T.n, 0, T.m, t);
+}
+
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_b_write(const WTask* __restrict__ tasks,
+                                                    const GItem* __restrict__ items, int nitems) {
+  const GItem& it = items[find_item(items, nitems, blockIdx.x)];
+  const WTask& T = tasks[it.task];
+  const int64_t t = (int64_t)blockIdx.x - it.w0;
+  const OutStrided out{T.out0, T.ostride};
+  if constexpr (K >= 0) {
+    ColSet in;
+#pragma unroll
+    for (int c = 0; c < K; ++c) in.c[c] = T.in.c[c];
+    write_expand_tile<K>(t, in, K, T.P, T.start, T.n, T.nbr, 0, T.m, T.split, out);
+  } else {
+    write_expand_tile<K>(t, T.in, T.k, T.P, T.start, T.n, T.nbr, 0, T.m, T.split, out);
+  }
+}
+
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_b_compact(const WTask* __restrict__ tasks,
+                                                      const GItem* __restrict__ items, int nitems,
+                                                      const int64_t* __restrict__ ts) {
+  const GItem& it = items[find_item(items, nitems, blockIdx.x)];
+  const WTask& T = tasks[it.task];
+  const int64_t tile = (int64_t)blockIdx.x - it.w0;
+  const int64_t base = ts[T.t0 + tile] - ts[T.t0];
+  const OutStrided out{T.out0, T.ostride};
+  if constexpr (K >= 0) {
+    ColSet in;
+#pragma unroll
+    for (int c = 0; c < K; ++c) in.c[c] = T.in.c[c];
+    compact_cols_tile<K>(tile, in, K, T.flags, T.n, base, out);
+  } else {
+    compact_cols_tile<K>(tile, T.in, T.k, T.flags, T.n, base, out);
+  }
+}
+
+#define GS_BLAUNCH(cls, bytes, ...)             \
+  do {                                          \
+    const bool _prof = prof_on(cls);            \
+    if (_prof) prof_begin(s, cls);              \
+    __VA_ARGS__;                                \
+    GS_HIP(hipGetLastError());                  \
+    if (_prof) prof_end(s, cls, bytes);         \
+  } while (0)
+
+template <int K>
+void launch_b_write(const WTask* t, const GItem* g, int ng, int64_t tiles, double bytes,
+                    hipStream_t s) {
+  GS_BLAUNCH(GSMAT_K_WRITE, bytes,
+             hipLaunchKernelGGL(k_b_write<K>, dim3((unsigned)tiles), dim3(kBlock), 0, s, t, g,
+                                ng));
+}
+template <int K>
+void launch_b_compact(const WTask* t, const GItem* g, int ng, const int64_t* ts, int64_t tiles,
+                      double bytes, hipStream_t s) {
+  GS_BLAUNCH(GSMAT_K_COMPACT, bytes,
+             hipLaunchKernelGGL(k_b_compact<K>, dim3((unsigned)tiles), dim3(kBlock), 0, s, t, g,
+                                ng, ts));
+}
+
+// Column counts with their own write / compaction instantiation.
+constexpr int kMaxK = 11;
+
+void b_write(int k, const WTask* t, const GItem* g, int ng, int64_t tiles, double bytes,
+             hipStream_t s) {
+  switch (k) {
+    case 0: return launch_b_write<0>(t, g, ng, tiles, bytes, s);
+    case 1: return launch_b_write<1>(t, g, ng, tiles, bytes, s);
+    case 2: return launch_b_write<2>(t, g, ng, tiles, bytes, s);
+    case 3: return launch_b_write<3>(t, g, ng, tiles, bytes, s);
+    case 4: return launch_b_write<4>(t, g, ng, tiles, bytes, s);
+    case 5: return launch_b_write<5>(t, g, ng, tiles, bytes, s);
+    case 6: return launch_b_write<6>(t, g, ng, tiles, bytes, s);
+    case 7: return launch_b_write<7>(t, g, ng, tiles, bytes, s);
+    case 8: return launch_b_write<8>(t, g, ng, tiles, bytes, s);
+    case 9: return launch_b_write<9>(t, g, ng, tiles, bytes, s);
+    case 10: return launch_b_write<10>(t, g, ng, tiles, bytes, s);
+    case 11: return launch_b_write<11>(t, g, ng, tiles, bytes, s);
+    default: return launch_b_write<-1>(t, g, ng, tiles, bytes, s);
+  }
+}
+void b_compact(int k, const WTask* t, const GItem* g, int ng, const int64_t* ts, int64_t tiles,
+               double bytes, hipStream_t s) {
+  switch (k) {
+    case 1: return launch_b_compact<1>(t, g, ng, ts, tiles, bytes, s);
+    case 2: return launch_b_compact<2>(t, g, ng, ts, tiles, bytes, s);
+    case 3: return launch_b_compact<3>(t, g, ng, ts, tiles, bytes, s);
+    case 4: return launch_b_compact<4>(t, g, ng, ts, tiles, bytes, s);
+    case 5: return launch_b_compact<5>(t, g, ng, ts, tiles, bytes, s);
+    case 6: return launch_b_compact<6>(t, g, ng, ts, tiles, bytes, s);
+    case 7: return launch_b_compact<7>(t, g, ng, ts, tiles, bytes, s);
+    case 8: return launch_b_compact<8>(t, g, ng, ts, tiles, bytes, s);
+    default: return launch_b_compact<-1>(t, g, ng, ts, tiles, bytes, s);
+  }
+}
+
+// ---------------------------------------------------------------- host side
+
+// Growable pinned host buffer (per thread and purpose).  A buffer is only
+// rewritten after the stream has synchronised past the copy that read it.
+struct Pinned {
+  void* p = nullptr;
+  size_t bytes = 0;
+  void* get(size_t want) {
+    if (want <= bytes) return p;
+    if (p) GS_HIP(hipHostFree(p));
+    p = nullptr;
+    bytes = 0;
+    size_t b = 1 << 16;
+    while (b < want) b <<= 1;
+    GS_HIP(hipHostMalloc(&p, b, hipHostMallocDefault));
+    bytes = b;
+    return p;
+  }
+};
+enum { kPinCount = 0, kPinWrite, kPinSample, kPinTotals, kPinParts, kPinLookup, kPinCount_ };
+Pinned* pins() {
+  thread_local Pinned p[kPinCount_];
+  return p;
+}
+
+// Byte layout of several device slices inside one arena (256-byte aligned).
+struct Layout {
+  size_t bytes = 0;
+  size_t add(size_t b) {
+    const size_t at = bytes;
+    bytes += (b + 255) / 256 * 256;
+    return at;
+  }
+};
+
+// Batched lookups: one launch and one synchronisation for all requests.
+std::vector<LookupRes> lookup_many(const gsmat_store* st, const std::vector<LookupReq>& req,
+                                   hipStream_t s) {
+  std::vector<LookupRes> out(req.size());
+  if (req.empty()) return out;
+  const size_t n = req.size();
+  Layout L;
+  const size_t o_req = L.add(sizeof(LookupReq) * n);
+  Arena a(st->mem.get(), L.bytes, s);
+  char* dev = (char*)a.p;
+  LookupReq* hreq = (LookupReq*)pins()[kPinLookup].get(sizeof(LookupReq) * n);
+  LookupRes* hres = (LookupRes*)pins()[kPinTotals].get(sizeof(LookupRes) * n);
+  std::memcpy(hreq, req.data(), sizeof(LookupReq) * n);
+  GS_HIP(hipMemcpyAsync(dev + o_req, hreq, sizeof(LookupReq) * n, hipMemcpyHostToDevice, s));
+  GS_BLAUNCH(GSMAT_K_OTHER, 32.0 * n,
+             hipLaunchKernelGGL(k_lookup_many, dim3((unsigned)ceil_div((int64_t)n, kBlock)),
+                                dim3(kBlock), 0, s, (const LookupReq*)(dev + o_req), (int32_t)n,
+                                st->out.d_desc, st->in.d_desc, st->out.keys, st->out.ptr,
+                                st->out.nbr, st->out.dense, st->in.keys, st->in.ptr, st->in.nbr,
+                                st->in.dense, hres));
+  host_sync(s);
+  std::memcpy(out.data(), hres, sizeof(LookupRes) * n);
+  return out;
+}
+
+enum QState { kActive, kDone, kFallback, kFailed };
+
+struct BQ {
+  const gsmat_query_plan* pl = nullptr;
+  std::unique_ptr<gsmat_result> res;
+  Table t;
+  uint32_t rem = 0;
+  int si = 0;
+  QState state = kActive;
+  gsmat_status status = GSMAT_OK;
+  std::string err;
+  gsmat_step_info sp{};
+  uint32_t next = 0;
+  int task = -1;        // this round's task
+  int lk0 = 0;          // first lookup result of this query (one per pattern with a constant)
+  int lk[kMaxPats];     // lookup index per pattern, -1 without constant
+  int cand0 = -1;       // first sampled candidate this round
+  StepChoice choice;
+  // pending task output (intersection result before it is combined)
+  int new_var = -1;
+};
+
+struct Batch {
+  gsmat_store* st;
+  hipStream_t s;
+  int64_t budget;
+  int64_t max_rows;
+  std::vector<BQ> q;
+  std::vector<LookupRes> lk;
+
+  DeviceMem* mem() { return st->mem.get(); }
+
+  void add_in(BQ& b, int64_t n) {
+    if (b.si < (int)b.res->step_in.size()) b.res->step_in[b.si] += n;
+  }
+  void add_out(BQ& b, int64_t m) {
+    if (b.si < (int)b.res->step_out.size()) b.res->step_out[b.si] += m;
+  }
+
+  void fail(BQ& b, gsmat_status st_, const std::string& msg) {
+    b.state = kFailed;
+    b.status = st_;
+    b.err = msg;
+    b.t = Table();
+    b.res.reset();
+  }
+
+  // Emits the finished table as the query's result.
+  void emit(BQ& b) {
+    const Table& t = b.t;
+    const int nv = b.pl->n_vars;
+    Segment seg;
+    seg.rows = t.n;
+    for (int v = 0; v < nv; ++v) {
+      const int c = t.col_of(v);
+      if (c < 0) throw StatusFail{GSMAT_EHIP, "internal: unbound variable at the end of the plan"};
+      seg.col[v] = t.col[c];
+    }
+    seg.keep = t.keep;
+    b.res->rows += seg.rows;
+    b.res->segs.push_back(seg);
+    b.state = kDone;
+    b.t = Table();
+    if (max_rows >= 0 && b.res->rows > max_rows)
+      fail(b, GSMAT_ETOOBIG, "result exceeds max_rows (" + std::to_string(max_rows) + ")");
+  }
+
+  // The query moves on with table t: the next step index, the patterns left.
+  void advance(BQ& b, Table t) {
+    b.t = std::move(t);
+    b.rem = b.next;
+    b.si += 1;
+    if (b.t.n == 0) {
+      b.state = kDone;
+      b.t = Table();
+    } else if (b.rem == 0) {
+      emit(b);
+    }
+  }
+
+  // Relation of one pattern as a view into the store (a scan step on the unit
+  // table); false when it is not a plain view (the (?x p ?x) diagonal).
+  bool scan_view(BQ& b, int tp, Table& t) {
+    const gsmat_pattern& p = b.pl->pats[tp];
+    if (is_var(p.s) && is_var(p.o)) {
+      if (p.s == p.o) return false;
+      const PredView pv = st->out.view(p.p);
+      t.n = pv.nnz;
+      t.k = 2;
+      t.col[0] = pv.src;
+      t.var[0] = var_of(p.s);
+      t.col[1] = pv.nbr;
+      t.var[1] = var_of(p.o);
+      return true;
+    }
+    const LookupRes& r = lk[b.lk[tp]];
+    if (!is_var(p.s) && is_var(p.o)) {
+      t.n = r.len;
+      t.k = 1;
+      t.col[0] = st->out.view(p.p).nbr + r.start;
+      t.var[0] = var_of(p.o);
+    } else if (is_var(p.s) && !is_var(p.o)) {
+      t.n = r.len;
+      t.k = 1;
+      t.col[0] = st->in.view(p.p).nbr + r.start;
+      t.var[0] = var_of(p.s);
+    } else {
+      t.n = r.found ? 1 : 0;
+      t.k = 0;
+    }
+    return true;
+  }
+
+  void run();
+  void round();
+};
+
+void Batch::run() {
+  // constant lookups of every query, in one launch
+  std::vector<LookupReq> req;
+  for (BQ& b : q) {
+    if (b.state != kActive) continue;
+    for (int tp = 0; tp < (int)b.pl->pats.size(); ++tp) {
+      const gsmat_pattern& p = b.pl->pats[tp];
+      b.lk[tp] = -1;
+      const bool sc = !is_var(p.s), oc = !is_var(p.o);
+      if (!sc && !oc) continue;
+      b.lk[tp] = (int)req.size();
+      if (sc && oc) req.push_back({0, p.p, p.s, p.o});
+      else if (sc) req.push_back({0, p.p, p.s, -1});
+      else req.push_back({1, p.p, p.o, -1});
+    }
+  }
+  lk = lookup_many(st, req, s);
+  for (;;) {
+    bool any = false;
+    for (const BQ& b : q) any |= b.state == kActive;
+    if (!any) break;
+    round();
+  }
+}
+
+void Batch::round() {
+  const int nq = (int)q.size();
+  // ---- step choice (adaptive queries sample their candidate expansions)
+  std::vector<SCand> cands;
+  for (BQ& b : q) {
+    if (b.state != kActive) continue;
+    b.task = -1;
+    b.cand0 = -1;
+    const gsmat_query_plan* pl = b.pl;
+    if (pl->mode == GSMAT_PLAN_ADAPTIVE && !b.t.unit()) {
+      b.choice = step_candidates(st, pl, b.t, b.rem);
+      const StepChoice& c = b.choice;
+      if (c.has_filter) b.sp = c.filter;
+      else if (c.nc == 0) b.sp = c.cartesian;
+      else if (c.nc == 1) b.sp = step_pick(pl, c, nullptr);
+      else {
+        b.cand0 = (int)cands.size();
+        for (int i = 0; i < c.nc; ++i) cands.push_back(SCand{c.col[i], c.pv[i], b.t.n});
+      }
+    } else {
+      b.sp = pl->steps[std::min<size_t>(b.si, pl->steps.size() - 1)];
+    }
+  }
+  if (!cands.empty()) {
+    const size_t nc = cands.size();
+    Layout L;
+    const size_t o_c = L.add(sizeof(SCand) * nc);
+    Arena a(mem(), L.bytes, s);
+    SCand* hc = (SCand*)pins()[kPinSample].get(sizeof(SCand) * nc);
+    int64_t* hp = (int64_t*)pins()[kPinParts].get(sizeof(int64_t) * nc * kSampleBlocks);
+    std::memcpy(hc, cands.data(), sizeof(SCand) * nc);
+    GS_HIP(hipMemcpyAsync((char*)a.p + o_c, hc, sizeof(SCand) * nc, hipMemcpyHostToDevice, s));
+    GS_BLAUNCH(GSMAT_K_OTHER, 0.0,
+               hipLaunchKernelGGL(k_b_sample, dim3((unsigned)(nc * kSampleBlocks)), dim3(kBlock),
+                                  0, s, (const SCand*)((char*)a.p + o_c), hp));
+    host_sync(s);
+    for (BQ& b : q) {
+      if (b.state != kActive || b.cand0 < 0) continue;
+      int64_t sum[kMaxPats];
+      for (int i = 0; i < b.choice.nc; ++i) {
+        sum[i] = 0;
+        for (int j = 0; j < kSampleBlocks; ++j) sum[i] += hp[(size_t)(b.cand0 + i) * kSampleBlocks + j];
+      }
+      b.sp = step_pick(b.pl, b.choice, sum);
+    }
+  }
+
+  // ---- count phase: tasks
+  std::vector<CTask> tasks;
+  std::vector<int> owner;  // query of each task
+  std::vector<ListRef> lists;
+  for (int qi = 0; qi < nq; ++qi) {
+    BQ& b = q[qi];
+    if (b.state != kActive) continue;
+    const gsmat_query_plan* pl = b.pl;
+    const gsmat_step_info& sp = b.sp;
+    b.next = b.rem & ~step_completes(pl, sp);
+    add_in(b, b.t.n);
+    const gsmat_pattern& p = pl->pats[sp.tp];
+    switch (sp.kind) {
+      case GSMAT_STEP_SCAN:
+      case GSMAT_STEP_CARTESIAN: {
+        Table r;
+        if (!b.t.unit() || !scan_view(b, sp.tp, r)) {
+          b.state = kFallback;
+          break;
+        }
+        add_out(b, r.n);
+        advance(b, r);
+        break;
+      }
+      case GSMAT_STEP_INTERSECT: {
+        if (!b.t.unit()) {
+          b.state = kFallback;
+          break;
+        }
+        const int32_t cterm = -(sp.var + 1);
+        ListRef ls[kMaxLists];
+        const int32_t* ids[kMaxLists];
+        int nl = 0;
+        for (int tp = 0; tp < (int)pl->pats.size(); ++tp) {
+          if (!(sp.members >> tp & 1)) continue;
+          const gsmat_pattern& m = pl->pats[tp];
+          ListRef l{};
+          if (m.s == cterm && is_var(m.o)) {
+            l.pv = st->out.view(m.p);
+            l.is_keys = 1;
+            l.len = l.pv.nr;
+            ids[nl] = l.pv.keys;
+          } else if (m.o == cterm && is_var(m.s)) {
+            l.pv = st->in.view(m.p);
+            l.is_keys = 1;
+            l.len = l.pv.nr;
+            ids[nl] = l.pv.keys;
+          } else if (m.s == cterm) {
+            const LookupRes& r = lk[b.lk[tp]];
+            l.seg = st->in.view(m.p).nbr + r.start;
+            l.len = r.len;
+            ids[nl] = l.seg;
+          } else {
+            const LookupRes& r = lk[b.lk[tp]];
+            l.seg = st->out.view(m.p).nbr + r.start;
+            l.len = r.len;
+            ids[nl] = l.seg;
+          }
+          ls[nl++] = l;
+        }
+        int d = 0;
+        for (int i = 1; i < nl; ++i)
+          if (ls[i].len < ls[d].len) d = i;
+        if (ls[d].len == 0) {
+          add_out(b, 0);
+          b.state = kDone;
+          b.t = Table();
+          break;
+        }
+        CTask c{};
+        c.kind = kTaskIntersect;
+        c.n = ls[d].len;
+        c.col = ids[d];
+        c.l0 = (int32_t)lists.size();
+        for (int i = 0; i < nl; ++i)
+          if (i != d) lists.push_back(ls[i]);
+        c.nl = (int32_t)lists.size() - c.l0;
+        b.new_var = sp.var;
+        b.task = (int)tasks.size();
+        tasks.push_back(c);
+        owner.push_back(qi);
+        break;
+      }
+      case GSMAT_STEP_FILTER: {
+        if (!is_var(p.s) && !is_var(p.o)) {
+          if (lk[b.lk[sp.tp]].found) {
+            add_out(b, b.t.n);
+            advance(b, b.t);
+          } else {
+            b.state = kDone;
+            b.t = Table();
+          }
+          break;
+        }
+        CTask c{};
+        c.kind = kTaskFilter;
+        c.n = b.t.n;
+        if (is_var(p.s)) c.pa.s_col = b.t.col[b.t.col_of(var_of(p.s))];
+        else c.pa.s_const = p.s;
+        if (is_var(p.o)) c.pa.o_col = b.t.col[b.t.col_of(var_of(p.o))];
+        else c.pa.o_const = p.o;
+        c.pv = st->out.view(p.p);
+        b.task = (int)tasks.size();
+        tasks.push_back(c);
+        owner.push_back(qi);
+        break;
+      }
+      case GSMAT_STEP_EXPAND: {
+        const int bound_var = sp.orient == 0 ? var_of(p.s) : var_of(p.o);
+        const int bc = b.t.col_of(bound_var);
+        if (bc < 0 || b.t.k + 1 > kMaxCols) {
+          b.state = kFallback;  // the single-query executor reports it
+          break;
+        }
+        CTask c{};
+        c.kind = kTaskExpand;
+        c.n = b.t.n;
+        c.col = b.t.col[bc];
+        c.pv = sp.orient == 0 ? st->out.view(p.p) : st->in.view(p.p);
+        b.new_var = sp.orient == 0 ? var_of(p.o) : var_of(p.s);
+        b.task = (int)tasks.size();
+        tasks.push_back(c);
+        owner.push_back(qi);
+        break;
+      }
+      default:
+        b.state = kFallback;
+    }
+  }
+  const int nt = (int)tasks.size();
+  if (nt == 0) return;
+
+  // scratch of the count phase
+  int64_t ntiles = 0;
+  std::vector<GItem> items(nt);
+  Layout LA;
+  std::vector<size_t> o_N(nt), o_start(nt), o_P(nt), o_flags(nt);
+  for (int i = 0; i < nt; ++i) {
+    items[i] = GItem{ntiles, i, 0};
+    ntiles += ceil_div(tasks[i].n, kTile);
+    const int64_t n = tasks[i].n;
+    if (tasks[i].kind == kTaskExpand) {
+      o_N[i] = LA.add(sizeof(int32_t) * n);
+      o_start[i] = LA.add(sizeof(int32_t) * n);
+      o_P[i] = LA.add(sizeof(int64_t) * (n + 1));
+    } else {
+      o_flags[i] = LA.add((size_t)n);
+    }
+  }
+  const size_t o_ts = LA.add(sizeof(int64_t) * (ntiles + 1));
+  const size_t o_tasks = LA.add(sizeof(CTask) * nt);
+  const size_t o_items = LA.add(sizeof(GItem) * nt);
+  const size_t o_lists = LA.add(sizeof(ListRef) * std::max<size_t>(lists.size(), 1));
+  auto A = std::make_shared<Arena>(mem(), LA.bytes, s);
+  char* da = (char*)A->p;
+  for (int i = 0; i < nt; ++i) {
+    if (tasks[i].kind == kTaskExpand) {
+      tasks[i].N = (int32_t*)(da + o_N[i]);
+      tasks[i].start = (int32_t*)(da + o_start[i]);
+    } else {
+      tasks[i].flags = (uint8_t*)(da + o_flags[i]);
+    }
+  }
+  int64_t* ts = (int64_t*)(da + o_ts);
+  {
+    const size_t up = o_lists + sizeof(ListRef) * lists.size() - o_tasks;
+    char* h = (char*)pins()[kPinCount].get(up);
+    std::memcpy(h, tasks.data(), sizeof(CTask) * nt);
+    std::memcpy(h + (o_items - o_tasks), items.data(), sizeof(GItem) * nt);
+    if (!lists.empty()) std::memcpy(h + (o_lists - o_tasks), lists.data(), sizeof(ListRef) * lists.size());
+    GS_HIP(hipMemcpyAsync(da + o_tasks, h, up, hipMemcpyHostToDevice, s));
+  }
+  int64_t* htot = (int64_t*)pins()[kPinTotals].get(sizeof(int64_t) * nt);
+  const CTask* dtasks = (const CTask*)(da + o_tasks);
+  const GItem* ditems = (const GItem*)(da + o_items);
+  GS_BLAUNCH(GSMAT_K_COUNT, 20.0 * ntiles * kTile,
+             hipLaunchKernelGGL(k_b_count, dim3((unsigned)ntiles), dim3(kBlock), 0, s, dtasks,
+                                ditems, nt, (const ListRef*)(da + o_lists), ts));
+  launch_scan_tile_sums(ts, ntiles, ts + ntiles, s, nullptr);
+  GS_BLAUNCH(GSMAT_K_SCAN, 16.0 * nt,
+             hipLaunchKernelGGL(k_b_totals, dim3((unsigned)ceil_div(nt, kBlock)), dim3(kBlock), 0,
+                                s, ditems, nt, ts, ntiles, htot));
+  host_sync(s);
+  std::vector<int64_t> tot(htot, htot + nt);
+
+  // ---- write phase: outputs
+  std::vector<WTask> w(nt);
+  std::vector<int> has_out(nt, 0);
+  Layout LB;  // output tables (kept by the next tables / results)
+  std::vector<size_t> o_out(nt);
+  int64_t round_bytes = 0;
+  for (int i = 0; i < nt; ++i) {
+    BQ& b = q[owner[i]];
+    const CTask& c = tasks[i];
+    const int64_t m = tot[i];
+    WTask& wt = w[i];
+    wt.n = c.n;
+    wt.m = m;
+    wt.t0 = items[i].w0;
+    int kout = 0;
+    if (c.kind == kTaskExpand) {
+      add_out(b, m);
+      if (m == 0) {
+        b.state = kDone;
+        b.t = Table();
+        continue;
+      }
+      kout = b.t.k + 1;
+    } else if (c.kind == kTaskFilter) {
+      add_out(b, m);
+      if (m == c.n) {  // nothing removed: the table goes on unchanged
+        advance(b, b.t);
+        continue;
+      }
+      if (m == 0) {
+        b.state = kDone;
+        b.t = Table();
+        continue;
+      }
+      kout = b.t.k;
+    } else {
+      if (m == c.n) {  // every driver id survives: the driver list itself
+        Table r;
+        r.n = m;
+        r.k = 1;
+        r.col[0] = c.col;
+        r.var[0] = b.new_var;
+        add_out(b, r.n);
+        advance(b, r);
+        continue;
+      }
+      if (m == 0) {
+        add_out(b, 0);
+        b.state = kDone;
+        b.t = Table();
+        continue;
+      }
+      kout = 1;
+    }
+    const size_t bytes = sizeof(int32_t) * (size_t)col_stride(m) * (size_t)kout;
+    if (budget > 0 && (m > budget / (4 * (int64_t)std::max(kout, 1)) ||
+                       round_bytes + (int64_t)bytes > budget)) {
+      // above the step budget (chunked alone) or the round's budget
+      b.state = kFallback;
+      b.t = Table();
+      continue;
+    }
+    round_bytes += (int64_t)bytes;
+    o_out[i] = LB.add(bytes);
+    has_out[i] = 1;
+  }
+  std::shared_ptr<Arena> B;
+  if (LB.bytes > 0) B = std::make_shared<Arena>(mem(), LB.bytes, s);
+
+  // expansion scratch (splits) and launch groups
+  Layout LC;
+  std::vector<size_t> o_split(nt);
+  std::vector<GItem> g_scan, g_part, g_write[kMaxK + 2], g_comp[kMaxK + 2];
+  int64_t n_scan = 0, n_part = 0, n_write[kMaxK + 2] = {}, n_comp[kMaxK + 2] = {};
+  double bytes_write[kMaxK + 2] = {}, bytes_comp[kMaxK + 2] = {};
+  for (int i = 0; i < nt; ++i) {
+    if (!has_out[i]) continue;
+    BQ& b = q[owner[i]];
+    const CTask& c = tasks[i];
+    WTask& wt = w[i];
+    wt.out0 = (int32_t*)((char*)B->p + o_out[i]);
+    wt.ostride = col_stride(wt.m);
+    const int64_t cnt_tiles = ceil_div(c.n, kTile);
+    if (c.kind == kTaskExpand) {
+      wt.k = b.t.k;
+      for (int cc = 0; cc < b.t.k; ++cc) wt.in.c[cc] = b.t.col[cc];
+      wt.nbr = c.pv.nbr;
+      wt.N = c.N;
+      wt.start = c.start;
+      wt.P = (int64_t*)(da + o_P[i]);
+      const int64_t pt = ceil_div(wt.n + wt.m, kTile);
+      o_split[i] = LC.add(sizeof(int64_t) * (pt + 1));
+      g_scan.push_back(GItem{n_scan, i, 0});
+      n_scan += cnt_tiles;
+      g_part.push_back(GItem{n_part, i, 0});
+      n_part += pt + 1;
+      const int gk = wt.k <= kMaxK ? wt.k : kMaxK + 1;
+      g_write[gk].push_back(GItem{n_write[gk], i, 0});
+      n_write[gk] += pt;
+      bytes_write[gk] += 4.0 * wt.m * (wt.k + 2) + wt.n * (4.0 * wt.k + 12.0);
+    } else {
+      const bool inter = c.kind == kTaskIntersect;
+      wt.k = inter ? 1 : b.t.k;
+      if (inter) wt.in.c[0] = c.col;
+      else
+        for (int cc = 0; cc < b.t.k; ++cc) wt.in.c[cc] = b.t.col[cc];
+      wt.flags = c.flags;
+      const int gk = wt.k <= kMaxK ? wt.k : kMaxK + 1;
+      g_comp[gk].push_back(GItem{n_comp[gk], i, 0});
+      n_comp[gk] += cnt_tiles;
+      bytes_comp[gk] += (1.0 + 4.0 * wt.k) * wt.n + 4.0 * wt.k * wt.m;
+    }
+  }
+  // one upload: tasks, then every group's items
+  const size_t o_w = LC.add(sizeof(WTask) * nt);
+  auto put_group = [&](std::vector<GItem>& g) { return LC.add(sizeof(GItem) * std::max<size_t>(g.size(), 1)); };
+  const size_t o_gscan = put_group(g_scan), o_gpart = put_group(g_part);
+  size_t o_gw[kMaxK + 2], o_gc[kMaxK + 2];
+  for (int k = 0; k < kMaxK + 2; ++k) {
+    o_gw[k] = put_group(g_write[k]);
+    o_gc[k] = put_group(g_comp[k]);
+  }
+  auto C = std::make_shared<Arena>(mem(), LC.bytes, s);
+  char* dc = (char*)C->p;
+  for (int i = 0; i < nt; ++i)
+    if (has_out[i] && tasks[i].kind == kTaskExpand) w[i].split = (int64_t*)(dc + o_split[i]);
+  {
+    const size_t up = LC.bytes - o_w;
+    char* h = (char*)pins()[kPinWrite].get(up);
+    std::memcpy(h, w.data(), sizeof(WTask) * nt);
+    auto copy_group = [&](std::vector<GItem>& g, size_t off) {
+      if (!g.empty()) std::memcpy(h + (off - o_w), g.data(), sizeof(GItem) * g.size());
+    };
+    copy_group(g_scan, o_gscan);
+    copy_group(g_part, o_gpart);
+    for (int k = 0; k < kMaxK + 2; ++k) {
+      copy_group(g_write[k], o_gw[k]);
+      copy_group(g_comp[k], o_gc[k]);
+    }
+    GS_HIP(hipMemcpyAsync(dc + o_w, h, up, hipMemcpyHostToDevice, s));
+  }
+  const WTask* dw = (const WTask*)(dc + o_w);
+  if (!g_scan.empty()) {
+    GS_BLAUNCH(GSMAT_K_SCAN, 12.0 * n_scan * kTile,
+               hipLaunchKernelGGL(k_b_scan_add, dim3((unsigned)n_scan), dim3(kBlock), 0, s, dw,
+                                  (const GItem*)(dc + o_gscan), (int)g_scan.size(), ts));
+    GS_BLAUNCH(GSMAT_K_OTHER, 8.0 * n_part,
+               hipLaunchKernelGGL(k_b_partition, dim3((unsigned)ceil_div(n_part, kBlock)),
+                                  dim3(kBlock), 0, s, dw, (const GItem*)(dc + o_gpart),
+                                  (int)g_part.size(), n_part));
+  }
+  for (int k = 0; k < kMaxK + 2; ++k) {
+    if (!g_write[k].empty())
+      b_write(k <= kMaxK ? k : -1, dw, (const GItem*)(dc + o_gw[k]), (int)g_write[k].size(),
+              n_write[k], bytes_write[k], s);
+    if (!g_comp[k].empty())
+      b_compact(k <= kMaxK ? k : -1, dw, (const GItem*)(dc + o_gc[k]), (int)g_comp[k].size(), ts,
+                n_comp[k], bytes_comp[k], s);
+  }
+
+  // ---- the queries move on with their new tables
+  for (int i = 0; i < nt; ++i) {
+    if (!has_out[i]) continue;
+    BQ& b = q[owner[i]];
+    const CTask& c = tasks[i];
+    const WTask& wt = w[i];
+    Table r;
+    r.n = wt.m;
+    r.keep = B;
+    if (c.kind == kTaskExpand) {
+      r.k = b.t.k + 1;
+      for (int cc = 0; cc < b.t.k; ++cc) r.var[cc] = b.t.var[cc];
+      r.var[b.t.k] = b.new_var;
+    } else if (c.kind == kTaskFilter) {
+      r.k = b.t.k;
+      for (int cc = 0; cc < b.t.k; ++cc) r.var[cc] = b.t.var[cc];
+    } else {
+      r.k = 1;
+      r.var[0] = b.new_var;
+      add_out(b, r.n);
+    }
+    for (int cc = 0; cc < r.k; ++cc) r.col[cc] = wt.out0 + (int64_t)cc * wt.ostride;
+    advance(b, r);
+  }
+  // A and C are released here, after the launches that read them (stream order)
+}
+
+}  // namespace
+
+extern "C" gsmat_status gsmat_join_batch(gsmat_store* st, const gsmat_query_plan* const* plans,
+                                         int32_t n_plans, int64_t budget_bytes, int64_t max_rows,
+                                         void* stream, gsmat_result** out, gsmat_status* status) {
+  return guarded([&]() -> gsmat_status {
+    if (n_plans < 0) throw StatusFail{GSMAT_EINVAL, "negative query count"};
+    if (n_plans > 0 && (!out || !plans)) throw StatusFail{GSMAT_EINVAL, "plans or out is NULL"};
+    for (int i = 0; i < n_plans; ++i) out[i] = nullptr;
+    if (!st) throw StatusFail{GSMAT_EINVAL, "store is NULL"};
+    if (!st->built) throw StatusFail{GSMAT_ESTATE, "index not built"};
+    for (int i = 0; i < n_plans; ++i)
+      if (!plans[i]) throw StatusFail{GSMAT_EINVAL, "plan " + std::to_string(i) + " is NULL"};
+    hipStream_t s = (hipStream_t)stream;
+    Batch bt{st, s, budget_bytes, max_rows, {}, {}};
+    bt.q.resize(n_plans);
+    for (int i = 0; i < n_plans; ++i) {
+      BQ& b = bt.q[i];
+      b.pl = plans[i];
+      b.res.reset(new gsmat_result);
+      b.res->st = st;
+      b.res->stream = s;
+      b.res->n_vars = b.pl->n_vars;
+      b.res->step_in.assign(b.pl->steps.size(), 0);
+      b.res->step_out.assign(b.pl->steps.size(), 0);
+      b.t.n = 1;
+      b.t.k = 0;
+      b.rem = b.pl->pats.size() >= 32 ? 0xFFFFFFFFu : ((1u << b.pl->pats.size()) - 1);
+      // a pattern over an absent predicate or vertex matches nothing
+      for (const gsmat_pattern& p : b.pl->pats)
+        if (p.p >= st->P || (!is_var(p.s) && p.s >= st->V) || (!is_var(p.o) && p.o >= st->V)) {
+          b.state = kDone;
+          b.t = Table();
+        }
+    }
+    bt.run();
+    // queries that left the batch run alone, from the start
+    for (int i = 0; i < n_plans; ++i) {
+      BQ& b = bt.q[i];
+      if (b.state != kFallback) continue;
+      b.res.reset(new gsmat_result);
+      b.res->st = st;
+      b.res->stream = s;
+      b.res->n_vars = b.pl->n_vars;
+      b.res->step_in.assign(b.pl->steps.size(), 0);
+      b.res->step_out.assign(b.pl->steps.size(), 0);
+      gsmat_result* r = b.res.get();
+      const gsmat_status rc = guarded([&]() -> gsmat_status {
+        run_query(st, b.pl, budget_bytes, max_rows, s, r);
+        return GSMAT_OK;
+      });
+      if (rc != GSMAT_OK) {
+        b.state = kFailed;
+        b.status = rc;
+        b.err = gsmat_last_error();
+        b.res.reset();
+      } else {
+        b.state = kDone;
+      }
+    }
+    GS_HIP(hipStreamSynchronize(s));
+    gsmat_status first = GSMAT_OK;
+    std::string first_err;
+    for (int i = 0; i < n_plans; ++i) {
+      BQ& b = bt.q[i];
+      if (status) status[i] = b.state == kFailed ? b.status : GSMAT_OK;
+      if (b.state == kFailed) {
+        if (first == GSMAT_OK) {
+          first = b.status;
+          first_err = "query " + std::to_string(i) + ": " + b.err;
+        }
+        continue;
+      }
+      out[i] = b.res.release();
+    }
+    if (first != GSMAT_OK) throw StatusFail{first, first_err};
+    return GSMAT_OK;
+  });
+}
+
+extern "C" gsmat_status gsmat_plan_batch(const gsmat_store* st, const gsmat_pattern* pats,
+                                         const int32_t* n_pats, int32_t n_queries, int32_t mode,
+                                         void* stream, gsmat_query_plan** out,
+                                         gsmat_status* status) {
+  return guarded([&]() -> gsmat_status {
+    if (n_queries < 0) throw StatusFail{GSMAT_EINVAL, "negative query count"};
+    if (n_queries > 0 && (!out || !n_pats || !pats))
+      throw StatusFail{GSMAT_EINVAL, "pats, n_pats or out is NULL"};
+    for (int i = 0; i < n_queries; ++i) out[i] = nullptr;
+    if (!st) throw StatusFail{GSMAT_EINVAL, "store is NULL"};
+    if (!st->built) throw StatusFail{GSMAT_ESTATE, "index not built"};
+    if (mode != GSMAT_PLAN_PAPER && mode != GSMAT_PLAN_DEFAULT && mode != GSMAT_PLAN_ADAPTIVE)
+      throw StatusFail{GSMAT_EINVAL, "unknown plan mode " + std::to_string(mode)};
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<int64_t> off(n_queries + 1, 0);
+    for (int i = 0; i < n_queries; ++i) {
+      if (n_pats[i] < 0) throw StatusFail{GSMAT_EINVAL, "negative pattern count"};
+      off[i + 1] = off[i] + n_pats[i];
+    }
+    std::vector<gsmat_status> rc(n_queries, GSMAT_OK);
+    std::vector<std::string> msg(n_queries);
+    std::vector<std::vector<TpStat>> stats(n_queries);
+    std::vector<LookupReq> req;
+    std::vector<std::vector<int>> req_of(n_queries);
+    for (int i = 0; i < n_queries; ++i) {
+      const gsmat_pattern* pq = pats + off[i];
+      const int n = n_pats[i];
+      int32_t nv = 0;
+      rc[i] = validate_patterns(pq, n, &nv, &msg[i]);
+      if (rc[i] != GSMAT_OK) continue;
+      // the statistics pattern_stats gathers, with the lookups pooled
+      auto& ts = stats[i];
+      ts.assign(n, TpStat{});
+      req_of[i].assign(n, -1);
+      for (int j = 0; j < n; ++j) {
+        const gsmat_pattern& p = pq[j];
+        TpStat& t = ts[j];
+        if (p.p < 0 || p.p >= st->P) continue;
+        t.stat = st->out.desc[p.p].nnz;
+        t.rows_s = st->out.desc[p.p].nr;
+        t.rows_o = st->in.desc[p.p].nr;
+        if (mode == GSMAT_PLAN_PAPER) continue;
+        const bool sc = !is_var(p.s), oc = !is_var(p.o);
+        if ((sc && p.s >= st->V) || (oc && p.o >= st->V)) {
+          t.stat = t.rows_s = t.rows_o = 0;
+          continue;
+        }
+        if (!sc && !oc) continue;
+        req_of[i][j] = (int)req.size();
+        if (sc && oc) req.push_back({0, p.p, p.s, p.o});
+        else if (sc) req.push_back({0, p.p, p.s, -1});
+        else req.push_back({1, p.p, p.o, -1});
+      }
+    }
+    const std::vector<LookupRes> res = lookup_many(st, req, s);
+    gsmat_status first = GSMAT_OK;
+    std::string first_err;
+    for (int i = 0; i < n_queries; ++i) {
+      if (rc[i] == GSMAT_OK) {
+        const gsmat_pattern* pq = pats + off[i];
+        for (int j = 0; j < n_pats[i]; ++j) {
+          const int r = req_of[i][j];
+          if (r < 0) continue;
+          const bool both = !is_var(pq[j].s) && !is_var(pq[j].o);
+          const int64_t v = both ? res[r].found : res[r].len;
+          stats[i][j].stat = stats[i][j].rows_s = stats[i][j].rows_o = v;
+        }
+        std::unique_ptr<gsmat_query_plan> pl(new gsmat_query_plan);
+        rc[i] = build_plan(pq, n_pats[i], mode, stats[i], pl.get(), &msg[i]);
+        if (rc[i] == GSMAT_OK) out[i] = pl.release();
+      }
+      if (status) status[i] = rc[i];
+      if (rc[i] != GSMAT_OK && first == GSMAT_OK) {
+        first = rc[i];
+        first_err = "query " + std::to_string(i) + ": " + msg[i];
+      }
+    }
+    if (first != GSMAT_OK) throw StatusFail{first, first_err};
+    return GSMAT_OK;
+  });
+}

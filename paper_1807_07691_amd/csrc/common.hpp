@@ -104,6 +104,8 @@ struct LookupRes {
   int32_t pad;
 };
 
+constexpr int kSampleBlocks = 8;  // workgroups per fan-out sample of one candidate
+
 // -------------------------------------------------------------------------
 // device memory
 // -------------------------------------------------------------------------
@@ -242,7 +244,6 @@ void launch_write_expand(ColSet in, int k, const int64_t* P, const int32_t* star
                          int64_t ntiles, OutSet out, double alg_bytes, hipStream_t s);
 void launch_cartesian(ColSet a, int ka, int64_t na, ColSet b, int kb, int64_t nb, int64_t J0,
                       int64_t J1, OutSet out, hipStream_t s);
-constexpr int kSampleBlocks = 8;  // workgroups per candidate in launch_sample_fanout
 // writes kSampleBlocks partial sums per candidate to part[cand * kSampleBlocks + b]
 void launch_sample_fanout(const SampleSet& ss, int64_t* part, hipStream_t s);
 void launch_pack_rows(ColSet cols, int k, int64_t row0, int64_t rows, int32_t* out,

@@ -15,51 +15,11 @@
 #include <cstring>
 #include <memory>
 
-#include "store.hpp"
+#include "exec.hpp"
 
 using namespace gsmat;
 
-namespace gsmat {
-struct Segment {
-  int64_t rows = 0;
-  const int32_t* col[kMaxCols] = {};  // variable order
-  void* owned = nullptr;
-  size_t owned_bytes = 0;
-};
-}  // namespace gsmat
-
-struct gsmat_result {
-  gsmat_store* st = nullptr;
-  hipStream_t stream = nullptr;
-  int32_t n_vars = 0;
-  int64_t rows = 0;
-  std::vector<gsmat::Segment> segs;
-  std::vector<int64_t> step_in, step_out;
-  ~gsmat_result() {
-    for (auto& s : segs)
-      if (s.owned) st->mem->free(s.owned, s.owned_bytes, stream);
-  }
-};
-
 namespace {
-
-inline bool is_var(int32_t t) { return t < 0; }
-inline int var_of(int32_t t) { return -t - 1; }
-
-struct Table {
-  int64_t n = 0;
-  int k = 0;
-  const int32_t* col[kMaxCols] = {};
-  int var[kMaxCols] = {};
-  void* owned = nullptr;
-  size_t owned_bytes = 0;
-  bool unit() const { return n == 1 && k == 0; }
-  int col_of(int v) const {
-    for (int c = 0; c < k; ++c)
-      if (var[c] == v) return c;
-    return -1;
-  }
-};
 
 template <class T>
 struct Tmp {
@@ -147,7 +107,7 @@ struct Exec {
     Table t;
     t.n = n;
     t.k = k;
-    const int64_t stride = (std::max<int64_t>(n, 1) + 63) / 64 * 64;
+    const int64_t stride = col_stride(n);
     const size_t bytes = sizeof(int32_t) * (size_t)stride * (size_t)std::max(k, 1);
     if (k > 0) {
       t.owned = mem()->alloc(bytes, s);
@@ -257,101 +217,31 @@ struct Exec {
     return t;
   }
 
-  // TPs a step completes: its own TP, or for a star-centre intersection the
-  // members whose other endpoint is a constant (their membership is exact).
-  uint32_t completes(const gsmat_step_info& sp) const {
-    if (sp.kind != GSMAT_STEP_INTERSECT) return 1u << sp.tp;
-    uint32_t m = 0;
-    const int32_t cterm = -(sp.var + 1);
-    for (int tp = 0; tp < (int)pl->pats.size(); ++tp) {
-      if (!(sp.members >> tp & 1)) continue;
-      const gsmat_pattern& q = pl->pats[tp];
-      const int32_t other = q.s == cterm ? q.o : q.s;
-      if (!is_var(other)) m |= 1u << tp;
-    }
-    return m;
-  }
+  uint32_t completes(const gsmat_step_info& sp) const { return step_completes(pl, sp); }
 
-  // Adaptive choice of the next step on the bound table t: connected patterns
-  // whose endpoints are all bound go first (filters never add rows); then the
-  // expansion with the smallest output, estimated by looking up a strided
-  // sample of the bound column on the device; with nothing connected, a
-  // Cartesian step with the smallest remaining pattern.
+  // Adaptive choice of the next step on the bound table t (fan-out samples
+  // of the candidate expansions are taken on the device).
   gsmat_step_info choose(const Table& t, uint32_t rem) {
-    uint64_t bound = 0;
-    for (int c = 0; c < t.k; ++c) bound |= 1ull << t.var[c];
-    auto is_bound = [&](int32_t term) { return !is_var(term) || (bound >> var_of(term) & 1); };
-    gsmat_step_info sp;
-    std::memset(&sp, 0, sizeof(sp));
-    sp.orient = -1;
-    sp.var = -1;
-    const int np = (int)pl->pats.size();
-    for (int tp = 0; tp < np; ++tp) {
-      if (!(rem >> tp & 1)) continue;
-      const gsmat_pattern& q = pl->pats[tp];
-      const bool connected = (is_var(q.s) && (bound >> var_of(q.s) & 1)) ||
-                             (is_var(q.o) && (bound >> var_of(q.o) & 1));
-      const bool all_const = !is_var(q.s) && !is_var(q.o);
-      if ((connected || all_const) && is_bound(q.s) && is_bound(q.o)) {
-        sp.kind = GSMAT_STEP_FILTER;
-        sp.tp = tp;
-        return sp;
-      }
-    }
+    const StepChoice c = step_candidates(st, pl, t, rem);
+    if (c.has_filter) return c.filter;
+    if (c.nc == 0) return c.cartesian;
+    if (c.nc == 1) return step_pick(pl, c, nullptr);
     SampleSet ss{};
-    int cand_tp[kMaxPats], cand_or[kMaxPats];
-    int nc = 0;
-    for (int tp = 0; tp < np; ++tp) {
-      if (!(rem >> tp & 1)) continue;
-      const gsmat_pattern& q = pl->pats[tp];
-      const bool sb = is_var(q.s) && (bound >> var_of(q.s) & 1);
-      const bool ob = is_var(q.o) && (bound >> var_of(q.o) & 1);
-      if (sb == ob) continue;  // not connected (both bound were handled above)
-      const int orient = sb ? 0 : 1;
-      const int32_t free_term = sb ? q.o : q.s;
-      if (!is_var(free_term)) continue;
-      ss.col[nc] = t.col[t.col_of(var_of(sb ? q.s : q.o))];
-      ss.pv[nc] = orient == 0 ? st->out.view(q.p) : st->in.view(q.p);
-      cand_tp[nc] = tp;
-      cand_or[nc] = orient;
-      ++nc;
+    for (int i = 0; i < c.nc; ++i) {
+      ss.col[i] = c.col[i];
+      ss.pv[i] = c.pv[i];
     }
-    if (nc > 0) {
-      int best = 0;
-      if (nc > 1) {
-        ss.n = t.n;
-        ss.ncand = nc;
-        PinnedArea* h = pinned();
-        launch_sample_fanout(ss, h->part, s);
-        sync_stream();
-        int64_t sum[kMaxPats];
-        for (int i = 0; i < nc; ++i) {
-          sum[i] = 0;
-          for (int b = 0; b < kSampleBlocks; ++b) sum[i] += h->part[i * kSampleBlocks + b];
-        }
-        for (int i = 1; i < nc; ++i)
-          if (sum[i] < sum[best]) best = i;
-      }
-      const gsmat_pattern& q = pl->pats[cand_tp[best]];
-      sp.kind = GSMAT_STEP_EXPAND;
-      sp.tp = cand_tp[best];
-      sp.orient = cand_or[best];
-      sp.var = cand_or[best] == 0 ? var_of(q.o) : var_of(q.s);
-      return sp;
+    ss.n = t.n;
+    ss.ncand = c.nc;
+    PinnedArea* h = pinned();
+    launch_sample_fanout(ss, h->part, s);
+    sync_stream();
+    int64_t sum[kMaxPats];
+    for (int i = 0; i < c.nc; ++i) {
+      sum[i] = 0;
+      for (int b = 0; b < kSampleBlocks; ++b) sum[i] += h->part[i * kSampleBlocks + b];
     }
-    int pick = -1;
-    int64_t best_nnz = INT64_MAX;
-    for (int tp = 0; tp < np; ++tp) {
-      if (!(rem >> tp & 1)) continue;
-      const int64_t z = st->out.desc[pl->pats[tp].p].nnz;
-      if (z < best_nnz) {
-        best_nnz = z;
-        pick = tp;
-      }
-    }
-    sp.kind = GSMAT_STEP_CARTESIAN;
-    sp.tp = pick;
-    return sp;
+    return step_pick(pl, c, sum);
   }
 
   void run(int si, Table& t, uint32_t rem) {
@@ -590,6 +480,123 @@ struct Exec {
   }
 };
 
+}  // namespace
+
+namespace gsmat {
+
+Arena::Arena(DeviceMem* m, size_t b, hipStream_t st) : mem(m), bytes(b), s(st) {
+  p = mem->alloc(bytes, s);
+  if (!p) throw OomFail{bytes};
+}
+Arena::~Arena() {
+  if (p) mem->free(p, bytes, s);
+}
+
+uint32_t step_completes(const gsmat_query_plan* pl, const gsmat_step_info& sp) {
+  if (sp.kind != GSMAT_STEP_INTERSECT) return 1u << sp.tp;
+  uint32_t m = 0;
+  const int32_t cterm = -(sp.var + 1);
+  for (int tp = 0; tp < (int)pl->pats.size(); ++tp) {
+    if (!(sp.members >> tp & 1)) continue;
+    const gsmat_pattern& q = pl->pats[tp];
+    const int32_t other = q.s == cterm ? q.o : q.s;
+    if (!is_var(other)) m |= 1u << tp;
+  }
+  return m;
+}
+
+StepChoice step_candidates(const gsmat_store* st, const gsmat_query_plan* pl, const Table& t,
+                           uint32_t rem) {
+  uint64_t bound = 0;
+  for (int c = 0; c < t.k; ++c) bound |= 1ull << t.var[c];
+  auto is_bound = [&](int32_t term) { return !is_var(term) || (bound >> var_of(term) & 1); };
+  StepChoice ch;
+  const int np = (int)pl->pats.size();
+  for (int tp = 0; tp < np; ++tp) {
+    if (!(rem >> tp & 1)) continue;
+    const gsmat_pattern& q = pl->pats[tp];
+    const bool connected = (is_var(q.s) && (bound >> var_of(q.s) & 1)) ||
+                           (is_var(q.o) && (bound >> var_of(q.o) & 1));
+    const bool all_const = !is_var(q.s) && !is_var(q.o);
+    if ((connected || all_const) && is_bound(q.s) && is_bound(q.o)) {
+      std::memset(&ch.filter, 0, sizeof(ch.filter));
+      ch.filter.kind = GSMAT_STEP_FILTER;
+      ch.filter.tp = tp;
+      ch.filter.orient = -1;
+      ch.filter.var = -1;
+      ch.has_filter = true;
+      return ch;
+    }
+  }
+  for (int tp = 0; tp < np; ++tp) {
+    if (!(rem >> tp & 1)) continue;
+    const gsmat_pattern& q = pl->pats[tp];
+    const bool sb = is_var(q.s) && (bound >> var_of(q.s) & 1);
+    const bool ob = is_var(q.o) && (bound >> var_of(q.o) & 1);
+    if (sb == ob) continue;  // not connected (both bound were handled above)
+    const int orient = sb ? 0 : 1;
+    const int32_t free_term = sb ? q.o : q.s;
+    if (!is_var(free_term)) continue;
+    ch.col[ch.nc] = t.col[t.col_of(var_of(sb ? q.s : q.o))];
+    ch.pv[ch.nc] = orient == 0 ? st->out.view(q.p) : st->in.view(q.p);
+    ch.cand_tp[ch.nc] = tp;
+    ch.cand_or[ch.nc] = orient;
+    ++ch.nc;
+  }
+  int pick = -1;
+  int64_t best_nnz = INT64_MAX;
+  for (int tp = 0; tp < np; ++tp) {
+    if (!(rem >> tp & 1)) continue;
+    const int64_t z = st->out.desc[pl->pats[tp].p].nnz;
+    if (z < best_nnz) {
+      best_nnz = z;
+      pick = tp;
+    }
+  }
+  std::memset(&ch.cartesian, 0, sizeof(ch.cartesian));
+  ch.cartesian.kind = GSMAT_STEP_CARTESIAN;
+  ch.cartesian.tp = pick;
+  ch.cartesian.orient = -1;
+  ch.cartesian.var = -1;
+  return ch;
+}
+
+gsmat_step_info step_pick(const gsmat_query_plan* pl, const StepChoice& c, const int64_t* sums) {
+  int best = 0;
+  if (sums)
+    for (int i = 1; i < c.nc; ++i)
+      if (sums[i] < sums[best]) best = i;
+  const gsmat_pattern& q = pl->pats[c.cand_tp[best]];
+  gsmat_step_info sp;
+  std::memset(&sp, 0, sizeof(sp));
+  sp.kind = GSMAT_STEP_EXPAND;
+  sp.tp = c.cand_tp[best];
+  sp.orient = c.cand_or[best];
+  sp.var = c.cand_or[best] == 0 ? var_of(q.o) : var_of(q.s);
+  return sp;
+}
+
+void run_query(gsmat_store* st, const gsmat_query_plan* pl, int64_t budget_bytes,
+               int64_t max_rows, hipStream_t s, gsmat_result* res) {
+  // a pattern over an absent predicate or vertex matches nothing
+  for (const gsmat_pattern& q : pl->pats) {
+    if (q.p >= st->P) return;
+    if (!is_var(q.s) && q.s >= st->V) return;
+    if (!is_var(q.o) && q.o >= st->V) return;
+  }
+  Exec ex{st, pl, s, budget_bytes, max_rows, res, pl->mode == GSMAT_PLAN_ADAPTIVE, {}};
+  Table unit;
+  unit.n = 1;
+  unit.k = 0;
+  const uint32_t all = pl->pats.size() >= 32 ? 0xFFFFFFFFu : ((1u << pl->pats.size()) - 1);
+  try {
+    ex.run(0, unit, all);
+  } catch (...) {
+    ex.release_all();
+    throw;
+  }
+}
+
 // Statistics of each pattern for the planner.
 std::vector<TpStat> pattern_stats(const gsmat_store* st, const gsmat_pattern* pats, int n,
                                   int mode, hipStream_t s) {
@@ -645,7 +652,7 @@ std::vector<TpStat> pattern_stats(const gsmat_store* st, const gsmat_pattern* pa
   return out;
 }
 
-}  // namespace
+}  // namespace gsmat
 
 extern "C" gsmat_status gsmat_plan(const gsmat_store* st, const gsmat_pattern* pats,
                                    int32_t n_pats, int32_t mode, void* stream, gsmat_query_plan** out) {
@@ -681,27 +688,8 @@ extern "C" gsmat_status gsmat_join(gsmat_store* st, const gsmat_query_plan* pl, 
     res->n_vars = pl->n_vars;
     res->step_in.assign(pl->steps.size(), 0);
     res->step_out.assign(pl->steps.size(), 0);
-    // a pattern over an absent predicate or vertex matches nothing
-    bool empty = false;
-    for (const gsmat_pattern& q : pl->pats) {
-      if (q.p >= st->P) empty = true;
-      if (!is_var(q.s) && q.s >= st->V) empty = true;
-      if (!is_var(q.o) && q.o >= st->V) empty = true;
-    }
-    if (!empty) {
-      Exec ex{st, pl, s, budget_bytes, max_rows, res.get(), pl->mode == GSMAT_PLAN_ADAPTIVE, {}};
-      Table unit;
-      unit.n = 1;
-      unit.k = 0;
-      const uint32_t all = pl->pats.size() >= 32 ? 0xFFFFFFFFu : ((1u << pl->pats.size()) - 1);
-      try {
-        ex.run(0, unit, all);
-      } catch (...) {
-        ex.release_all();
-        throw;
-      }
-      GS_HIP(hipStreamSynchronize(s));
-    }
+    run_query(st, pl, budget_bytes, max_rows, s, res.get());
+    GS_HIP(hipStreamSynchronize(s));
     *out = res.release();
     return GSMAT_OK;
   });

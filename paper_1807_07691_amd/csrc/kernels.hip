@@ -10,128 +10,13 @@
 #include <hip/hip_runtime.h>
 
 #include "common.hpp"
+#include "device.hpp"
 
 namespace gsmat {
 
 namespace {
 
-__device__ inline int lane_id() { return threadIdx.x & 63; }
-__device__ inline int wave_id() { return threadIdx.x >> 6; }
-constexpr int kWaves = kBlock / 64;
-
-__device__ inline uint32_t mbcnt(uint64_t m) {
-  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-}
-
-__device__ inline int64_t wave_incl_scan(int64_t v) {
-  const int lane = lane_id();
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    int64_t t = __shfl_up(v, d, 64);
-    if (lane >= d) v += t;
-  }
-  return v;
-}
-
-__device__ inline int64_t wave_sum(int64_t v) {
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
-  return v;
-}
-
-// Exclusive scan of one value per thread over the workgroup.  Contains
-// barriers: every thread of the block must call it.
-__device__ inline int64_t block_excl_scan(int64_t v, int64_t* total) {
-  __shared__ int64_t ws[kWaves];
-  const int64_t inc = wave_incl_scan(v);
-  if (lane_id() == 63) ws[wave_id()] = inc;
-  __syncthreads();
-  int64_t off = 0, tot = 0;
-#pragma unroll
-  for (int i = 0; i < kWaves; ++i) {
-    if (i < wave_id()) off += ws[i];
-    tot += ws[i];
-  }
-  __syncthreads();
-  *total = tot;
-  return off + inc - v;
-}
-
-__device__ inline int64_t block_sum(int64_t v) {
-  __shared__ int64_t ws[kWaves];
-  v = wave_sum(v);
-  if (lane_id() == 0) ws[wave_id()] = v;
-  __syncthreads();
-  int64_t tot = 0;
-#pragma unroll
-  for (int i = 0; i < kWaves; ++i) tot += ws[i];
-  __syncthreads();
-  return tot;
-}
-
-__device__ inline int32_t lower_bound_i32(const int32_t* __restrict__ a, int32_t n, int32_t v) {
-  int32_t lo = 0, len = n;
-  while (len > 0) {
-    int32_t half = len >> 1;
-    if (a[lo + half] < v) {
-      lo += half + 1;
-      len -= half + 1;
-    } else {
-      len = half;
-    }
-  }
-  return lo;
-}
-
-// Row of vertex v in one predicate's compressed matrix: (start, len), len 0
-// when v has no entry.
-__device__ inline void row_lookup(const PredView& pv, int32_t v, int32_t& start, int32_t& len) {
-  if (pv.dense) {
-    start = pv.dense[v];
-    len = pv.dense[v + 1] - start;
-    return;
-  }
-  const int32_t r = lower_bound_i32(pv.keys, pv.nr, v);
-  if (r < pv.nr && pv.keys[r] == v) {
-    start = pv.ptr[r];
-    len = pv.ptr[r + 1] - start;
-  } else {
-    start = 0;
-    len = 0;
-  }
-}
-
-__device__ inline bool seg_contains(const int32_t* __restrict__ a, int32_t n, int32_t v) {
-  const int32_t r = lower_bound_i32(a, n, v);
-  return r < n && a[r] == v;
-}
-
-// Stable compaction of one tile: emit(i, pos) for each kept item i, pos
-// counted from base.  Barriers inside: all threads must call.
-template <class Keep, class Emit>
-__device__ inline void compact_tile(int64_t n, int64_t base, Keep keep, Emit emit) {
-  __shared__ uint32_t wtot[kWaves];
-  const int64_t tile0 = (int64_t)blockIdx.x * kTile;
-  int64_t running = base;
-  for (int j = 0; j < kItems; ++j) {
-    const int64_t i = tile0 + (int64_t)j * kBlock + threadIdx.x;
-    const bool f = (i < n) && keep(i);
-    const uint64_t m = __ballot(f);
-    const uint32_t rank = mbcnt(m);
-    if (lane_id() == 0) wtot[wave_id()] = (uint32_t)__popcll(m);
-    __syncthreads();
-    uint32_t wp = 0, tot = 0;
-#pragma unroll
-    for (int q = 0; q < kWaves; ++q) {
-      const uint32_t c = wtot[q];
-      if (q < wave_id()) wp += c;
-      tot += c;
-    }
-    if (f) emit(i, running + wp + rank);
-    running += tot;
-    __syncthreads();
-  }
-}
+using namespace dev;
 
 // ---------------------------------------------------------------- prefix sums
 __global__ __launch_bounds__(kBlock) void k_scan_tile_sums(int64_t* ts, int64_t nt,
@@ -166,31 +51,7 @@ template <class Tin, class Tout>
 __global__ __launch_bounds__(kBlock) void k_scan_add(const Tin* __restrict__ x, int64_t n,
                                                      const int64_t* __restrict__ tile_off,
                                                      Tout* __restrict__ out, int write_total) {
-  __shared__ int64_t s[kTile];
-  const int64_t tile0 = (int64_t)blockIdx.x * kTile;
-#pragma unroll
-  for (int j = 0; j < kItems; ++j) {
-    const int64_t i = tile0 + (int64_t)j * kBlock + threadIdx.x;
-    s[j * kBlock + threadIdx.x] = i < n ? (int64_t)x[i] : 0;
-  }
-  __syncthreads();
-  int64_t loc = 0;
-#pragma unroll
-  for (int j = 0; j < kItems; ++j) loc += s[threadIdx.x * kItems + j];
-  int64_t tot;
-  int64_t ex = block_excl_scan(loc, &tot) + tile_off[blockIdx.x];
-#pragma unroll
-  for (int j = 0; j < kItems; ++j) {
-    const int64_t v = s[threadIdx.x * kItems + j];
-    s[threadIdx.x * kItems + j] = ex;
-    ex += v;
-  }
-  __syncthreads();
-#pragma unroll
-  for (int j = 0; j < kItems; ++j) {
-    const int64_t i = tile0 + (int64_t)j * kBlock + threadIdx.x;
-    if (i < n) out[i] = (Tout)s[j * kBlock + threadIdx.x];
-  }
+  const int64_t tot = scan_add_tile<Tin, Tout>(blockIdx.x, x, n, tile_off[blockIdx.x], out);
   if (write_total && threadIdx.x == 0 && blockIdx.x == gridDim.x - 1)
     out[n] = (Tout)(tile_off[blockIdx.x] + tot);
 }
@@ -311,7 +172,7 @@ __global__ __launch_bounds__(kBlock) void k_compact_u64(const uint64_t* __restri
                                                         const int64_t* __restrict__ tile_off,
                                                         uint64_t* __restrict__ out) {
   compact_tile(
-      n, tile_off[blockIdx.x], [&](int64_t i) { return flags[i] != 0; },
+      blockIdx.x, n, tile_off[blockIdx.x], [&](int64_t i) { return flags[i] != 0; },
       [&](int64_t i, int64_t pos) { out[pos] = in[i]; });
 }
 
@@ -320,7 +181,7 @@ __global__ __launch_bounds__(kBlock) void k_compact_index(const uint8_t* __restr
                                                           const int64_t* __restrict__ tile_off,
                                                           int64_t* __restrict__ out) {
   compact_tile(
-      n, tile_off[blockIdx.x], [&](int64_t i) { return flags[i] != 0; },
+      blockIdx.x, n, tile_off[blockIdx.x], [&](int64_t i) { return flags[i] != 0; },
       [&](int64_t i, int64_t pos) { out[pos] = i; });
 }
 
@@ -382,35 +243,14 @@ __global__ void k_ptr_sentinels(const PredDesc* __restrict__ d, int32_t P, int32
   if (p < P) ptr[d[p].ptr_base + d[p].nr] = (int32_t)d[p].nnz;
 }
 
-__device__ inline PredView view_of(const PredDesc& d, const int32_t* keys, const int32_t* ptr,
-                                   const int32_t* nbr, const int32_t* dense) {
-  PredView pv;
-  pv.keys = keys + d.row_base;
-  pv.ptr = ptr + d.ptr_base;
-  pv.nbr = nbr + d.nbr_base;
-  pv.src = nullptr;
-  pv.dense = d.dense_base >= 0 ? dense + d.dense_base : nullptr;
-  pv.nr = (int32_t)d.nr;
-  pv.nnz = (int32_t)d.nnz;
-  return pv;
-}
-
 __global__ void k_lookup(LookupBatch b, const PredDesc* dout, const PredDesc* din,
                          const int32_t* keys_out, const int32_t* ptr_out, const int32_t* nbr_out,
                          const int32_t* dense_out, const int32_t* keys_in, const int32_t* ptr_in,
                          const int32_t* nbr_in, const int32_t* dense_in, LookupRes* res) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= b.n) return;
-  const LookupReq q = b.req[i];
-  const PredView pv = q.orient == 0
-                          ? view_of(dout[q.pred], keys_out, ptr_out, nbr_out, dense_out)
-                          : view_of(din[q.pred], keys_in, ptr_in, nbr_in, dense_in);
-  LookupRes r;
-  row_lookup(pv, q.v, r.start, r.len);
-  r.found = (q.member >= 0 && r.len > 0) ? (seg_contains(pv.nbr + r.start, r.len, q.member) ? 1 : 0)
-                                         : 0;
-  r.pad = 0;
-  res[i] = r;
+  res[i] = lookup_one(b.req[i], dout, din, keys_out, ptr_out, nbr_out, dense_out, keys_in, ptr_in,
+                      nbr_in, dense_in);
 }
 
 // ---------------------------------------------------------------- join steps
@@ -419,42 +259,14 @@ __global__ __launch_bounds__(kBlock) void k_count_expand(const int32_t* __restri
                                                          int32_t* __restrict__ N,
                                                          int32_t* __restrict__ start,
                                                          int64_t* __restrict__ ts) {
-  const int64_t tile0 = (int64_t)blockIdx.x * kTile;
-  int64_t loc = 0;
-#pragma unroll
-  for (int j = 0; j < kItems; ++j) {
-    const int64_t i = tile0 + (int64_t)j * kBlock + threadIdx.x;
-    if (i < n) {
-      int32_t st, len;
-      row_lookup(pv, col[i], st, len);
-      N[i] = len;
-      start[i] = st;
-      loc += len;
-    }
-  }
-  const int64_t t = block_sum(loc);
+  const int64_t t = count_expand_tile(blockIdx.x, col, n, pv, N, start);
   if (threadIdx.x == 0) ts[blockIdx.x] = t;
 }
 
 __global__ __launch_bounds__(kBlock) void k_flag_filter(ProbeArgs pa, int64_t n, PredView pv,
                                                         uint8_t* __restrict__ flags,
                                                         int64_t* __restrict__ ts) {
-  const int64_t tile0 = (int64_t)blockIdx.x * kTile;
-  int64_t loc = 0;
-#pragma unroll
-  for (int j = 0; j < kItems; ++j) {
-    const int64_t i = tile0 + (int64_t)j * kBlock + threadIdx.x;
-    if (i < n) {
-      const int32_t sv = pa.s_col ? pa.s_col[i] : pa.s_const;
-      const int32_t ov = pa.o_col ? pa.o_col[i] : pa.o_const;
-      int32_t st, len;
-      row_lookup(pv, sv, st, len);
-      const uint8_t f = (len > 0 && seg_contains(pv.nbr + st, len, ov)) ? 1 : 0;
-      flags[i] = f;
-      loc += f;
-    }
-  }
-  const int64_t t = block_sum(loc);
+  const int64_t t = flag_filter_tile(blockIdx.x, pa, n, pv, flags);
   if (threadIdx.x == 0) ts[blockIdx.x] = t;
 }
 
@@ -481,29 +293,7 @@ __global__ __launch_bounds__(kBlock) void k_flag_intersect(const int32_t* __rest
                                                            int64_t n, ListSet ls,
                                                            uint8_t* __restrict__ flags,
                                                            int64_t* __restrict__ ts) {
-  const int64_t tile0 = (int64_t)blockIdx.x * kTile;
-  int64_t loc = 0;
-#pragma unroll
-  for (int j = 0; j < kItems; ++j) {
-    const int64_t i = tile0 + (int64_t)j * kBlock + threadIdx.x;
-    if (i < n) {
-      const int32_t x = driver[i];
-      bool keep = true;
-      for (int l = 0; l < ls.n && keep; ++l) {
-        const ListRef& L = ls.l[l];
-        if (L.is_keys) {
-          int32_t st, len;
-          row_lookup(L.pv, x, st, len);
-          keep = len > 0;
-        } else {
-          keep = seg_contains(L.seg, (int32_t)L.len, x);
-        }
-      }
-      flags[i] = keep ? 1 : 0;
-      loc += keep ? 1 : 0;
-    }
-  }
-  const int64_t t = block_sum(loc);
+  const int64_t t = flag_intersect_tile(blockIdx.x, driver, n, ls.l, ls.n, flags);
   if (threadIdx.x == 0) ts[blockIdx.x] = t;
 }
 
@@ -513,19 +303,7 @@ __global__ __launch_bounds__(kBlock) void k_compact_cols(ColSet in, int kdyn,
                                                          int64_t n,
                                                          const int64_t* __restrict__ tile_off,
                                                          OutSet out) {
-  compact_tile(
-      n, tile_off[blockIdx.x], [&](int64_t i) { return flags[i] != 0; },
-      [&](int64_t i, int64_t pos) {
-        if (K >= 0) {
-          int32_t x[K > 0 ? K : 1];
-#pragma unroll
-          for (int c = 0; c < K; ++c) x[c] = in.c[c][i];
-#pragma unroll
-          for (int c = 0; c < K; ++c) out.c[c][pos] = x[c];
-        } else {
-          for (int c = 0; c < kdyn; ++c) out.c[c][pos] = in.c[c][i];
-        }
-      });
+  compact_cols_tile<K>(blockIdx.x, in, kdyn, flags, n, tile_off[blockIdx.x], OutCols{&out});
 }
 
 // Merge path over A = row ends E[i] = P[i+1] (i < n) and B = output indices
@@ -535,82 +313,7 @@ __global__ void k_mp_partition(const int64_t* __restrict__ P, int64_t n, int64_t
                                int64_t* __restrict__ split, int64_t ntiles) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t > ntiles) return;
-  const int64_t nb = J1 - J0;
-  const int64_t d = min(t * (int64_t)kTile, n + nb);
-  int64_t lo = max((int64_t)0, d - nb), hi = min(d, n);
-  while (lo < hi) {
-    const int64_t mid = (lo + hi) >> 1;
-    if (P[mid + 1] <= J0 + (d - 1 - mid)) lo = mid + 1;
-    else hi = mid;
-  }
-  split[t] = lo;
-}
-
-// Expansion write: output j in [P_i, P_{i+1}) copies the parent row i and
-// appends the (j - P_i)-th member of row i's segment (start_i) in nbr.
-//
-// A tile is kTile consecutive items of the merge path over (row ends, output
-// indices); split[t] gives the rows consumed before it, so the tile covers
-// rows a0..a1 and outputs jb + [0, nbt).  Per row the tile keeps in LDS the
-// row end relative to jb (clamped to [-1, kTile + 1], which preserves every
-// comparison the walk makes) and rb = start_i + (jb - P_i), so that output o of
-// row r reads nbr[rb[r] + o]; both fit int32.  Each thread walks kItems path
-// items to label outputs with their row; then the tile's outputs are written
-// column by column with unit stride.
-//
-// The write loop is laid out for the memory system: output columns start on
-// 256-byte boundaries and the loop is shifted by the tile's offset modulo 64,
-// so every wave store covers whole 128-byte lines (unaligned tile starts
-// halved the store bandwidth); each thread handles two outputs per iteration
-// and issues all their loads (neighbour ids, K parent values) before any
-// store.  K is a compile-time column count (-1: any count, in groups of 4).
-template <int K>
-__device__ inline void write_outputs(const ColSet& in, int kdyn, const int32_t* __restrict__ nbr,
-                                     const uint16_t* sRow, const int32_t* sRb, int64_t a0,
-                                     int64_t ob, int nbt, OutSet& out) {
-  const int k = K >= 0 ? K : kdyn;
-  const int al = (int)(ob & 63);
-  const int span = nbt + al;
-  for (int q = threadIdx.x; q < span; q += 2 * kBlock) {
-    const int o1 = q - al, o2 = q + kBlock - al;
-    const bool ok1 = o1 >= 0 && o1 < nbt, ok2 = o2 >= 0 && o2 < nbt;
-    const int r1 = ok1 ? sRow[o1] : 0, r2 = ok2 ? sRow[o2] : 0;
-    const int32_t v1 = ok1 ? nbr[sRb[r1] + o1] : 0;
-    const int32_t v2 = ok2 ? nbr[sRb[r2] + o2] : 0;
-    const int64_t row1 = a0 + r1, row2 = a0 + r2;
-    if (K >= 0) {
-      int32_t x1[K > 0 ? K : 1], x2[K > 0 ? K : 1];
-#pragma unroll
-      for (int c = 0; c < K; ++c) {
-        x1[c] = ok1 ? in.c[c][row1] : 0;
-        x2[c] = ok2 ? in.c[c][row2] : 0;
-      }
-      if (ok1) {
-#pragma unroll
-        for (int c = 0; c < K; ++c) __builtin_nontemporal_store(x1[c], &out.c[c][ob + o1]);
-      }
-      if (ok2) {
-#pragma unroll
-        for (int c = 0; c < K; ++c) __builtin_nontemporal_store(x2[c], &out.c[c][ob + o2]);
-      }
-    } else {
-      for (int c0 = 0; c0 < k; c0 += 4) {
-        int32_t x1[4], x2[4];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          x1[c] = (ok1 && c0 + c < k) ? in.c[c0 + c][row1] : 0;
-          x2[c] = (ok2 && c0 + c < k) ? in.c[c0 + c][row2] : 0;
-        }
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          if (ok1 && c0 + c < k) __builtin_nontemporal_store(x1[c], &out.c[c0 + c][ob + o1]);
-          if (ok2 && c0 + c < k) __builtin_nontemporal_store(x2[c], &out.c[c0 + c][ob + o2]);
-        }
-      }
-    }
-    if (ok1) __builtin_nontemporal_store(v1, &out.c[k][ob + o1]);
-    if (ok2) __builtin_nontemporal_store(v2, &out.c[k][ob + o2]);
-  }
+  split[t] = mp_split(P, n, J0, J1, t);
 }
 
 template <int K>
@@ -622,48 +325,7 @@ __global__ __launch_bounds__(kBlock) void k_write_expand(ColSet in, int kdyn,
                                                          int64_t J0, int64_t J1,
                                                          const int64_t* __restrict__ split,
                                                          OutSet out) {
-  __shared__ int32_t sE[kTile + 1];
-  __shared__ int32_t sRb[kTile + 1];
-  __shared__ uint16_t sRow[kTile];
-  const int64_t t = blockIdx.x;
-  const int64_t nb = J1 - J0;
-  const int64_t total = n + nb;
-  const int64_t d0 = t * (int64_t)kTile;
-  const int64_t d1 = min(d0 + (int64_t)kTile, total);
-  const int64_t a0 = split[t], a1 = split[t + 1];
-  const int64_t b0 = d0 - a0, b1 = d1 - a1;
-  const int nat = (int)(a1 - a0), nbt = (int)(b1 - b0);
-  if (nbt <= 0) return;  // block-uniform
-  const int64_t jb = J0 + b0;
-  const int64_t rl = min(a1, n - 1);
-  const int nr = (int)(rl - a0 + 1);
-  for (int i = threadIdx.x; i < nr; i += kBlock) {
-    const int64_t pb = P[a0 + i], pe = P[a0 + i + 1];
-    const int64_t er = pe - jb;
-    sE[i] = er > (int64_t)kTile + 1 ? kTile + 1 : (er < -1 ? -1 : (int32_t)er);
-    sRb[i] = (int32_t)((int64_t)start[a0 + i] + (jb - pb));
-  }
-  __syncthreads();
-  const int dl = min((int)threadIdx.x * kItems, nat + nbt);
-  const int de = min((int)threadIdx.x * kItems + kItems, nat + nbt);
-  int lo = max(0, dl - nbt), hi = min(dl, nat);
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (sE[mid] <= dl - 1 - mid) lo = mid + 1;
-    else hi = mid;
-  }
-  int a = lo, b = dl - lo;
-  for (int step = dl; step < de; ++step) {
-    const bool takeA = (a < nat) && (b >= nbt || sE[a] <= b);
-    if (takeA) {
-      ++a;
-    } else {
-      sRow[b] = (uint16_t)a;
-      ++b;
-    }
-  }
-  __syncthreads();
-  write_outputs<K>(in, kdyn, nbr, sRow, sRb, a0, jb - J0, nbt, out);
+  write_expand_tile<K>(blockIdx.x, in, kdyn, P, start, n, nbr, J0, J1, split, OutCols{&out});
 }
 
 __global__ void k_cartesian(ColSet a, int ka, ColSet b, int kb, int64_t nb, int64_t J0,
@@ -677,25 +339,11 @@ __global__ void k_cartesian(ColSet a, int ka, ColSet b, int kb, int64_t nb, int6
   }
 }
 
-constexpr int64_t kSampleRows = 16384;
-
 // Sum of row lengths over a strided sample of the bound column; blockIdx.y
 // selects the candidate, blockIdx.x one of kSampleBlocks slices of the sample.
 __global__ __launch_bounds__(kBlock) void k_sample_fanout(SampleSet ss, int64_t* __restrict__ part) {
   const int cand = blockIdx.y;
-  const int64_t n = ss.n;
-  const int64_t S = n < kSampleRows ? n : kSampleRows;
-  const int64_t stride = S > 0 ? n / S : 1;
-  const int32_t* col = ss.col[cand];
-  const PredView pv = ss.pv[cand];
-  int64_t loc = 0;
-  for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < S;
-       j += (int64_t)kSampleBlocks * kBlock) {
-    int32_t st, len;
-    row_lookup(pv, col[j * stride], st, len);
-    loc += len;
-  }
-  const int64_t t = block_sum(loc);
+  const int64_t t = sample_fanout_slice(blockIdx.x, ss.col[cand], ss.n, ss.pv[cand]);
   if (threadIdx.x == 0) part[cand * kSampleBlocks + blockIdx.x] = t;
 }
 

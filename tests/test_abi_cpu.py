@@ -164,3 +164,17 @@ def test_default_plan_is_valid(G, seed):
         unit = unit and not vs
     assert done == set(range(len(tps)))
     assert bound == set(range(nv))
+
+
+def test_batch_entry_points_validate_before_device_work(G):
+    lib = G.lib()
+    out = (ctypes.c_void_p * 1)()
+    st = np.full(1, -7, np.int32)
+    n = np.ones(1, np.int32)
+    pats = np.array([[-1, 0, -2]], np.int32)
+    assert lib.gsmat_join_batch(None, None, 0, 0, -1, None, None, None) == G.GSMAT_EINVAL
+    assert lib.gsmat_join_batch(None, None, -1, 0, -1, None, None, None) == G.GSMAT_EINVAL
+    assert lib.gsmat_plan_batch(None, None, None, -1, 1, None, None, None) == G.GSMAT_EINVAL
+    assert lib.gsmat_plan_batch(None, G._p(pats), G._p(n), 1, 1, None, out, G._p(st)) == \
+        G.GSMAT_EINVAL
+    assert out[0] is None

@@ -1,0 +1,238 @@
+"""Batched join parity: every query of a batch yields exactly the rows (in the
+same order) and per-step row counts it yields alone through gsmat_join, and
+the oracle's row multiset.  Batches mix shapes, sizes, plan modes, repeated
+queries, empty results and the cases the batch hands to the single-query
+executor (Cartesian steps, (?x p ?x) patterns, budget overflow)."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def _sorted(a):
+    a = np.asarray(a)
+    if a.ndim != 2 or len(a) == 0 or a.shape[1] == 0:
+        return a
+    return a[np.lexsort(a.T[::-1])]
+
+
+@pytest.fixture(scope="module")
+def G():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1807_07691_amd as G
+    return G
+
+
+@pytest.fixture(scope="module")
+def O():
+    import oracle
+    return oracle
+
+
+def _store(G, s, p, o, V, P, **kw):
+    st = G.gsmat_load_triples(s, p, o, V, P)
+    G.gsmat_build_index(st, **kw)
+    return st
+
+
+def _single(G, st, tps, mode, budget=0, max_rows=-1):
+    pl = G.gsmat_plan(st, tps, mode)
+    try:
+        r = G.gsmat_join(st, pl, budget, max_rows)
+        try:
+            return G.gsmat_fetch_bindings(r), G.gsmat_result_info(r)
+        finally:
+            r.close()
+    finally:
+        pl.close()
+
+
+def _check_batch(G, st, queries, mode, budget=0, oracle_rows=None):
+    """Batch vs alone (exact order and step counts) and vs the oracle."""
+    plans, stat = G.gsmat_plan_batch(st, queries, mode)
+    assert stat == [0] * len(queries)
+    try:
+        for tps, pl in zip(queries, plans):
+            one = G.gsmat_plan(st, tps, mode)
+            assert G.gsmat_plan_info(pl) == G.gsmat_plan_info(one)
+            one.close()
+        results, stat = G.gsmat_join_batch(st, plans, budget)
+        assert stat == [0] * len(queries)
+        try:
+            for i, (tps, r) in enumerate(zip(queries, results)):
+                got = G.gsmat_fetch_bindings(r)
+                info = G.gsmat_result_info(r)
+                alone, info1 = _single(G, st, tps, mode, budget)
+                assert np.array_equal(got, alone), (i, tps)
+                assert info == info1, (i, tps)
+                if oracle_rows is not None:
+                    want = oracle_rows[i]
+                    assert np.array_equal(_sorted(got), want), (i, tps)
+        finally:
+            for r in results:
+                r.close()
+    finally:
+        for pl in plans:
+            pl.close()
+
+
+# ------------------------------------------------------------------ tiny workload
+@pytest.fixture(scope="module")
+def tiny(G, O):
+    import workload as W
+    spec, (s, p, o), gi, qs = W.make_workload("tiny")
+    st = _store(G, s, p, o, spec.V, spec.P)
+    want = [O.join(s, p, o, q.tps, q.n_vars) for q in qs]
+    return spec, s, p, o, qs, st, want
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_batch_tiny_workload(G, tiny, mode):
+    spec, s, p, o, qs, st, want = tiny
+    print(f"[gpu] batch tiny mode={mode}", flush=True)
+    queries = [q.tps for q in qs] * 2  # each query twice in the batch
+    _check_batch(G, st, queries, mode, oracle_rows=want * 2)
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_batch_tiny_budget_fallback(G, tiny, mode):
+    """A budget below some steps' outputs: those queries finish alone."""
+    spec, s, p, o, qs, st, want = tiny
+    print(f"[gpu] batch tiny budget mode={mode}", flush=True)
+    for budget in (4 * 4 * 997, 4 * 4 * 50_000):
+        _check_batch(G, st, [q.tps for q in qs], mode, budget=budget, oracle_rows=want)
+
+
+def test_batch_max_rows_fails_only_that_query(G, tiny):
+    spec, s, p, o, qs, st, want = tiny
+    big = max(range(len(qs)), key=lambda i: qs[i].count)
+    plans, _ = G.gsmat_plan_batch(st, [q.tps for q in qs], G.PLAN_ADAPTIVE)
+    limit = qs[big].count - 1
+    results, stat = G.gsmat_join_batch(st, plans, max_rows=limit, raise_on_error=False)
+    for i, q in enumerate(qs):
+        if q.count > limit:
+            assert stat[i] == G.GSMAT_ETOOBIG and results[i] is None
+        else:
+            assert stat[i] == 0
+            assert np.array_equal(_sorted(G.gsmat_fetch_bindings(results[i])), want[i])
+            results[i].close()
+    with pytest.raises(G.GsmatError) as e:
+        G.gsmat_join_batch(st, plans, max_rows=limit)
+    assert e.value.status == G.GSMAT_ETOOBIG
+    for pl in plans:
+        pl.close()
+
+
+def test_batch_empty_and_errors(G, tiny):
+    spec, s, p, o, qs, st, want = tiny
+    assert G.gsmat_join_batch(st, []) == ([], [])
+    plans, stat = G.gsmat_plan_batch(st, [[[-1, 0, -2]], [[-1, -1, -2]], [[-1, 0, -3]]],
+                                     raise_on_error=False)
+    assert stat == [0, G.GSMAT_EUNSUPPORTED, G.GSMAT_EINVAL]
+    assert plans[0] is not None and plans[1] is None and plans[2] is None
+    plans[0].close()
+
+
+# ------------------------------------------------------------------ shapes and random graphs
+SHAPES = [
+    ([[-1, 0, -2], [-2, 1, -3], [-3, 0, -1]], 3),      # triangle
+    ([[-1, 0, -1], [-1, 1, -2]], 2),                   # self loop + expansion
+    ([[-1, 2, -1]], 1),                                # self loop only (runs alone)
+    ([[-1, 0, -2], [-1, 0, -2], [-2, 1, -3]], 3),      # repeated pattern
+    ([[-1, 0, -2], [-3, 1, -4]], 4),                   # disconnected (runs alone)
+    ([[1, 0, 2]], 0),                                  # all constant
+    ([[1, 0, 2], [5, 1, 5]], 0),                       # all constant, false
+    ([[1, 0, -1], [-1, 1, -2]], 2),                    # constant subject chain
+    ([[-1, 0, 2], [-1, 1, -2], [-1, 2, -3]], 3),       # star with a constant object
+    ([[-1, 0, -2], [-2, 0, -1]], 2),                   # two-cycle
+    ([[-2, 0, -1], [-3, 1, -1], [-4, 2, -1]], 4),      # object star
+    ([[-1, 0, -2], [-2, 1, -3], [-1, 2, -3]], 3),      # filter with both ends bound
+    ([[-1, 0, 99], [-1, 1, -2]], 2),                   # absent constant
+    ([[-1, 7, -2]], 2),                                # absent predicate
+    ([[-1, 1, -2]], 2),                                # one pattern
+    ([[1, 0, -1], [-1, 1, 2]], 1),                     # constants at both ends of a chain
+]
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_batch_shapes(G, O, mode):
+    rng = np.random.default_rng(7)
+    V, P = 12, 3
+    s, p, o = (rng.integers(0, V, 150).astype(np.int32), rng.integers(0, P, 150).astype(np.int32),
+               rng.integers(0, V, 150).astype(np.int32))
+    s = np.concatenate([s, [1, 2, 3, 4]]).astype(np.int32)
+    p = np.concatenate([p, [0, 0, 0, 2]]).astype(np.int32)
+    o = np.concatenate([o, [2, 2, 3, 4]]).astype(np.int32)
+    st = _store(G, s, p, o, 100, 8)
+    print(f"[gpu] batch shapes mode={mode}", flush=True)
+    want = [O.join(s, p, o, t, nv) for t, nv in SHAPES]
+    _check_batch(G, st, [t for t, _ in SHAPES], mode, oracle_rows=want)
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_batch_random_graphs(G, O, seed):
+    rng = np.random.default_rng(900 + seed)
+    V = int(rng.integers(5, 3000))
+    P = int(rng.integers(1, 6))
+    n = int(rng.integers(10, 40000))
+    s, p, o = (rng.integers(0, V, n).astype(np.int32), rng.integers(0, P, n).astype(np.int32),
+               rng.integers(0, V, n).astype(np.int32))
+    st = _store(G, s, p, o, V, P, dense_div=int(rng.choice([1, 32, 10**6])))
+    queries, want = [], []
+    while len(queries) < 24:
+        ntp = int(rng.integers(1, 5))
+        nvars = int(rng.integers(1, 5))
+        tps = []
+        for _ in range(ntp):
+            def term():
+                return int(rng.integers(0, V)) if rng.random() < 0.25 else -int(rng.integers(0, nvars)) - 1
+            tps.append([term(), int(rng.integers(0, P)), term()])
+        used = sorted({-t - 1 for tp in tps for t in (tp[0], tp[2]) if t < 0})
+        remap = {x: i for i, x in enumerate(used)}
+        tps = [[(-remap[-a - 1] - 1) if a < 0 else a, b, (-remap[-c - 1] - 1) if c < 0 else c]
+               for a, b, c in tps]
+        try:
+            w = O.join(s, p, o, tps, len(used), cap_rows=3_000_000)
+        except ValueError:
+            continue  # too large for this test
+        queries.append(np.array(tps, np.int32))
+        want.append(w)
+    print(f"[gpu] batch random seed={seed} V={V} P={P} n={n}", flush=True)
+    for mode in (0, 1, 2):
+        _check_batch(G, st, queries, mode, oracle_rows=want)
+
+
+# ------------------------------------------------------------------ medium graph
+@pytest.mark.timeout(600)
+def test_batch_medium_workload(G, O):
+    """The medium graph's 64 BGPs (up to 1e7 rows) in one batch: identical to
+    the single-query join; the oracle's rows or row fingerprint."""
+    import workload as W
+    spec, (s, p, o), gi, qs = W.make_workload("medium")
+    gi.close()
+    st = _store(G, s, p, o, spec.V, spec.P)
+    ds = O.Dataset(s, p, o)
+    queries = [q.tps for q in qs]
+    plans, _ = G.gsmat_plan_batch(st, queries, G.PLAN_ADAPTIVE)
+    results, _ = G.gsmat_join_batch(st, plans, 64 * 2**30)
+    checked = 0
+    for i, (q, r) in enumerate(zip(qs, results)):
+        print(f"[gpu] batch medium q{i} rows={q.count}", flush=True)
+        got = G.gsmat_fetch_bindings(r)
+        assert len(got) == q.count
+        alone, _ = _single(G, st, q.tps, G.PLAN_ADAPTIVE, 64 * 2**30)
+        assert np.array_equal(got, alone), i
+        try:
+            if q.count <= 2 * 10**6:
+                assert np.array_equal(_sorted(got), ds.join(q.tps, q.n_vars, cap_rows=5 * 10**7))
+            else:
+                want = ds.join(q.tps, q.n_vars, cap_rows=5 * 10**7, fingerprint=True)
+                assert O.fingerprint_rows(got) == want
+            checked += 1
+        except ValueError:
+            pass  # the oracle's intermediate exceeded its cap; the count pins it
+        r.close()
+    for pl in plans:
+        pl.close()
+    assert checked >= 50
