@@ -1,8 +1,17 @@
-"""Benchmark: plain (one query at a time) sparse-matrix BGP joins on one MI355X.
+"""Benchmark: sparse-matrix BGP joins on one MI355X.
 
-One "step" is one pass of the query set through the hot path: for every BGP,
-gsmat_plan (statistics lookups + ordering) and gsmat_join (scan / intersect /
-count / prefix sum / allocate / write / chunk) on the device-resident store.
+Workload "batch" (the default): the 200M-triple graph with 4096 BGPs whose
+result sizes spread log-uniformly over 1..1e6 rows.  One "step" is one pass
+of all 4096 queries through the batched path (gsmat_plan_batch +
+gsmat_join_batch); the same queries are also run once one at a time
+(gsmat_plan + gsmat_join per query) for the plain figures, and a sample of
+results is compared row for row between the two.
+
+Workloads "tiny", "medium", "large": one step is one pass of the query set
+through the plain path: for every BGP, gsmat_plan (statistics lookups +
+ordering) and gsmat_join (scan / intersect / count / prefix sum / allocate /
+write / chunk).
+
 The store is built once before timing (load + build are reported apart, as
 the paper times queries only).  Results stay in HBM; fetching them to the host
 (PCIe) is measured separately on a sample and never enters `value`.
@@ -21,23 +30,38 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-PMC_SUMMARY = os.path.join(ROOT, "profiles", "write_expand_large_pmc.md")
-KERNELS_SRC = os.path.join(ROOT, "paper_1807_07691_amd", "csrc", "kernels.hip")
+CSRC = os.path.join(ROOT, "paper_1807_07691_amd", "csrc")
+# committed counter summaries: workload -> (file, kernel sources it depends on)
+PMC_SUMMARY = {
+    "large": ("write_expand_large_pmc.md", ["kernels.hip", "device.hpp"]),
+    "batch": ("write_batch_pmc.md", ["batch.hip", "device.hpp"]),
+}
+
+
+def source_hash(files):
+    import hashlib
+    h = hashlib.sha256()
+    for f in files:
+        h.update(open(os.path.join(CSRC, f), "rb").read())
+    return h.hexdigest()
 
 
 def counter_traffic(workload):
-    """HBM bytes per k_write_expand launch from the committed counter summary,
-    only if it was taken on this workload with the current kernel source."""
-    import hashlib
-    if workload != "large" or not os.path.exists(PMC_SUMMARY):
+    """HBM bytes per launch of the dominant write kernel from the committed
+    counter summary, only if it was taken on this workload with the current
+    kernel sources."""
+    if workload not in PMC_SUMMARY:
+        return None
+    name, files = PMC_SUMMARY[workload]
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
         return None
     vals = {}
-    for line in open(PMC_SUMMARY):
-        if ":" in line and line.split(":", 1)[0] in ("traffic_bytes_per_launch", "kernels_hip_sha256"):
+    for line in open(path):
+        if ":" in line and line.split(":", 1)[0] in ("traffic_bytes_per_launch", "sources_sha256"):
             k, v = line.split(":", 1)
             vals[k] = v.strip()
-    cur = hashlib.sha256(open(KERNELS_SRC, "rb").read()).hexdigest()
-    if vals.get("kernels_hip_sha256") != cur or "traffic_bytes_per_launch" not in vals:
+    if vals.get("sources_sha256") != source_hash(files) or "traffic_bytes_per_launch" not in vals:
         return None
     return int(vals["traffic_bytes_per_launch"])
 
@@ -72,7 +96,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="large", choices=["tiny", "medium", "large"])
+    ap.add_argument("--workload", default="batch", choices=["tiny", "medium", "large", "batch"])
     ap.add_argument("--budget-gb", type=float, default=64.0,
                     help="per-step output budget; larger steps are chunked")
     ap.add_argument("--plan-mode", type=int, default=2,
@@ -99,13 +123,16 @@ def main():
     torch.cuda.set_device(0)
     import paper_1807_07691_amd as G
 
-    spec, qspec = W.CONFIGS[args.workload]
+    batch = args.workload == "batch"
+    spec, qspec = W.CONFIGS["large" if batch else args.workload]
+    if batch:
+        qspec = W.BATCH
     t0 = time.perf_counter()
     log(f"generating graph {spec.name}: V={spec.V} P={spec.P} T={spec.T}")
     s, p, o = W.gen_graph(spec)
     log(f"graph done in {time.perf_counter() - t0:.1f}s; drawing queries")
     gi = W.GraphIndex(s, p, o, spec.V, spec.P)
-    queries = W.gen_queries(gi, spec, qspec)
+    queries = W.gen_batch_queries(gi, spec) if batch else W.gen_queries(gi, spec, qspec)
     gi.close()
     del gi
     if args.max_queries:
@@ -130,6 +157,12 @@ def main():
 
     budget = int(args.budget_gb * 2**30)
     mode = args.plan_mode
+    if batch:
+        out = bench_batch(args, G, W, spec, qspec, queries, st, sh, budget, mode, stats,
+                          load_s, build_s, s, p, o)
+        print(json.dumps(out), flush=True)
+        st.close()
+        return
 
     def run_pass(lat=None, counts=None):
         rows = 0
@@ -233,43 +266,7 @@ def main():
         r.close()
         pl.close()
 
-    cpu = None
-    if not args.no_cpu_baseline:
-        import oracle as O
-        log("cpu baseline: oracle on a bounded sample")
-        a = time.perf_counter()
-        ds = O.Dataset(s, p, o)
-        ds_s = time.perf_counter() - a
-        done = 0
-        capped = 0
-        rows = 0
-        spent = 0.0
-        for q in queries:
-            if q.count > 2 * 10**6:
-                continue
-            a = time.perf_counter()
-            try:
-                # the oracle joins in query order; an intermediate above the cap
-                # (host memory) marks the query as capped, its time still counts
-                n = ds.join(q.tps, q.n_vars, cap_rows=2 * 10**7, fingerprint=True)[0]
-            except ValueError:
-                n = None
-            spent += time.perf_counter() - a
-            if n is None:
-                capped += 1
-            else:
-                rows += n
-                done += 1
-            if spent > args.cpu_sample_s:
-                break
-        ds.close()
-        cpu = {"value": round(rows / spent, 1) if spent > 0 else None, "unit": "bindings/s",
-               "cores": 1, "kind": "oracle",
-               "sample": f"{done} of {len(queries)} queries (those with <= 2e6 rows, in order; "
-                         f"{capped} more stopped at a 2e7-row intermediate cap, time counted) "
-                         f"on the same graph; single-threaded hash/Cartesian join; triple-set "
-                         f"construction ({ds_s:.1f}s) excluded",
-               "cpu_model": cpu_model(), "host_threads": os.cpu_count()}
+    cpu = None if args.no_cpu_baseline else cpu_baseline(queries, s, p, o, args.cpu_sample_s)
 
     out = {
         "metric": "joined bindings/sec (plain one-query-at-a-time GPU join) + query p50/p99 latency",
@@ -317,6 +314,215 @@ def main():
         del a_, b_
     print(json.dumps(out), flush=True)
     st.close()
+
+
+def cpu_baseline(queries, s, p, o, sample_s):
+    """The oracle on a bounded sample of the queries (time counted per query)."""
+    import oracle as O
+    log("cpu baseline: oracle on a bounded sample")
+    a = time.perf_counter()
+    ds = O.Dataset(s, p, o)
+    ds_s = time.perf_counter() - a
+    done = capped = rows = 0
+    spent = 0.0
+    for q in queries:
+        if q.count > 2 * 10**6:
+            continue
+        a = time.perf_counter()
+        try:
+            # the oracle joins in query order; an intermediate above the cap
+            # (host memory) marks the query as capped, its time still counts
+            n = ds.join(q.tps, q.n_vars, cap_rows=2 * 10**7, fingerprint=True)[0]
+        except ValueError:
+            n = None
+        spent += time.perf_counter() - a
+        if n is None:
+            capped += 1
+        else:
+            rows += n
+            done += 1
+        if spent > sample_s:
+            break
+    ds.close()
+    return {"value": round(rows / spent, 1) if spent > 0 else None, "unit": "bindings/s",
+            "cores": 1, "kind": "oracle",
+            "sample": f"{done} of {len(queries)} queries (those with <= 2e6 rows, in order; "
+                      f"{capped} more stopped at a 2e7-row intermediate cap, time counted) "
+                      f"on the same graph; single-threaded hash/Cartesian join; triple-set "
+                      f"construction ({ds_s:.1f}s) excluded",
+            "cpu_model": cpu_model(), "host_threads": os.cpu_count()}
+
+
+def bench_batch(args, G, W, spec, qspec, queries, st, sh, budget, mode, stats, load_s, build_s,
+                s, p, o):
+    """Plain (one pass, per-query latency) vs batched (warmup + timed steps)."""
+    import numpy as np
+    import torch
+    nq = len(queries)
+    tps = [q.tps for q in queries]
+
+    # ---- plain: every query alone, in order (one untimed pass first)
+    G.gsmat_prof_enable(0)
+    for w in range(min(1, args.warmup)):
+        log(f"plain warmup pass over {nq} queries")
+        for q in queries:
+            pl = G.gsmat_plan(st, q.tps, mode, stream=sh)
+            G.gsmat_join(st, pl, budget, -1, stream=sh).close()
+            pl.close()
+    log(f"plain pass over {nq} queries")
+    torch.cuda.synchronize()
+    lat = []
+    plain_counts = []
+    t0 = time.perf_counter()
+    for q in queries:
+        a = time.perf_counter()
+        pl = G.gsmat_plan(st, q.tps, mode, stream=sh)
+        r = G.gsmat_join(st, pl, budget, -1, stream=sh)
+        lat.append(time.perf_counter() - a)
+        plain_counts.append(G.gsmat_result_info(r)["rows"])
+        r.close()
+        pl.close()
+    torch.cuda.synchronize()
+    plain_wall = time.perf_counter() - t0
+    plain_rows = sum(plain_counts)
+    done_at = np.cumsum(lat)  # completion times when all queries arrive together
+    log(f"plain: {plain_wall:.3f}s, {plain_rows} rows")
+
+    packed = G.pack_queries(tps)
+
+    def batch_pass(phase=None):
+        a = time.perf_counter()
+        plans, _ = G.gsmat_plan_batch(st, packed, mode, stream=sh, as_set=True)
+        b = time.perf_counter()
+        results, _ = G.gsmat_join_batch(st, plans, budget, -1, stream=sh, as_set=True)
+        c = time.perf_counter()
+        if phase is not None:
+            phase.append((b - a, c - b))
+        return plans, results
+
+    # ---- batched: warmup (diagnostics, count and row checks), then timed
+    log(f"batched warmup x{max(1, args.warmup)}")
+    G.gsmat_prof_enable(0x1F)
+    for w in range(max(1, args.warmup)):
+        plans, results = batch_pass()
+        if w == 0:
+            wprof = G.gsmat_prof_read()
+            whost = G.gsmat_prof_host()
+            batch_counts = results.rows().tolist()
+            sample = list(range(0, nq, max(1, nq // 64)))
+            same = 0
+            for i in sample:
+                pl = G.gsmat_plan(st, queries[i].tps, mode, stream=sh)
+                r = G.gsmat_join(st, pl, budget, -1, stream=sh)
+                same += int(np.array_equal(G.gsmat_fetch_bindings(results[i], stream=sh),
+                                           G.gsmat_fetch_bindings(r, stream=sh)))
+                r.close()
+                pl.close()
+        results.close()
+        plans.close()
+    G.gsmat_prof_enable(0)
+    log(f"  warmup host: {whost}")
+    for k_, v_ in wprof.items():
+        log(f"  warmup class {k_:8s}: {v_['launches']:6d} launches {v_['ms']:10.2f} ms "
+            f"{v_['bytes'] / 1e9:10.2f} GB alg")
+    want = [q.count for q in queries]
+    ok_plain = sum(int(a == b) for a, b in zip(want, plain_counts))
+    ok_batch = sum(int(a == b) for a, b in zip(want, batch_counts))
+    log(f"count check vs the workload's independent tree counts: plain {ok_plain}/{nq}, "
+        f"batched {ok_batch}/{nq}; rows identical to the plain join on {same}/{len(sample)} "
+        f"sampled queries")
+
+    torch.cuda.synchronize()
+    G.gsmat_prof_enable(1 << G.K_WRITE)
+    step_s = []
+    phase = []
+    total_rows = 0
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        a = time.perf_counter()
+        h0 = G.gsmat_prof_host()
+        plans, results = batch_pass(phase)
+        total_rows += int(results.rows().sum())
+        results.close()
+        plans.close()
+        step_s.append(time.perf_counter() - a)
+        h1 = G.gsmat_prof_host()
+        log(f"step {k + 1}/{args.steps}: {step_s[-1] * 1e3:.1f} ms (plan {phase[-1][0] * 1e3:.1f}, "
+            f"join {phase[-1][1] * 1e3:.1f}; host alloc {h1['alloc_ms'] - h0['alloc_ms']:.1f} ms "
+            f"in {h1['allocs'] - h0['allocs']}, sync {h1['sync_ms'] - h0['sync_ms']:.1f} ms "
+            f"in {h1['syncs'] - h0['syncs']})")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    total_cells = sum(q.count * q.n_vars for q in queries) * args.steps
+    prof = G.gsmat_prof_read()
+    G.gsmat_prof_enable(0)
+    value = total_rows / wall
+    wr = prof["write"]
+    achieved = (wr["bytes"] / (wr["ms"] / 1e3) / 1e9) if wr["ms"] > 0 else 0.0
+    roofline = {
+        "bound": "hbm",
+        "achieved": round(achieved, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": counter_traffic("batch"),
+        "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+        "kernel": "k_b_write (batched expansion write, all column counts)",
+        "launches": wr["launches"],
+        "avg_launch_ms": round(wr["ms"] / max(1, wr["launches"]), 4),
+        "alg_bytes_per_launch": round(wr["bytes"] / max(1, wr["launches"]), 1),
+    }
+    cpu = None if args.no_cpu_baseline else cpu_baseline(queries, s, p, o, args.cpu_sample_s)
+    ms = lambda x: round(x * 1e3, 3)  # noqa: E731
+    return {
+        "metric": "joined bindings/sec + query p50/p99 latency, batched vs plain, bit-exact",
+        "value": round(value, 1),
+        "unit": "bindings/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"batch: {spec.V} vertices, {spec.P} predicates Zipf({spec.zipf_s}), "
+                        f"{spec.T} triples; {nq} random-walk BGPs of 1-6 patterns, result "
+                        f"sizes log-uniform over 1..1e6 rows",
+            "mode": "batched (gsmat_plan_batch + gsmat_join_batch over all queries per step)",
+            "plan_mode": mode,
+            "budget_bytes": budget,
+            "parallelism": "single-gpu",
+        },
+        # every query of a step is submitted together and completes with the batch
+        "p50_ms": ms(percentile(step_s, 0.5)),
+        "p99_ms": ms(percentile(step_s, 0.99)),
+        "plan_batch_ms": ms(sum(x for x, _ in phase) / len(phase)),
+        "join_batch_ms": ms(sum(y for _, y in phase) / len(phase)),
+        "plain": {
+            "value": round(plain_rows / plain_wall, 1),
+            "unit": "bindings/s",
+            "pass_ms": ms(plain_wall),
+            "service_p50_ms": ms(percentile(lat, 0.5)),
+            "service_p99_ms": ms(percentile(lat, 0.99)),
+            "completion_p50_ms": ms(percentile(list(done_at), 0.5)),
+            "completion_p99_ms": ms(percentile(list(done_at), 0.99)),
+        },
+        "speedup_vs_plain": round(value / (plain_rows / plain_wall), 2),
+        "latency_note": "all queries of a pass arrive at once; batched latency = the pass; "
+                        "plain completion = cumulative service time in query order",
+        "cells_per_s": round(total_cells / wall, 1),
+        "rows_per_step": total_rows // max(1, args.steps),
+        "count_check": f"plain {ok_plain}/{nq}, batched {ok_batch}/{nq}",
+        "bitexact_check": f"{same}/{len(sample)} sampled queries: batched rows == plain rows",
+        "load_s": round(load_s, 3),
+        "build_s": round(build_s, 3),
+        "index_bytes": stats["device_bytes"],
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
 
 
 if __name__ == "__main__":

@@ -212,6 +212,15 @@ gsmat_status gsmat_join_batch(gsmat_store* st, const gsmat_query_plan* const* pl
                               int32_t n_plans, int64_t budget_bytes, int64_t max_rows,
                               void* stream, gsmat_result** out, gsmat_status* status);
 
+/* Frees n plans (NULL entries are skipped) and sets every entry to NULL. */
+void gsmat_plan_free_many(gsmat_query_plan** plans, int32_t n);
+
+/* Frees n results (NULL entries are skipped) and sets every entry to NULL. */
+void gsmat_result_free_many(gsmat_result** results, int32_t n);
+
+/* rows[i] = row count of results[i], or -1 for a NULL entry. */
+gsmat_status gsmat_result_rows_many(const gsmat_result* const* results, int32_t n, int64_t* rows);
+
 /* Result shape; per-step rows in/out (arrays of n_steps entries, may be NULL)
  * are summed over chunks. */
 gsmat_status gsmat_result_info(const gsmat_result* r, int64_t* n_rows, int32_t* n_vars,

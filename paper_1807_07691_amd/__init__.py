@@ -35,7 +35,8 @@ EXPORTED = [
     "gsmat_plan_info", "gsmat_plan_free", "gsmat_join", "gsmat_result_info",
     "gsmat_fetch_bindings", "gsmat_result_free", "gsmat_last_error", "gsmat_prof_enable",
     "gsmat_prof_read", "gsmat_prof_host", "gsmat_release_pools", "gsmat_plan_batch",
-    "gsmat_join_batch",
+    "gsmat_join_batch", "gsmat_plan_free_many", "gsmat_result_free_many",
+    "gsmat_result_rows_many",
 ]
 
 
@@ -112,6 +113,12 @@ def _load():
     L.gsmat_plan_batch.argtypes = [vp, vp, vp, i32, i32, vp, vp, vp]
     L.gsmat_join_batch.restype = i32
     L.gsmat_join_batch.argtypes = [vp, vp, i32, i64, i64, vp, vp, vp]
+    L.gsmat_plan_free_many.restype = None
+    L.gsmat_plan_free_many.argtypes = [vp, i32]
+    L.gsmat_result_free_many.restype = None
+    L.gsmat_result_free_many.argtypes = [vp, i32]
+    L.gsmat_result_rows_many.restype = i32
+    L.gsmat_result_rows_many.argtypes = [vp, i32, vp]
     return L
 
 
@@ -315,47 +322,123 @@ def gsmat_join(store, plan, budget_bytes=0, max_rows=-1, stream=None):
     return Result(h, store)
 
 
-def gsmat_plan_batch(store, queries, mode=PLAN_DEFAULT, stream=None, raise_on_error=True):
-    """Plans of several BGPs (a list of (n, 3) pattern arrays) with one device
-    round trip.  Returns (plans, statuses); a rejected query's plan is None.
-    With raise_on_error, the first failure raises after freeing the rest."""
-    nq = len(queries)
+class _Handle:
+    """A borrowed handle (owned by a PlanSet or ResultSet)."""
+
+    def __init__(self, h, owner):
+        self.h = h
+        self.owner = owner
+
+
+class PlanSet:
+    """n plans held in one handle array (one call frees them all)."""
+
+    def __init__(self, arr, n):
+        self.arr = arr
+        self.n = n
+        _live_plans.add(self)
+
+    def __len__(self):
+        return self.n
+
+    def __getitem__(self, i):
+        h = self.arr[i]
+        return _Handle(ctypes.c_void_p(h), self) if h else None
+
+    def close(self):
+        if self.arr is not None:
+            _lib.gsmat_plan_free_many(self.arr, self.n)
+            self.arr = None
+
+    def __del__(self):
+        self.close()
+
+
+class ResultSet:
+    """n results held in one handle array (one call frees them all)."""
+
+    def __init__(self, arr, n, store):
+        self.arr = arr
+        self.n = n
+        self.store = store
+        _live_results.add(self)
+
+    def __len__(self):
+        return self.n
+
+    def __getitem__(self, i):
+        h = self.arr[i]
+        return _Handle(ctypes.c_void_p(h), self) if h else None
+
+    def rows(self):
+        out = np.zeros(max(self.n, 1), np.int64)
+        _check(_lib.gsmat_result_rows_many(self.arr, self.n, _p(out)))
+        return out[: self.n]
+
+    def close(self):
+        if self.arr is not None:
+            _lib.gsmat_result_free_many(self.arr, self.n)
+            self.arr = None
+
+    def __del__(self):
+        self.close()
+
+
+def pack_queries(queries):
+    """(flat (N, 3) int32 patterns, per-query pattern counts) for gsmat_plan_batch."""
     ts = [np.asarray(t, dtype=np.int32).reshape(-1, 3) for t in queries]
     n_pats = np.array([len(t) for t in ts], np.int32)
-    flat = np.ascontiguousarray(np.concatenate(ts) if nq else np.zeros((0, 3), np.int32))
+    flat = np.ascontiguousarray(np.concatenate(ts) if ts else np.zeros((0, 3), np.int32))
+    return flat, n_pats
+
+
+def gsmat_plan_batch(store, queries, mode=PLAN_DEFAULT, stream=None, raise_on_error=True,
+                     as_set=False):
+    """Plans of several BGPs with one device round trip.  queries: a list of
+    (n, 3) pattern arrays, or the (flat, n_pats) pair of pack_queries.
+    Returns (plans, statuses): a list of Plan (None where a query was
+    rejected), or with as_set one PlanSet.  With raise_on_error, the first
+    failure raises after freeing the rest."""
+    flat, n_pats = queries if isinstance(queries, tuple) else pack_queries(queries)
+    nq = len(n_pats)
     hs = (ctypes.c_void_p * max(nq, 1))()
     st = np.zeros(max(nq, 1), np.int32)
     rc = _lib.gsmat_plan_batch(store.h, _p(flat), _p(n_pats), nq, mode, _stream(stream), hs,
                                _p(st))
     msg = _lib.gsmat_last_error().decode(errors="replace") if rc != GSMAT_OK else ""
-    plans = [Plan(ctypes.c_void_p(hs[i])) if hs[i] else None for i in range(nq)]
     if rc != GSMAT_OK and raise_on_error:
-        for pl in plans:
-            if pl is not None:
-                pl.close()
+        _lib.gsmat_plan_free_many(hs, nq)
         raise GsmatError(rc, msg)
-    return plans, [int(x) for x in st[:nq]]
+    statuses = st[:nq].tolist()
+    if as_set:
+        return PlanSet(hs, nq), statuses
+    return [Plan(ctypes.c_void_p(hs[i])) if hs[i] else None for i in range(nq)], statuses
 
 
 def gsmat_join_batch(store, plans, budget_bytes=0, max_rows=-1, stream=None,
-                     raise_on_error=True):
-    """Evaluates several plans together.  Returns (results, statuses); a failed
-    query's result is None.  With raise_on_error, the first failure raises
-    after freeing the rest."""
-    nq = len(plans)
-    ph = (ctypes.c_void_p * max(nq, 1))(*[pl.h for pl in plans])
+                     raise_on_error=True, as_set=False):
+    """Evaluates several plans (a list of Plan, or a PlanSet) together.  Returns
+    (results, statuses): a list of Result (None where a query failed), or with
+    as_set one ResultSet.  With raise_on_error, the first failure raises after
+    freeing the rest."""
+    if isinstance(plans, PlanSet):
+        nq = plans.n
+        ph = plans.arr
+    else:
+        nq = len(plans)
+        ph = (ctypes.c_void_p * max(nq, 1))(*[pl.h for pl in plans])
     hs = (ctypes.c_void_p * max(nq, 1))()
     st = np.zeros(max(nq, 1), np.int32)
     rc = _lib.gsmat_join_batch(store.h, ph, nq, budget_bytes, max_rows, _stream(stream), hs,
                                _p(st))
     msg = _lib.gsmat_last_error().decode(errors="replace") if rc != GSMAT_OK else ""
-    results = [Result(ctypes.c_void_p(hs[i]), store) if hs[i] else None for i in range(nq)]
     if rc != GSMAT_OK and raise_on_error:
-        for r in results:
-            if r is not None:
-                r.close()
+        _lib.gsmat_result_free_many(hs, nq)
         raise GsmatError(rc, msg)
-    return results, [int(x) for x in st[:nq]]
+    statuses = st[:nq].tolist()
+    if as_set:
+        return ResultSet(hs, nq, store), statuses
+    return [Result(ctypes.c_void_p(hs[i]), store) if hs[i] else None for i in range(nq)], statuses
 
 
 def gsmat_result_info(result):

@@ -1044,3 +1044,29 @@ extern "C" gsmat_status gsmat_plan_batch(const gsmat_store* st, const gsmat_patt
     return GSMAT_OK;
   });
 }
+
+extern "C" void gsmat_plan_free_many(gsmat_query_plan** plans, int32_t n) {
+  if (!plans) return;
+  for (int32_t i = 0; i < n; ++i) {
+    delete plans[i];
+    plans[i] = nullptr;
+  }
+}
+
+extern "C" void gsmat_result_free_many(gsmat_result** results, int32_t n) {
+  if (!results) return;
+  for (int32_t i = 0; i < n; ++i) {
+    delete results[i];
+    results[i] = nullptr;
+  }
+}
+
+extern "C" gsmat_status gsmat_result_rows_many(const gsmat_result* const* results, int32_t n,
+                                               int64_t* rows) {
+  return guarded([&]() -> gsmat_status {
+    if (n < 0) throw StatusFail{GSMAT_EINVAL, "negative count"};
+    if (n > 0 && (!results || !rows)) throw StatusFail{GSMAT_EINVAL, "results or rows is NULL"};
+    for (int32_t i = 0; i < n; ++i) rows[i] = results[i] ? results[i]->rows : -1;
+    return GSMAT_OK;
+  });
+}
