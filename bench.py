@@ -104,6 +104,8 @@ def main():
     ap.add_argument("--max-queries", type=int, default=0, help="0 = all")
     ap.add_argument("--cpu-sample-s", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="batch workload: skip the plain one-query-at-a-time comparison")
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
                     help="after the run, copy a buffer of this size device-to-device 3 times "
                          "(a plain copy kernel of known size for counter calibration)")
@@ -160,6 +162,7 @@ def main():
     if batch:
         out = bench_batch(args, G, W, spec, qspec, queries, st, sh, budget, mode, stats,
                           load_s, build_s, s, p, o)
+        calib_copy(args, out)
         print(json.dumps(out), flush=True)
         st.close()
         return
@@ -303,17 +306,24 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
-    if args.calib_copy_gib > 0:
-        n = int(args.calib_copy_gib * 2**30) // 4
-        a_ = torch.empty(n, dtype=torch.int32, device="cuda").fill_(1)
-        b_ = torch.empty_like(a_)
-        for _ in range(3):
-            b_.copy_(a_)
-        torch.cuda.synchronize()
-        out["calib_copy_bytes"] = n * 4
-        del a_, b_
+    calib_copy(args, out)
     print(json.dumps(out), flush=True)
     st.close()
+
+
+def calib_copy(args, out):
+    """A plain device copy of known size after the run (counter calibration)."""
+    if args.calib_copy_gib <= 0:
+        return
+    import torch
+    n = int(args.calib_copy_gib * 2**30) // 4
+    a_ = torch.empty(n, dtype=torch.int32, device="cuda").fill_(1)
+    b_ = torch.empty_like(a_)
+    for _ in range(3):
+        b_.copy_(a_)
+    torch.cuda.synchronize()
+    out["calib_copy_bytes"] = n * 4
+    del a_, b_
 
 
 def cpu_baseline(queries, s, p, o, sample_s):
@@ -362,31 +372,32 @@ def bench_batch(args, G, W, spec, qspec, queries, st, sh, budget, mode, stats, l
     tps = [q.tps for q in queries]
 
     # ---- plain: every query alone, in order (one untimed pass first)
+    lat = []
+    plain_counts = []
+    plain_wall = None
     G.gsmat_prof_enable(0)
-    for w in range(min(1, args.warmup)):
+    for w in range(0 if args.no_plain else min(1, args.warmup)):
         log(f"plain warmup pass over {nq} queries")
         for q in queries:
             pl = G.gsmat_plan(st, q.tps, mode, stream=sh)
             G.gsmat_join(st, pl, budget, -1, stream=sh).close()
             pl.close()
-    log(f"plain pass over {nq} queries")
-    torch.cuda.synchronize()
-    lat = []
-    plain_counts = []
-    t0 = time.perf_counter()
-    for q in queries:
-        a = time.perf_counter()
-        pl = G.gsmat_plan(st, q.tps, mode, stream=sh)
-        r = G.gsmat_join(st, pl, budget, -1, stream=sh)
-        lat.append(time.perf_counter() - a)
-        plain_counts.append(G.gsmat_result_info(r)["rows"])
-        r.close()
-        pl.close()
-    torch.cuda.synchronize()
-    plain_wall = time.perf_counter() - t0
-    plain_rows = sum(plain_counts)
+    if not args.no_plain:
+        log(f"plain pass over {nq} queries")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for q in queries:
+            a = time.perf_counter()
+            pl = G.gsmat_plan(st, q.tps, mode, stream=sh)
+            r = G.gsmat_join(st, pl, budget, -1, stream=sh)
+            lat.append(time.perf_counter() - a)
+            plain_counts.append(G.gsmat_result_info(r)["rows"])
+            r.close()
+            pl.close()
+        torch.cuda.synchronize()
+        plain_wall = time.perf_counter() - t0
+        log(f"plain: {plain_wall:.3f}s, {sum(plain_counts)} rows")
     done_at = np.cumsum(lat)  # completion times when all queries arrive together
-    log(f"plain: {plain_wall:.3f}s, {plain_rows} rows")
 
     packed = G.pack_queries(tps)
 
@@ -409,7 +420,7 @@ def bench_batch(args, G, W, spec, qspec, queries, st, sh, budget, mode, stats, l
             wprof = G.gsmat_prof_read()
             whost = G.gsmat_prof_host()
             batch_counts = results.rows().tolist()
-            sample = list(range(0, nq, max(1, nq // 64)))
+            sample = [] if args.no_plain else list(range(0, nq, max(1, nq // 64)))
             same = 0
             for i in sample:
                 pl = G.gsmat_plan(st, queries[i].tps, mode, stream=sh)
@@ -426,7 +437,7 @@ def bench_batch(args, G, W, spec, qspec, queries, st, sh, budget, mode, stats, l
         log(f"  warmup class {k_:8s}: {v_['launches']:6d} launches {v_['ms']:10.2f} ms "
             f"{v_['bytes'] / 1e9:10.2f} GB alg")
     want = [q.count for q in queries]
-    ok_plain = sum(int(a == b) for a, b in zip(want, plain_counts))
+    ok_plain = sum(int(a == b) for a, b in zip(want, plain_counts)) if plain_counts else None
     ok_batch = sum(int(a == b) for a, b in zip(want, batch_counts))
     log(f"count check vs the workload's independent tree counts: plain {ok_plain}/{nq}, "
         f"batched {ok_batch}/{nq}; rows identical to the plain join on {same}/{len(sample)} "
@@ -501,8 +512,8 @@ def bench_batch(args, G, W, spec, qspec, queries, st, sh, budget, mode, stats, l
         "p99_ms": ms(percentile(step_s, 0.99)),
         "plan_batch_ms": ms(sum(x for x, _ in phase) / len(phase)),
         "join_batch_ms": ms(sum(y for _, y in phase) / len(phase)),
-        "plain": {
-            "value": round(plain_rows / plain_wall, 1),
+        "plain": None if plain_wall is None else {
+            "value": round(sum(plain_counts) / plain_wall, 1),
             "unit": "bindings/s",
             "pass_ms": ms(plain_wall),
             "service_p50_ms": ms(percentile(lat, 0.5)),
@@ -510,12 +521,14 @@ def bench_batch(args, G, W, spec, qspec, queries, st, sh, budget, mode, stats, l
             "completion_p50_ms": ms(percentile(list(done_at), 0.5)),
             "completion_p99_ms": ms(percentile(list(done_at), 0.99)),
         },
-        "speedup_vs_plain": round(value / (plain_rows / plain_wall), 2),
+        "speedup_vs_plain": None if plain_wall is None else
+        round(value / (sum(plain_counts) / plain_wall), 2),
         "latency_note": "all queries of a pass arrive at once; batched latency = the pass; "
                         "plain completion = cumulative service time in query order",
         "cells_per_s": round(total_cells / wall, 1),
         "rows_per_step": total_rows // max(1, args.steps),
-        "count_check": f"plain {ok_plain}/{nq}, batched {ok_batch}/{nq}",
+        "count_check": f"plain {ok_plain}/{nq}, batched {ok_batch}/{nq}" if ok_plain is not None
+        else f"batched {ok_batch}/{nq}",
         "bitexact_check": f"{same}/{len(sample)} sampled queries: batched rows == plain rows",
         "load_s": round(load_s, 3),
         "build_s": round(build_s, 3),

@@ -91,14 +91,10 @@ __device__ inline int find_item(const GItem* __restrict__ g, int n, int64_t b) {
 }
 
 __global__ void k_lookup_many(const LookupReq* __restrict__ req, int32_t n, const PredDesc* dout,
-                              const PredDesc* din, const int32_t* keys_out, const int32_t* ptr_out,
-                              const int32_t* nbr_out, const int32_t* dense_out,
-                              const int32_t* keys_in, const int32_t* ptr_in, const int32_t* nbr_in,
-                              const int32_t* dense_in, LookupRes* res) {
+                              const PredDesc* din, OriPtrs out, OriPtrs in, LookupRes* res) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  res[i] = lookup_one(req[i], dout, din, keys_out, ptr_out, nbr_out, dense_out, keys_in, ptr_in,
-                      nbr_in, dense_in);
+  res[i] = lookup_one(req[i], dout, din, out, in);
 }
 
 __global__ __launch_bounds__(kBlock) void k_b_sample(const SCand* __restrict__ c,
@@ -314,9 +310,8 @@ std::vector<LookupRes> lookup_many(const gsmat_store* st, const std::vector<Look
   GS_BLAUNCH(GSMAT_K_OTHER, 32.0 * n,
              hipLaunchKernelGGL(k_lookup_many, dim3((unsigned)ceil_div((int64_t)n, kBlock)),
                                 dim3(kBlock), 0, s, (const LookupReq*)(dev + o_req), (int32_t)n,
-                                st->out.d_desc, st->in.d_desc, st->out.keys, st->out.ptr,
-                                st->out.nbr, st->out.dense, st->in.keys, st->in.ptr, st->in.nbr,
-                                st->in.dense, hres));
+                                st->out.d_desc, st->in.d_desc, st->out.ptrs(), st->in.ptrs(),
+                                hres));
   host_sync(s);
   std::memcpy(out.data(), hres, sizeof(LookupRes) * n);
   return out;

@@ -33,14 +33,29 @@ struct OutSet {
 //   nbr[nnz]      members, ascending within a row
 //   src[nnz]      row id of each member (row-compressed orientation only)
 //   dense[V + 1]  optional: ptr value of the first row >= v, for every vertex v
+//   dir[nb + 1]   optional (predicates without dense): index of the first row
+//                 whose id is >= b << dir_shift, for every bucket b of ids
 struct PredView {
   const int32_t* keys;
   const int32_t* ptr;
   const int32_t* nbr;
   const int32_t* src;
   const int32_t* dense;
+  const int32_t* dir;
   int32_t nr;
   int32_t nnz;
+  int32_t dir_shift;
+  int32_t pad;
+};
+
+// Global arrays of one orientation (the per-predicate views are offsets into
+// them, given by the orientation's PredDesc table).
+struct OriPtrs {
+  const int32_t* keys;
+  const int32_t* ptr;
+  const int32_t* nbr;
+  const int32_t* dense;
+  const int32_t* dir;
 };
 
 // Host record of one predicate in one orientation (offsets into the global
@@ -52,6 +67,9 @@ struct PredDesc {
   int64_t dense_base = -1; // first entry in dense, -1 if none
   int64_t nnz = 0;
   int64_t nr = 0;
+  int64_t dir_base = -1;   // first entry in dir, -1 if none
+  int32_t dir_shift = 0;   // bucket b holds ids [b << dir_shift, (b + 1) << dir_shift)
+  int32_t pad = 0;
 };
 
 // A list taking part in a star-centre intersection: either a predicate's
@@ -105,6 +123,7 @@ struct LookupRes {
 };
 
 constexpr int kSampleBlocks = 8;  // workgroups per fan-out sample of one candidate
+constexpr int64_t kDirKeys = 4;   // target rows per bucket of a row directory
 
 // -------------------------------------------------------------------------
 // device memory
@@ -217,14 +236,13 @@ void launch_fill_rows(const uint64_t* k, const int64_t* row_pos, int64_t R, int 
                       hipStream_t s);
 void launch_fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t s);
 void launch_dense_ptr(PredView pv, int64_t V, int32_t* dense, hipStream_t s);
+// dir[b] = first row index with id >= b << shift, for b in [0, nb]
+void launch_row_dir(PredView pv, int32_t shift, int64_t nb, int32_t* dir, hipStream_t s);
 void launch_ptr_sentinels(const PredDesc* d, int32_t P, int32_t* ptr, hipStream_t s);
 
 // lookups (planner statistics, constant scans)
 void launch_lookup(const LookupBatch& b, const PredDesc* desc_out, const PredDesc* desc_in,
-                   const int32_t* keys_out, const int32_t* ptr_out, const int32_t* nbr_out,
-                   const int32_t* dense_out, const int32_t* keys_in, const int32_t* ptr_in,
-                   const int32_t* nbr_in, const int32_t* dense_in, LookupRes* res,
-                   hipStream_t s);
+                   OriPtrs out, OriPtrs in, LookupRes* res, hipStream_t s);
 
 // join steps
 void launch_count_expand(const int32_t* col, int64_t n, PredView pv, int32_t* N, int32_t* start,

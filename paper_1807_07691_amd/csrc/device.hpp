@@ -88,7 +88,14 @@ __device__ inline void row_lookup(const PredView& pv, int32_t v, int32_t& start,
     len = pv.dense[v + 1] - start;
     return;
   }
-  const int32_t r = lower_bound_i32(pv.keys, pv.nr, v);
+  // the bucket directory narrows the search to a few neighbouring keys
+  int32_t lo = 0, n = pv.nr;
+  if (pv.dir) {
+    const int32_t b = v >> pv.dir_shift;
+    lo = pv.dir[b];
+    n = pv.dir[b + 1] - lo;
+  }
+  const int32_t r = lo + lower_bound_i32(pv.keys + lo, n, v);
   if (r < pv.nr && pv.keys[r] == v) {
     start = pv.ptr[r];
     len = pv.ptr[r + 1] - start;
@@ -131,15 +138,18 @@ __device__ inline void compact_tile(int64_t tile, int64_t n, int64_t base, Keep 
 }
 
 __device__ inline PredView view_of(const PredDesc& d, const int32_t* keys, const int32_t* ptr,
-                                   const int32_t* nbr, const int32_t* dense) {
+                                   const int32_t* nbr, const int32_t* dense, const int32_t* dir) {
   PredView pv;
   pv.keys = keys + d.row_base;
   pv.ptr = ptr + d.ptr_base;
   pv.nbr = nbr + d.nbr_base;
   pv.src = nullptr;
   pv.dense = d.dense_base >= 0 ? dense + d.dense_base : nullptr;
+  pv.dir = d.dir_base >= 0 ? dir + d.dir_base : nullptr;
   pv.nr = (int32_t)d.nr;
   pv.nnz = (int32_t)d.nnz;
+  pv.dir_shift = d.dir_shift;
+  pv.pad = 0;
   return pv;
 }
 
@@ -156,14 +166,11 @@ struct OutStrided {  // columns at a fixed stride from one base
 
 // One lookup request against the two orientations' descriptor tables.
 __device__ inline LookupRes lookup_one(const LookupReq& q, const PredDesc* dout,
-                                       const PredDesc* din, const int32_t* keys_out,
-                                       const int32_t* ptr_out, const int32_t* nbr_out,
-                                       const int32_t* dense_out, const int32_t* keys_in,
-                                       const int32_t* ptr_in, const int32_t* nbr_in,
-                                       const int32_t* dense_in) {
+                                       const PredDesc* din, const OriPtrs& out,
+                                       const OriPtrs& in) {
   const PredView pv = q.orient == 0
-                          ? view_of(dout[q.pred], keys_out, ptr_out, nbr_out, dense_out)
-                          : view_of(din[q.pred], keys_in, ptr_in, nbr_in, dense_in);
+                          ? view_of(dout[q.pred], out.keys, out.ptr, out.nbr, out.dense, out.dir)
+                          : view_of(din[q.pred], in.keys, in.ptr, in.nbr, in.dense, in.dir);
   LookupRes r;
   row_lookup(pv, q.v, r.start, r.len);
   r.found = (q.member >= 0 && r.len > 0) ? (seg_contains(pv.nbr + r.start, r.len, q.member) ? 1 : 0)

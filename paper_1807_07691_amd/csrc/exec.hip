@@ -127,8 +127,7 @@ struct Exec {
     b.req[0] = LookupReq{orient, p, v, member};
     b.n = 1;
     PinnedArea* h = pinned();
-    launch_lookup(b, st->out.d_desc, st->in.d_desc, st->out.keys, st->out.ptr, st->out.nbr,
-                  st->out.dense, st->in.keys, st->in.ptr, st->in.nbr, st->in.dense, h->res, s);
+    launch_lookup(b, st->out.d_desc, st->in.d_desc, st->out.ptrs(), st->in.ptrs(), h->res, s);
     host_sync(s);
     return h->res[0];
   }
@@ -634,8 +633,7 @@ std::vector<TpStat> pattern_stats(const gsmat_store* st, const gsmat_pattern* pa
     for (size_t i = 0; i < reqs.size(); ++i) b.req[i] = reqs[i];
     b.n = (int32_t)reqs.size();
     PinnedArea* h = pinned();
-    launch_lookup(b, st->out.d_desc, st->in.d_desc, st->out.keys, st->out.ptr, st->out.nbr,
-                  st->out.dense, st->in.keys, st->in.ptr, st->in.nbr, st->in.dense, h->res, s);
+    launch_lookup(b, st->out.d_desc, st->in.d_desc, st->out.ptrs(), st->in.ptrs(), h->res, s);
     host_sync(s);
     std::vector<LookupRes> res(h->res, h->res + reqs.size());
     for (int i = 0; i < n; ++i) {

@@ -238,19 +238,24 @@ __global__ void k_dense_ptr(PredView pv, int64_t V, int32_t* __restrict__ dense)
   }
 }
 
+__global__ void k_row_dir(PredView pv, int32_t shift, int64_t nb, int32_t* __restrict__ dir) {
+  for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b <= nb;
+       b += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t v = b << shift;
+    dir[b] = v >= (int64_t)INT32_MAX ? pv.nr : lower_bound_i32(pv.keys, pv.nr, (int32_t)v);
+  }
+}
+
 __global__ void k_ptr_sentinels(const PredDesc* __restrict__ d, int32_t P, int32_t* __restrict__ ptr) {
   const int32_t p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p < P) ptr[d[p].ptr_base + d[p].nr] = (int32_t)d[p].nnz;
 }
 
-__global__ void k_lookup(LookupBatch b, const PredDesc* dout, const PredDesc* din,
-                         const int32_t* keys_out, const int32_t* ptr_out, const int32_t* nbr_out,
-                         const int32_t* dense_out, const int32_t* keys_in, const int32_t* ptr_in,
-                         const int32_t* nbr_in, const int32_t* dense_in, LookupRes* res) {
+__global__ void k_lookup(LookupBatch b, const PredDesc* dout, const PredDesc* din, OriPtrs out,
+                         OriPtrs in, LookupRes* res) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= b.n) return;
-  res[i] = lookup_one(b.req[i], dout, din, keys_out, ptr_out, nbr_out, dense_out, keys_in, ptr_in,
-                      nbr_in, dense_in);
+  res[i] = lookup_one(b.req[i], dout, din, out, in);
 }
 
 // ---------------------------------------------------------------- join steps
@@ -509,6 +514,12 @@ void launch_dense_ptr(PredView pv, int64_t V, int32_t* dense, hipStream_t s) {
                                dense));
 }
 
+void launch_row_dir(PredView pv, int32_t shift, int64_t nb, int32_t* dir, hipStream_t s) {
+  GS_LAUNCH(GSMAT_K_OTHER, 4.0 * (nb + 1),
+            hipLaunchKernelGGL(k_row_dir, dim3(grid_for(nb + 1)), dim3(kBlock), 0, s, pv, shift, nb,
+                               dir));
+}
+
 void launch_ptr_sentinels(const PredDesc* d, int32_t P, int32_t* ptr, hipStream_t s) {
   if (P <= 0) return;
   GS_LAUNCH(GSMAT_K_OTHER, 0.0,
@@ -517,14 +528,10 @@ void launch_ptr_sentinels(const PredDesc* d, int32_t P, int32_t* ptr, hipStream_
 }
 
 void launch_lookup(const LookupBatch& b, const PredDesc* desc_out, const PredDesc* desc_in,
-                   const int32_t* keys_out, const int32_t* ptr_out, const int32_t* nbr_out,
-                   const int32_t* dense_out, const int32_t* keys_in, const int32_t* ptr_in,
-                   const int32_t* nbr_in, const int32_t* dense_in, LookupRes* res,
-                   hipStream_t s) {
+                   OriPtrs out, OriPtrs in, LookupRes* res, hipStream_t s) {
   if (b.n <= 0) return;
   GS_LAUNCH(GSMAT_K_OTHER, 32.0 * b.n,
-            hipLaunchKernelGGL(k_lookup, dim3(1), dim3(64), 0, s, b, desc_out, desc_in, keys_out,
-                               ptr_out, nbr_out, dense_out, keys_in, ptr_in, nbr_in, dense_in,
+            hipLaunchKernelGGL(k_lookup, dim3(1), dim3(64), 0, s, b, desc_out, desc_in, out, in,
                                res));
 }
 

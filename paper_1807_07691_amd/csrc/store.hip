@@ -60,8 +60,11 @@ PredView Orientation::view(int32_t p) const {
   v.nbr = nbr + d.nbr_base;
   v.src = src ? src + d.nbr_base : nullptr;
   v.dense = d.dense_base >= 0 ? dense + d.dense_base : nullptr;
+  v.dir = d.dir_base >= 0 ? dir + d.dir_base : nullptr;
   v.nr = (int32_t)d.nr;
   v.nnz = (int32_t)d.nnz;
+  v.dir_shift = d.dir_shift;
+  v.pad = 0;
   return v;
 }
 
@@ -143,13 +146,23 @@ void build_orientation(gsmat_store* st, const uint64_t* keys, int64_t U, Orienta
         throw StatusFail{GSMAT_EUNSUPPORTED, "a predicate has 2^31 or more pairs"};
     }
   }
-  // dense row pointers for predicates with many non-empty rows
-  int64_t dense_len = 0;
+  // dense row pointers for predicates with many non-empty rows; the others
+  // get a bucket directory over the id range with about kDirKeys rows per
+  // bucket, so a lookup searches a few adjacent keys instead of all of them
+  int64_t dense_len = 0, dir_len = 0;
+  const int64_t V = st->V;
   for (int32_t p = 0; p < P; ++p) {
     PredDesc& d = ori.desc[p];
-    if (d.nr > 0 && d.nr * (int64_t)dense_div >= (int64_t)st->V) {
+    if (d.nr > 0 && d.nr * (int64_t)dense_div >= V) {
       d.dense_base = dense_len;
-      dense_len += (int64_t)st->V + 1;
+      dense_len += V + 1;
+    } else if (d.nr > kDirKeys && V > 1) {
+      // largest bucket width 2^s with V / 2^s >= nr / kDirKeys buckets
+      int s = 0;
+      while (s < 30 && ((V - 1) >> (s + 1)) + 1 >= d.nr / kDirKeys) ++s;
+      d.dir_shift = s;
+      d.dir_base = dir_len;
+      dir_len += ((V - 1) >> s) + 2;
     }
   }
   ori.nbr = (int32_t*)st->dalloc(sizeof(int32_t) * (size_t)U, s, true);
@@ -158,6 +171,8 @@ void build_orientation(gsmat_store* st, const uint64_t* keys, int64_t U, Orienta
   ori.ptr = (int32_t*)st->dalloc(sizeof(int32_t) * (size_t)(R + P), s, true);
   ori.dense = dense_len ? (int32_t*)st->dalloc(sizeof(int32_t) * (size_t)dense_len, s, true) : nullptr;
   ori.dense_len = dense_len;
+  ori.dir = dir_len ? (int32_t*)st->dalloc(sizeof(int32_t) * (size_t)dir_len, s, true) : nullptr;
+  ori.dir_len = dir_len;
   ori.d_desc = (PredDesc*)st->dalloc(sizeof(PredDesc) * (size_t)P, s, true);
   GS_HIP(hipMemcpyAsync(ori.d_desc, ori.desc.data(), sizeof(PredDesc) * P, hipMemcpyHostToDevice, s));
   if (U > 0) {
@@ -168,8 +183,16 @@ void build_orientation(gsmat_store* st, const uint64_t* keys, int64_t U, Orienta
     GS_HIP(hipStreamSynchronize(s));  // d_pfe is a host-copied source
   }
   launch_ptr_sentinels(ori.d_desc, P, ori.ptr, s);
-  for (int32_t p = 0; p < P; ++p)
-    if (ori.desc[p].dense_base >= 0) launch_dense_ptr(ori.view(p), st->V, ori.dense + ori.desc[p].dense_base, s);
+  for (int32_t p = 0; p < P; ++p) {
+    const PredDesc& d = ori.desc[p];
+    if (d.dense_base >= 0) launch_dense_ptr(ori.view(p), st->V, ori.dense + d.dense_base, s);
+    if (d.dir_base >= 0) {
+      // the view without its directory: the directory is built from the keys
+      PredView pv = ori.view(p);
+      pv.dir = nullptr;
+      launch_row_dir(pv, d.dir_shift, ((V - 1) >> d.dir_shift) + 1, ori.dir + d.dir_base, s);
+    }
+  }
   GS_HIP(hipStreamSynchronize(s));
 }
 

@@ -17,11 +17,14 @@ struct Orientation {
   int32_t* keys = nullptr;   // [R] non-empty row ids per predicate
   int32_t* ptr = nullptr;    // [R + P] row offsets per predicate, one sentinel each
   int32_t* dense = nullptr;  // dense row pointers of heavy predicates
+  int32_t* dir = nullptr;    // bucket directories of the other predicates
   int64_t R = 0;
   int64_t dense_len = 0;
+  int64_t dir_len = 0;
   std::vector<PredDesc> desc;   // [P]
   PredDesc* d_desc = nullptr;   // device copy
   PredView view(int32_t p) const;
+  OriPtrs ptrs() const { return OriPtrs{keys, ptr, nbr, dense, dir}; }
 };
 
 struct Alloc {
