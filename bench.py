@@ -34,7 +34,7 @@ CSRC = os.path.join(ROOT, "paper_1807_07691_amd", "csrc")
 # committed counter summaries: workload -> (file, kernel sources it depends on)
 PMC_SUMMARY = {
     "large": ("write_expand_large_pmc.md", ["kernels.hip", "device.hpp"]),
-    "batch": ("write_batch_pmc.md", ["batch.hip", "device.hpp"]),
+    "batch": ("write_batch_pmc.md", ["kernels_batch.hip", "device.hpp"]),
 }
 
 

@@ -62,6 +62,7 @@ enum {
 typedef struct gsmat_store gsmat_store;   /* device CSR/CSC of every predicate */
 typedef struct gsmat_query_plan gsmat_query_plan; /* host-only ordered step list */
 typedef struct gsmat_result gsmat_result; /* device binding table, possibly in segments */
+typedef struct gsmat_server gsmat_server; /* request loop over one store (continuous batching) */
 
 /* Optional device allocator.  alloc returns NULL on failure.  free receives
  * the pointer and size that alloc returned.  Both are called on the host
@@ -233,6 +234,47 @@ gsmat_status gsmat_fetch_bindings(const gsmat_result* r, int64_t row_offset, int
                                   int32_t* host_rows, int64_t* n_written, void* stream);
 
 void gsmat_result_free(gsmat_result* r);
+
+/* ---- serving (continuous batching) ---------------------------------------- */
+
+/* A request loop over one built store, on one stream.  Submitted plans wait
+ * in arrival order until admitted: a query is admitted when a slot is free
+ * (at most max_active admitted) and the bytes the admitted queries hold or
+ * are estimated to need, plus its own estimate, stay within
+ * mem_budget_bytes (a query is always admitted when none is).  The estimate
+ * is the plan's largest table: the first step's relation size from the
+ * planning lookups, each later expansion multiplying it by the mean row
+ * length of its predicate, capped by the Theorem 1 bound (Sec. 6.2).  Each
+ * gsmat_server_step admits what fits and runs one step of every admitted
+ * query as one batched round (as in gsmat_join_batch), so queries that
+ * arrive while others run join them at the next round.  A round whose
+ * outputs would exceed mem_budget_bytes defers the later queries' steps to
+ * the next round (the first always runs).  step_budget_bytes and max_rows
+ * apply per query as in gsmat_join (a step above step_budget_bytes finishes
+ * alone, chunked).  Every query yields the rows, in the same order, that
+ * gsmat_join gives it.  The store must outlive the server; plans must stay
+ * alive until their result is polled.  Not thread-safe: one caller thread. */
+gsmat_status gsmat_server_new(gsmat_store* st, int64_t mem_budget_bytes,
+                              int64_t step_budget_bytes, int64_t max_rows, int32_t max_active,
+                              void* stream, gsmat_server** out);
+
+/* Queues a plan with the caller's tag (no device work). */
+gsmat_status gsmat_server_submit(gsmat_server* sv, const gsmat_query_plan* pl, int64_t tag);
+
+/* Admits waiting queries and runs one round.  Outputs (may be NULL): queries
+ * admitted and unfinished, waiting, and finished but not yet polled. */
+gsmat_status gsmat_server_step(gsmat_server* sv, int32_t* n_active, int32_t* n_waiting,
+                               int32_t* n_done);
+
+/* Hands over up to cap finished queries in completion order: tags[i],
+ * results[i] (owned by the caller, NULL when the query failed) and
+ * status[i].  *n_out = entries written.  Synchronises the stream first, so
+ * the results are complete. */
+gsmat_status gsmat_server_poll(gsmat_server* sv, int32_t cap, int64_t* tags,
+                               gsmat_result** results, gsmat_status* status, int32_t* n_out);
+
+/* Frees the server, its waiting queue and unpolled results. */
+void gsmat_server_free(gsmat_server* sv);
 
 /* Thread-local message for the last non-OK status of this thread. */
 const char* gsmat_last_error(void);

@@ -36,7 +36,8 @@ EXPORTED = [
     "gsmat_fetch_bindings", "gsmat_result_free", "gsmat_last_error", "gsmat_prof_enable",
     "gsmat_prof_read", "gsmat_prof_host", "gsmat_release_pools", "gsmat_plan_batch",
     "gsmat_join_batch", "gsmat_plan_free_many", "gsmat_result_free_many",
-    "gsmat_result_rows_many",
+    "gsmat_result_rows_many", "gsmat_server_new", "gsmat_server_submit", "gsmat_server_step",
+    "gsmat_server_poll", "gsmat_server_free",
 ]
 
 
@@ -119,6 +120,16 @@ def _load():
     L.gsmat_result_free_many.argtypes = [vp, i32]
     L.gsmat_result_rows_many.restype = i32
     L.gsmat_result_rows_many.argtypes = [vp, i32, vp]
+    L.gsmat_server_new.restype = i32
+    L.gsmat_server_new.argtypes = [vp, i64, i64, i64, i32, vp, pp]
+    L.gsmat_server_submit.restype = i32
+    L.gsmat_server_submit.argtypes = [vp, vp, i64]
+    L.gsmat_server_step.restype = i32
+    L.gsmat_server_step.argtypes = [vp, vp, vp, vp]
+    L.gsmat_server_poll.restype = i32
+    L.gsmat_server_poll.argtypes = [vp, i32, vp, vp, vp, vp]
+    L.gsmat_server_free.restype = None
+    L.gsmat_server_free.argtypes = [vp]
     return L
 
 
@@ -439,6 +450,62 @@ def gsmat_join_batch(store, plans, budget_bytes=0, max_rows=-1, stream=None,
     if as_set:
         return ResultSet(hs, nq, store), statuses
     return [Result(ctypes.c_void_p(hs[i]), store) if hs[i] else None for i in range(nq)], statuses
+
+
+class Server:
+    """Continuous-batching request loop over one store (gsmat_server_*)."""
+
+    def __init__(self, handle, store):
+        self.h = handle
+        self.store = store
+        self.plans = {}  # tag -> plan, kept alive until its result is polled
+        _live_results.add(self)
+
+    def close(self):
+        if self.h:
+            _lib.gsmat_server_free(self.h)
+            self.h = None
+        self.plans = {}
+
+    def __del__(self):
+        self.close()
+
+
+def gsmat_server_new(store, mem_budget_bytes=0, step_budget_bytes=0, max_rows=-1,
+                     max_active=4096, stream=None):
+    h = ctypes.c_void_p()
+    _check(_lib.gsmat_server_new(store.h, mem_budget_bytes, step_budget_bytes, max_rows,
+                                 max_active, _stream(stream), ctypes.byref(h)))
+    return Server(h, store)
+
+
+def gsmat_server_submit(server, plan, tag):
+    """plan: a Plan or a borrowed handle; it is kept alive until polled."""
+    _check(_lib.gsmat_server_submit(server.h, plan.h, tag))
+    server.plans[tag] = plan
+
+
+def gsmat_server_step(server):
+    """One admission + batched round: (active, waiting, done)."""
+    a, w, d = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(_lib.gsmat_server_step(server.h, ctypes.byref(a), ctypes.byref(w), ctypes.byref(d)))
+    return a.value, w.value, d.value
+
+
+def gsmat_server_poll(server, cap=4096):
+    """Finished queries: a list of (tag, Result or None, status)."""
+    tags = np.zeros(max(cap, 1), np.int64)
+    st = np.zeros(max(cap, 1), np.int32)
+    hs = (ctypes.c_void_p * max(cap, 1))()
+    n = ctypes.c_int32()
+    _check(_lib.gsmat_server_poll(server.h, cap, _p(tags), hs, _p(st), ctypes.byref(n)))
+    out = []
+    for i in range(n.value):
+        tag = int(tags[i])
+        server.plans.pop(tag, None)
+        out.append((tag, Result(ctypes.c_void_p(hs[i]), server.store) if hs[i] else None,
+                    int(st[i])))
+    return out
 
 
 def gsmat_result_info(result):

@@ -21,242 +21,15 @@
 // rule on the same tables), so its result rows come out in the same order.
 #include <algorithm>
 #include <cstring>
+#include <deque>
 #include <memory>
 
-#include "device.hpp"
+#include "batch.hpp"
 #include "exec.hpp"
 
 using namespace gsmat;
 
 namespace {
-
-using namespace gsmat::dev;
-
-enum : int32_t { kTaskExpand = 0, kTaskFilter = 1, kTaskIntersect = 2 };
-
-// Count-phase task: one step of one query.
-struct CTask {
-  int64_t n;           // input rows (intersection: driver list length)
-  int32_t kind;
-  int32_t l0, nl;      // intersection: lists[l0, l0 + nl)
-  int32_t pad;
-  PredView pv;         // expansion: view of the bound orientation; filter: by subject
-  ProbeArgs pa;        // filter
-  const int32_t* col;  // expansion: bound column; intersection: driver list
-  int32_t* N;          // expansion: output count per row
-  int32_t* start;      // expansion: row offset per row
-  uint8_t* flags;      // filter, intersection: keep flags
-};
-
-// Write-phase task.
-struct WTask {
-  int64_t n, m;        // input rows, output rows
-  int64_t t0;          // first tile of the task in the count launch
-  ColSet in;           // input columns
-  int32_t* out0;       // output column c at out0 + c * ostride
-  int64_t ostride;
-  int32_t k;           // input columns
-  int32_t pad;
-  const int32_t* nbr;  // expansion: members of the predicate view
-  const int32_t* N;
-  const int32_t* start;
-  int64_t* P;          // expansion: row offsets (n + 1)
-  int64_t* split;      // expansion: merge-path splits (path tiles + 1)
-  const uint8_t* flags;
-};
-
-// One task inside a launch: its tiles start at w0 of the launch's tiles.
-struct GItem {
-  int64_t w0;
-  int32_t task;
-  int32_t pad;
-};
-
-// Candidate expansion whose fan-out is sampled.
-struct SCand {
-  const int32_t* col;
-  PredView pv;
-  int64_t n;
-};
-
-// Index of the item owning tile b: the last item with w0 <= b.
-__device__ inline int find_item(const GItem* __restrict__ g, int n, int64_t b) {
-  int lo = 0, hi = n - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (g[mid].w0 <= b) lo = mid;
-    else hi = mid - 1;
-  }
-  return lo;
-}
-
-__global__ void k_lookup_many(const LookupReq* __restrict__ req, int32_t n, const PredDesc* dout,
-                              const PredDesc* din, OriPtrs out, OriPtrs in, LookupRes* res) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  res[i] = lookup_one(req[i], dout, din, out, in);
-}
-
-__global__ __launch_bounds__(kBlock) void k_b_sample(const SCand* __restrict__ c,
-                                                     int64_t* __restrict__ part) {
-  const int cand = blockIdx.x / kSampleBlocks;
-  const int slice = blockIdx.x % kSampleBlocks;
-  const SCand& sc = c[cand];
-  const int64_t t = sample_fanout_slice(slice, sc.col, sc.n, sc.pv);
-  if (threadIdx.x == 0) part[blockIdx.x] = t;
-}
-
-// Count / flag tiles of every task; tile sums to ts.
-__global__ __launch_bounds__(kBlock) void k_b_count(const CTask* __restrict__ tasks,
-                                                    const GItem* __restrict__ items, int nitems,
-                                                    const ListRef* __restrict__ lists,
-                                                    int64_t* __restrict__ ts) {
-  const GItem& it = items[find_item(items, nitems, blockIdx.x)];
-  const CTask& T = tasks[it.task];
-  const int64_t tile = (int64_t)blockIdx.x - it.w0;
-  int64_t sum;
-  if (T.kind == kTaskExpand) {
-    const PredView pv = T.pv;
-    sum = count_expand_tile(tile, T.col, T.n, pv, T.N, T.start);
-  } else if (T.kind == kTaskFilter) {
-    const PredView pv = T.pv;
-    const ProbeArgs pa = T.pa;
-    sum = flag_filter_tile(tile, pa, T.n, pv, T.flags);
-  } else {
-    sum = flag_intersect_tile(tile, T.col, T.n, lists + T.l0, T.nl, T.flags);
-  }
-  if (threadIdx.x == 0) ts[blockIdx.x] = sum;
-}
-
-// Output size of every task from the scanned tile sums (exclusive, with the
-// grand total at ts[ntiles]); written to pinned host memory.
-__global__ void k_b_totals(const GItem* __restrict__ items, int nitems, const int64_t* ts,
-                           int64_t ntiles, int64_t* __restrict__ out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nitems) return;
-  const int64_t a = items[i].w0;
-  const int64_t b = i + 1 < nitems ? items[i + 1].w0 : ntiles;
-  out[items[i].task] = ts[b] - ts[a];
-}
-
-// Expansion row offsets P (relative to the task) from the tile offsets.
-__global__ __launch_bounds__(kBlock) void k_b_scan_add(const WTask* __restrict__ tasks,
-                                                       const GItem* __restrict__ items,
-                                                       int nitems, const int64_t* __restrict__ ts) {
-  const GItem& it = items[find_item(items, nitems, blockIdx.x)];
-  const WTask& T = tasks[it.task];
-  const int64_t tile = (int64_t)blockIdx.x - it.w0;
-  const int64_t base = ts[T.t0 + tile] - ts[T.t0];
-  const int64_t tot = scan_add_tile<int32_t, int64_t>(tile, T.N, T.n, base, T.P);
-  if (threadIdx.x == 0 && (tile + 1) * kTile >= T.n) T.P[T.n] = base + tot;
-}
-
-// Merge-path splits of every expansion: one thread per split entry.
-__global__ void k_b_partition(const WTask* __restrict__ tasks, const GItem* __restrict__ items,
-                              int nitems, int64_t total) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= total) return;
-  const GItem& it = items[find_item(items, nitems, g)];
-  const WTask& T = tasks[it.task];
-  const int64_t t = g - it.w0;
-  T.split[t] = mp_split(T.P, T.n, 0, T.m, t);
-}
-
-template <int K>
-__global__ __launch_bounds__(kBlock) void k_b_write(const WTask* __restrict__ tasks,
-                                                    const GItem* __restrict__ items, int nitems) {
-  const GItem& it = items[find_item(items, nitems, blockIdx.x)];
-  const WTask& T = tasks[it.task];
-  const int64_t t = (int64_t)blockIdx.x - it.w0;
-  const OutStrided out{T.out0, T.ostride};
-  if constexpr (K >= 0) {
-    ColSet in;
-#pragma unroll
-    for (int c = 0; c < K; ++c) in.c[c] = T.in.c[c];
-    write_expand_tile<K>(t, in, K, T.P, T.start, T.n, T.nbr, 0, T.m, T.split, out);
-  } else {
-    write_expand_tile<K>(t, T.in, T.k, T.P, T.start, T.n, T.nbr, 0, T.m, T.split, out);
-  }
-}
-
-template <int K>
-__global__ __launch_bounds__(kBlock) void k_b_compact(const WTask* __restrict__ tasks,
-                                                      const GItem* __restrict__ items, int nitems,
-                                                      const int64_t* __restrict__ ts) {
-  const GItem& it = items[find_item(items, nitems, blockIdx.x)];
-  const WTask& T = tasks[it.task];
-  const int64_t tile = (int64_t)blockIdx.x - it.w0;
-  const int64_t base = ts[T.t0 + tile] - ts[T.t0];
-  const OutStrided out{T.out0, T.ostride};
-  if constexpr (K >= 0) {
-    ColSet in;
-#pragma unroll
-    for (int c = 0; c < K; ++c) in.c[c] = T.in.c[c];
-    compact_cols_tile<K>(tile, in, K, T.flags, T.n, base, out);
-  } else {
-    compact_cols_tile<K>(tile, T.in, T.k, T.flags, T.n, base, out);
-  }
-}
-
-#define GS_BLAUNCH(cls, bytes, ...)             \
-  do {                                          \
-    const bool _prof = prof_on(cls);            \
-    if (_prof) prof_begin(s, cls);              \
-    __VA_ARGS__;                                \
-    GS_HIP(hipGetLastError());                  \
-    if (_prof) prof_end(s, cls, bytes);         \
-  } while (0)
-
-template <int K>
-void launch_b_write(const WTask* t, const GItem* g, int ng, int64_t tiles, double bytes,
-                    hipStream_t s) {
-  GS_BLAUNCH(GSMAT_K_WRITE, bytes,
-             hipLaunchKernelGGL(k_b_write<K>, dim3((unsigned)tiles), dim3(kBlock), 0, s, t, g,
-                                ng));
-}
-template <int K>
-void launch_b_compact(const WTask* t, const GItem* g, int ng, const int64_t* ts, int64_t tiles,
-                      double bytes, hipStream_t s) {
-  GS_BLAUNCH(GSMAT_K_COMPACT, bytes,
-             hipLaunchKernelGGL(k_b_compact<K>, dim3((unsigned)tiles), dim3(kBlock), 0, s, t, g,
-                                ng, ts));
-}
-
-// Column counts with their own write / compaction instantiation.
-constexpr int kMaxK = 11;
-
-void b_write(int k, const WTask* t, const GItem* g, int ng, int64_t tiles, double bytes,
-             hipStream_t s) {
-  switch (k) {
-    case 0: return launch_b_write<0>(t, g, ng, tiles, bytes, s);
-    case 1: return launch_b_write<1>(t, g, ng, tiles, bytes, s);
-    case 2: return launch_b_write<2>(t, g, ng, tiles, bytes, s);
-    case 3: return launch_b_write<3>(t, g, ng, tiles, bytes, s);
-    case 4: return launch_b_write<4>(t, g, ng, tiles, bytes, s);
-    case 5: return launch_b_write<5>(t, g, ng, tiles, bytes, s);
-    case 6: return launch_b_write<6>(t, g, ng, tiles, bytes, s);
-    case 7: return launch_b_write<7>(t, g, ng, tiles, bytes, s);
-    case 8: return launch_b_write<8>(t, g, ng, tiles, bytes, s);
-    case 9: return launch_b_write<9>(t, g, ng, tiles, bytes, s);
-    case 10: return launch_b_write<10>(t, g, ng, tiles, bytes, s);
-    case 11: return launch_b_write<11>(t, g, ng, tiles, bytes, s);
-    default: return launch_b_write<-1>(t, g, ng, tiles, bytes, s);
-  }
-}
-void b_compact(int k, const WTask* t, const GItem* g, int ng, const int64_t* ts, int64_t tiles,
-               double bytes, hipStream_t s) {
-  switch (k) {
-    case 1: return launch_b_compact<1>(t, g, ng, ts, tiles, bytes, s);
-    case 2: return launch_b_compact<2>(t, g, ng, ts, tiles, bytes, s);
-    case 3: return launch_b_compact<3>(t, g, ng, ts, tiles, bytes, s);
-    case 4: return launch_b_compact<4>(t, g, ng, ts, tiles, bytes, s);
-    case 5: return launch_b_compact<5>(t, g, ng, ts, tiles, bytes, s);
-    case 6: return launch_b_compact<6>(t, g, ng, ts, tiles, bytes, s);
-    case 7: return launch_b_compact<7>(t, g, ng, ts, tiles, bytes, s);
-    case 8: return launch_b_compact<8>(t, g, ng, ts, tiles, bytes, s);
-    default: return launch_b_compact<-1>(t, g, ng, ts, tiles, bytes, s);
-  }
-}
 
 // ---------------------------------------------------------------- host side
 
@@ -307,11 +80,8 @@ std::vector<LookupRes> lookup_many(const gsmat_store* st, const std::vector<Look
   LookupRes* hres = (LookupRes*)pins()[kPinTotals].get(sizeof(LookupRes) * n);
   std::memcpy(hreq, req.data(), sizeof(LookupReq) * n);
   GS_HIP(hipMemcpyAsync(dev + o_req, hreq, sizeof(LookupReq) * n, hipMemcpyHostToDevice, s));
-  GS_BLAUNCH(GSMAT_K_OTHER, 32.0 * n,
-             hipLaunchKernelGGL(k_lookup_many, dim3((unsigned)ceil_div((int64_t)n, kBlock)),
-                                dim3(kBlock), 0, s, (const LookupReq*)(dev + o_req), (int32_t)n,
-                                st->out.d_desc, st->in.d_desc, st->out.ptrs(), st->in.ptrs(),
-                                hres));
+  launch_lookup_many((const LookupReq*)(dev + o_req), (int32_t)n, st->out.d_desc, st->in.d_desc,
+                     st->out.ptrs(), st->in.ptrs(), hres, s);
   host_sync(s);
   std::memcpy(out.data(), hres, sizeof(LookupRes) * n);
   return out;
@@ -331,8 +101,9 @@ struct BQ {
   gsmat_step_info sp{};
   uint32_t next = 0;
   int task = -1;        // this round's task
-  int lk0 = 0;          // first lookup result of this query (one per pattern with a constant)
-  int lk[kMaxPats];     // lookup index per pattern, -1 without constant
+  LookupRes lk[kMaxPats];  // row lookup of each pattern with a constant
+  int64_t tag = 0;         // caller's id (server)
+  int64_t est_bytes = 0;   // admission estimate (server)
   int cand0 = -1;       // first sampled candidate this round
   StepChoice choice;
   // pending task output (intersection result before it is combined)
@@ -345,7 +116,8 @@ struct Batch {
   int64_t budget;
   int64_t max_rows;
   std::vector<BQ> q;
-  std::vector<LookupRes> lk;
+  int64_t round_budget = 0;    // outputs of one round (<= 0: none)
+  bool defer = false;          // over the round budget: wait a round (else run alone)
 
   DeviceMem* mem() { return st->mem.get(); }
 
@@ -412,7 +184,7 @@ struct Batch {
       t.var[1] = var_of(p.o);
       return true;
     }
-    const LookupRes& r = lk[b.lk[tp]];
+    const LookupRes& r = b.lk[tp];
     if (!is_var(p.s) && is_var(p.o)) {
       t.n = r.len;
       t.k = 1;
@@ -430,27 +202,43 @@ struct Batch {
     return true;
   }
 
+  void admit(size_t first);
   void run();
   void round();
 };
 
-void Batch::run() {
-  // constant lookups of every query, in one launch
+// Constant lookups of queries [first, q.size()): the plan's where it made
+// them on this store, the rest in one launch.
+void Batch::admit(size_t first) {
   std::vector<LookupReq> req;
-  for (BQ& b : q) {
+  std::vector<LookupRes*> req_at;
+  for (size_t i = first; i < q.size(); ++i) {
+    BQ& b = q[i];
     if (b.state != kActive) continue;
-    for (int tp = 0; tp < (int)b.pl->pats.size(); ++tp) {
-      const gsmat_pattern& p = b.pl->pats[tp];
-      b.lk[tp] = -1;
+    const gsmat_query_plan* pl = b.pl;
+    const bool have = pl->lk_store == st->uid && pl->lk.size() == pl->pats.size();
+    for (int tp = 0; tp < (int)pl->pats.size(); ++tp) {
+      const gsmat_pattern& p = pl->pats[tp];
       const bool sc = !is_var(p.s), oc = !is_var(p.o);
       if (!sc && !oc) continue;
-      b.lk[tp] = (int)req.size();
+      if (have && pl->lk[tp].valid) {
+        const gsmat_pat_lookup& l = pl->lk[tp];
+        b.lk[tp] = LookupRes{l.start, l.len, l.found, 0};
+        continue;
+      }
+      req_at.push_back(&b.lk[tp]);
       if (sc && oc) req.push_back({0, p.p, p.s, p.o});
       else if (sc) req.push_back({0, p.p, p.s, -1});
       else req.push_back({1, p.p, p.o, -1});
     }
   }
-  lk = lookup_many(st, req, s);
+  if (req.empty()) return;
+  const std::vector<LookupRes> r = lookup_many(st, req, s);
+  for (size_t j = 0; j < r.size(); ++j) *req_at[j] = r[j];
+}
+
+void Batch::run() {
+  admit(0);
   for (;;) {
     bool any = false;
     for (const BQ& b : q) any |= b.state == kActive;
@@ -469,14 +257,19 @@ void Batch::round() {
     b.cand0 = -1;
     const gsmat_query_plan* pl = b.pl;
     if (pl->mode == GSMAT_PLAN_ADAPTIVE && !b.t.unit()) {
-      b.choice = step_candidates(st, pl, b.t, b.rem);
+      step_candidates(st, pl, b.t, b.rem, b.choice);
       const StepChoice& c = b.choice;
       if (c.has_filter) b.sp = c.filter;
       else if (c.nc == 0) b.sp = c.cartesian;
       else if (c.nc == 1) b.sp = step_pick(pl, c, nullptr);
       else {
         b.cand0 = (int)cands.size();
-        for (int i = 0; i < c.nc; ++i) cands.push_back(SCand{c.col[i], c.pv[i], b.t.n});
+        for (int i = 0; i < c.nc; ++i) {
+          SCand sc;
+          candidate_view(st, pl, b.t, c, i, &sc.col, &sc.pv);
+          sc.n = b.t.n;
+          cands.push_back(sc);
+        }
       }
     } else {
       b.sp = pl->steps[std::min<size_t>(b.si, pl->steps.size() - 1)];
@@ -491,9 +284,7 @@ void Batch::round() {
     int64_t* hp = (int64_t*)pins()[kPinParts].get(sizeof(int64_t) * nc * kSampleBlocks);
     std::memcpy(hc, cands.data(), sizeof(SCand) * nc);
     GS_HIP(hipMemcpyAsync((char*)a.p + o_c, hc, sizeof(SCand) * nc, hipMemcpyHostToDevice, s));
-    GS_BLAUNCH(GSMAT_K_OTHER, 0.0,
-               hipLaunchKernelGGL(k_b_sample, dim3((unsigned)(nc * kSampleBlocks)), dim3(kBlock),
-                                  0, s, (const SCand*)((char*)a.p + o_c), hp));
+    launch_b_sample((const SCand*)((char*)a.p + o_c), (int64_t)nc, hp, s);
     host_sync(s);
     for (BQ& b : q) {
       if (b.state != kActive || b.cand0 < 0) continue;
@@ -554,12 +345,12 @@ void Batch::round() {
             l.len = l.pv.nr;
             ids[nl] = l.pv.keys;
           } else if (m.s == cterm) {
-            const LookupRes& r = lk[b.lk[tp]];
+            const LookupRes& r = b.lk[tp];
             l.seg = st->in.view(m.p).nbr + r.start;
             l.len = r.len;
             ids[nl] = l.seg;
           } else {
-            const LookupRes& r = lk[b.lk[tp]];
+            const LookupRes& r = b.lk[tp];
             l.seg = st->out.view(m.p).nbr + r.start;
             l.len = r.len;
             ids[nl] = l.seg;
@@ -591,7 +382,7 @@ void Batch::round() {
       }
       case GSMAT_STEP_FILTER: {
         if (!is_var(p.s) && !is_var(p.o)) {
-          if (lk[b.lk[sp.tp]].found) {
+          if (b.lk[sp.tp].found) {
             add_out(b, b.t.n);
             advance(b, b.t);
           } else {
@@ -656,40 +447,42 @@ void Batch::round() {
     }
   }
   const size_t o_ts = LA.add(sizeof(int64_t) * (ntiles + 1));
+  // uploaded together: tasks, items, lists, then the zeroed non-empty counters
   const size_t o_tasks = LA.add(sizeof(CTask) * nt);
   const size_t o_items = LA.add(sizeof(GItem) * nt);
   const size_t o_lists = LA.add(sizeof(ListRef) * std::max<size_t>(lists.size(), 1));
+  const size_t o_ne = LA.add(sizeof(int64_t) * nt);
   auto A = std::make_shared<Arena>(mem(), LA.bytes, s);
   char* da = (char*)A->p;
+  int64_t* dne = (int64_t*)(da + o_ne);
   for (int i = 0; i < nt; ++i) {
     if (tasks[i].kind == kTaskExpand) {
       tasks[i].N = (int32_t*)(da + o_N[i]);
       tasks[i].start = (int32_t*)(da + o_start[i]);
+      tasks[i].nonempty = dne + i;
     } else {
       tasks[i].flags = (uint8_t*)(da + o_flags[i]);
     }
   }
   int64_t* ts = (int64_t*)(da + o_ts);
   {
-    const size_t up = o_lists + sizeof(ListRef) * lists.size() - o_tasks;
+    const size_t up = o_ne + sizeof(int64_t) * nt - o_tasks;
     char* h = (char*)pins()[kPinCount].get(up);
     std::memcpy(h, tasks.data(), sizeof(CTask) * nt);
     std::memcpy(h + (o_items - o_tasks), items.data(), sizeof(GItem) * nt);
     if (!lists.empty()) std::memcpy(h + (o_lists - o_tasks), lists.data(), sizeof(ListRef) * lists.size());
+    std::memset(h + (o_ne - o_tasks), 0, sizeof(int64_t) * nt);
     GS_HIP(hipMemcpyAsync(da + o_tasks, h, up, hipMemcpyHostToDevice, s));
   }
-  int64_t* htot = (int64_t*)pins()[kPinTotals].get(sizeof(int64_t) * nt);
+  int64_t* htot = (int64_t*)pins()[kPinTotals].get(2 * sizeof(int64_t) * nt);
   const CTask* dtasks = (const CTask*)(da + o_tasks);
   const GItem* ditems = (const GItem*)(da + o_items);
-  GS_BLAUNCH(GSMAT_K_COUNT, 20.0 * ntiles * kTile,
-             hipLaunchKernelGGL(k_b_count, dim3((unsigned)ntiles), dim3(kBlock), 0, s, dtasks,
-                                ditems, nt, (const ListRef*)(da + o_lists), ts));
+  launch_b_count(dtasks, ditems, nt, (const ListRef*)(da + o_lists), ts, ntiles,
+                 20.0 * ntiles * kTile, s);
   launch_scan_tile_sums(ts, ntiles, ts + ntiles, s, nullptr);
-  GS_BLAUNCH(GSMAT_K_SCAN, 16.0 * nt,
-             hipLaunchKernelGGL(k_b_totals, dim3((unsigned)ceil_div(nt, kBlock)), dim3(kBlock), 0,
-                                s, ditems, nt, ts, ntiles, htot));
+  launch_b_totals(ditems, nt, ts, ntiles, dne, htot, s);
   host_sync(s);
-  std::vector<int64_t> tot(htot, htot + nt);
+  std::vector<int64_t> tot(htot, htot + nt), nonempty(htot + nt, htot + 2 * nt);
 
   // ---- write phase: outputs
   std::vector<WTask> w(nt);
@@ -707,20 +500,21 @@ void Batch::round() {
     wt.t0 = items[i].w0;
     int kout = 0;
     if (c.kind == kTaskExpand) {
-      add_out(b, m);
       if (m == 0) {
+        add_out(b, 0);
         b.state = kDone;
         b.t = Table();
         continue;
       }
       kout = b.t.k + 1;
     } else if (c.kind == kTaskFilter) {
-      add_out(b, m);
       if (m == c.n) {  // nothing removed: the table goes on unchanged
+        add_out(b, m);
         advance(b, b.t);
         continue;
       }
       if (m == 0) {
+        add_out(b, 0);
         b.state = kDone;
         b.t = Table();
         continue;
@@ -746,13 +540,23 @@ void Batch::round() {
       kout = 1;
     }
     const size_t bytes = sizeof(int32_t) * (size_t)col_stride(m) * (size_t)kout;
-    if (budget > 0 && (m > budget / (4 * (int64_t)std::max(kout, 1)) ||
-                       round_bytes + (int64_t)bytes > budget)) {
-      // above the step budget (chunked alone) or the round's budget
+    if (budget > 0 && m > budget / (4 * (int64_t)std::max(kout, 1))) {
+      // above the step budget: chunked by the single-query executor
       b.state = kFallback;
       b.t = Table();
       continue;
     }
+    if (round_budget > 0 && round_bytes > 0 && round_bytes + (int64_t)bytes > round_budget) {
+      if (defer) {
+        // the round is full: this query repeats the step next round
+        if (b.si < (int)b.res->step_in.size()) b.res->step_in[b.si] -= b.t.n;
+        continue;
+      }
+      b.state = kFallback;
+      b.t = Table();
+      continue;
+    }
+    if (c.kind != kTaskIntersect) add_out(b, m);
     round_bytes += (int64_t)bytes;
     o_out[i] = LB.add(bytes);
     has_out[i] = 1;
@@ -790,7 +594,9 @@ void Batch::round() {
       const int gk = wt.k <= kMaxK ? wt.k : kMaxK + 1;
       g_write[gk].push_back(GItem{n_write[gk], i, 0});
       n_write[gk] += pt;
-      bytes_write[gk] += 4.0 * wt.m * (wt.k + 2) + wt.n * (4.0 * wt.k + 12.0);
+      // outputs written (k + 1 columns), one member id read per output, the
+      // offsets and starts of every row, the k values of rows with output
+      bytes_write[gk] += 4.0 * wt.m * (wt.k + 2) + 12.0 * wt.n + 4.0 * wt.k * nonempty[i];
     } else {
       const bool inter = c.kind == kTaskIntersect;
       wt.k = inter ? 1 : b.t.k;
@@ -834,20 +640,16 @@ void Batch::round() {
   }
   const WTask* dw = (const WTask*)(dc + o_w);
   if (!g_scan.empty()) {
-    GS_BLAUNCH(GSMAT_K_SCAN, 12.0 * n_scan * kTile,
-               hipLaunchKernelGGL(k_b_scan_add, dim3((unsigned)n_scan), dim3(kBlock), 0, s, dw,
-                                  (const GItem*)(dc + o_gscan), (int)g_scan.size(), ts));
-    GS_BLAUNCH(GSMAT_K_OTHER, 8.0 * n_part,
-               hipLaunchKernelGGL(k_b_partition, dim3((unsigned)ceil_div(n_part, kBlock)),
-                                  dim3(kBlock), 0, s, dw, (const GItem*)(dc + o_gpart),
-                                  (int)g_part.size(), n_part));
+    launch_b_scan_add(dw, (const GItem*)(dc + o_gscan), (int)g_scan.size(), ts, n_scan,
+                      12.0 * n_scan * kTile, s);
+    launch_b_partition(dw, (const GItem*)(dc + o_gpart), (int)g_part.size(), n_part, s);
   }
   for (int k = 0; k < kMaxK + 2; ++k) {
     if (!g_write[k].empty())
-      b_write(k <= kMaxK ? k : -1, dw, (const GItem*)(dc + o_gw[k]), (int)g_write[k].size(),
+      launch_b_write(k, dw, (const GItem*)(dc + o_gw[k]), (int)g_write[k].size(),
               n_write[k], bytes_write[k], s);
     if (!g_comp[k].empty())
-      b_compact(k <= kMaxK ? k : -1, dw, (const GItem*)(dc + o_gc[k]), (int)g_comp[k].size(), ts,
+      launch_b_compact(k, dw, (const GItem*)(dc + o_gc[k]), (int)g_comp[k].size(), ts,
                 n_comp[k], bytes_comp[k], s);
   }
 
@@ -880,6 +682,260 @@ void Batch::round() {
 
 }  // namespace
 
+// ---------------------------------------------------------------- serving
+
+namespace {
+
+// Admission estimate of a plan's largest table in bytes: the first step's
+// relation exactly (from the planning lookups where there are any), each
+// later expansion multiplying the rows by the mean row length of its
+// predicate in the expanded direction, filters and intersections adding
+// none; capped by the plan's Theorem 1 bound.
+int64_t estimate_bytes(const gsmat_store* st, const gsmat_query_plan* pl) {
+  const bool have = pl->lk_store == st->uid && pl->lk.size() == pl->pats.size();
+  auto rel_rows = [&](int tp) -> double {
+    const gsmat_pattern& p = pl->pats[tp];
+    if (p.p < 0 || p.p >= st->P) return 0.0;
+    const PredDesc& o = st->out.desc[p.p];
+    const PredDesc& i = st->in.desc[p.p];
+    const bool sc = !is_var(p.s), oc = !is_var(p.o);
+    if (!sc && !oc) return (double)o.nnz;
+    if (have && pl->lk[tp].valid) return sc && oc ? pl->lk[tp].found : pl->lk[tp].len;
+    if (sc && oc) return 1.0;
+    const PredDesc& d = sc ? o : i;
+    return d.nr ? (double)d.nnz / (double)d.nr : 0.0;
+  };
+  double rows = 1.0, peak = 0.0;
+  int k = 0;
+  uint64_t bound = 0;
+  auto bind = [&](int tp) {
+    const gsmat_pattern& p = pl->pats[tp];
+    for (int32_t t : {p.s, p.o})
+      if (is_var(t) && !(bound >> var_of(t) & 1)) {
+        bound |= 1ull << var_of(t);
+        ++k;
+      }
+  };
+  for (const gsmat_step_info& sp : pl->steps) {
+    const gsmat_pattern& p = pl->pats[sp.tp];
+    switch (sp.kind) {
+      case GSMAT_STEP_SCAN:
+      case GSMAT_STEP_CARTESIAN:
+        rows *= rel_rows(sp.tp);
+        bind(sp.tp);
+        break;
+      case GSMAT_STEP_INTERSECT: {
+        double m = -1.0;
+        for (int tp = 0; tp < (int)pl->pats.size(); ++tp) {
+          if (!(sp.members >> tp & 1)) continue;
+          const gsmat_pattern& q = pl->pats[tp];
+          const bool centre_s = q.s == -(sp.var + 1);
+          const bool other_const = !is_var(centre_s ? q.o : q.s);
+          const double len = other_const ? rel_rows(tp)
+                                         : (double)(centre_s ? st->out.desc[q.p].nr
+                                                             : st->in.desc[q.p].nr);
+          m = m < 0 ? len : std::min(m, len);
+        }
+        rows *= std::max(m, 0.0);
+        if (!(bound >> sp.var & 1)) {
+          bound |= 1ull << sp.var;
+          ++k;
+        }
+        break;
+      }
+      case GSMAT_STEP_EXPAND: {
+        const PredDesc& d = sp.orient == 0 ? st->out.desc[p.p] : st->in.desc[p.p];
+        rows *= d.nr ? (double)d.nnz / (double)d.nr : 0.0;
+        bind(sp.tp);
+        break;
+      }
+      default:
+        break;
+    }
+    rows = std::min(rows, (double)sp.est_rows);
+    peak = std::max(peak, rows * 4.0 * std::max(k, 1));
+  }
+  return (int64_t)std::min(peak, 9.0e18);
+}
+
+struct Pending {
+  const gsmat_query_plan* pl;
+  int64_t tag;
+  int64_t est;
+};
+
+struct Finished {
+  int64_t tag;
+  gsmat_result* res;
+  gsmat_status status;
+};
+
+}  // namespace
+
+// A request loop over one resident store: submitted plans wait in arrival
+// order until admission (estimated bytes within the memory budget, a free
+// slot); every step admits what fits and then runs one round of the batched
+// executor over all admitted queries, so queries that arrive while others
+// run join them at the next round.
+struct gsmat_server {
+  gsmat_store* st;
+  hipStream_t s;
+  int64_t mem_budget;
+  int32_t max_active;
+  Batch bt;
+  std::deque<Pending> waiting;
+  std::deque<Finished> done;
+
+  gsmat_server(gsmat_store* st_, int64_t mem, int64_t step, int64_t max_rows, int32_t slots,
+               hipStream_t s_)
+      : st(st_), s(s_), mem_budget(mem), max_active(slots),
+        bt{st_, s_, step, max_rows, {}, mem, true} {}
+
+  ~gsmat_server() {
+    for (Finished& f : done) delete f.res;
+  }
+
+  // Bytes the admitted queries hold or are expected to need.
+  int64_t committed() const {
+    int64_t c = 0;
+    for (const BQ& b : bt.q) {
+      const int64_t held = b.t.keep ? 4 * col_stride(b.t.n) * (int64_t)b.t.k : 0;
+      c += std::max(held, b.est_bytes);
+    }
+    return c;
+  }
+
+  void admit() {
+    if (waiting.empty()) return;
+    int64_t c = committed();
+    const size_t first = bt.q.size();
+    while (!waiting.empty() && (int32_t)bt.q.size() < max_active) {
+      const Pending& w = waiting.front();
+      if (!bt.q.empty() && mem_budget > 0 && c + w.est > mem_budget) break;
+      bt.q.emplace_back();
+      BQ& b = bt.q.back();
+      b.pl = w.pl;
+      b.tag = w.tag;
+      b.est_bytes = w.est;
+      b.res.reset(new gsmat_result);
+      b.res->st = st;
+      b.res->stream = s;
+      b.res->n_vars = w.pl->n_vars;
+      b.res->step_in.assign(w.pl->steps.size(), 0);
+      b.res->step_out.assign(w.pl->steps.size(), 0);
+      b.t.n = 1;
+      b.t.k = 0;
+      b.rem = w.pl->pats.size() >= 32 ? 0xFFFFFFFFu : ((1u << w.pl->pats.size()) - 1);
+      for (const gsmat_pattern& p : w.pl->pats)
+        if (p.p >= st->P || (!is_var(p.s) && p.s >= st->V) || (!is_var(p.o) && p.o >= st->V)) {
+          b.state = kDone;
+          b.t = Table();
+        }
+      c += w.est;
+      waiting.pop_front();
+    }
+    bt.admit(first);
+  }
+
+  // Moves finished queries to the done list (queries that left the batch
+  // are run alone first).
+  void collect() {
+    size_t keep = 0;
+    for (size_t i = 0; i < bt.q.size(); ++i) {
+      BQ& b = bt.q[i];
+      if (b.state == kActive) {
+        if (keep != i) bt.q[keep] = std::move(b);
+        ++keep;
+        continue;
+      }
+      if (b.state == kFallback) {
+        b.res.reset(new gsmat_result);
+        b.res->st = st;
+        b.res->stream = s;
+        b.res->n_vars = b.pl->n_vars;
+        b.res->step_in.assign(b.pl->steps.size(), 0);
+        b.res->step_out.assign(b.pl->steps.size(), 0);
+        gsmat_result* r = b.res.get();
+        const gsmat_status rc = guarded([&]() -> gsmat_status {
+          run_query(st, b.pl, bt.budget, bt.max_rows, s, r);
+          return GSMAT_OK;
+        });
+        b.state = rc == GSMAT_OK ? kDone : kFailed;
+        b.status = rc;
+        if (rc != GSMAT_OK) b.res.reset();
+      }
+      done.push_back(Finished{b.tag, b.state == kDone ? b.res.release() : nullptr,
+                              b.state == kDone ? GSMAT_OK : b.status});
+    }
+    bt.q.resize(keep);
+  }
+};
+
+extern "C" gsmat_status gsmat_server_new(gsmat_store* st, int64_t mem_budget_bytes,
+                                         int64_t step_budget_bytes, int64_t max_rows,
+                                         int32_t max_active, void* stream, gsmat_server** out) {
+  return guarded([&]() -> gsmat_status {
+    if (!out) throw StatusFail{GSMAT_EINVAL, "out is NULL"};
+    *out = nullptr;
+    if (!st) throw StatusFail{GSMAT_EINVAL, "store is NULL"};
+    if (!st->built) throw StatusFail{GSMAT_ESTATE, "index not built"};
+    if (max_active < 1) throw StatusFail{GSMAT_EINVAL, "max_active must be at least 1"};
+    *out = new gsmat_server(st, mem_budget_bytes, step_budget_bytes, max_rows, max_active,
+                            (hipStream_t)stream);
+    return GSMAT_OK;
+  });
+}
+
+extern "C" gsmat_status gsmat_server_submit(gsmat_server* sv, const gsmat_query_plan* pl,
+                                            int64_t tag) {
+  return guarded([&]() -> gsmat_status {
+    if (!sv || !pl) throw StatusFail{GSMAT_EINVAL, "server or plan is NULL"};
+    sv->waiting.push_back(Pending{pl, tag, estimate_bytes(sv->st, pl)});
+    return GSMAT_OK;
+  });
+}
+
+extern "C" gsmat_status gsmat_server_step(gsmat_server* sv, int32_t* n_active, int32_t* n_waiting,
+                                          int32_t* n_done) {
+  return guarded([&]() -> gsmat_status {
+    if (!sv) throw StatusFail{GSMAT_EINVAL, "server is NULL"};
+    sv->admit();
+    bool any = false;
+    for (const BQ& b : sv->bt.q) any |= b.state == kActive;
+    if (any) sv->bt.round();
+    sv->collect();
+    if (n_active) *n_active = (int32_t)sv->bt.q.size();
+    if (n_waiting) *n_waiting = (int32_t)sv->waiting.size();
+    if (n_done) *n_done = (int32_t)sv->done.size();
+    return GSMAT_OK;
+  });
+}
+
+extern "C" gsmat_status gsmat_server_poll(gsmat_server* sv, int32_t cap, int64_t* tags,
+                                          gsmat_result** results, gsmat_status* status,
+                                          int32_t* n_out) {
+  return guarded([&]() -> gsmat_status {
+    if (!sv || !n_out) throw StatusFail{GSMAT_EINVAL, "server or n_out is NULL"};
+    if (cap < 0) throw StatusFail{GSMAT_EINVAL, "negative capacity"};
+    if (cap > 0 && (!tags || !results || !status))
+      throw StatusFail{GSMAT_EINVAL, "tags, results or status is NULL"};
+    int32_t n = 0;
+    if (cap > 0 && !sv->done.empty()) GS_HIP(hipStreamSynchronize(sv->s));
+    while (n < cap && !sv->done.empty()) {
+      const Finished& f = sv->done.front();
+      tags[n] = f.tag;
+      results[n] = f.res;
+      status[n] = f.status;
+      ++n;
+      sv->done.pop_front();
+    }
+    *n_out = n;
+    return GSMAT_OK;
+  });
+}
+
+extern "C" void gsmat_server_free(gsmat_server* sv) { delete sv; }
+
 extern "C" gsmat_status gsmat_join_batch(gsmat_store* st, const gsmat_query_plan* const* plans,
                                          int32_t n_plans, int64_t budget_bytes, int64_t max_rows,
                                          void* stream, gsmat_result** out, gsmat_status* status) {
@@ -892,7 +948,7 @@ extern "C" gsmat_status gsmat_join_batch(gsmat_store* st, const gsmat_query_plan
     for (int i = 0; i < n_plans; ++i)
       if (!plans[i]) throw StatusFail{GSMAT_EINVAL, "plan " + std::to_string(i) + " is NULL"};
     hipStream_t s = (hipStream_t)stream;
-    Batch bt{st, s, budget_bytes, max_rows, {}, {}};
+    Batch bt{st, s, budget_bytes, max_rows, {}, budget_bytes, false};
     bt.q.resize(n_plans);
     for (int i = 0; i < n_plans; ++i) {
       BQ& b = bt.q[i];
@@ -1027,6 +1083,14 @@ extern "C" gsmat_status gsmat_plan_batch(const gsmat_store* st, const gsmat_patt
         }
         std::unique_ptr<gsmat_query_plan> pl(new gsmat_query_plan);
         rc[i] = build_plan(pq, n_pats[i], mode, stats[i], pl.get(), &msg[i]);
+        if (rc[i] == GSMAT_OK && mode != GSMAT_PLAN_PAPER) {
+          pl->lk.assign(n_pats[i], gsmat_pat_lookup{});
+          for (int j = 0; j < n_pats[i]; ++j) {
+            const int r = req_of[i][j];
+            if (r >= 0) pl->lk[j] = gsmat_pat_lookup{res[r].start, res[r].len, res[r].found, 1};
+          }
+          pl->lk_store = st->uid;
+        }
         if (rc[i] == GSMAT_OK) out[i] = pl.release();
       }
       if (status) status[i] = rc[i];

@@ -1,0 +1,80 @@
+// Batched join: task descriptors shared by the host executor (batch.hip)
+// and the batched kernels (kernels_batch.hip), and the launchers.
+#pragma once
+
+#include "common.hpp"
+
+namespace gsmat {
+
+enum : int32_t { kTaskExpand = 0, kTaskFilter = 1, kTaskIntersect = 2 };
+
+// Count-phase task: one step of one query.
+struct CTask {
+  int64_t n;           // input rows (intersection: driver list length)
+  int32_t kind;
+  int32_t l0, nl;      // intersection: lists[l0, l0 + nl)
+  int32_t pad;
+  PredView pv;         // expansion: view of the bound orientation; filter: by subject
+  ProbeArgs pa;        // filter
+  const int32_t* col;  // expansion: bound column; intersection: driver list
+  int32_t* N;          // expansion: output count per row
+  int32_t* start;      // expansion: row offset per row
+  uint8_t* flags;      // filter, intersection: keep flags
+  int64_t* nonempty;   // expansion: rows with output (starts at 0)
+};
+
+// Write-phase task.
+struct WTask {
+  int64_t n, m;        // input rows, output rows
+  int64_t t0;          // first tile of the task in the count launch
+  ColSet in;           // input columns
+  int32_t* out0;       // output column c at out0 + c * ostride
+  int64_t ostride;
+  int32_t k;           // input columns
+  int32_t pad;
+  const int32_t* nbr;  // expansion: members of the predicate view
+  const int32_t* N;
+  const int32_t* start;
+  int64_t* P;          // expansion: row offsets (n + 1)
+  int64_t* split;      // expansion: merge-path splits (path tiles + 1)
+  const uint8_t* flags;
+};
+
+// One task inside a launch: its tiles start at w0 of the launch's tiles.
+struct GItem {
+  int64_t w0;
+  int32_t task;
+  int32_t pad;
+};
+
+// Candidate expansion whose fan-out is sampled.
+struct SCand {
+  const int32_t* col;
+  PredView pv;
+  int64_t n;
+};
+
+// Column counts with their own write / compaction instantiation.
+constexpr int kMaxK = 11;
+
+void launch_lookup_many(const LookupReq* req, int32_t n, const PredDesc* dout, const PredDesc* din,
+                        OriPtrs out, OriPtrs in, LookupRes* res, hipStream_t s);
+// fan-out samples: kSampleBlocks partial sums per candidate to part[c * kSampleBlocks + b]
+void launch_b_sample(const SCand* cands, int64_t nc, int64_t* part, hipStream_t s);
+// count / flag tiles of every task (items in task order) -> tile sums ts[ntiles]
+void launch_b_count(const CTask* tasks, const GItem* items, int nitems, const ListRef* lists,
+                    int64_t* ts, int64_t ntiles, double bytes, hipStream_t s);
+// out[task] = output rows, out[nitems + task] = non-empty rows (expansions)
+void launch_b_totals(const GItem* items, int nitems, const int64_t* ts, int64_t ntiles,
+                     const int64_t* ne, int64_t* out, hipStream_t s);
+void launch_b_scan_add(const WTask* tasks, const GItem* items, int nitems, const int64_t* ts,
+                       int64_t tiles, double bytes, hipStream_t s);
+void launch_b_partition(const WTask* tasks, const GItem* items, int nitems, int64_t total,
+                        hipStream_t s);
+// k > kMaxK selects the generic instantiation
+void launch_b_write(int k, const WTask* tasks, const GItem* items, int nitems, int64_t tiles,
+                    double bytes, hipStream_t s);
+void launch_b_compact(int k, const WTask* tasks, const GItem* items, int nitems,
+                      const int64_t* ts, int64_t tiles, double bytes, hipStream_t s);
+
+}  // namespace gsmat

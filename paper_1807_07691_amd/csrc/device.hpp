@@ -202,7 +202,11 @@ __device__ inline int64_t sample_fanout_slice(int slice, const int32_t* __restri
 // Each returns the workgroup's sum of its per-item results (for the tile
 // sums that feed the offsets' prefix sum).
 
-// Expansion count: N_i = length of row col[i], start_i its offset.
+// Expansion count: N_i = length of row col[i], start_i its offset.  With
+// kNonEmpty the result also carries, above bit kNonEmptyShift, the number of
+// rows with N_i > 0 (a tile's length sum stays below 2^kNonEmptyShift).
+constexpr int kNonEmptyShift = 48;
+template <bool kNonEmpty = false>
 __device__ inline int64_t count_expand_tile(int64_t tile, const int32_t* __restrict__ col,
                                             int64_t n, const PredView& pv,
                                             int32_t* __restrict__ N,
@@ -218,6 +222,7 @@ __device__ inline int64_t count_expand_tile(int64_t tile, const int32_t* __restr
       N[i] = len;
       start[i] = st;
       loc += len;
+      if (kNonEmpty && len > 0) loc += (int64_t)1 << kNonEmptyShift;
     }
   }
   return block_sum(loc);

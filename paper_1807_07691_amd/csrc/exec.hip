@@ -122,6 +122,16 @@ struct Exec {
     return t;
   }
 
+  // Lookup of pattern tp's constant endpoint(s): the plan's, when it was
+  // planned on this store, else one device lookup.
+  LookupRes lookup_tp(int tp, int orient, int32_t p, int32_t v, int32_t member) {
+    if (pl->lk_store == st->uid && tp < (int)pl->lk.size() && pl->lk[tp].valid) {
+      const gsmat_pat_lookup& l = pl->lk[tp];
+      return LookupRes{l.start, l.len, l.found, 0};
+    }
+    return lookup(orient, p, v, member);
+  }
+
   LookupRes lookup(int orient, int32_t p, int32_t v, int32_t member) {
     LookupBatch b{};
     b.req[0] = LookupReq{orient, p, v, member};
@@ -193,7 +203,7 @@ struct Exec {
       return o;
     }
     if (!is_var(q.s) && is_var(q.o)) {
-      const LookupRes r = lookup(0, p, q.s, -1);
+      const LookupRes r = lookup_tp(tp, 0, p, q.s, -1);
       const PredView pv = st->out.view(p);
       t.n = r.len;
       t.k = 1;
@@ -202,7 +212,7 @@ struct Exec {
       return t;
     }
     if (is_var(q.s) && !is_var(q.o)) {
-      const LookupRes r = lookup(1, p, q.o, -1);
+      const LookupRes r = lookup_tp(tp, 1, p, q.o, -1);
       const PredView pv = st->in.view(p);
       t.n = r.len;
       t.k = 1;
@@ -210,7 +220,7 @@ struct Exec {
       t.var[0] = var_of(q.s);
       return t;
     }
-    const LookupRes r = lookup(0, p, q.s, q.o);
+    const LookupRes r = lookup_tp(tp, 0, p, q.s, q.o);
     t.n = r.found ? 1 : 0;
     t.k = 0;
     return t;
@@ -221,15 +231,13 @@ struct Exec {
   // Adaptive choice of the next step on the bound table t (fan-out samples
   // of the candidate expansions are taken on the device).
   gsmat_step_info choose(const Table& t, uint32_t rem) {
-    const StepChoice c = step_candidates(st, pl, t, rem);
+    StepChoice c;
+    step_candidates(st, pl, t, rem, c);
     if (c.has_filter) return c.filter;
     if (c.nc == 0) return c.cartesian;
     if (c.nc == 1) return step_pick(pl, c, nullptr);
     SampleSet ss{};
-    for (int i = 0; i < c.nc; ++i) {
-      ss.col[i] = c.col[i];
-      ss.pv[i] = c.pv[i];
-    }
+    for (int i = 0; i < c.nc; ++i) candidate_view(st, pl, t, c, i, &ss.col[i], &ss.pv[i]);
     ss.n = t.n;
     ss.ncand = c.nc;
     PinnedArea* h = pinned();
@@ -342,12 +350,12 @@ struct Exec {
         l.ref.len = l.ref.pv.nr;
         l.ids = l.ref.pv.keys;
       } else if (q.s == cterm) {  // (v p c): v among the subjects of object c
-        const LookupRes r = lookup(1, q.p, q.o, -1);
+        const LookupRes r = lookup_tp(tp, 1, q.p, q.o, -1);
         l.ref.seg = st->in.view(q.p).nbr + r.start;
         l.ref.len = r.len;
         l.ids = l.ref.seg;
       } else {  // (c p v): v among the objects of subject c
-        const LookupRes r = lookup(0, q.p, q.s, -1);
+        const LookupRes r = lookup_tp(tp, 0, q.p, q.s, -1);
         l.ref.seg = st->out.view(q.p).nbr + r.start;
         l.ref.len = r.len;
         l.ids = l.ref.seg;
@@ -393,7 +401,7 @@ struct Exec {
   void filter(int si, const gsmat_step_info& sp, Table& t, uint32_t next) {
     const gsmat_pattern& q = pl->pats[sp.tp];
     if (!is_var(q.s) && !is_var(q.o)) {
-      const LookupRes r = lookup(0, q.p, q.s, q.o);
+      const LookupRes r = lookup_tp(sp.tp, 0, q.p, q.s, q.o);
       if (r.found) {
         add_out(si, t.n);
         run(si + 1, t, next);
@@ -504,12 +512,13 @@ uint32_t step_completes(const gsmat_query_plan* pl, const gsmat_step_info& sp) {
   return m;
 }
 
-StepChoice step_candidates(const gsmat_store* st, const gsmat_query_plan* pl, const Table& t,
-                           uint32_t rem) {
+void step_candidates(const gsmat_store* st, const gsmat_query_plan* pl, const Table& t,
+                     uint32_t rem, StepChoice& ch) {
   uint64_t bound = 0;
   for (int c = 0; c < t.k; ++c) bound |= 1ull << t.var[c];
   auto is_bound = [&](int32_t term) { return !is_var(term) || (bound >> var_of(term) & 1); };
-  StepChoice ch;
+  ch.has_filter = false;
+  ch.nc = 0;
   const int np = (int)pl->pats.size();
   for (int tp = 0; tp < np; ++tp) {
     if (!(rem >> tp & 1)) continue;
@@ -524,7 +533,7 @@ StepChoice step_candidates(const gsmat_store* st, const gsmat_query_plan* pl, co
       ch.filter.orient = -1;
       ch.filter.var = -1;
       ch.has_filter = true;
-      return ch;
+      return;
     }
   }
   for (int tp = 0; tp < np; ++tp) {
@@ -533,13 +542,10 @@ StepChoice step_candidates(const gsmat_store* st, const gsmat_query_plan* pl, co
     const bool sb = is_var(q.s) && (bound >> var_of(q.s) & 1);
     const bool ob = is_var(q.o) && (bound >> var_of(q.o) & 1);
     if (sb == ob) continue;  // not connected (both bound were handled above)
-    const int orient = sb ? 0 : 1;
     const int32_t free_term = sb ? q.o : q.s;
     if (!is_var(free_term)) continue;
-    ch.col[ch.nc] = t.col[t.col_of(var_of(sb ? q.s : q.o))];
-    ch.pv[ch.nc] = orient == 0 ? st->out.view(q.p) : st->in.view(q.p);
-    ch.cand_tp[ch.nc] = tp;
-    ch.cand_or[ch.nc] = orient;
+    ch.cand_tp[ch.nc] = (int8_t)tp;
+    ch.cand_or[ch.nc] = sb ? 0 : 1;
     ++ch.nc;
   }
   int pick = -1;
@@ -557,7 +563,14 @@ StepChoice step_candidates(const gsmat_store* st, const gsmat_query_plan* pl, co
   ch.cartesian.tp = pick;
   ch.cartesian.orient = -1;
   ch.cartesian.var = -1;
-  return ch;
+}
+
+void candidate_view(const gsmat_store* st, const gsmat_query_plan* pl, const Table& t,
+                    const StepChoice& c, int i, const int32_t** col, PredView* pv) {
+  const gsmat_pattern& q = pl->pats[c.cand_tp[i]];
+  const bool from_s = c.cand_or[i] == 0;
+  *col = t.col[t.col_of(var_of(from_s ? q.s : q.o))];
+  *pv = from_s ? st->out.view(q.p) : st->in.view(q.p);
 }
 
 gsmat_step_info step_pick(const gsmat_query_plan* pl, const StepChoice& c, const int64_t* sums) {
@@ -598,8 +611,9 @@ void run_query(gsmat_store* st, const gsmat_query_plan* pl, int64_t budget_bytes
 
 // Statistics of each pattern for the planner.
 std::vector<TpStat> pattern_stats(const gsmat_store* st, const gsmat_pattern* pats, int n,
-                                  int mode, hipStream_t s) {
+                                  int mode, hipStream_t s, std::vector<gsmat_pat_lookup>* lk) {
   std::vector<TpStat> out(n);
+  if (lk) lk->assign(n, gsmat_pat_lookup{});
   std::vector<LookupReq> reqs;
   std::vector<int> req_of(n, -1);
   for (int i = 0; i < n; ++i) {
@@ -639,6 +653,7 @@ std::vector<TpStat> pattern_stats(const gsmat_store* st, const gsmat_pattern* pa
     for (int i = 0; i < n; ++i) {
       if (req_of[i] < 0) continue;
       const LookupRes& r = res[req_of[i]];
+      if (lk) (*lk)[i] = gsmat_pat_lookup{r.start, r.len, r.found, 1};
       const gsmat_pattern& q = pats[i];
       const bool sc = !is_var(q.s), oc = !is_var(q.o);
       const int64_t v = (sc && oc) ? r.found : r.len;
@@ -663,10 +678,15 @@ extern "C" gsmat_status gsmat_plan(const gsmat_store* st, const gsmat_pattern* p
     gsmat_status rc = validate_patterns(pats, n_pats, &nv, &err);
     if (rc != GSMAT_OK) throw StatusFail{rc, err};
     if (!st->built) throw StatusFail{GSMAT_ESTATE, "index not built"};
-    std::vector<TpStat> ts = pattern_stats(st, pats, n_pats, mode, (hipStream_t)stream);
+    std::vector<gsmat_pat_lookup> lk;
+    std::vector<TpStat> ts = pattern_stats(st, pats, n_pats, mode, (hipStream_t)stream, &lk);
     std::unique_ptr<gsmat_query_plan> pl(new gsmat_query_plan);
     rc = build_plan(pats, n_pats, mode, ts, pl.get(), &err);
     if (rc != GSMAT_OK) throw StatusFail{rc, err};
+    if (mode != GSMAT_PLAN_PAPER) {
+      pl->lk = std::move(lk);
+      pl->lk_store = st->uid;
+    }
     *out = pl.release();
     return GSMAT_OK;
   });

@@ -60,21 +60,22 @@ uint32_t step_completes(const gsmat_query_plan* pl, const gsmat_step_info& sp);
 
 // Adaptive choice on a bound table, first half: a filter when a remaining
 // connected pattern has both endpoints bound (filters never add rows), else
-// the connected expansions whose fan-out is to be sampled (nc of them; the
-// sample reads the bound column col[i] through view pv[i]).  With nothing
-// connected, `cartesian` names the smallest remaining pattern.
+// the connected expansions whose fan-out is to be sampled (nc of them:
+// pattern cand_tp[i] from its bound side, cand_or[i] = 0 subject, 1 object).
+// With nothing connected, `cartesian` names the smallest remaining pattern.
 struct StepChoice {
   bool has_filter = false;
   gsmat_step_info filter{};
   int nc = 0;
-  int cand_tp[kMaxPats];
-  int cand_or[kMaxPats];
-  const int32_t* col[kMaxPats];
-  PredView pv[kMaxPats];
+  int8_t cand_tp[kMaxPats];
+  int8_t cand_or[kMaxPats];
   gsmat_step_info cartesian{};
 };
-StepChoice step_candidates(const gsmat_store* st, const gsmat_query_plan* pl, const Table& t,
-                           uint32_t rem);
+void step_candidates(const gsmat_store* st, const gsmat_query_plan* pl, const Table& t,
+                     uint32_t rem, StepChoice& out);
+// Bound column and predicate view that candidate i's fan-out sample reads.
+void candidate_view(const gsmat_store* st, const gsmat_query_plan* pl, const Table& t,
+                    const StepChoice& c, int i, const int32_t** col, PredView* pv);
 // Second half: the expansion with the smallest sampled fan-out (the first
 // on ties); sums may be null when nc == 1.
 gsmat_step_info step_pick(const gsmat_query_plan* pl, const StepChoice& c, const int64_t* sums);
@@ -86,7 +87,8 @@ void run_query(gsmat_store* st, const gsmat_query_plan* pl, int64_t budget_bytes
 // Per-pattern statistics for the planner; lookups of constant endpoints go
 // to the device in one batch.
 std::vector<TpStat> pattern_stats(const gsmat_store* st, const gsmat_pattern* pats, int n,
-                                  int mode, hipStream_t s);
+                                  int mode, hipStream_t s,
+                                  std::vector<gsmat_pat_lookup>* lk = nullptr);
 
 }  // namespace gsmat
 

@@ -25,11 +25,22 @@ gsmat_status validate_patterns(const gsmat_pattern* pats, int32_t n, int32_t* n_
 
 }  // namespace gsmat
 
+// Row lookup of a pattern's constant endpoint(s), as taken while planning:
+// the row's offset and length in the orientation keyed by the constant, and
+// for an all-constant pattern whether the pair exists.
+struct gsmat_pat_lookup {
+  int32_t start = 0, len = 0, found = 0, valid = 0;
+};
+
 struct gsmat_query_plan {
   std::vector<gsmat_pattern> pats;
   int32_t n_vars = 0;
   int32_t mode = 0;
   std::vector<gsmat_step_info> steps;
+  // lookups of every pattern with a constant, valid for the index build
+  // with uid `lk_store` (empty when planning made none)
+  std::vector<gsmat_pat_lookup> lk;
+  uint64_t lk_store = 0;
 };
 
 namespace gsmat {

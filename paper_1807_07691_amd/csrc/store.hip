@@ -8,6 +8,7 @@
 //   row ids + row offsets (the Row / Rpos auxiliary arrays of Sec. 6.3) and
 //   member lists -> optional dense row pointers for heavy predicates.
 #include <algorithm>
+#include <atomic>
 #include <cstring>
 
 #include "store.hpp"
@@ -292,6 +293,8 @@ extern "C" gsmat_status gsmat_build_index(gsmat_store* st, int32_t dense_div, vo
     mem->free(st->d_o, raw, s);
     st->d_s = st->d_p = st->d_o = nullptr;
     GS_HIP(hipStreamSynchronize(s));
+    static std::atomic<uint64_t> next_uid{1};
+    st->uid = next_uid.fetch_add(1);
     st->built = true;
     return GSMAT_OK;
   });

@@ -43,6 +43,7 @@ struct gsmat_store {
   int32_t* d_p = nullptr;
   int32_t* d_o = nullptr;
   bool built = false;
+  uint64_t uid = 0;        // distinct for every index build in the process
   int64_t T = 0;           // distinct triples
   gsmat::Orientation out;  // by subject: rows = subjects, members = objects
   gsmat::Orientation in;   // by object: rows = objects, members = subjects

@@ -178,3 +178,15 @@ def test_batch_entry_points_validate_before_device_work(G):
     assert lib.gsmat_plan_batch(None, G._p(pats), G._p(n), 1, 1, None, out, G._p(st)) == \
         G.GSMAT_EINVAL
     assert out[0] is None
+
+
+def test_server_entry_points_validate_before_device_work(G):
+    lib = G.lib()
+    out = ctypes.c_void_p()
+    n = ctypes.c_int32()
+    assert lib.gsmat_server_new(None, 0, 0, -1, 1, None, ctypes.byref(out)) == G.GSMAT_EINVAL
+    assert out.value is None
+    assert lib.gsmat_server_submit(None, None, 0) == G.GSMAT_EINVAL
+    assert lib.gsmat_server_step(None, None, None, None) == G.GSMAT_EINVAL
+    assert lib.gsmat_server_poll(None, 0, None, None, None, ctypes.byref(n)) == G.GSMAT_EINVAL
+    lib.gsmat_server_free(None)
