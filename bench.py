@@ -96,7 +96,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="batch", choices=["tiny", "medium", "large", "batch"])
+    ap.add_argument("--workload", default="batch",
+                    choices=["tiny", "medium", "large", "batch", "serve"])
+    ap.add_argument("--rates", default="500,2000,8000",
+                    help="serve workload: Poisson arrival rates (queries/s)")
+    ap.add_argument("--serve-seconds", type=float, default=2.0,
+                    help="serve workload: arrival window per rate")
     ap.add_argument("--budget-gb", type=float, default=64.0,
                     help="per-step output budget; larger steps are chunked")
     ap.add_argument("--plan-mode", type=int, default=2,
@@ -125,7 +130,7 @@ def main():
     torch.cuda.set_device(0)
     import paper_1807_07691_amd as G
 
-    batch = args.workload == "batch"
+    batch = args.workload in ("batch", "serve")
     spec, qspec = W.CONFIGS["large" if batch else args.workload]
     if batch:
         qspec = W.BATCH
@@ -159,6 +164,16 @@ def main():
 
     budget = int(args.budget_gb * 2**30)
     mode = args.plan_mode
+    if args.workload == "serve":
+        gi = W.GraphIndex(s, p, o, spec.V, spec.P)
+        heavy = W.gen_heavy_queries(gi, spec)
+        gi.close()
+        log(f"heavy pool: {len(heavy)} queries of {min(q.count for q in heavy)}-"
+            f"{max(q.count for q in heavy)} rows")
+        out = bench_serve(args, G, spec, queries, heavy, st, sh, mode, stats, load_s, build_s)
+        print(json.dumps(out), flush=True)
+        st.close()
+        return
     if batch:
         out = bench_batch(args, G, W, spec, qspec, queries, st, sh, budget, mode, stats,
                           load_s, build_s, s, p, o)
@@ -535,6 +550,179 @@ def bench_batch(args, G, W, spec, qspec, queries, st, sh, budget, mode, stats, l
         "index_bytes": stats["device_bytes"],
         "roofline": roofline,
         "cpu_baseline": cpu,
+    }
+
+
+def bench_serve(args, G, spec, light, heavy, st, sh, mode, stats, load_s, build_s):
+    """Open-loop Poisson arrivals at each rate: the continuous-batching server
+    against a plain FIFO loop (one query at a time), same arrival sequence."""
+    import numpy as np
+    import torch
+    mem = 200 * 10**9  # admission budget (bytes of HBM for intermediates)
+
+    def arrivals(rate, seconds, seed):
+        rng = np.random.default_rng(seed)
+        n = int(rate * seconds)
+        t = np.cumsum(rng.exponential(1.0 / rate, n))
+        is_heavy = rng.random(n) < 0.01
+        pick = np.where(is_heavy, rng.integers(0, len(heavy), n), rng.integers(0, len(light), n))
+        qs = [heavy[k] if h else light[k] for h, k in zip(is_heavy, pick)]
+        return t, qs, int(is_heavy.sum())
+
+    def run_served(t_arr, qs):
+        sv = G.gsmat_server_new(st, mem, mem, -1, 1 << 20, stream=sh)
+        slow.clear()
+        n = len(qs)
+        lat = np.zeros(n)
+        rows = 0
+        nxt = done = steps = 0
+        rounds_active = 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        while done < n:
+            now = time.perf_counter() - t0
+            k = nxt
+            while k < n and t_arr[k] <= now:
+                k += 1
+            if k > nxt:
+                plans, _ = G.gsmat_plan_batch(st, [q.tps for q in qs[nxt:k]], mode, stream=sh,
+                                              as_set=True)
+                for i in range(k - nxt):
+                    G.gsmat_server_submit(sv, plans[i], nxt + i)
+                sv.plans[("set", nxt)] = plans  # freed with the server
+                nxt = k
+            ts_ = time.perf_counter()
+            a, w, d = G.gsmat_server_step(sv)
+            dt_ = time.perf_counter() - ts_
+            if dt_ > 0.002:
+                slow.append((round(dt_ * 1e3, 2), round(ts_ - t0, 4), a, w))
+            steps += 1
+            rounds_active += a
+            if d:
+                fin = G.gsmat_server_poll(sv)
+                tf = time.perf_counter() - t0
+                for tag, r, status in fin:
+                    lat[tag] = tf - t_arr[tag]
+                    rows += G.gsmat_result_info(r)["rows"]
+                    r.close()
+                done += len(fin)
+            if a == 0 and w == 0 and nxt < n:
+                while time.perf_counter() - t0 < t_arr[nxt]:
+                    pass
+        wall = time.perf_counter() - t0
+        sv.close()
+        return lat, rows, wall, steps, rounds_active / max(1, steps)
+
+    def run_plain(t_arr, qs):
+        n = len(qs)
+        lat = np.zeros(n)
+        rows = 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i, q in enumerate(qs):
+            while time.perf_counter() - t0 < t_arr[i]:
+                pass
+            pl = G.gsmat_plan(st, q.tps, mode, stream=sh)
+            r = G.gsmat_join(st, pl, mem, -1, stream=sh)
+            rows += G.gsmat_result_info(r)["rows"]
+            r.close()
+            pl.close()
+            lat[i] = time.perf_counter() - t0 - t_arr[i]
+        wall = time.perf_counter() - t0
+        return lat, rows, wall
+
+    slow = []  # served steps over 2 ms: (ms, at s, active, waiting)
+    gc_pauses = []
+    import gc
+
+    def gc_cb(phase, info, _t=[0.0]):
+        if phase == "start":
+            _t[0] = time.perf_counter()
+        else:
+            gc_pauses.append((info.get("generation"), round((time.perf_counter() - _t[0]) * 1e3, 2)))
+    gc.callbacks.append(gc_cb)
+    ms = lambda x: round(float(x) * 1e3, 3)  # noqa: E731
+    # warm both paths (allocator, pinned buffers, code objects)
+    t_w, q_w, _ = arrivals(2000, 0.25, 99)
+    run_served(t_w, q_w)
+    run_plain(t_w, q_w)
+    # the driver loops are Python: objects made before timing are frozen and
+    # the collector is off while requests run (a full collection paused the
+    # loop for ~47 ms), for the served and the plain loop alike
+    gc.collect()
+    gc.freeze()
+    res = []
+    for ri, rate in enumerate(float(x) for x in args.rates.split(",")):
+        t_arr, qs, n_heavy = arrivals(rate, args.serve_seconds, 1000 + ri)
+        log(f"rate {rate:.0f}/s: {len(qs)} arrivals ({n_heavy} heavy)")
+        gc_pauses.clear()
+        gc.disable()
+        lat_s, rows_s, wall_s, steps, mean_active = run_served(t_arr, qs)
+        gc.enable()
+        worst = sorted(slow, reverse=True)[:8]
+        log(f"  served: {len(slow)} steps over 2 ms, worst {worst}; gc pauses "
+            f"{sorted(gc_pauses, key=lambda x: -x[1])[:6]}")
+        gc.disable()
+        lat_p, rows_p, wall_p = run_plain(t_arr, qs)
+        gc.enable()
+        gc.collect()
+        assert rows_s == rows_p == sum(q.count for q in qs), (rows_s, rows_p)
+        r = {
+            "rate_qps": rate,
+            "arrivals": len(qs),
+            "heavy": n_heavy,
+            "rows": rows_s,
+            "served": {"bindings_per_s": round(rows_s / wall_s, 1),
+                       "p50_ms": ms(np.percentile(lat_s, 50)),
+                       "p99_ms": ms(np.percentile(lat_s, 99)),
+                       "makespan_s": round(wall_s, 3), "steps": steps,
+                       "mean_active": round(mean_active, 1)},
+            "plain": {"bindings_per_s": round(rows_p / wall_p, 1),
+                      "p50_ms": ms(np.percentile(lat_p, 50)),
+                      "p99_ms": ms(np.percentile(lat_p, 99)),
+                      "makespan_s": round(wall_p, 3)},
+        }
+        log(f"  served p50 {r['served']['p50_ms']} ms p99 {r['served']['p99_ms']} ms "
+            f"{r['served']['bindings_per_s']:.3g} b/s ({steps} steps, {mean_active:.1f} active); "
+            f"plain p50 {r['plain']['p50_ms']} ms p99 {r['plain']['p99_ms']} ms "
+            f"{r['plain']['bindings_per_s']:.3g} b/s")
+        res.append(r)
+    top = res[-1]
+    return {
+        "metric": "served bindings/sec + p50/p99 latency (open-loop Poisson), served vs plain",
+        "value": top["served"]["bindings_per_s"],
+        "unit": "bindings/s",
+        "n_gpus": 1,
+        "steps": len(res),
+        "warmup": 1,
+        "ms_per_step": round(top["served"]["makespan_s"] * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"serve: {spec.V} vertices, {spec.P} predicates Zipf({spec.zipf_s}), "
+                        f"{spec.T} triples; Poisson arrivals at {args.rates} q/s for "
+                        f"{args.serve_seconds}s each, drawn from {len(light)} BGPs with "
+                        f"log-uniform 1..1e6-row results plus 1% from {len(heavy)} heavy BGPs "
+                        f"(5e7-2e8 rows)",
+            "mode": "served (gsmat_server: continuous batching, 200 GB admission budget)",
+            "plan_mode": mode,
+            "parallelism": "single-gpu",
+        },
+        "p50_ms": top["served"]["p50_ms"],
+        "p99_ms": top["served"]["p99_ms"],
+        "latency_note": "latency = result polled minus arrival, planning included; value and "
+                        "p50/p99 are the highest rate's served figures; rows count every "
+                        "result, checked equal between served and plain; the Python garbage "
+                        "collector is off during both timed loops",
+        "rates": res,
+        "load_s": round(load_s, 3),
+        "build_s": round(build_s, 3),
+        "index_bytes": stats["device_bytes"],
+        "roofline": None,
+        "cpu_baseline": None,
     }
 
 

@@ -367,6 +367,36 @@ def gen_batch_queries(gi: GraphIndex, spec: GraphSpec, qs: QuerySpec = BATCH, n_
     return [out[i] for i in perm]
 
 
+def gen_heavy_queries(gi: GraphIndex, spec: GraphSpec, n_queries=16, lo=5 * 10**7,
+                      hi=2 * 10**8, seed_offset=11, round_size=64, max_rounds=100):
+    """n_queries BGPs with exact counts in [lo, hi] (the heavy share of a
+    served mix): constant-free walks of 2-4 patterns, counted exactly and
+    accepted in candidate order."""
+    seed = (spec.seed + seed_offset) & (2**64 - 1)
+    kinds = [KIND_CHAIN, KIND_SSTAR, KIND_OSTAR, KIND_SNOW]
+    out = []
+    j = 0
+    for _ in range(max_rounds):
+        if len(out) >= n_queries:
+            break
+        pend = []
+        for _ in range(round_size):
+            ctr = j + 1
+            j += 1
+            kind = kinds[int(_rng_u64(seed, 2 * ctr) % 4)]
+            nt = int(4 if kind == KIND_SNOW else 2 + _rng_u64(seed, 2 * ctr + 1) % 3)
+            w = gi.walk(kind, nt, 0, -1, seed, ctr, SHAPE_BIAS[kind])
+            if w is not None:
+                pend.append((kind, w))
+        counts = gi.count_many([(w[0], w[2]) for _, w in pend])
+        for (kind, (tp, wit, nv)), cnt in zip(pend, counts):
+            if lo <= cnt <= hi and len(out) < n_queries:
+                out.append(Query(tp, nv, wit, int(cnt), kind, 0))
+    if len(out) < n_queries:
+        raise RuntimeError("could not draw the heavy queries")
+    return out
+
+
 def make_workload(name: str):
     spec, qs = CONFIGS[name]
     s, p, o = gen_graph(spec)
