@@ -113,3 +113,47 @@ def test_large_counts_and_sampled_rows(G):
         r.close()
         pl.close()
     assert sampled >= len(sample) // 2
+
+
+@pytest.mark.timeout(900)
+def test_batch_workload_full_size(G):
+    """The 4096-query batch set on the 200M-triple graph in one gsmat_join_batch
+    (the benchmark's launch configuration): every count against the
+    generator's tree count; 48 sampled queries row for row against the plain
+    join, and the smallest of them against the oracle."""
+    import oracle as O
+    import workload as W
+    spec, _ = W.CONFIGS["large"]
+    s, p, o = W.gen_graph(spec)
+    gi = W.GraphIndex(s, p, o, spec.V, spec.P)
+    qs = W.gen_batch_queries(gi, spec)
+    gi.close()
+    st = G.gsmat_load_triples(s, p, o, spec.V, spec.P)
+    G.gsmat_build_index(st)
+    print(f"[gpu] batch full size: {len(qs)} queries", flush=True)
+    plans, _ = G.gsmat_plan_batch(st, [q.tps for q in qs], G.PLAN_ADAPTIVE, as_set=True)
+    results, _ = G.gsmat_join_batch(st, plans, BUDGET, as_set=True)
+    rows = results.rows()
+    assert rows.tolist() == [q.count for q in qs]
+    sample = list(range(0, len(qs), len(qs) // 48))[:48]
+    ds = O.Dataset(s, p, o)
+    oracle_checked = 0
+    for i in sample:
+        q = qs[i]
+        got = G.gsmat_fetch_bindings(results[i])
+        pl = G.gsmat_plan(st, q.tps, G.PLAN_ADAPTIVE)
+        r = G.gsmat_join(st, pl, BUDGET)
+        assert np.array_equal(got, G.gsmat_fetch_bindings(r)), i
+        r.close()
+        pl.close()
+        if q.count <= 10**4:
+            try:
+                want = ds.join(q.tps, q.n_vars, cap_rows=2 * 10**7)
+            except ValueError:  # the oracle's query-order intermediate is above its cap
+                continue
+            assert np.array_equal(_sorted(got), want), i
+            oracle_checked += 1
+    print(f"[gpu] batch full size: {oracle_checked} sampled queries against the oracle", flush=True)
+    assert oracle_checked >= 8
+    results.close()
+    plans.close()
