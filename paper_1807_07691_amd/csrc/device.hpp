@@ -105,6 +105,93 @@ __device__ inline void row_lookup(const PredView& pv, int32_t v, int32_t& start,
   }
 }
 
+// Lower bounds of N values, v[j] in a[lo[j], lo[j] + n[j]): the searches
+// advance in lockstep, one round of N independent loads per halving; on
+// return lo[j] is the position of the first element >= v[j].
+template <int N>
+__device__ inline void lower_bound_n(const int32_t* __restrict__ a, const int32_t (&v)[N],
+                                     int32_t (&lo)[N], int32_t (&n)[N]) {
+  for (;;) {
+    int32_t kv[N];
+    bool any = false;
+#pragma unroll
+    for (int j = 0; j < N; ++j) kv[j] = n[j] > 0 ? a[lo[j] + (n[j] >> 1)] : 0;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      if (n[j] > 0) {
+        const int32_t h = n[j] >> 1;
+        if (kv[j] < v[j]) {
+          lo[j] += h + 1;
+          n[j] -= h + 1;
+        } else {
+          n[j] = h;
+        }
+      }
+      any |= n[j] > 0;
+    }
+    if (!any) break;
+  }
+}
+
+// Row lookups of N values at once: the N searches advance in lockstep, so
+// each round of their loads is issued together instead of one search after
+// another.  ok[j] false: start = len = 0.
+template <int N>
+__device__ inline void row_lookup_n(const PredView& pv, const int32_t (&v)[N], const bool (&ok)[N],
+                                    int32_t (&start)[N], int32_t (&len)[N]) {
+  if (pv.dense) {
+    int32_t a[N], b[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      a[j] = ok[j] ? pv.dense[v[j]] : 0;
+      b[j] = ok[j] ? pv.dense[v[j] + 1] : 0;
+    }
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      start[j] = a[j];
+      len[j] = b[j] - a[j];
+    }
+    return;
+  }
+  int32_t lo[N], n[N];
+  if (pv.dir) {
+    int32_t a[N], b[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const int32_t bk = v[j] >> pv.dir_shift;
+      a[j] = ok[j] ? pv.dir[bk] : 0;
+      b[j] = ok[j] ? pv.dir[bk + 1] : 0;
+    }
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      lo[j] = a[j];
+      n[j] = b[j] - a[j];
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      lo[j] = 0;
+      n[j] = ok[j] ? pv.nr : 0;
+    }
+  }
+  lower_bound_n<N>(pv.keys, v, lo, n);
+  int32_t k[N];
+#pragma unroll
+  for (int j = 0; j < N; ++j) k[j] = (ok[j] && lo[j] < pv.nr) ? pv.keys[lo[j]] : -1;
+  int32_t a[N], b[N];
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    const bool hit = ok[j] && k[j] == v[j];
+    a[j] = hit ? pv.ptr[lo[j]] : 0;
+    b[j] = hit ? pv.ptr[lo[j] + 1] : 0;
+  }
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    start[j] = a[j];
+    len[j] = b[j] - a[j];
+  }
+}
+
 __device__ inline bool seg_contains(const int32_t* __restrict__ a, int32_t n, int32_t v) {
   const int32_t r = lower_bound_i32(a, n, v);
   return r < n && a[r] == v;
@@ -212,17 +299,24 @@ __device__ inline int64_t count_expand_tile(int64_t tile, const int32_t* __restr
                                             int32_t* __restrict__ N,
                                             int32_t* __restrict__ start) {
   const int64_t tile0 = tile * kTile;
+  int32_t v[kItems], st[kItems], len[kItems];
+  bool ok[kItems];
+#pragma unroll
+  for (int j = 0; j < kItems; ++j) {
+    const int64_t i = tile0 + (int64_t)j * kBlock + threadIdx.x;
+    ok[j] = i < n;
+    v[j] = ok[j] ? col[i] : 0;
+  }
+  row_lookup_n<kItems>(pv, v, ok, st, len);
   int64_t loc = 0;
 #pragma unroll
   for (int j = 0; j < kItems; ++j) {
     const int64_t i = tile0 + (int64_t)j * kBlock + threadIdx.x;
-    if (i < n) {
-      int32_t st, len;
-      row_lookup(pv, col[i], st, len);
-      N[i] = len;
-      start[i] = st;
-      loc += len;
-      if (kNonEmpty && len > 0) loc += (int64_t)1 << kNonEmptyShift;
+    if (ok[j]) {
+      N[i] = len[j];
+      start[i] = st[j];
+      loc += len[j];
+      if (kNonEmpty && len[j] > 0) loc += (int64_t)1 << kNonEmptyShift;
     }
   }
   return block_sum(loc);
@@ -232,16 +326,32 @@ __device__ inline int64_t count_expand_tile(int64_t tile, const int32_t* __restr
 __device__ inline int64_t flag_filter_tile(int64_t tile, const ProbeArgs& pa, int64_t n,
                                            const PredView& pv, uint8_t* __restrict__ flags) {
   const int64_t tile0 = tile * kTile;
+  int32_t sv[kItems], ov[kItems], st[kItems], len[kItems];
+  bool ok[kItems];
+#pragma unroll
+  for (int j = 0; j < kItems; ++j) {
+    const int64_t i = tile0 + (int64_t)j * kBlock + threadIdx.x;
+    ok[j] = i < n;
+    sv[j] = ok[j] ? (pa.s_col ? pa.s_col[i] : pa.s_const) : 0;
+    ov[j] = ok[j] ? (pa.o_col ? pa.o_col[i] : pa.o_const) : 0;
+  }
+  row_lookup_n<kItems>(pv, sv, ok, st, len);
+  // o_i among the members of row s_i
+  int32_t lo[kItems], cnt[kItems], k[kItems];
+#pragma unroll
+  for (int j = 0; j < kItems; ++j) {
+    lo[j] = st[j];
+    cnt[j] = len[j];
+  }
+  lower_bound_n<kItems>(pv.nbr, ov, lo, cnt);
+#pragma unroll
+  for (int j = 0; j < kItems; ++j) k[j] = (len[j] > 0 && lo[j] < st[j] + len[j]) ? pv.nbr[lo[j]] : -1;
   int64_t loc = 0;
 #pragma unroll
   for (int j = 0; j < kItems; ++j) {
     const int64_t i = tile0 + (int64_t)j * kBlock + threadIdx.x;
-    if (i < n) {
-      const int32_t sv = pa.s_col ? pa.s_col[i] : pa.s_const;
-      const int32_t ov = pa.o_col ? pa.o_col[i] : pa.o_const;
-      int32_t st, len;
-      row_lookup(pv, sv, st, len);
-      const uint8_t f = (len > 0 && seg_contains(pv.nbr + st, len, ov)) ? 1 : 0;
+    if (ok[j]) {
+      const uint8_t f = (len[j] > 0 && k[j] == ov[j]) ? 1 : 0;
       flags[i] = f;
       loc += f;
     }
@@ -254,25 +364,42 @@ __device__ inline int64_t flag_intersect_tile(int64_t tile, const int32_t* __res
                                               int64_t n, const ListRef* lists, int nl,
                                               uint8_t* __restrict__ flags) {
   const int64_t tile0 = tile * kTile;
+  int32_t x[kItems];
+  bool keep[kItems];
+#pragma unroll
+  for (int j = 0; j < kItems; ++j) {
+    const int64_t i = tile0 + (int64_t)j * kBlock + threadIdx.x;
+    keep[j] = i < n;
+    x[j] = keep[j] ? driver[i] : 0;
+  }
+  for (int l = 0; l < nl; ++l) {
+    const ListRef& L = lists[l];
+    if (L.is_keys) {
+      int32_t st[kItems], len[kItems];
+      row_lookup_n<kItems>(L.pv, x, keep, st, len);
+#pragma unroll
+      for (int j = 0; j < kItems; ++j) keep[j] = keep[j] && len[j] > 0;
+    } else {
+      int32_t lo[kItems], cnt[kItems], k[kItems];
+#pragma unroll
+      for (int j = 0; j < kItems; ++j) {
+        lo[j] = 0;
+        cnt[j] = keep[j] ? (int32_t)L.len : 0;
+      }
+      lower_bound_n<kItems>(L.seg, x, lo, cnt);
+#pragma unroll
+      for (int j = 0; j < kItems; ++j) k[j] = (keep[j] && lo[j] < (int32_t)L.len) ? L.seg[lo[j]] : -1;
+#pragma unroll
+      for (int j = 0; j < kItems; ++j) keep[j] = keep[j] && k[j] == x[j];
+    }
+  }
   int64_t loc = 0;
 #pragma unroll
   for (int j = 0; j < kItems; ++j) {
     const int64_t i = tile0 + (int64_t)j * kBlock + threadIdx.x;
     if (i < n) {
-      const int32_t x = driver[i];
-      bool keep = true;
-      for (int l = 0; l < nl && keep; ++l) {
-        const ListRef& L = lists[l];
-        if (L.is_keys) {
-          int32_t st, len;
-          row_lookup(L.pv, x, st, len);
-          keep = len > 0;
-        } else {
-          keep = seg_contains(L.seg, (int32_t)L.len, x);
-        }
-      }
-      flags[i] = keep ? 1 : 0;
-      loc += keep ? 1 : 0;
+      flags[i] = keep[j] ? 1 : 0;
+      loc += keep[j] ? 1 : 0;
     }
   }
   return block_sum(loc);
