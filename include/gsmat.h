@@ -63,6 +63,7 @@ typedef struct gsmat_store gsmat_store;   /* device CSR/CSC of every predicate *
 typedef struct gsmat_query_plan gsmat_query_plan; /* host-only ordered step list */
 typedef struct gsmat_result gsmat_result; /* device binding table, possibly in segments */
 typedef struct gsmat_server gsmat_server; /* request loop over one store (continuous batching) */
+typedef struct gsmat_dict gsmat_dict;     /* host string dictionary (h_p, h_so) */
 
 /* Optional device allocator.  alloc returns NULL on failure.  free receives
  * the pointer and size that alloc returned.  Both are called on the host
@@ -234,6 +235,55 @@ gsmat_status gsmat_fetch_bindings(const gsmat_result* r, int64_t row_offset, int
                                   int32_t* host_rows, int64_t* n_written, void* stream);
 
 void gsmat_result_free(gsmat_result* r);
+
+/* ---- text boundary: dictionary and BGP parser (Sec. 5.2, Sec. 6.3) -------- */
+
+/* A host dictionary: the bijections h_p (predicates) and h_so (subjects and
+ * objects together), each assigning codes by order of occurrence (Sec. 5.2).
+ * Codes are 0-based (the paper's codes minus one).  Host only; no device
+ * work; not thread-safe. */
+gsmat_status gsmat_dict_new(gsmat_dict** out);
+void gsmat_dict_free(gsmat_dict* d);
+
+/* Parses text triples, one per line, each ended by '.' or the line break:
+ * terms are <iri>, "literal" (optional @lang or ^^<iri>), _:blank or any
+ * other token without white space; '#' starts a comment.  Terms are coded in
+ * order of occurrence (subject, predicate, object of each triple in turn),
+ * continuing the dictionary's earlier codes.  The triples' codes are kept
+ * for gsmat_dict_triples (replacing the previous text's).  EINVAL on a
+ * syntax error (message names the line); the dictionary is then unchanged. */
+gsmat_status gsmat_dict_load_text(gsmat_dict* d, const char* text, size_t len,
+                                  int64_t* n_triples);
+
+/* Copies the last loaded text's triple codes: s, p, o each [n_triples]. */
+gsmat_status gsmat_dict_triples(const gsmat_dict* d, int32_t* s, int32_t* p, int32_t* o);
+
+/* Number of subject/object terms and of predicates coded so far (the
+ * n_vertices and n_predicates to load the triples with). */
+gsmat_status gsmat_dict_sizes(const gsmat_dict* d, int32_t* n_terms, int32_t* n_predicates);
+
+/* Code of one term (is_predicate selects h_p or h_so), -1 if absent. */
+gsmat_status gsmat_dict_lookup(const gsmat_dict* d, const char* term, size_t len,
+                               int32_t is_predicate, int32_t* code);
+
+/* The term of a code (the decoding of results, Sec. 6.3): *len = its length;
+ * with buf, copies it NUL-terminated (ETOOBIG if cap is too small).  EINVAL
+ * for a code the dictionary does not have. */
+gsmat_status gsmat_dict_term(const gsmat_dict* d, int32_t code, int32_t is_predicate, char* buf,
+                             size_t cap, size_t* len);
+
+/* Parses a BGP: either "SELECT ... WHERE { patterns }" or the bare pattern
+ * list, patterns separated by '.'.  ?name and $name are variables, numbered
+ * 0.. by first appearance (every variable is returned; a projection list is
+ * not used); other terms are constants coded with the dictionary, a term it
+ * has not seen getting one past its last code (it matches nothing).
+ * Writes *n_pats (ETOOBIG with *n_pats set when it exceeds cap) and
+ * *n_vars; var_names (may be NULL) receives the variable names without
+ * their sigil, NUL-separated, in variable order.  EUNSUPPORTED on a
+ * variable predicate. */
+gsmat_status gsmat_parse_bgp(const gsmat_dict* d, const char* text, size_t len,
+                             gsmat_pattern* pats, int32_t cap, int32_t* n_pats, int32_t* n_vars,
+                             char* var_names, size_t names_cap);
 
 /* ---- serving (continuous batching) ---------------------------------------- */
 

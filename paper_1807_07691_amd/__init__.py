@@ -37,7 +37,9 @@ EXPORTED = [
     "gsmat_prof_read", "gsmat_prof_host", "gsmat_release_pools", "gsmat_plan_batch",
     "gsmat_join_batch", "gsmat_plan_free_many", "gsmat_result_free_many",
     "gsmat_result_rows_many", "gsmat_server_new", "gsmat_server_submit", "gsmat_server_step",
-    "gsmat_server_poll", "gsmat_server_free",
+    "gsmat_server_poll", "gsmat_server_free", "gsmat_dict_new", "gsmat_dict_free",
+    "gsmat_dict_load_text", "gsmat_dict_triples", "gsmat_dict_sizes", "gsmat_dict_lookup",
+    "gsmat_dict_term", "gsmat_parse_bgp",
 ]
 
 
@@ -130,6 +132,23 @@ def _load():
     L.gsmat_server_poll.argtypes = [vp, i32, vp, vp, vp, vp]
     L.gsmat_server_free.restype = None
     L.gsmat_server_free.argtypes = [vp]
+    sz = ctypes.c_size_t
+    L.gsmat_dict_new.restype = i32
+    L.gsmat_dict_new.argtypes = [pp]
+    L.gsmat_dict_free.restype = None
+    L.gsmat_dict_free.argtypes = [vp]
+    L.gsmat_dict_load_text.restype = i32
+    L.gsmat_dict_load_text.argtypes = [vp, ctypes.c_char_p, sz, vp]
+    L.gsmat_dict_triples.restype = i32
+    L.gsmat_dict_triples.argtypes = [vp, vp, vp, vp]
+    L.gsmat_dict_sizes.restype = i32
+    L.gsmat_dict_sizes.argtypes = [vp, vp, vp]
+    L.gsmat_dict_lookup.restype = i32
+    L.gsmat_dict_lookup.argtypes = [vp, ctypes.c_char_p, sz, i32, vp]
+    L.gsmat_dict_term.restype = i32
+    L.gsmat_dict_term.argtypes = [vp, i32, i32, vp, sz, vp]
+    L.gsmat_parse_bgp.restype = i32
+    L.gsmat_parse_bgp.argtypes = [vp, ctypes.c_char_p, sz, vp, i32, vp, vp, vp, sz]
     return L
 
 
@@ -506,6 +525,81 @@ def gsmat_server_poll(server, cap=4096):
         out.append((tag, Result(ctypes.c_void_p(hs[i]), server.store) if hs[i] else None,
                     int(st[i])))
     return out
+
+
+class Dict:
+    """Host dictionary of terms (gsmat_dict_*)."""
+
+    def __init__(self, handle):
+        self.h = handle
+        _live_plans.add(self)
+
+    def close(self):
+        if self.h:
+            _lib.gsmat_dict_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+
+def gsmat_dict_new():
+    h = ctypes.c_void_p()
+    _check(_lib.gsmat_dict_new(ctypes.byref(h)))
+    return Dict(h)
+
+
+def gsmat_dict_load_text(d, text):
+    """Codes the text's triples; returns (s, p, o) int32 arrays."""
+    b = text.encode() if isinstance(text, str) else bytes(text)
+    n = ctypes.c_int64()
+    _check(_lib.gsmat_dict_load_text(d.h, b, len(b), ctypes.byref(n)))
+    s, p, o = (np.empty(n.value, np.int32) for _ in range(3))
+    _check(_lib.gsmat_dict_triples(d.h, _p(s), _p(p), _p(o)))
+    return s, p, o
+
+
+def gsmat_dict_sizes(d):
+    a, b = ctypes.c_int32(), ctypes.c_int32()
+    _check(_lib.gsmat_dict_sizes(d.h, ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
+
+
+def gsmat_dict_lookup(d, term, is_predicate=False):
+    b = term.encode()
+    c = ctypes.c_int32()
+    _check(_lib.gsmat_dict_lookup(d.h, b, len(b), int(is_predicate), ctypes.byref(c)))
+    return c.value
+
+
+def gsmat_dict_term(d, code, is_predicate=False):
+    n = ctypes.c_size_t()
+    _check(_lib.gsmat_dict_term(d.h, int(code), int(is_predicate), None, 0, ctypes.byref(n)))
+    buf = ctypes.create_string_buffer(n.value + 1)
+    _check(_lib.gsmat_dict_term(d.h, int(code), int(is_predicate), buf, n.value + 1,
+                                ctypes.byref(n)))
+    return buf.value.decode()
+
+
+def gsmat_parse_bgp(d, text):
+    """(patterns (n, 3) int32, variable names)."""
+    b = text.encode()
+    n, nv = ctypes.c_int32(), ctypes.c_int32()
+    rc = _lib.gsmat_parse_bgp(d.h, b, len(b), None, 0, ctypes.byref(n), ctypes.byref(nv), None, 0)
+    if rc not in (GSMAT_OK, GSMAT_ETOOBIG):
+        _check(rc)
+    arr = (_Pattern * max(n.value, 1))()
+    names = ctypes.create_string_buffer(len(b) + 1)
+    _check(_lib.gsmat_parse_bgp(d.h, b, len(b), arr, n.value, ctypes.byref(n), ctypes.byref(nv),
+                                names, len(b) + 1))
+    tps = np.array([[arr[i].s, arr[i].p, arr[i].o] for i in range(n.value)], np.int32).reshape(-1, 3)
+    raw = names.raw
+    out, at = [], 0
+    for _ in range(nv.value):
+        end = raw.index(b"\0", at)
+        out.append(raw[at:end].decode())
+        at = end + 1
+    return tps, out
 
 
 def gsmat_result_info(result):
