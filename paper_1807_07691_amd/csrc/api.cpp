@@ -51,6 +51,11 @@ void host_sync(hipStream_t s) {
   GS_HIP(hipStreamSynchronize(s));
 }
 
+void host_event_sync(hipEvent_t e) {
+  HostTimer t(&g_sync_ms, &g_syncs);
+  GS_HIP(hipEventSynchronize(e));
+}
+
 // Device memory: a caching block allocator per device.  Blocks come from
 // hipMalloc and are never returned to the driver while the process runs
 // (unless an allocation fails, or gsmat_release_pools is called): a freed

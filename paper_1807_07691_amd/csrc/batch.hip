@@ -51,10 +51,26 @@ struct Pinned {
   }
 };
 enum { kPinCount = 0, kPinWrite, kPinSample, kPinTotals, kPinParts, kPinLookup, kPinCount_ };
-Pinned* pins() {
-  thread_local Pinned p[kPinCount_];
-  return p;
+// Per slot (a batch may use its own set).
+Pinned* pins(int slot = 0) {
+  thread_local Pinned p[2][kPinCount_];
+  return p[slot];
 }
+
+// An event owned by one batch (created on first use).
+struct Event {
+  hipEvent_t e = nullptr;
+  Event() = default;
+  Event(const Event&) = delete;
+  Event& operator=(const Event&) = delete;
+  ~Event() {
+    if (e) (void)hipEventDestroy(e);
+  }
+  hipEvent_t get() {
+    if (!e) GS_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    return e;
+  }
+};
 
 // Byte layout of several device slices inside one arena (256-byte aligned).
 struct Layout {
@@ -118,6 +134,23 @@ struct Batch {
   std::vector<BQ> q;
   int64_t round_budget = 0;    // outputs of one round (<= 0: none)
   bool defer = false;          // over the round budget: wait a round (else run alone)
+  int slot = 0;                // pinned buffer set
+  Event ev;                    // end of the last phase's launches
+
+  // state of the round in progress, carried from one phase to the next
+  struct Round {
+    bool sampled = false;
+    int64_t* hp = nullptr;  // fan-out sample partials (pinned)
+    int nt = 0;             // tasks of the count launch
+    int64_t ntiles = 0;
+    std::vector<CTask> tasks;
+    std::vector<int> owner;  // query of each task
+    std::vector<GItem> items;
+    std::vector<size_t> o_P;
+    std::shared_ptr<Arena> A;  // count-phase scratch
+    int64_t* ts = nullptr;
+    int64_t* htot = nullptr;
+  } R;
 
   DeviceMem* mem() { return st->mem.get(); }
 
@@ -204,7 +237,19 @@ struct Batch {
 
   void admit(size_t first);
   void run();
-  void round();
+  // One round in three phases, each ending with launches and an event the
+  // next phase waits for.  (Interleaving the phases of two half batches on one
+  // stream was measured slower: half-size launches cost more than the overlap
+  // of host work saves.)
+  bool phase_sample();  // false when no query is active
+  void phase_count();
+  void phase_write();
+  void round() {
+    if (phase_sample()) {
+      phase_count();
+      phase_write();
+    }
+  }
 };
 
 // Constant lookups of queries [first, q.size()): the plan's where it made
@@ -247,12 +292,14 @@ void Batch::run() {
   }
 }
 
-void Batch::round() {
-  const int nq = (int)q.size();
+bool Batch::phase_sample() {
   // ---- step choice (adaptive queries sample their candidate expansions)
+  R = Round();
+  bool any = false;
   std::vector<SCand> cands;
   for (BQ& b : q) {
     if (b.state != kActive) continue;
+    any = true;
     b.task = -1;
     b.cand0 = -1;
     const gsmat_query_plan* pl = b.pl;
@@ -279,13 +326,23 @@ void Batch::round() {
     const size_t nc = cands.size();
     Layout L;
     const size_t o_c = L.add(sizeof(SCand) * nc);
-    Arena a(mem(), L.bytes, s);
-    SCand* hc = (SCand*)pins()[kPinSample].get(sizeof(SCand) * nc);
-    int64_t* hp = (int64_t*)pins()[kPinParts].get(sizeof(int64_t) * nc * kSampleBlocks);
+    Arena a(mem(), L.bytes, s);  // freed in stream order after the launch
+    SCand* hc = (SCand*)pins(slot)[kPinSample].get(sizeof(SCand) * nc);
+    R.hp = (int64_t*)pins(slot)[kPinParts].get(sizeof(int64_t) * nc * kSampleBlocks);
     std::memcpy(hc, cands.data(), sizeof(SCand) * nc);
     GS_HIP(hipMemcpyAsync((char*)a.p + o_c, hc, sizeof(SCand) * nc, hipMemcpyHostToDevice, s));
-    launch_b_sample((const SCand*)((char*)a.p + o_c), (int64_t)nc, hp, s);
-    host_sync(s);
+    launch_b_sample((const SCand*)((char*)a.p + o_c), (int64_t)nc, R.hp, s);
+    GS_HIP(hipEventRecord(ev.get(), s));
+    R.sampled = true;
+  }
+  return any;
+}
+
+void Batch::phase_count() {
+  const int nq = (int)q.size();
+  if (R.sampled) {
+    host_event_sync(ev.get());
+    const int64_t* hp = R.hp;
     for (BQ& b : q) {
       if (b.state != kActive || b.cand0 < 0) continue;
       int64_t sum[kMaxPats];
@@ -298,8 +355,8 @@ void Batch::round() {
   }
 
   // ---- count phase: tasks
-  std::vector<CTask> tasks;
-  std::vector<int> owner;  // query of each task
+  std::vector<CTask>& tasks = R.tasks;
+  std::vector<int>& owner = R.owner;
   std::vector<ListRef> lists;
   for (int qi = 0; qi < nq; ++qi) {
     BQ& b = q[qi];
@@ -427,13 +484,17 @@ void Batch::round() {
     }
   }
   const int nt = (int)tasks.size();
+  R.nt = nt;
   if (nt == 0) return;
 
   // scratch of the count phase
   int64_t ntiles = 0;
-  std::vector<GItem> items(nt);
+  std::vector<GItem>& items = R.items;
+  items.resize(nt);
   Layout LA;
-  std::vector<size_t> o_N(nt), o_start(nt), o_P(nt), o_flags(nt);
+  std::vector<size_t>& o_P = R.o_P;
+  o_P.resize(nt);
+  std::vector<size_t> o_N(nt), o_start(nt), o_flags(nt);
   for (int i = 0; i < nt; ++i) {
     items[i] = GItem{ntiles, i, 0};
     ntiles += ceil_div(tasks[i].n, kTile);
@@ -452,8 +513,8 @@ void Batch::round() {
   const size_t o_items = LA.add(sizeof(GItem) * nt);
   const size_t o_lists = LA.add(sizeof(ListRef) * std::max<size_t>(lists.size(), 1));
   const size_t o_ne = LA.add(sizeof(int64_t) * nt);
-  auto A = std::make_shared<Arena>(mem(), LA.bytes, s);
-  char* da = (char*)A->p;
+  R.A = std::make_shared<Arena>(mem(), LA.bytes, s);
+  char* da = (char*)R.A->p;
   int64_t* dne = (int64_t*)(da + o_ne);
   for (int i = 0; i < nt; ++i) {
     if (tasks[i].kind == kTaskExpand) {
@@ -467,21 +528,37 @@ void Batch::round() {
   int64_t* ts = (int64_t*)(da + o_ts);
   {
     const size_t up = o_ne + sizeof(int64_t) * nt - o_tasks;
-    char* h = (char*)pins()[kPinCount].get(up);
+    char* h = (char*)pins(slot)[kPinCount].get(up);
     std::memcpy(h, tasks.data(), sizeof(CTask) * nt);
     std::memcpy(h + (o_items - o_tasks), items.data(), sizeof(GItem) * nt);
     if (!lists.empty()) std::memcpy(h + (o_lists - o_tasks), lists.data(), sizeof(ListRef) * lists.size());
     std::memset(h + (o_ne - o_tasks), 0, sizeof(int64_t) * nt);
     GS_HIP(hipMemcpyAsync(da + o_tasks, h, up, hipMemcpyHostToDevice, s));
   }
-  int64_t* htot = (int64_t*)pins()[kPinTotals].get(2 * sizeof(int64_t) * nt);
+  int64_t* htot = (int64_t*)pins(slot)[kPinTotals].get(2 * sizeof(int64_t) * nt);
   const CTask* dtasks = (const CTask*)(da + o_tasks);
   const GItem* ditems = (const GItem*)(da + o_items);
   launch_b_count(dtasks, ditems, nt, (const ListRef*)(da + o_lists), ts, ntiles,
                  20.0 * ntiles * kTile, s);
   launch_scan_tile_sums(ts, ntiles, ts + ntiles, s, nullptr);
   launch_b_totals(ditems, nt, ts, ntiles, dne, htot, s);
-  host_sync(s);
+  GS_HIP(hipEventRecord(ev.get(), s));
+  R.ntiles = ntiles;
+  R.ts = ts;
+  R.htot = htot;
+}
+
+void Batch::phase_write() {
+  const int nt = R.nt;
+  if (nt == 0) return;
+  host_event_sync(ev.get());
+  const std::vector<CTask>& tasks = R.tasks;
+  const std::vector<int>& owner = R.owner;
+  const std::vector<GItem>& items = R.items;
+  const std::vector<size_t>& o_P = R.o_P;
+  char* da = (char*)R.A->p;
+  const int64_t* ts = R.ts;
+  const int64_t* htot = R.htot;
   std::vector<int64_t> tot(htot, htot + nt), nonempty(htot + nt, htot + 2 * nt);
 
   // ---- write phase: outputs
@@ -625,7 +702,7 @@ void Batch::round() {
     if (has_out[i] && tasks[i].kind == kTaskExpand) w[i].split = (int64_t*)(dc + o_split[i]);
   {
     const size_t up = LC.bytes - o_w;
-    char* h = (char*)pins()[kPinWrite].get(up);
+    char* h = (char*)pins(slot)[kPinWrite].get(up);
     std::memcpy(h, w.data(), sizeof(WTask) * nt);
     auto copy_group = [&](std::vector<GItem>& g, size_t off) {
       if (!g.empty()) std::memcpy(h + (off - o_w), g.data(), sizeof(GItem) * g.size());
@@ -677,7 +754,7 @@ void Batch::round() {
     for (int cc = 0; cc < r.k; ++cc) r.col[cc] = wt.out0 + (int64_t)cc * wt.ostride;
     advance(b, r);
   }
-  // A and C are released here, after the launches that read them (stream order)
+  R = Round();  // the scratch arenas go back in stream order, after these launches
 }
 
 }  // namespace

@@ -193,6 +193,7 @@ gsmat_status guarded(F&& f) {
 // -------------------------------------------------------------------------
 void prof_begin(hipStream_t s, int cls);
 void host_sync(hipStream_t s);  // hipStreamSynchronize, timed for instrumentation
+void host_event_sync(hipEvent_t e);  // hipEventSynchronize, timed likewise
 void prof_end(hipStream_t s, int cls, double bytes);
 bool prof_on(int cls);
 

@@ -91,8 +91,8 @@ def tiny(G, O):
 def test_batch_tiny_workload(G, tiny, mode):
     spec, s, p, o, qs, st, want = tiny
     print(f"[gpu] batch tiny mode={mode}", flush=True)
-    queries = [q.tps for q in qs] * 2  # each query twice in the batch
-    _check_batch(G, st, queries, mode, oracle_rows=want * 2)
+    queries = [q.tps for q in qs] * 8  # each query 8 times in one batch
+    _check_batch(G, st, queries, mode, oracle_rows=want * 8)
 
 
 @pytest.mark.parametrize("mode", [1, 2])
@@ -180,7 +180,7 @@ def test_batch_random_graphs(G, O, seed):
                rng.integers(0, V, n).astype(np.int32))
     st = _store(G, s, p, o, V, P, dense_div=int(rng.choice([1, 32, 10**6])))
     queries, want = [], []
-    while len(queries) < 24:
+    while len(queries) < 70:
         ntp = int(rng.integers(1, 5))
         nvars = int(rng.integers(1, 5))
         tps = []
