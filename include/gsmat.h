@@ -141,6 +141,16 @@ gsmat_status gsmat_build_index(gsmat_store* st, int32_t dense_div, void* stream)
 gsmat_status gsmat_store_stats(const gsmat_store* st, int64_t* n_triples, int32_t* n_predicates,
                                int64_t* device_bytes);
 
+/* Hub bitmaps (an index option, Sec. 5.3 storage): in each orientation the
+ * longest rows with at least min_len members (longest first, while their
+ * bitmaps fit in max_bytes) also get a bitmap over all vertex ids, so a
+ * membership test against such a row (a filter, or an intersection with a
+ * constant's row) reads one bit instead of searching the row.  Results do not
+ * change.  Off by default (min_len 16384, max_bytes 0); min_len <= 0 or
+ * max_bytes <= 0 disables them.  Must precede gsmat_build_index (ESTATE
+ * after). */
+gsmat_status gsmat_set_hub_options(gsmat_store* st, int64_t min_len, int64_t max_bytes);
+
 /* Statistics of one predicate: pairs, distinct subjects, distinct objects. */
 gsmat_status gsmat_pred_stats(const gsmat_store* st, int32_t pred, int64_t* nnz, int64_t* n_rows,
                               int64_t* n_cols);

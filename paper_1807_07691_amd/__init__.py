@@ -39,7 +39,7 @@ EXPORTED = [
     "gsmat_result_rows_many", "gsmat_server_new", "gsmat_server_submit", "gsmat_server_step",
     "gsmat_server_poll", "gsmat_server_free", "gsmat_dict_new", "gsmat_dict_free",
     "gsmat_dict_load_text", "gsmat_dict_triples", "gsmat_dict_sizes", "gsmat_dict_lookup",
-    "gsmat_dict_term", "gsmat_parse_bgp",
+    "gsmat_dict_term", "gsmat_parse_bgp", "gsmat_set_hub_options",
 ]
 
 
@@ -76,6 +76,8 @@ def _load():
     pp = ctypes.POINTER(ctypes.c_void_p)
     L.gsmat_load_triples.restype = i32
     L.gsmat_load_triples.argtypes = [vp, vp, vp, i64, i32, i32, vp, vp, pp]
+    L.gsmat_set_hub_options.restype = i32
+    L.gsmat_set_hub_options.argtypes = [vp, i64, i64]
     L.gsmat_build_index.restype = i32
     L.gsmat_build_index.argtypes = [vp, i32, vp]
     L.gsmat_store_stats.restype = i32
@@ -287,6 +289,10 @@ def gsmat_load_triples(s, p, o, n_vertices, n_predicates, stream=None, allocator
     st = Store(h, n_vertices, n_predicates)
     st._alloc_keep = keep
     return st
+
+
+def gsmat_set_hub_options(store, min_len, max_bytes):
+    _check(_lib.gsmat_set_hub_options(store.h, min_len, max_bytes))
 
 
 def gsmat_build_index(store, dense_div=0, stream=None):

@@ -404,11 +404,13 @@ void Batch::phase_count() {
           } else if (m.s == cterm) {
             const LookupRes& r = b.lk[tp];
             l.seg = st->in.view(m.p).nbr + r.start;
+            l.bm = st->in.row_bitmap(m.p, m.o);
             l.len = r.len;
             ids[nl] = l.seg;
           } else {
             const LookupRes& r = b.lk[tp];
             l.seg = st->out.view(m.p).nbr + r.start;
+            l.bm = st->out.row_bitmap(m.p, m.s);
             l.len = r.len;
             ids[nl] = l.seg;
           }

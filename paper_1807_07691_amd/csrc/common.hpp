@@ -35,6 +35,9 @@ struct OutSet {
 //   dense[V + 1]  optional: ptr value of the first row >= v, for every vertex v
 //   dir[nb + 1]   optional (predicates without dense): index of the first row
 //                 whose id is >= b << dir_shift, for every bucket b of ids
+//   hub_keys[hub_n]  optional: ids of the rows (of at least hub_min members)
+//                    that also have a bitmap, ascending; row hub_keys[h] has
+//                    bit u of hub_bm[h * hub_words ...] set iff u is a member
 struct PredView {
   const int32_t* keys;
   const int32_t* ptr;
@@ -42,9 +45,14 @@ struct PredView {
   const int32_t* src;
   const int32_t* dense;
   const int32_t* dir;
+  const int32_t* hub_keys;
+  const uint32_t* hub_bm;
+  int64_t hub_words;
   int32_t nr;
   int32_t nnz;
   int32_t dir_shift;
+  int32_t hub_n;
+  int32_t hub_min;
   int32_t pad;
 };
 
@@ -56,6 +64,10 @@ struct OriPtrs {
   const int32_t* nbr;
   const int32_t* dense;
   const int32_t* dir;
+  const int32_t* hub_keys;
+  const uint32_t* hub_bm;
+  int64_t hub_words;
+  int32_t hub_min;
 };
 
 // Host record of one predicate in one orientation (offsets into the global
@@ -69,7 +81,8 @@ struct PredDesc {
   int64_t nr = 0;
   int64_t dir_base = -1;   // first entry in dir, -1 if none
   int32_t dir_shift = 0;   // bucket b holds ids [b << dir_shift, (b + 1) << dir_shift)
-  int32_t pad = 0;
+  int32_t hub_n = 0;       // rows with a bitmap
+  int64_t hub_base = 0;    // first of them in the hub key list and the bitmap pool
 };
 
 // A list taking part in a star-centre intersection: either a predicate's
@@ -77,6 +90,7 @@ struct PredDesc {
 struct ListRef {
   PredView pv;         // used when is_keys
   const int32_t* seg;  // used when !is_keys
+  const uint32_t* bm;  // !is_keys: the segment's row bitmap, if it has one
   int64_t len;
   int32_t is_keys;
   int32_t pad;
@@ -239,6 +253,12 @@ void launch_fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t s);
 void launch_dense_ptr(PredView pv, int64_t V, int32_t* dense, hipStream_t s);
 // dir[b] = first row index with id >= b << shift, for b in [0, nb]
 void launch_row_dir(PredView pv, int32_t shift, int64_t nb, int32_t* dir, hipStream_t s);
+// appends (row id, length) of every row with at least min_len members to
+// out[2 * i], out[2 * i + 1] for i < *count (count must start at 0)
+void launch_long_rows(PredView pv, int32_t min_len, int32_t* out, int32_t* count, int32_t cap,
+                      hipStream_t s);
+// sets the bits of the members of row v in the bitmap bm (zeroed before)
+void launch_row_bitmap(PredView pv, int32_t v, int64_t len, uint32_t* bm, hipStream_t s);
 void launch_ptr_sentinels(const PredDesc* d, int32_t P, int32_t* ptr, hipStream_t s);
 
 // lookups (planner statistics, constant scans)

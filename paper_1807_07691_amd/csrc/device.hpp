@@ -133,6 +133,10 @@ __device__ inline void lower_bound_n(const int32_t* __restrict__ a, const int32_
   }
 }
 
+__device__ inline bool bit_set(const uint32_t* __restrict__ bm, int32_t u) {
+  return (bm[u >> 5] >> (u & 31)) & 1u;
+}
+
 // Row lookups of N values at once: the N searches advance in lockstep, so
 // each round of their loads is issued together instead of one search after
 // another.  ok[j] false: start = len = 0.
@@ -224,8 +228,12 @@ __device__ inline void compact_tile(int64_t tile, int64_t n, int64_t base, Keep 
   }
 }
 
-__device__ inline PredView view_of(const PredDesc& d, const int32_t* keys, const int32_t* ptr,
-                                   const int32_t* nbr, const int32_t* dense, const int32_t* dir) {
+__device__ inline PredView view_of(const PredDesc& d, const OriPtrs& o) {
+  const int32_t* keys = o.keys;
+  const int32_t* ptr = o.ptr;
+  const int32_t* nbr = o.nbr;
+  const int32_t* dense = o.dense;
+  const int32_t* dir = o.dir;
   PredView pv;
   pv.keys = keys + d.row_base;
   pv.ptr = ptr + d.ptr_base;
@@ -233,9 +241,14 @@ __device__ inline PredView view_of(const PredDesc& d, const int32_t* keys, const
   pv.src = nullptr;
   pv.dense = d.dense_base >= 0 ? dense + d.dense_base : nullptr;
   pv.dir = d.dir_base >= 0 ? dir + d.dir_base : nullptr;
+  pv.hub_keys = d.hub_n ? o.hub_keys + d.hub_base : nullptr;
+  pv.hub_bm = d.hub_n ? o.hub_bm + d.hub_base * o.hub_words : nullptr;
+  pv.hub_words = o.hub_words;
   pv.nr = (int32_t)d.nr;
   pv.nnz = (int32_t)d.nnz;
   pv.dir_shift = d.dir_shift;
+  pv.hub_n = d.hub_n;
+  pv.hub_min = o.hub_min;
   pv.pad = 0;
   return pv;
 }
@@ -255,9 +268,7 @@ struct OutStrided {  // columns at a fixed stride from one base
 __device__ inline LookupRes lookup_one(const LookupReq& q, const PredDesc* dout,
                                        const PredDesc* din, const OriPtrs& out,
                                        const OriPtrs& in) {
-  const PredView pv = q.orient == 0
-                          ? view_of(dout[q.pred], out.keys, out.ptr, out.nbr, out.dense, out.dir)
-                          : view_of(din[q.pred], in.keys, in.ptr, in.nbr, in.dense, in.dir);
+  const PredView pv = q.orient == 0 ? view_of(dout[q.pred], out) : view_of(din[q.pred], in);
   LookupRes r;
   row_lookup(pv, q.v, r.start, r.len);
   r.found = (q.member >= 0 && r.len > 0) ? (seg_contains(pv.nbr + r.start, r.len, q.member) ? 1 : 0)
@@ -336,16 +347,38 @@ __device__ inline int64_t flag_filter_tile(int64_t tile, const ProbeArgs& pa, in
     ov[j] = ok[j] ? (pa.o_col ? pa.o_col[i] : pa.o_const) : 0;
   }
   row_lookup_n<kItems>(pv, sv, ok, st, len);
+  // rows with a bitmap answer with one bit; the others are searched
+  int32_t hub[kItems];
+#pragma unroll
+  for (int j = 0; j < kItems; ++j) hub[j] = -1;
+  if (pv.hub_n > 0) {
+    int32_t hl[kItems], hn[kItems], hk[kItems];
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+      hl[j] = 0;
+      hn[j] = len[j] >= pv.hub_min ? pv.hub_n : 0;
+    }
+    lower_bound_n<kItems>(pv.hub_keys, sv, hl, hn);
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) hk[j] = (len[j] >= pv.hub_min && hl[j] < pv.hub_n) ? pv.hub_keys[hl[j]] : -1;
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) hub[j] = (len[j] > 0 && hk[j] == sv[j]) ? hl[j] : -1;
+  }
   // o_i among the members of row s_i
   int32_t lo[kItems], cnt[kItems], k[kItems];
 #pragma unroll
   for (int j = 0; j < kItems; ++j) {
     lo[j] = st[j];
-    cnt[j] = len[j];
+    cnt[j] = hub[j] >= 0 ? 0 : len[j];
   }
   lower_bound_n<kItems>(pv.nbr, ov, lo, cnt);
 #pragma unroll
-  for (int j = 0; j < kItems; ++j) k[j] = (len[j] > 0 && lo[j] < st[j] + len[j]) ? pv.nbr[lo[j]] : -1;
+  for (int j = 0; j < kItems; ++j) {
+    if (hub[j] >= 0)
+      k[j] = bit_set(pv.hub_bm + (int64_t)hub[j] * pv.hub_words, ov[j]) ? ov[j] : -1;
+    else
+      k[j] = (len[j] > 0 && lo[j] < st[j] + len[j]) ? pv.nbr[lo[j]] : -1;
+  }
   int64_t loc = 0;
 #pragma unroll
   for (int j = 0; j < kItems; ++j) {
@@ -379,6 +412,9 @@ __device__ inline int64_t flag_intersect_tile(int64_t tile, const int32_t* __res
       row_lookup_n<kItems>(L.pv, x, keep, st, len);
 #pragma unroll
       for (int j = 0; j < kItems; ++j) keep[j] = keep[j] && len[j] > 0;
+    } else if (L.bm) {
+#pragma unroll
+      for (int j = 0; j < kItems; ++j) keep[j] = keep[j] && bit_set(L.bm, x[j]);
     } else {
       int32_t lo[kItems], cnt[kItems], k[kItems];
 #pragma unroll

@@ -352,11 +352,13 @@ struct Exec {
       } else if (q.s == cterm) {  // (v p c): v among the subjects of object c
         const LookupRes r = lookup_tp(tp, 1, q.p, q.o, -1);
         l.ref.seg = st->in.view(q.p).nbr + r.start;
+        l.ref.bm = st->in.row_bitmap(q.p, q.o);
         l.ref.len = r.len;
         l.ids = l.ref.seg;
       } else {  // (c p v): v among the objects of subject c
         const LookupRes r = lookup_tp(tp, 0, q.p, q.s, -1);
         l.ref.seg = st->out.view(q.p).nbr + r.start;
+        l.ref.bm = st->out.row_bitmap(q.p, q.s);
         l.ref.len = r.len;
         l.ids = l.ref.seg;
       }

@@ -246,6 +246,31 @@ __global__ void k_row_dir(PredView pv, int32_t shift, int64_t nb, int32_t* __res
   }
 }
 
+__global__ void k_long_rows(PredView pv, int32_t min_len, int32_t* __restrict__ out,
+                            int32_t* __restrict__ count, int32_t cap) {
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < pv.nr;
+       r += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t len = pv.ptr[r + 1] - pv.ptr[r];
+    if (len >= min_len) {
+      const int32_t i = atomicAdd(count, 1);
+      if (i < cap) {
+        out[2 * i] = pv.keys[r];
+        out[2 * i + 1] = len;
+      }
+    }
+  }
+}
+
+__global__ void k_row_bitmap(PredView pv, int32_t v, uint32_t* __restrict__ bm) {
+  int32_t st, len;
+  row_lookup(pv, v, st, len);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t u = pv.nbr[st + i];
+    atomicOr(&bm[u >> 5], 1u << (u & 31));
+  }
+}
+
 __global__ void k_ptr_sentinels(const PredDesc* __restrict__ d, int32_t P, int32_t* __restrict__ ptr) {
   const int32_t p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p < P) ptr[d[p].ptr_base + d[p].nr] = (int32_t)d[p].nnz;
@@ -518,6 +543,18 @@ void launch_row_dir(PredView pv, int32_t shift, int64_t nb, int32_t* dir, hipStr
   GS_LAUNCH(GSMAT_K_OTHER, 4.0 * (nb + 1),
             hipLaunchKernelGGL(k_row_dir, dim3(grid_for(nb + 1)), dim3(kBlock), 0, s, pv, shift, nb,
                                dir));
+}
+
+void launch_long_rows(PredView pv, int32_t min_len, int32_t* out, int32_t* count, int32_t cap,
+                      hipStream_t s) {
+  GS_LAUNCH(GSMAT_K_OTHER, 8.0 * pv.nr,
+            hipLaunchKernelGGL(k_long_rows, dim3(grid_for(pv.nr)), dim3(kBlock), 0, s, pv, min_len,
+                               out, count, cap));
+}
+
+void launch_row_bitmap(PredView pv, int32_t v, int64_t len, uint32_t* bm, hipStream_t s) {
+  GS_LAUNCH(GSMAT_K_OTHER, 8.0 * len,
+            hipLaunchKernelGGL(k_row_bitmap, dim3(grid_for(len)), dim3(kBlock), 0, s, pv, v, bm));
 }
 
 void launch_ptr_sentinels(const PredDesc* d, int32_t P, int32_t* ptr, hipStream_t s) {

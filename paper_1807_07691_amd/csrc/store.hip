@@ -62,11 +62,25 @@ PredView Orientation::view(int32_t p) const {
   v.src = src ? src + d.nbr_base : nullptr;
   v.dense = d.dense_base >= 0 ? dense + d.dense_base : nullptr;
   v.dir = d.dir_base >= 0 ? dir + d.dir_base : nullptr;
+  v.hub_keys = d.hub_n ? hub_keys + d.hub_base : nullptr;
+  v.hub_bm = d.hub_n ? hub_bm + d.hub_base * hub_words : nullptr;
+  v.hub_words = hub_words;
   v.nr = (int32_t)d.nr;
   v.nnz = (int32_t)d.nnz;
   v.dir_shift = d.dir_shift;
+  v.hub_n = d.hub_n;
+  v.hub_min = hub_min;
   v.pad = 0;
   return v;
+}
+
+const uint32_t* Orientation::row_bitmap(int32_t p, int32_t v) const {
+  const PredDesc& d = desc[p];
+  if (!d.hub_n) return nullptr;
+  const int32_t* a = hub_keys_host.data() + d.hub_base;
+  const int32_t* it = std::lower_bound(a, a + d.hub_n, v);
+  if (it == a + d.hub_n || *it != v) return nullptr;
+  return hub_bm + (d.hub_base + (it - a)) * hub_words;
 }
 
 }  // namespace gsmat
@@ -91,6 +105,8 @@ void gsmat_store::dfree_index(hipStream_t s) {
 }
 
 namespace {
+
+void build_hubs(gsmat_store* st, Orientation& ori, hipStream_t s);
 
 // Builds one orientation from sorted distinct keys (p << 2vb | row << vb | member).
 void build_orientation(gsmat_store* st, const uint64_t* keys, int64_t U, Orientation& ori,
@@ -195,6 +211,69 @@ void build_orientation(gsmat_store* st, const uint64_t* keys, int64_t U, Orienta
     }
   }
   GS_HIP(hipStreamSynchronize(s));
+  build_hubs(st, ori, s);
+}
+
+// Bitmaps of the longest rows (at least hub_min_len members), longest first
+// while they fit in hub_max_bytes: a membership test on such a row reads one
+// bit instead of searching the row.
+void build_hubs(gsmat_store* st, Orientation& ori, hipStream_t s) {
+  const int32_t P = st->P;
+  const int64_t V = st->V;
+  if (st->hub_min_len <= 0 || st->hub_max_bytes <= 0 || V <= 0) return;
+  const int64_t words = (V + 31) / 32;
+  const int64_t bm_bytes = 4 * words;
+  const int64_t max_hubs = st->hub_max_bytes / bm_bytes;
+  if (max_hubs <= 0) return;
+  const int32_t min_len = (int32_t)std::min<int64_t>(st->hub_min_len, INT32_MAX);
+  struct Cand {
+    int32_t p, row, len;
+  };
+  std::vector<Cand> cand;
+  DeviceMem* mem = st->mem.get();
+  for (int32_t p = 0; p < P; ++p) {
+    const PredDesc& d = ori.desc[p];
+    if (d.nnz < min_len) continue;
+    const int32_t cap = (int32_t)std::min<int64_t>(d.nnz / min_len + 1, d.nr);
+    Tmp<int32_t> out(mem, 2 * (int64_t)cap + 1, s);
+    GS_HIP(hipMemsetAsync(out.p + 2 * cap, 0, sizeof(int32_t), s));
+    launch_long_rows(ori.view(p), min_len, out.p, out.p + 2 * cap, cap, s);
+    std::vector<int32_t> h(2 * (size_t)cap + 1);
+    GS_HIP(hipMemcpyAsync(h.data(), out.p, sizeof(int32_t) * h.size(), hipMemcpyDeviceToHost, s));
+    GS_HIP(hipStreamSynchronize(s));
+    const int32_t n = std::min(h[2 * cap], cap);
+    for (int32_t i = 0; i < n; ++i) cand.push_back(Cand{p, h[2 * i], h[2 * i + 1]});
+  }
+  if (cand.empty()) return;
+  std::sort(cand.begin(), cand.end(), [](const Cand& a, const Cand& b) {
+    return a.len != b.len ? a.len > b.len : (a.p != b.p ? a.p < b.p : a.row < b.row);
+  });
+  if ((int64_t)cand.size() > max_hubs) cand.resize((size_t)max_hubs);
+  std::sort(cand.begin(), cand.end(), [](const Cand& a, const Cand& b) {
+    return a.p != b.p ? a.p < b.p : a.row < b.row;
+  });
+  const int64_t H = (int64_t)cand.size();
+  ori.hub_words = words;
+  ori.hub_min = min_len;
+  ori.hub_keys_host.resize(H);
+  for (int64_t i = 0; i < H; ++i) {
+    ori.hub_keys_host[i] = cand[i].row;
+    PredDesc& d = ori.desc[cand[i].p];
+    if (d.hub_n == 0) d.hub_base = i;
+    ++d.hub_n;
+  }
+  ori.hub_keys = (int32_t*)st->dalloc(sizeof(int32_t) * H, s, true);
+  ori.hub_bm = (uint32_t*)st->dalloc(sizeof(uint32_t) * H * words, s, true);
+  GS_HIP(hipMemcpyAsync(ori.hub_keys, ori.hub_keys_host.data(), sizeof(int32_t) * H,
+                        hipMemcpyHostToDevice, s));
+  GS_HIP(hipMemsetAsync(ori.hub_bm, 0, sizeof(uint32_t) * H * words, s));
+  // each bitmap from its row's members (found by a device lookup of the row)
+  for (int64_t i = 0; i < H; ++i) {
+    const PredView pv = ori.view(cand[i].p);
+    launch_row_bitmap(pv, cand[i].row, cand[i].len, ori.hub_bm + i * words, s);
+  }
+  GS_HIP(hipMemcpyAsync(ori.d_desc, ori.desc.data(), sizeof(PredDesc) * P, hipMemcpyHostToDevice, s));
+  GS_HIP(hipStreamSynchronize(s));
 }
 
 // Sort + deduplicate one key array in place; returns the distinct count.
@@ -263,6 +342,17 @@ extern "C" gsmat_status gsmat_load_triples(const int32_t* s, const int32_t* p, c
     }
     GS_HIP(hipStreamSynchronize(hs));
     *out = st.release();
+    return GSMAT_OK;
+  });
+}
+
+extern "C" gsmat_status gsmat_set_hub_options(gsmat_store* st, int64_t min_len,
+                                              int64_t max_bytes) {
+  return guarded([&]() -> gsmat_status {
+    if (!st) throw StatusFail{GSMAT_EINVAL, "store is NULL"};
+    if (st->built) throw StatusFail{GSMAT_ESTATE, "index already built"};
+    st->hub_min_len = min_len;
+    st->hub_max_bytes = max_bytes;
     return GSMAT_OK;
   });
 }

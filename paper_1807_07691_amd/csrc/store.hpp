@@ -18,13 +18,20 @@ struct Orientation {
   int32_t* ptr = nullptr;    // [R + P] row offsets per predicate, one sentinel each
   int32_t* dense = nullptr;  // dense row pointers of heavy predicates
   int32_t* dir = nullptr;    // bucket directories of the other predicates
+  int32_t* hub_keys = nullptr;  // row ids of the rows with a bitmap, per predicate
+  uint32_t* hub_bm = nullptr;   // their bitmaps, hub_words words each
+  int64_t hub_words = 0;
+  int32_t hub_min = 0;          // rows shorter than this have no bitmap
+  std::vector<int32_t> hub_keys_host;
   int64_t R = 0;
   int64_t dense_len = 0;
   int64_t dir_len = 0;
   std::vector<PredDesc> desc;   // [P]
   PredDesc* d_desc = nullptr;   // device copy
   PredView view(int32_t p) const;
-  OriPtrs ptrs() const { return OriPtrs{keys, ptr, nbr, dense, dir}; }
+  OriPtrs ptrs() const { return OriPtrs{keys, ptr, nbr, dense, dir, hub_keys, hub_bm, hub_words, hub_min}; }
+  // bitmap of predicate p's row v, or null
+  const uint32_t* row_bitmap(int32_t p, int32_t v) const;
 };
 
 struct Alloc {
@@ -43,6 +50,8 @@ struct gsmat_store {
   int32_t* d_p = nullptr;
   int32_t* d_o = nullptr;
   bool built = false;
+  int64_t hub_min_len = 1 << 14;  // rows this long get a bitmap ...
+  int64_t hub_max_bytes = 0;      // ... within this many bytes per orientation (0: none)
   uint64_t uid = 0;        // distinct for every index build in the process
   int64_t T = 0;           // distinct triples
   gsmat::Orientation out;  // by subject: rows = subjects, members = objects

@@ -190,3 +190,7 @@ def test_server_entry_points_validate_before_device_work(G):
     assert lib.gsmat_server_step(None, None, None, None) == G.GSMAT_EINVAL
     assert lib.gsmat_server_poll(None, 0, None, None, None, ctypes.byref(n)) == G.GSMAT_EINVAL
     lib.gsmat_server_free(None)
+
+
+def test_hub_options_validate(G):
+    assert G.lib().gsmat_set_hub_options(None, 2, 1) == G.GSMAT_EINVAL

@@ -178,7 +178,10 @@ def test_batch_random_graphs(G, O, seed):
     n = int(rng.integers(10, 40000))
     s, p, o = (rng.integers(0, V, n).astype(np.int32), rng.integers(0, P, n).astype(np.int32),
                rng.integers(0, V, n).astype(np.int32))
-    st = _store(G, s, p, o, V, P, dense_div=int(rng.choice([1, 32, 10**6])))
+    st = G.gsmat_load_triples(s, p, o, V, P)
+    if seed % 2:  # bitmaps for the rows of at least 1-7 members
+        G.gsmat_set_hub_options(st, int(rng.integers(1, 8)), 1 << 26)
+    G.gsmat_build_index(st, dense_div=int(rng.choice([1, 32, 10**6])))
     queries, want = [], []
     while len(queries) < 70:
         ntp = int(rng.integers(1, 5))

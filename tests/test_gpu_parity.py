@@ -120,6 +120,36 @@ def test_tiny_queries(G, O, tiny, mode, qi):
         assert np.array_equal(got, want)
 
 
+@pytest.fixture(scope="module")
+def tiny_hub(G, tiny):
+    """The tiny graph with a bitmap for every row of at least 2 members."""
+    spec, s, p, o, qs, st, st_dense = tiny
+    h = G.gsmat_load_triples(s, p, o, spec.V, spec.P)
+    G.gsmat_set_hub_options(h, 2, 1 << 30)
+    G.gsmat_build_index(h)
+    assert G.gsmat_store_stats(h)["device_bytes"] > G.gsmat_store_stats(st)["device_bytes"]
+    return h
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_tiny_queries_with_hub_bitmaps(G, O, tiny, tiny_hub, mode):
+    """Filters and constant-row intersections answered by bitmaps give the
+    same rows, in the same order, as searching the rows."""
+    spec, s, p, o, qs, st, st_dense = tiny
+    print(f"[gpu] tiny queries with hub bitmaps mode={mode}", flush=True)
+    for q in qs:
+        want = O.join(s, p, o, q.tps, q.n_vars)
+        got = G.evaluate(tiny_hub, q.tps, mode)
+        assert np.array_equal(_sorted(got), want)
+        assert np.array_equal(got, G.evaluate(st, q.tps, mode))
+    # stars through constants and filters with both ends bound
+    for tps, nv in [([[-1, 0, int(o[0])], [-1, 1, -2], [-1, 2, int(o[5])]], 2),
+                    ([[int(s[3]), 0, -1], [-1, 1, -2], [int(s[3]), 2, -2]], 2),
+                    ([[-1, 0, -2], [-2, 1, -3], [-1, 2, -3]], 3)]:
+        want = O.join(s, p, o, tps, nv)
+        assert np.array_equal(_sorted(G.evaluate(tiny_hub, tps, mode)), want)
+
+
 @pytest.mark.parametrize("qi", [1, 4, 5])
 def test_tiny_chunked(G, O, tiny, qi):
     """A tiny byte budget forces every expansion to be cut into output ranges."""
@@ -215,7 +245,10 @@ def test_random_bgps(G, O, seed):
     s = np.concatenate([s, s[:20]])  # duplicates: the store keeps the set
     p = np.concatenate([p, p[:20]])
     o = np.concatenate([o, o[:20]])
-    st = _store(G, s, p, o, V, P, dense_div=int(rng.choice([1, 32, 10**6])))
+    st = G.gsmat_load_triples(s, p, o, V, P)
+    if rng.random() < 0.5:  # bitmaps for the rows of at least 1-7 members
+        G.gsmat_set_hub_options(st, int(rng.integers(1, 8)), 1 << 26)
+    G.gsmat_build_index(st, dense_div=int(rng.choice([1, 32, 10**6])))
     for trial in range(4):
         ntp = int(rng.integers(1, 6))
         nvars = int(rng.integers(1, 5))
