@@ -46,10 +46,11 @@ def source_hash(files):
     return h.hexdigest()
 
 
-def counter_traffic(workload):
+def counter_traffic(workload, sparse_theta=None):
     """HBM bytes per launch of the dominant write kernel from the committed
     counter summary, only if it was taken on this workload with the current
-    kernel sources."""
+    kernel sources (and, for the batch workload, the same sparse-expansion
+    threshold, which decides how the writes split into launches)."""
     if workload not in PMC_SUMMARY:
         return None
     name, files = PMC_SUMMARY[workload]
@@ -58,10 +59,13 @@ def counter_traffic(workload):
         return None
     vals = {}
     for line in open(path):
-        if ":" in line and line.split(":", 1)[0] in ("traffic_bytes_per_launch", "sources_sha256"):
+        if ":" in line and line.split(":", 1)[0] in ("traffic_bytes_per_launch", "sources_sha256",
+                                                     "sparse_theta"):
             k, v = line.split(":", 1)
             vals[k] = v.strip()
     if vals.get("sources_sha256") != source_hash(files) or "traffic_bytes_per_launch" not in vals:
+        return None
+    if sparse_theta is not None and float(vals.get("sparse_theta", "nan")) != float(sparse_theta):
         return None
     return int(vals["traffic_bytes_per_launch"])
 
@@ -109,6 +113,8 @@ def main():
     ap.add_argument("--max-queries", type=int, default=0, help="0 = all")
     ap.add_argument("--cpu-sample-s", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--sparse-theta", type=float, default=-1.0,
+                    help="batch workload: sparse-expansion threshold (< 0: autotune)")
     ap.add_argument("--no-plain", action="store_true",
                     help="batch workload: skip the plain one-query-at-a-time comparison")
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
@@ -426,6 +432,16 @@ def bench_batch(args, G, W, spec, qspec, queries, st, sh, budget, mode, stats, l
             phase.append((b - a, c - b))
         return plans, results
 
+    # ---- autotuning (setup, untimed): the sparse-expansion threshold
+    if args.sparse_theta < 0:
+        plans, _ = G.gsmat_plan_batch(st, packed, mode, stream=sh, as_set=True)
+        theta, tune_ms = G.gsmat_autotune_batch(st, plans, budget, stream=sh)
+        plans.close()
+        log(f"autotune: theta={theta} ms per candidate {tune_ms}")
+    else:
+        theta, tune_ms = args.sparse_theta, {}
+        G.gsmat_set_sparse_expand(st, theta)
+
     # ---- batched: warmup (diagnostics, count and row checks), then timed
     log(f"batched warmup x{max(1, args.warmup)}")
     G.gsmat_prof_enable(0x1F)
@@ -491,7 +507,7 @@ def bench_batch(args, G, W, spec, qspec, queries, st, sh, budget, mode, stats, l
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": counter_traffic("batch"),
+        "traffic": counter_traffic("batch", theta),
         "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
         "kernel": "k_b_write (batched expansion write, all column counts)",
         "launches": wr["launches"],
@@ -525,6 +541,8 @@ def bench_batch(args, G, W, spec, qspec, queries, st, sh, budget, mode, stats, l
         # every query of a step is submitted together and completes with the batch
         "p50_ms": ms(percentile(step_s, 0.5)),
         "p99_ms": ms(percentile(step_s, 0.99)),
+        "autotune": {"sparse_theta": theta,
+                     "candidate_ms": {str(k): round(v, 3) for k, v in tune_ms.items()}},
         "plan_batch_ms": ms(sum(x for x, _ in phase) / len(phase)),
         "join_batch_ms": ms(sum(y for _, y in phase) / len(phase)),
         "plain": None if plain_wall is None else {

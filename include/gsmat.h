@@ -233,6 +233,23 @@ void gsmat_result_free_many(gsmat_result** results, int32_t n);
 /* rows[i] = row count of results[i], or -1 for a NULL entry. */
 gsmat_status gsmat_result_rows_many(const gsmat_result* const* results, int32_t n, int64_t* rows);
 
+/* Sparse expansions in the batched join: an expansion of at least min_rows
+ * input rows of which fewer than the fraction theta have any output first
+ * compacts its rows with output (in order, with their output offsets) and
+ * then walks only those in the merge-path write; the rows written and their
+ * order do not change.  theta in [0, 1], 0 never; defaults 0.5 and 4096. */
+gsmat_status gsmat_set_sparse_expand(gsmat_store* st, double theta, int64_t min_rows);
+
+/* Autotuner: runs gsmat_join_batch on the plans once untimed, then with each
+ * candidate theta (0, 0.25, 0.5, 0.75, 1; the fastest of three runs each,
+ * results discarded), keeps the fastest
+ * for the store and returns it in *theta; ms[5] (may be NULL) receives each
+ * candidate's wall time in milliseconds.  The rows of any later join do not
+ * depend on the choice. */
+gsmat_status gsmat_autotune_batch(gsmat_store* st, const gsmat_query_plan* const* plans,
+                                  int32_t n_plans, int64_t budget_bytes, void* stream,
+                                  double* theta, double* ms);
+
 /* Result shape; per-step rows in/out (arrays of n_steps entries, may be NULL)
  * are summed over chunks. */
 gsmat_status gsmat_result_info(const gsmat_result* r, int64_t* n_rows, int32_t* n_vars,

@@ -39,7 +39,8 @@ EXPORTED = [
     "gsmat_result_rows_many", "gsmat_server_new", "gsmat_server_submit", "gsmat_server_step",
     "gsmat_server_poll", "gsmat_server_free", "gsmat_dict_new", "gsmat_dict_free",
     "gsmat_dict_load_text", "gsmat_dict_triples", "gsmat_dict_sizes", "gsmat_dict_lookup",
-    "gsmat_dict_term", "gsmat_parse_bgp", "gsmat_set_hub_options",
+    "gsmat_dict_term", "gsmat_parse_bgp", "gsmat_set_hub_options", "gsmat_set_sparse_expand",
+    "gsmat_autotune_batch",
 ]
 
 
@@ -76,6 +77,10 @@ def _load():
     pp = ctypes.POINTER(ctypes.c_void_p)
     L.gsmat_load_triples.restype = i32
     L.gsmat_load_triples.argtypes = [vp, vp, vp, i64, i32, i32, vp, vp, pp]
+    L.gsmat_set_sparse_expand.restype = i32
+    L.gsmat_set_sparse_expand.argtypes = [vp, ctypes.c_double, i64]
+    L.gsmat_autotune_batch.restype = i32
+    L.gsmat_autotune_batch.argtypes = [vp, vp, i32, i64, vp, vp, vp]
     L.gsmat_set_hub_options.restype = i32
     L.gsmat_set_hub_options.argtypes = [vp, i64, i64]
     L.gsmat_build_index.restype = i32
@@ -606,6 +611,28 @@ def gsmat_parse_bgp(d, text):
         out.append(raw[at:end].decode())
         at = end + 1
     return tps, out
+
+
+def gsmat_set_sparse_expand(store, theta, min_rows=4096):
+    _check(_lib.gsmat_set_sparse_expand(store.h, float(theta), int(min_rows)))
+
+
+SPARSE_CANDIDATES = (0.0, 0.25, 0.5, 0.75, 1.0)
+
+
+def gsmat_autotune_batch(store, plans, budget_bytes=0, stream=None):
+    """Times the batch under each sparse-expansion threshold and keeps the
+    fastest for the store: (theta, {candidate: ms})."""
+    if isinstance(plans, PlanSet):
+        nq, ph = plans.n, plans.arr
+    else:
+        nq = len(plans)
+        ph = (ctypes.c_void_p * max(nq, 1))(*[pl.h for pl in plans])
+    theta = ctypes.c_double()
+    ms = (ctypes.c_double * len(SPARSE_CANDIDATES))()
+    _check(_lib.gsmat_autotune_batch(store.h, ph, nq, budget_bytes, _stream(stream),
+                                     ctypes.byref(theta), ms))
+    return theta.value, {c: ms[i] for i, c in enumerate(SPARSE_CANDIDATES)}
 
 
 def gsmat_result_info(result):

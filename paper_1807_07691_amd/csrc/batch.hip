@@ -20,6 +20,7 @@
 // Each query takes exactly the steps it takes alone (same plan, same choice
 // rule on the same tables), so its result rows come out in the same order.
 #include <algorithm>
+#include <chrono>
 #include <cstring>
 #include <deque>
 #include <memory>
@@ -105,6 +106,7 @@ std::vector<LookupRes> lookup_many(const gsmat_store* st, const std::vector<Look
 
 enum QState { kActive, kDone, kFallback, kFailed };
 
+
 struct BQ {
   const gsmat_query_plan* pl = nullptr;
   std::unique_ptr<gsmat_result> res;
@@ -149,8 +151,13 @@ struct Batch {
     std::vector<size_t> o_P;
     std::shared_ptr<Arena> A;  // count-phase scratch
     int64_t* ts = nullptr;
+    int64_t* tsn = nullptr;  // rows with output per count tile (expansions)
     int64_t* htot = nullptr;
   } R;
+  // expansions of at least sparse_min_rows input rows of which fewer than
+  // this fraction have output walk only those rows (0: never)
+  double sparse_theta = 0.0;
+  int64_t sparse_min_rows = 4096;
 
   DeviceMem* mem() { return st->mem.get(); }
 
@@ -510,6 +517,7 @@ void Batch::phase_count() {
     }
   }
   const size_t o_ts = LA.add(sizeof(int64_t) * (ntiles + 1));
+  const size_t o_tsn = LA.add(sizeof(int64_t) * (ntiles + 1));
   // uploaded together: tasks, items, lists, then the zeroed non-empty counters
   const size_t o_tasks = LA.add(sizeof(CTask) * nt);
   const size_t o_items = LA.add(sizeof(GItem) * nt);
@@ -528,6 +536,7 @@ void Batch::phase_count() {
     }
   }
   int64_t* ts = (int64_t*)(da + o_ts);
+  int64_t* tsn = (int64_t*)(da + o_tsn);
   {
     const size_t up = o_ne + sizeof(int64_t) * nt - o_tasks;
     char* h = (char*)pins(slot)[kPinCount].get(up);
@@ -540,13 +549,14 @@ void Batch::phase_count() {
   int64_t* htot = (int64_t*)pins(slot)[kPinTotals].get(2 * sizeof(int64_t) * nt);
   const CTask* dtasks = (const CTask*)(da + o_tasks);
   const GItem* ditems = (const GItem*)(da + o_items);
-  launch_b_count(dtasks, ditems, nt, (const ListRef*)(da + o_lists), ts, ntiles,
+  launch_b_count(dtasks, ditems, nt, (const ListRef*)(da + o_lists), ts, tsn, ntiles,
                  20.0 * ntiles * kTile, s);
-  launch_scan_tile_sums(ts, ntiles, ts + ntiles, s, nullptr);
+  launch_scan_tile_sums2(ts, tsn, ntiles, s);
   launch_b_totals(ditems, nt, ts, ntiles, dne, htot, s);
   GS_HIP(hipEventRecord(ev.get(), s));
   R.ntiles = ntiles;
   R.ts = ts;
+  R.tsn = tsn;
   R.htot = htot;
 }
 
@@ -559,7 +569,7 @@ void Batch::phase_write() {
   const std::vector<GItem>& items = R.items;
   const std::vector<size_t>& o_P = R.o_P;
   char* da = (char*)R.A->p;
-  const int64_t* ts = R.ts;
+  int64_t* ts = R.ts;
   const int64_t* htot = R.htot;
   std::vector<int64_t> tot(htot, htot + nt), nonempty(htot + nt, htot + 2 * nt);
 
@@ -643,12 +653,16 @@ void Batch::phase_write() {
   std::shared_ptr<Arena> B;
   if (LB.bytes > 0) B = std::make_shared<Arena>(mem(), LB.bytes, s);
 
-  // expansion scratch (splits) and launch groups
+  // expansion scratch (splits, compacted rows) and launch groups
   Layout LC;
-  std::vector<size_t> o_split(nt);
-  std::vector<GItem> g_scan, g_part, g_write[kMaxK + 2], g_comp[kMaxK + 2];
-  int64_t n_scan = 0, n_part = 0, n_write[kMaxK + 2] = {}, n_comp[kMaxK + 2] = {};
-  double bytes_write[kMaxK + 2] = {}, bytes_comp[kMaxK + 2] = {};
+  std::vector<size_t> o_split(nt), o_ridx(nt), o_cstart(nt), o_cP(nt);
+  std::vector<char> sparse(nt, 0);
+  std::vector<GItem> g_scan, g_crow, g_part, g_write[kMaxK + 2], g_wi[kMaxK + 2],
+      g_comp[kMaxK + 2];
+  int64_t n_scan = 0, n_crow = 0, n_part = 0, n_write[kMaxK + 2] = {}, n_wi[kMaxK + 2] = {},
+          n_comp[kMaxK + 2] = {};
+  double bytes_write[kMaxK + 2] = {}, bytes_wi[kMaxK + 2] = {}, bytes_comp[kMaxK + 2] = {};
+  double bytes_crow = 0;
   for (int i = 0; i < nt; ++i) {
     if (!has_out[i]) continue;
     BQ& b = q[owner[i]];
@@ -662,20 +676,44 @@ void Batch::phase_write() {
       for (int cc = 0; cc < b.t.k; ++cc) wt.in.c[cc] = b.t.col[cc];
       wt.nbr = c.pv.nbr;
       wt.N = c.N;
-      wt.start = c.start;
-      wt.P = (int64_t*)(da + o_P[i]);
+      const int gk = wt.k <= kMaxK ? wt.k : kMaxK + 1;
+      // sparse: few input rows have output; the write walks only those
+      sparse[i] = sparse_theta > 0 && c.n >= sparse_min_rows &&
+                  (double)nonempty[i] < sparse_theta * (double)c.n;
+      if (sparse[i]) {
+        const int64_t ne = nonempty[i];
+        wt.n_in = c.n;
+        wt.n = ne;
+        wt.start_in = c.start;
+        o_ridx[i] = LC.add(sizeof(int32_t) * ne);
+        o_cstart[i] = LC.add(sizeof(int32_t) * ne);
+        o_cP[i] = LC.add(sizeof(int64_t) * (ne + 1));
+        g_crow.push_back(GItem{n_crow, i, 0});
+        n_crow += cnt_tiles;
+        // N of every input row; index, start and offset of every compacted row
+        bytes_crow += 4.0 * c.n + 20.0 * ne;
+      } else {
+        wt.start = c.start;
+        wt.P = (int64_t*)(da + o_P[i]);
+        g_scan.push_back(GItem{n_scan, i, 0});
+        n_scan += cnt_tiles;
+      }
       const int64_t pt = ceil_div(wt.n + wt.m, kTile);
       o_split[i] = LC.add(sizeof(int64_t) * (pt + 1));
-      g_scan.push_back(GItem{n_scan, i, 0});
-      n_scan += cnt_tiles;
       g_part.push_back(GItem{n_part, i, 0});
       n_part += pt + 1;
-      const int gk = wt.k <= kMaxK ? wt.k : kMaxK + 1;
-      g_write[gk].push_back(GItem{n_write[gk], i, 0});
-      n_write[gk] += pt;
       // outputs written (k + 1 columns), one member id read per output, the
-      // offsets and starts of every row, the k values of rows with output
-      bytes_write[gk] += 4.0 * wt.m * (wt.k + 2) + 12.0 * wt.n + 4.0 * wt.k * nonempty[i];
+      // offsets and starts of every row walked (and its index when
+      // compacted), the k values of rows with output
+      if (sparse[i]) {
+        g_wi[gk].push_back(GItem{n_wi[gk], i, 0});
+        n_wi[gk] += pt;
+        bytes_wi[gk] += 4.0 * wt.m * (wt.k + 2) + 16.0 * wt.n + 4.0 * wt.k * wt.n;
+      } else {
+        g_write[gk].push_back(GItem{n_write[gk], i, 0});
+        n_write[gk] += pt;
+        bytes_write[gk] += 4.0 * wt.m * (wt.k + 2) + 12.0 * wt.n + 4.0 * wt.k * nonempty[i];
+      }
     } else {
       const bool inter = c.kind == kTaskIntersect;
       wt.k = inter ? 1 : b.t.k;
@@ -692,16 +730,25 @@ void Batch::phase_write() {
   // one upload: tasks, then every group's items
   const size_t o_w = LC.add(sizeof(WTask) * nt);
   auto put_group = [&](std::vector<GItem>& g) { return LC.add(sizeof(GItem) * std::max<size_t>(g.size(), 1)); };
-  const size_t o_gscan = put_group(g_scan), o_gpart = put_group(g_part);
-  size_t o_gw[kMaxK + 2], o_gc[kMaxK + 2];
+  const size_t o_gscan = put_group(g_scan), o_gcrow = put_group(g_crow), o_gpart = put_group(g_part);
+  size_t o_gw[kMaxK + 2], o_gwi[kMaxK + 2], o_gc[kMaxK + 2];
   for (int k = 0; k < kMaxK + 2; ++k) {
     o_gw[k] = put_group(g_write[k]);
+    o_gwi[k] = put_group(g_wi[k]);
     o_gc[k] = put_group(g_comp[k]);
   }
   auto C = std::make_shared<Arena>(mem(), LC.bytes, s);
   char* dc = (char*)C->p;
-  for (int i = 0; i < nt; ++i)
-    if (has_out[i] && tasks[i].kind == kTaskExpand) w[i].split = (int64_t*)(dc + o_split[i]);
+  for (int i = 0; i < nt; ++i) {
+    if (!has_out[i] || tasks[i].kind != kTaskExpand) continue;
+    w[i].split = (int64_t*)(dc + o_split[i]);
+    if (sparse[i]) {
+      w[i].ridx = (int32_t*)(dc + o_ridx[i]);
+      w[i].cstart = (int32_t*)(dc + o_cstart[i]);
+      w[i].start = w[i].cstart;
+      w[i].P = (int64_t*)(dc + o_cP[i]);
+    }
+  }
   {
     const size_t up = LC.bytes - o_w;
     char* h = (char*)pins(slot)[kPinWrite].get(up);
@@ -710,23 +757,33 @@ void Batch::phase_write() {
       if (!g.empty()) std::memcpy(h + (off - o_w), g.data(), sizeof(GItem) * g.size());
     };
     copy_group(g_scan, o_gscan);
+    copy_group(g_crow, o_gcrow);
     copy_group(g_part, o_gpart);
     for (int k = 0; k < kMaxK + 2; ++k) {
       copy_group(g_write[k], o_gw[k]);
+      copy_group(g_wi[k], o_gwi[k]);
       copy_group(g_comp[k], o_gc[k]);
     }
     GS_HIP(hipMemcpyAsync(dc + o_w, h, up, hipMemcpyHostToDevice, s));
   }
   const WTask* dw = (const WTask*)(dc + o_w);
-  if (!g_scan.empty()) {
+  if (!g_scan.empty())
     launch_b_scan_add(dw, (const GItem*)(dc + o_gscan), (int)g_scan.size(), ts, n_scan,
                       12.0 * n_scan * kTile, s);
-    launch_b_partition(dw, (const GItem*)(dc + o_gpart), (int)g_part.size(), n_part, s);
+  if (!g_crow.empty()) {
+    const int64_t* tsn = R.tsn;
+    launch_b_compact_rows(dw, (const GItem*)(dc + o_gcrow), (int)g_crow.size(), ts, tsn, n_crow,
+                          bytes_crow, s);
   }
+  if (!g_part.empty())
+    launch_b_partition(dw, (const GItem*)(dc + o_gpart), (int)g_part.size(), n_part, s);
   for (int k = 0; k < kMaxK + 2; ++k) {
     if (!g_write[k].empty())
       launch_b_write(k, dw, (const GItem*)(dc + o_gw[k]), (int)g_write[k].size(),
               n_write[k], bytes_write[k], s);
+    if (!g_wi[k].empty())
+      launch_b_write_idx(k, dw, (const GItem*)(dc + o_gwi[k]), (int)g_wi[k].size(), n_wi[k],
+                         bytes_wi[k], s);
     if (!g_comp[k].empty())
       launch_b_compact(k, dw, (const GItem*)(dc + o_gc[k]), (int)g_comp[k].size(), ts,
                 n_comp[k], bytes_comp[k], s);
@@ -760,6 +817,9 @@ void Batch::phase_write() {
 }
 
 }  // namespace
+
+// Candidate fill thresholds the autotuner times.
+constexpr int kTuneCandidates = 5;
 
 // ---------------------------------------------------------------- serving
 
@@ -979,6 +1039,8 @@ extern "C" gsmat_status gsmat_server_step(gsmat_server* sv, int32_t* n_active, i
   return guarded([&]() -> gsmat_status {
     if (!sv) throw StatusFail{GSMAT_EINVAL, "server is NULL"};
     sv->admit();
+    sv->bt.sparse_theta = sv->st->sparse_theta;
+    sv->bt.sparse_min_rows = sv->st->sparse_min_rows;
     bool any = false;
     for (const BQ& b : sv->bt.q) any |= b.state == kActive;
     if (any) sv->bt.round();
@@ -1028,6 +1090,8 @@ extern "C" gsmat_status gsmat_join_batch(gsmat_store* st, const gsmat_query_plan
       if (!plans[i]) throw StatusFail{GSMAT_EINVAL, "plan " + std::to_string(i) + " is NULL"};
     hipStream_t s = (hipStream_t)stream;
     Batch bt{st, s, budget_bytes, max_rows, {}, budget_bytes, false};
+    bt.sparse_theta = st->sparse_theta;
+    bt.sparse_min_rows = st->sparse_min_rows;
     bt.q.resize(n_plans);
     for (int i = 0; i < n_plans; ++i) {
       BQ& b = bt.q[i];
@@ -1205,6 +1269,57 @@ extern "C" gsmat_status gsmat_result_rows_many(const gsmat_result* const* result
     if (n < 0) throw StatusFail{GSMAT_EINVAL, "negative count"};
     if (n > 0 && (!results || !rows)) throw StatusFail{GSMAT_EINVAL, "results or rows is NULL"};
     for (int32_t i = 0; i < n; ++i) rows[i] = results[i] ? results[i]->rows : -1;
+    return GSMAT_OK;
+  });
+}
+
+extern "C" gsmat_status gsmat_set_sparse_expand(gsmat_store* st, double theta, int64_t min_rows) {
+  return guarded([&]() -> gsmat_status {
+    if (!st) throw StatusFail{GSMAT_EINVAL, "store is NULL"};
+    if (!(theta >= 0.0 && theta <= 1.0)) throw StatusFail{GSMAT_EINVAL, "theta must be in [0, 1]"};
+    if (min_rows < 1) throw StatusFail{GSMAT_EINVAL, "min_rows must be at least 1"};
+    st->sparse_theta = theta;
+    st->sparse_min_rows = min_rows;
+    return GSMAT_OK;
+  });
+}
+
+extern "C" gsmat_status gsmat_autotune_batch(gsmat_store* st,
+                                             const gsmat_query_plan* const* plans,
+                                             int32_t n_plans, int64_t budget_bytes, void* stream,
+                                             double* theta, double* ms) {
+  return guarded([&]() -> gsmat_status {
+    if (!st || !theta) throw StatusFail{GSMAT_EINVAL, "store or theta is NULL"};
+    static const double kCand[kTuneCandidates] = {0.0, 0.25, 0.5, 0.75, 1.0};
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<gsmat_result*> res(std::max(n_plans, 1));
+    double best_ms = 0;
+    int best = -1;
+    for (int c = -1; c < kTuneCandidates; ++c) {
+      // c = -1: one untimed run first (allocator and caches warm)
+      st->sparse_theta = kCand[c < 0 ? 0 : c];
+      double t_min = 0;
+      for (int rep = 0; rep < (c < 0 ? 1 : 3); ++rep) {  // the fastest of three runs
+        GS_HIP(hipStreamSynchronize(s));
+        const auto t0 = std::chrono::steady_clock::now();
+        const gsmat_status rc =
+            gsmat_join_batch(st, plans, n_plans, budget_bytes, -1, stream, res.data(), nullptr);
+        GS_HIP(hipStreamSynchronize(s));
+        const double t = std::chrono::duration<double, std::milli>(
+                             std::chrono::steady_clock::now() - t0).count();
+        for (int i = 0; i < n_plans; ++i) gsmat_result_free(res[i]);
+        if (rc != GSMAT_OK) throw StatusFail{rc, gsmat_last_error()};
+        t_min = rep == 0 ? t : std::min(t_min, t);
+      }
+      if (c < 0) continue;
+      if (ms) ms[c] = t_min;
+      if (best < 0 || t_min < best_ms) {
+        best = c;
+        best_ms = t_min;
+      }
+    }
+    st->sparse_theta = kCand[best];
+    *theta = kCand[best];
     return GSMAT_OK;
   });
 }

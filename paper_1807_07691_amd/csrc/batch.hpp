@@ -33,11 +33,17 @@ struct WTask {
   int32_t k;           // input columns
   int32_t pad;
   const int32_t* nbr;  // expansion: members of the predicate view
-  const int32_t* N;
-  const int32_t* start;
-  int64_t* P;          // expansion: row offsets (n + 1)
+  const int32_t* N;    // expansion: output count per input row
+  const int32_t* start;  // expansion: row offset per row of the write
+  int64_t* P;          // expansion: output offsets per row of the write (+ 1)
   int64_t* split;      // expansion: merge-path splits (path tiles + 1)
   const uint8_t* flags;
+  // sparse expansion: the write covers only the n input rows with output,
+  // compacted from n_in rows; ridx[i] is row i's input row
+  int32_t* ridx;
+  int32_t* cstart;     // start of each compacted row (start points here)
+  const int32_t* start_in;
+  int64_t n_in;
 };
 
 // One task inside a launch: its tiles start at w0 of the launch's tiles.
@@ -62,8 +68,13 @@ void launch_lookup_many(const LookupReq* req, int32_t n, const PredDesc* dout, c
 // fan-out samples: kSampleBlocks partial sums per candidate to part[c * kSampleBlocks + b]
 void launch_b_sample(const SCand* cands, int64_t nc, int64_t* part, hipStream_t s);
 // count / flag tiles of every task (items in task order) -> tile sums ts[ntiles]
+// and, per tile, the expansion rows with output tsn[ntiles]
 void launch_b_count(const CTask* tasks, const GItem* items, int nitems, const ListRef* lists,
-                    int64_t* ts, int64_t ntiles, double bytes, hipStream_t s);
+                    int64_t* ts, int64_t* tsn, int64_t ntiles, double bytes, hipStream_t s);
+// sparse expansions: the rows with output of every count tile, compacted in
+// order, with their output offsets (ts, tsn scanned)
+void launch_b_compact_rows(const WTask* tasks, const GItem* items, int nitems, const int64_t* ts,
+                           const int64_t* tsn, int64_t tiles, double bytes, hipStream_t s);
 // out[task] = output rows, out[nitems + task] = non-empty rows (expansions)
 void launch_b_totals(const GItem* items, int nitems, const int64_t* ts, int64_t ntiles,
                      const int64_t* ne, int64_t* out, hipStream_t s);
@@ -74,6 +85,9 @@ void launch_b_partition(const WTask* tasks, const GItem* items, int nitems, int6
 // k > kMaxK selects the generic instantiation
 void launch_b_write(int k, const WTask* tasks, const GItem* items, int nitems, int64_t tiles,
                     double bytes, hipStream_t s);
+// the same over compacted rows (sparse expansions)
+void launch_b_write_idx(int k, const WTask* tasks, const GItem* items, int nitems, int64_t tiles,
+                        double bytes, hipStream_t s);
 void launch_b_compact(int k, const WTask* tasks, const GItem* items, int nitems,
                       const int64_t* ts, int64_t tiles, double bytes, hipStream_t s);
 

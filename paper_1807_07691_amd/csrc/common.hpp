@@ -221,6 +221,8 @@ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 // to host_total[0] (pinned host memory, valid after the stream synchronizes)
 void launch_scan_tile_sums(int64_t* tile_sum, int64_t nt, int64_t* total, hipStream_t s,
                            int64_t* host_total);
+// two tile-sum arrays [nt + 1] scanned together (totals at [nt])
+void launch_scan_tile_sums2(int64_t* ts, int64_t* ts2, int64_t nt, hipStream_t s);
 void launch_scan_add_i32(const int32_t* N, int64_t n, const int64_t* tile_off, int64_t* P,
                          hipStream_t s);
 void launch_tile_reduce_u32(const uint32_t* x, int64_t n, int64_t* tile_sum, hipStream_t s);

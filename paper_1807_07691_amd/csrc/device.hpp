@@ -530,8 +530,9 @@ __device__ inline int64_t mp_split(const int64_t* __restrict__ P, int64_t n, int
 // store.  K is a compile-time column count (-1: any count, in groups of 4).
 template <int K, class Out>
 __device__ inline void write_outputs(const ColSet& in, int kdyn, const int32_t* __restrict__ nbr,
-                                     const uint16_t* sRow, const int32_t* sRb, int64_t a0,
-                                     int64_t ob, int nbt, const Out& out) {
+                                     const uint16_t* sRow, const int32_t* sRb,
+                                     const int32_t* sIdx, int64_t a0, int64_t ob, int nbt,
+                                     const Out& out) {
   const int k = K >= 0 ? K : kdyn;
   const int al = (int)(ob & 63);
   const int span = nbt + al;
@@ -541,7 +542,9 @@ __device__ inline void write_outputs(const ColSet& in, int kdyn, const int32_t* 
     const int r1 = ok1 ? sRow[o1] : 0, r2 = ok2 ? sRow[o2] : 0;
     const int32_t v1 = ok1 ? nbr[sRb[r1] + o1] : 0;
     const int32_t v2 = ok2 ? nbr[sRb[r2] + o2] : 0;
-    const int64_t row1 = a0 + r1, row2 = a0 + r2;
+    // parent rows: consecutive, or (compacted rows) their original indices
+    const int64_t row1 = sIdx ? (int64_t)sIdx[r1] : a0 + r1;
+    const int64_t row2 = sIdx ? (int64_t)sIdx[r2] : a0 + r2;
     if (K >= 0) {
       int32_t x1[K > 0 ? K : 1], x2[K > 0 ? K : 1];
 #pragma unroll
@@ -578,15 +581,19 @@ __device__ inline void write_outputs(const ColSet& in, int kdyn, const int32_t* 
 }
 
 // One path tile t of an expansion (all threads of the workgroup call it).
-template <int K, class Out>
+// With ridx (kIdx), the rows are a compacted list: row i of P/start is the
+// input row ridx[i].
+template <int K, class Out, bool kIdx = false>
 __device__ inline void write_expand_tile(int64_t t, const ColSet& in, int kdyn,
                                          const int64_t* __restrict__ P,
                                          const int32_t* __restrict__ start, int64_t n,
                                          const int32_t* __restrict__ nbr, int64_t J0, int64_t J1,
-                                         const int64_t* __restrict__ split, const Out& out) {
+                                         const int64_t* __restrict__ split, const Out& out,
+                                         const int32_t* __restrict__ ridx = nullptr) {
   __shared__ int32_t sE[kTile + 1];
   __shared__ int32_t sRb[kTile + 1];
   __shared__ uint16_t sRow[kTile];
+  __shared__ int32_t sIdx[kIdx ? kTile + 1 : 1];
   const int64_t nb = J1 - J0;
   const int64_t total = n + nb;
   const int64_t d0 = t * (int64_t)kTile;
@@ -603,6 +610,7 @@ __device__ inline void write_expand_tile(int64_t t, const ColSet& in, int kdyn,
     const int64_t er = pe - jb;
     sE[i] = er > (int64_t)kTile + 1 ? kTile + 1 : (er < -1 ? -1 : (int32_t)er);
     sRb[i] = (int32_t)((int64_t)start[a0 + i] + (jb - pb));
+    if (kIdx) sIdx[i] = ridx[a0 + i];
   }
   __syncthreads();
   const int dl = min((int)threadIdx.x * kItems, nat + nbt);
@@ -624,7 +632,7 @@ __device__ inline void write_expand_tile(int64_t t, const ColSet& in, int kdyn,
     }
   }
   __syncthreads();
-  write_outputs<K, Out>(in, kdyn, nbr, sRow, sRb, a0, jb - J0, nbt, out);
+  write_outputs<K, Out>(in, kdyn, nbr, sRow, sRb, kIdx ? sIdx : nullptr, a0, jb - J0, nbt, out);
 }
 
 }  // namespace dev

@@ -47,6 +47,42 @@ __global__ __launch_bounds__(kBlock) void k_scan_tile_sums(int64_t* ts, int64_t 
   }
 }
 
+// Two tile-sum arrays scanned in one pass (the second may be null).
+__global__ __launch_bounds__(kBlock) void k_scan_tile_sums2(int64_t* ts, int64_t* ts2, int64_t nt) {
+  int64_t carry = 0, carry2 = 0;
+  for (int64_t c0 = 0; c0 < nt; c0 += kTile) {
+    int64_t v[kItems], w[kItems];
+    int64_t loc = 0, loc2 = 0;
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+      const int64_t i = c0 + (int64_t)threadIdx.x * kItems + j;
+      v[j] = i < nt ? ts[i] : 0;
+      w[j] = i < nt ? ts2[i] : 0;
+      loc += v[j];
+      loc2 += w[j];
+    }
+    int64_t tot, tot2;
+    int64_t ex = block_excl_scan(loc, &tot) + carry;
+    int64_t ex2 = block_excl_scan(loc2, &tot2) + carry2;
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+      const int64_t i = c0 + (int64_t)threadIdx.x * kItems + j;
+      if (i < nt) {
+        ts[i] = ex;
+        ts2[i] = ex2;
+      }
+      ex += v[j];
+      ex2 += w[j];
+    }
+    carry += tot;
+    carry2 += tot2;
+  }
+  if (threadIdx.x == 0) {
+    ts[nt] = carry;
+    ts2[nt] = carry2;
+  }
+}
+
 template <class Tin, class Tout>
 __global__ __launch_bounds__(kBlock) void k_scan_add(const Tin* __restrict__ x, int64_t n,
                                                      const int64_t* __restrict__ tile_off,
@@ -412,6 +448,11 @@ void launch_scan_tile_sums(int64_t* tile_sum, int64_t nt, int64_t* total, hipStr
   GS_LAUNCH(GSMAT_K_SCAN, 16.0 * nt,
             hipLaunchKernelGGL(k_scan_tile_sums, dim3(1), dim3(kBlock), 0, s, tile_sum, nt, total,
                                host_total));
+}
+
+void launch_scan_tile_sums2(int64_t* ts, int64_t* ts2, int64_t nt, hipStream_t s) {
+  GS_LAUNCH(GSMAT_K_SCAN, 32.0 * nt,
+            hipLaunchKernelGGL(k_scan_tile_sums2, dim3(1), dim3(kBlock), 0, s, ts, ts2, nt));
 }
 
 void launch_scan_add_i32(const int32_t* N, int64_t n, const int64_t* tile_off, int64_t* P,

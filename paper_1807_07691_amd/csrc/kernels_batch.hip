@@ -44,16 +44,17 @@ __global__ __launch_bounds__(kBlock) void k_b_sample(const SCand* __restrict__ c
 __global__ __launch_bounds__(kBlock) void k_b_count(const CTask* __restrict__ tasks,
                                                     const GItem* __restrict__ items, int nitems,
                                                     const ListRef* __restrict__ lists,
-                                                    int64_t* __restrict__ ts) {
+                                                    int64_t* __restrict__ ts,
+                                                    int64_t* __restrict__ tsn) {
   const GItem& it = items[find_item(items, nitems, blockIdx.x)];
   const CTask& T = tasks[it.task];
   const int64_t tile = (int64_t)blockIdx.x - it.w0;
-  int64_t sum;
+  int64_t sum, ne = 0;
   if (T.kind == kTaskExpand) {
     const PredView pv = T.pv;
     const int64_t packed = count_expand_tile<true>(tile, T.col, T.n, pv, T.N, T.start);
     sum = packed & (((int64_t)1 << kNonEmptyShift) - 1);
-    const int64_t ne = packed >> kNonEmptyShift;
+    ne = packed >> kNonEmptyShift;
     if (threadIdx.x == 0 && ne > 0) atomicAdd((unsigned long long*)T.nonempty, (unsigned long long)ne);
   } else if (T.kind == kTaskFilter) {
     const PredView pv = T.pv;
@@ -62,7 +63,59 @@ __global__ __launch_bounds__(kBlock) void k_b_count(const CTask* __restrict__ ta
   } else {
     sum = flag_intersect_tile(tile, T.col, T.n, lists + T.l0, T.nl, T.flags);
   }
-  if (threadIdx.x == 0) ts[blockIdx.x] = sum;
+  if (threadIdx.x == 0) {
+    ts[blockIdx.x] = sum;
+    tsn[blockIdx.x] = ne;
+  }
+}
+
+// Sparse expansion, one count tile: the tile's output offsets (exclusive
+// scan of N from the tile's base), then the rows with output compacted in
+// order with their offsets and starts.
+__global__ __launch_bounds__(kBlock) void k_b_compact_rows(const WTask* __restrict__ tasks,
+                                                           const GItem* __restrict__ items,
+                                                           int nitems,
+                                                           const int64_t* __restrict__ ts,
+                                                           const int64_t* __restrict__ tsn) {
+  __shared__ int64_t s[kTile];
+  const GItem& it = items[find_item(items, nitems, blockIdx.x)];
+  const WTask& T = tasks[it.task];
+  const int64_t tile = (int64_t)blockIdx.x - it.w0;
+  const int64_t tile0 = tile * kTile;
+  const int64_t base = ts[T.t0 + tile] - ts[T.t0];
+  const int64_t cbase = tsn[T.t0 + tile] - tsn[T.t0];
+  const int64_t n = T.n_in;
+#pragma unroll
+  for (int j = 0; j < kItems; ++j) {
+    const int64_t i = tile0 + (int64_t)j * kBlock + threadIdx.x;
+    s[j * kBlock + threadIdx.x] = i < n ? (int64_t)T.N[i] : 0;
+  }
+  __syncthreads();
+  int64_t loc = 0;
+#pragma unroll
+  for (int j = 0; j < kItems; ++j) loc += s[threadIdx.x * kItems + j];
+  int64_t tot;
+  int64_t ex = block_excl_scan(loc, &tot) + base;
+#pragma unroll
+  for (int j = 0; j < kItems; ++j) {
+    const int64_t v = s[threadIdx.x * kItems + j];
+    s[threadIdx.x * kItems + j] = ex;
+    ex += v;
+  }
+  __syncthreads();
+  int32_t* __restrict__ ridx = T.ridx;
+  int32_t* __restrict__ cstart = T.cstart;
+  int64_t* __restrict__ P = T.P;
+  const int32_t* __restrict__ N = T.N;
+  const int32_t* __restrict__ st = T.start_in;
+  compact_tile(
+      tile, n, cbase, [&](int64_t i) { return N[i] > 0; },
+      [&](int64_t i, int64_t pos) {
+        ridx[pos] = (int32_t)i;
+        cstart[pos] = st[i];
+        P[pos] = s[i - tile0];
+      });
+  if (threadIdx.x == 0 && tile0 + kTile >= n) P[T.n] = T.m;
 }
 
 // Output size of every task from the scanned tile sums (exclusive, with the
@@ -121,6 +174,26 @@ __global__ __launch_bounds__(kBlock) void k_b_write(const WTask* __restrict__ ta
 }
 
 template <int K>
+__global__ __launch_bounds__(kBlock) void k_b_write_idx(const WTask* __restrict__ tasks,
+                                                        const GItem* __restrict__ items,
+                                                        int nitems) {
+  const GItem& it = items[find_item(items, nitems, blockIdx.x)];
+  const WTask& T = tasks[it.task];
+  const int64_t t = (int64_t)blockIdx.x - it.w0;
+  const OutStrided out{T.out0, T.ostride};
+  if constexpr (K >= 0) {
+    ColSet in;
+#pragma unroll
+    for (int c = 0; c < K; ++c) in.c[c] = T.in.c[c];
+    write_expand_tile<K, OutStrided, true>(t, in, K, T.P, T.start, T.n, T.nbr, 0, T.m, T.split,
+                                           out, T.ridx);
+  } else {
+    write_expand_tile<K, OutStrided, true>(t, T.in, T.k, T.P, T.start, T.n, T.nbr, 0, T.m,
+                                           T.split, out, T.ridx);
+  }
+}
+
+template <int K>
 __global__ __launch_bounds__(kBlock) void k_b_compact(const WTask* __restrict__ tasks,
                                                       const GItem* __restrict__ items, int nitems,
                                                       const int64_t* __restrict__ ts) {
@@ -156,6 +229,13 @@ void b_write(const WTask* t, const GItem* g, int ng, int64_t tiles, double bytes
                                 ng));
 }
 template <int K>
+void b_write_idx(const WTask* t, const GItem* g, int ng, int64_t tiles, double bytes,
+                 hipStream_t s) {
+  GS_BLAUNCH(GSMAT_K_WRITE, bytes,
+             hipLaunchKernelGGL(k_b_write_idx<K>, dim3((unsigned)tiles), dim3(kBlock), 0, s, t, g,
+                                ng));
+}
+template <int K>
 void b_compact(const WTask* t, const GItem* g, int ng, const int64_t* ts, int64_t tiles,
                double bytes, hipStream_t s) {
   GS_BLAUNCH(GSMAT_K_COMPACT, bytes,
@@ -181,10 +261,17 @@ void launch_b_sample(const SCand* cands, int64_t nc, int64_t* part, hipStream_t 
 }
 
 void launch_b_count(const CTask* tasks, const GItem* items, int nitems, const ListRef* lists,
-                    int64_t* ts, int64_t ntiles, double bytes, hipStream_t s) {
+                    int64_t* ts, int64_t* tsn, int64_t ntiles, double bytes, hipStream_t s) {
   GS_BLAUNCH(GSMAT_K_COUNT, bytes,
              hipLaunchKernelGGL(k_b_count, dim3((unsigned)ntiles), dim3(kBlock), 0, s, tasks,
-                                items, nitems, lists, ts));
+                                items, nitems, lists, ts, tsn));
+}
+
+void launch_b_compact_rows(const WTask* tasks, const GItem* items, int nitems, const int64_t* ts,
+                           const int64_t* tsn, int64_t tiles, double bytes, hipStream_t s) {
+  GS_BLAUNCH(GSMAT_K_SCAN, bytes,
+             hipLaunchKernelGGL(k_b_compact_rows, dim3((unsigned)tiles), dim3(kBlock), 0, s, tasks,
+                                items, nitems, ts, tsn));
 }
 
 void launch_b_totals(const GItem* items, int nitems, const int64_t* ts, int64_t ntiles,
@@ -224,6 +311,22 @@ void launch_b_write(int k, const WTask* t, const GItem* g, int ng, int64_t tiles
     case 10: return b_write<10>(t, g, ng, tiles, bytes, s);
     case 11: return b_write<11>(t, g, ng, tiles, bytes, s);
     default: return b_write<-1>(t, g, ng, tiles, bytes, s);
+  }
+}
+
+void launch_b_write_idx(int k, const WTask* t, const GItem* g, int ng, int64_t tiles, double bytes,
+                        hipStream_t s) {
+  switch (k) {
+    case 0: return b_write_idx<0>(t, g, ng, tiles, bytes, s);
+    case 1: return b_write_idx<1>(t, g, ng, tiles, bytes, s);
+    case 2: return b_write_idx<2>(t, g, ng, tiles, bytes, s);
+    case 3: return b_write_idx<3>(t, g, ng, tiles, bytes, s);
+    case 4: return b_write_idx<4>(t, g, ng, tiles, bytes, s);
+    case 5: return b_write_idx<5>(t, g, ng, tiles, bytes, s);
+    case 6: return b_write_idx<6>(t, g, ng, tiles, bytes, s);
+    case 7: return b_write_idx<7>(t, g, ng, tiles, bytes, s);
+    case 8: return b_write_idx<8>(t, g, ng, tiles, bytes, s);
+    default: return b_write_idx<-1>(t, g, ng, tiles, bytes, s);
   }
 }
 

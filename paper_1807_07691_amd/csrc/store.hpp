@@ -50,6 +50,8 @@ struct gsmat_store {
   int32_t* d_p = nullptr;
   int32_t* d_o = nullptr;
   bool built = false;
+  double sparse_theta = 0.5;       // batched expansions: compact rows below this fill ...
+  int64_t sparse_min_rows = 4096;  // ... in expansions of at least this many rows
   int64_t hub_min_len = 1 << 14;  // rows this long get a bitmap ...
   int64_t hub_max_bytes = 0;      // ... within this many bytes per orientation (0: none)
   uint64_t uid = 0;        // distinct for every index build in the process

@@ -87,12 +87,38 @@ def tiny(G, O):
     return spec, s, p, o, qs, st, want
 
 
+# sparse expansions: off, default, and forced on every expansion with an
+# empty row (theta 1, any size)
+SPARSE = [(0.0, 4096), (0.5, 4096), (1.0, 1)]
+
+
+@pytest.mark.parametrize("sparse", SPARSE)
 @pytest.mark.parametrize("mode", [0, 1, 2])
-def test_batch_tiny_workload(G, tiny, mode):
+def test_batch_tiny_workload(G, tiny, mode, sparse):
     spec, s, p, o, qs, st, want = tiny
-    print(f"[gpu] batch tiny mode={mode}", flush=True)
-    queries = [q.tps for q in qs] * 8  # each query 8 times in one batch
-    _check_batch(G, st, queries, mode, oracle_rows=want * 8)
+    print(f"[gpu] batch tiny mode={mode} sparse={sparse}", flush=True)
+    G.gsmat_set_sparse_expand(st, *sparse)
+    try:
+        queries = [q.tps for q in qs] * 8  # each query 8 times in one batch
+        _check_batch(G, st, queries, mode, oracle_rows=want * 8)
+    finally:
+        G.gsmat_set_sparse_expand(st, 0.5, 4096)
+
+
+def test_batch_autotune(G, tiny):
+    """The tuner keeps one of its candidates; results do not depend on it."""
+    spec, s, p, o, qs, st, want = tiny
+    G.gsmat_set_sparse_expand(st, 0.5, 1)
+    try:
+        queries = [q.tps for q in qs] * 8
+        plans, _ = G.gsmat_plan_batch(st, queries, G.PLAN_ADAPTIVE, as_set=True)
+        theta, ms = G.gsmat_autotune_batch(st, plans)
+        print(f"[gpu] autotune: theta={theta} ms={ms}", flush=True)
+        assert theta in G.SPARSE_CANDIDATES and len(ms) == 5 and all(v > 0 for v in ms.values())
+        _check_batch(G, st, queries, G.PLAN_ADAPTIVE, oracle_rows=want * 8)
+        plans.close()
+    finally:
+        G.gsmat_set_sparse_expand(st, 0.5, 4096)
 
 
 @pytest.mark.parametrize("mode", [1, 2])
@@ -182,6 +208,7 @@ def test_batch_random_graphs(G, O, seed):
     if seed % 2:  # bitmaps for the rows of at least 1-7 members
         G.gsmat_set_hub_options(st, int(rng.integers(1, 8)), 1 << 26)
     G.gsmat_build_index(st, dense_div=int(rng.choice([1, 32, 10**6])))
+    G.gsmat_set_sparse_expand(st, *SPARSE[seed % 3])
     queries, want = [], []
     while len(queries) < 70:
         ntp = int(rng.integers(1, 5))
@@ -215,6 +242,7 @@ def test_batch_medium_workload(G, O):
     spec, (s, p, o), gi, qs = W.make_workload("medium")
     gi.close()
     st = _store(G, s, p, o, spec.V, spec.P)
+    G.gsmat_set_sparse_expand(st, 1.0, 1)  # every expansion with an empty row compacted
     ds = O.Dataset(s, p, o)
     queries = [q.tps for q in qs]
     plans, _ = G.gsmat_plan_batch(st, queries, G.PLAN_ADAPTIVE)
