@@ -242,8 +242,9 @@ gsmat_status gsmat_set_sparse_expand(gsmat_store* st, double theta, int64_t min_
 
 /* Autotuner: runs gsmat_join_batch on the plans once untimed, then with each
  * candidate theta (0, 0.25, 0.5, 0.75, 1; the fastest of three runs each,
- * results discarded), keeps the fastest
- * for the store and returns it in *theta; ms[5] (may be NULL) receives each
+ * results discarded), keeps the fastest for the store (the store's current
+ * theta stays unless another candidate is faster by more than 3 %) and
+ * returns the kept value in *theta; ms[5] (may be NULL) receives each
  * candidate's wall time in milliseconds.  The rows of any later join do not
  * depend on the choice. */
 gsmat_status gsmat_autotune_batch(gsmat_store* st, const gsmat_query_plan* const* plans,

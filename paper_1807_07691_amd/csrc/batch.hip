@@ -818,8 +818,10 @@ void Batch::phase_write() {
 
 }  // namespace
 
-// Candidate fill thresholds the autotuner times.
+// Candidate fill thresholds the autotuner times; a candidate replaces the
+// current threshold only when it is faster by more than 3 %.
 constexpr int kTuneCandidates = 5;
+constexpr double kTuneMargin = 0.97;
 
 // ---------------------------------------------------------------- serving
 
@@ -1291,7 +1293,9 @@ extern "C" gsmat_status gsmat_autotune_batch(gsmat_store* st,
   return guarded([&]() -> gsmat_status {
     if (!st || !theta) throw StatusFail{GSMAT_EINVAL, "store or theta is NULL"};
     static const double kCand[kTuneCandidates] = {0.0, 0.25, 0.5, 0.75, 1.0};
+    const double current = st->sparse_theta;
     hipStream_t s = (hipStream_t)stream;
+    double current_ms = -1.0;
     std::vector<gsmat_result*> res(std::max(n_plans, 1));
     double best_ms = 0;
     int best = -1;
@@ -1313,13 +1317,17 @@ extern "C" gsmat_status gsmat_autotune_batch(gsmat_store* st,
       }
       if (c < 0) continue;
       if (ms) ms[c] = t_min;
+      if (kCand[c] == current) current_ms = t_min;
       if (best < 0 || t_min < best_ms) {
         best = c;
         best_ms = t_min;
       }
     }
-    st->sparse_theta = kCand[best];
-    *theta = kCand[best];
+    // the current threshold stays unless another is faster by a clear margin
+    const double chosen =
+        (current_ms > 0 && best_ms > kTuneMargin * current_ms) ? current : kCand[best];
+    st->sparse_theta = chosen;
+    *theta = chosen;
     return GSMAT_OK;
   });
 }
