@@ -24,8 +24,10 @@
  *
  * Conventions for every entry point:
  *   - Return value: a gsmat_status; GSMAT_OK on success.  On error nothing is
- *     returned through output pointers and gsmat_last_error() describes the
- *     failure (thread-local).  No entry point throws or aborts.
+ *     returned through output pointers (except the batch entry points, which
+ *     hand back every query that succeeded and a status per query) and
+ *     gsmat_last_error() describes the failure (thread-local).  No entry
+ *     point throws or aborts.
  *   - Argument validation happens before any device work.
  *   - Handles (store, plan, result) are owned by the caller and released with
  *     the matching *_free.  A plan or result must not outlive its store.
@@ -35,8 +37,14 @@
  *   - Device memory comes from the library's caching block allocator (blocks
  *     from hipMalloc, reused per stream, cross-stream reuse ordered by events)
  *     unless an allocator is given to gsmat_load_triples.
- *   - The store is immutable after gsmat_build_index; concurrent gsmat_join
- *     calls on different streams (and different results) are allowed.
+ *   - The store's index is immutable after gsmat_build_index; concurrent
+ *     gsmat_join calls on different streams (and different results) are
+ *     allowed.  gsmat_set_sparse_expand and gsmat_autotune_batch change a
+ *     tuning setting of the store and must not overlap other calls on it.
+ *   - A result's (and a server's) memory is returned to the allocator on the
+ *     stream it was made on: that stream must outlive them.
+ *   - After a non-OK gsmat_server_step the server's state is unspecified:
+ *     free it.
  */
 #ifndef GSMAT_H
 #define GSMAT_H

@@ -7,15 +7,20 @@
 // and star-centre intersections become tasks of one count/flag launch whose
 // tiles are the concatenation of every task's tiles; one scan of all tile
 // sums and one per-task reduction give every task's output size, read back
-// with a single stream synchronisation.  The host then allocates one arena
-// for all outputs of the round and issues one prefix-sum launch, one
-// merge-path partition launch, and one write (expansions) or compaction
-// (filters, intersections) launch per column count.  Steps needing no kernel
-// (pattern scans, which are views into the store) are applied on the host.
-// The adaptive step choice samples every query's candidate expansions in one
-// launch per round.  A query whose next step would be a Cartesian product, a
-// (?x p ?x) scan, or an output above the byte budget leaves the batch and is
-// run on its own by the single-query executor, which handles those cases.
+// with a single wait.  The host then allocates one arena for all outputs of
+// the round and issues one prefix-sum launch, one merge-path partition
+// launch, and one write (expansions) or compaction (filters, intersections)
+// launch per column count.  Expansions in which few input rows have output
+// first compact those rows (their offsets come from the same prefix sum) and
+// are written by a variant that walks only them; the fill threshold is the
+// store's, set directly or by the autotuner at the end of this file.  Steps
+// needing no kernel (pattern scans, which are views into the store) are
+// applied on the host.  The adaptive step choice samples every query's
+// candidate expansions in one launch per round.  A query whose next step
+// would be a Cartesian product, a (?x p ?x) scan, or an output above the byte
+// budget leaves the batch and is run on its own by the single-query
+// executor, which handles those cases.  The serving loop (gsmat_server_*)
+// keeps a batch alive across calls and admits new queries between rounds.
 //
 // Each query takes exactly the steps it takes alone (same plan, same choice
 // rule on the same tables), so its result rows come out in the same order.
