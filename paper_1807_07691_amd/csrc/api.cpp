@@ -313,7 +313,7 @@ extern "C" gsmat_status gsmat_plan_from_stats(const gsmat_pattern* pats, int32_t
       ts[i].stat = ts[i].rows_s = ts[i].rows_o = stat[i];
     }
     std::unique_ptr<gsmat_query_plan> pl(new gsmat_query_plan);
-    rc = build_plan(pats, n_pats, mode, ts, pl.get(), &err);
+    rc = build_plan(pats, n_pats, mode, ts.data(), pl.get(), &err);
     if (rc != GSMAT_OK) throw StatusFail{rc, err};
     *out = pl.release();
     return GSMAT_OK;

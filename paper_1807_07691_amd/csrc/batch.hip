@@ -123,7 +123,6 @@ struct BQ {
   std::string err;
   gsmat_step_info sp{};
   uint32_t next = 0;
-  int task = -1;        // this round's task
   LookupRes lk[kMaxPats];  // row lookup of each pattern with a constant
   int64_t tag = 0;         // caller's id (server)
   int64_t est_bytes = 0;   // admission estimate (server)
@@ -312,7 +311,6 @@ bool Batch::phase_sample() {
   for (BQ& b : q) {
     if (b.state != kActive) continue;
     any = true;
-    b.task = -1;
     b.cand0 = -1;
     const gsmat_query_plan* pl = b.pl;
     if (pl->mode == GSMAT_PLAN_ADAPTIVE && !b.t.unit()) {
@@ -446,7 +444,6 @@ void Batch::phase_count() {
           if (i != d) lists.push_back(ls[i]);
         c.nl = (int32_t)lists.size() - c.l0;
         b.new_var = sp.var;
-        b.task = (int)tasks.size();
         tasks.push_back(c);
         owner.push_back(qi);
         break;
@@ -470,7 +467,6 @@ void Batch::phase_count() {
         if (is_var(p.o)) c.pa.o_col = b.t.col[b.t.col_of(var_of(p.o))];
         else c.pa.o_const = p.o;
         c.pv = st->out.view(p.p);
-        b.task = (int)tasks.size();
         tasks.push_back(c);
         owner.push_back(qi);
         break;
@@ -488,7 +484,6 @@ void Batch::phase_count() {
         c.col = b.t.col[bc];
         c.pv = sp.orient == 0 ? st->out.view(p.p) : st->in.view(p.p);
         b.new_var = sp.orient == 0 ? var_of(p.o) : var_of(p.s);
-        b.task = (int)tasks.size();
         tasks.push_back(c);
         owner.push_back(qi);
         break;
@@ -1178,16 +1173,21 @@ extern "C" gsmat_status gsmat_plan_batch(const gsmat_store* st, const gsmat_patt
     if (mode != GSMAT_PLAN_PAPER && mode != GSMAT_PLAN_DEFAULT && mode != GSMAT_PLAN_ADAPTIVE)
       throw StatusFail{GSMAT_EINVAL, "unknown plan mode " + std::to_string(mode)};
     hipStream_t s = (hipStream_t)stream;
-    std::vector<int64_t> off(n_queries + 1, 0);
+    // off: first pattern of each query; so: its first statistics slot (a
+    // query over the pattern limit fails validation and takes none)
+    std::vector<int64_t> off(n_queries + 1, 0), so(n_queries + 1, 0);
     for (int i = 0; i < n_queries; ++i) {
       if (n_pats[i] < 0) throw StatusFail{GSMAT_EINVAL, "negative pattern count"};
       off[i + 1] = off[i] + n_pats[i];
+      so[i + 1] = so[i] + (n_pats[i] <= kMaxPats ? n_pats[i] : 0);
     }
     std::vector<gsmat_status> rc(n_queries, GSMAT_OK);
     std::vector<std::string> msg(n_queries);
-    std::vector<std::vector<TpStat>> stats(n_queries);
+    // per pattern, flat over the batch: statistics and lookup request index
+    std::vector<TpStat> stats(so[n_queries]);
+    std::vector<int> req_of(so[n_queries], -1);
     std::vector<LookupReq> req;
-    std::vector<std::vector<int>> req_of(n_queries);
+    req.reserve(so[n_queries]);
     for (int i = 0; i < n_queries; ++i) {
       const gsmat_pattern* pq = pats + off[i];
       const int n = n_pats[i];
@@ -1195,9 +1195,8 @@ extern "C" gsmat_status gsmat_plan_batch(const gsmat_store* st, const gsmat_patt
       rc[i] = validate_patterns(pq, n, &nv, &msg[i]);
       if (rc[i] != GSMAT_OK) continue;
       // the statistics pattern_stats gathers, with the lookups pooled
-      auto& ts = stats[i];
-      ts.assign(n, TpStat{});
-      req_of[i].assign(n, -1);
+      TpStat* ts = stats.data() + so[i];
+      int* ro = req_of.data() + so[i];
       for (int j = 0; j < n; ++j) {
         const gsmat_pattern& p = pq[j];
         TpStat& t = ts[j];
@@ -1212,7 +1211,7 @@ extern "C" gsmat_status gsmat_plan_batch(const gsmat_store* st, const gsmat_patt
           continue;
         }
         if (!sc && !oc) continue;
-        req_of[i][j] = (int)req.size();
+        ro[j] = (int)req.size();
         if (sc && oc) req.push_back({0, p.p, p.s, p.o});
         else if (sc) req.push_back({0, p.p, p.s, -1});
         else req.push_back({1, p.p, p.o, -1});
@@ -1224,19 +1223,21 @@ extern "C" gsmat_status gsmat_plan_batch(const gsmat_store* st, const gsmat_patt
     for (int i = 0; i < n_queries; ++i) {
       if (rc[i] == GSMAT_OK) {
         const gsmat_pattern* pq = pats + off[i];
+        TpStat* ts = stats.data() + so[i];
+        const int* ro = req_of.data() + so[i];
         for (int j = 0; j < n_pats[i]; ++j) {
-          const int r = req_of[i][j];
+          const int r = ro[j];
           if (r < 0) continue;
           const bool both = !is_var(pq[j].s) && !is_var(pq[j].o);
           const int64_t v = both ? res[r].found : res[r].len;
-          stats[i][j].stat = stats[i][j].rows_s = stats[i][j].rows_o = v;
+          ts[j].stat = ts[j].rows_s = ts[j].rows_o = v;
         }
         std::unique_ptr<gsmat_query_plan> pl(new gsmat_query_plan);
-        rc[i] = build_plan(pq, n_pats[i], mode, stats[i], pl.get(), &msg[i]);
+        rc[i] = build_plan(pq, n_pats[i], mode, ts, pl.get(), &msg[i]);
         if (rc[i] == GSMAT_OK && mode != GSMAT_PLAN_PAPER) {
           pl->lk.assign(n_pats[i], gsmat_pat_lookup{});
           for (int j = 0; j < n_pats[i]; ++j) {
-            const int r = req_of[i][j];
+            const int r = ro[j];
             if (r >= 0) pl->lk[j] = gsmat_pat_lookup{res[r].start, res[r].len, res[r].found, 1};
           }
           pl->lk_store = st->uid;

@@ -683,7 +683,7 @@ extern "C" gsmat_status gsmat_plan(const gsmat_store* st, const gsmat_pattern* p
     std::vector<gsmat_pat_lookup> lk;
     std::vector<TpStat> ts = pattern_stats(st, pats, n_pats, mode, (hipStream_t)stream, &lk);
     std::unique_ptr<gsmat_query_plan> pl(new gsmat_query_plan);
-    rc = build_plan(pats, n_pats, mode, ts, pl.get(), &err);
+    rc = build_plan(pats, n_pats, mode, ts.data(), pl.get(), &err);
     if (rc != GSMAT_OK) throw StatusFail{rc, err};
     if (mode != GSMAT_PLAN_PAPER) {
       pl->lk = std::move(lk);

@@ -18,7 +18,6 @@
 // endpoints are all bound (filters) go before expansions.
 #include <algorithm>
 #include <cstring>
-#include <numeric>
 #include <string>
 #include <vector>
 
@@ -77,8 +76,8 @@ gsmat_status validate_patterns(const gsmat_pattern* pats, int32_t n, int32_t* n_
   return GSMAT_OK;
 }
 
-gsmat_status build_plan(const gsmat_pattern* pats, int32_t n, int32_t mode,
-                        const std::vector<TpStat>& st, gsmat_query_plan* out, std::string* err) {
+gsmat_status build_plan(const gsmat_pattern* pats, int32_t n, int32_t mode, const TpStat* st,
+                        gsmat_query_plan* out, std::string* err) {
   int32_t nv = 0;
   gsmat_status rc = validate_patterns(pats, n, &nv, err);
   if (rc != GSMAT_OK) return rc;
@@ -90,13 +89,20 @@ gsmat_status build_plan(const gsmat_pattern* pats, int32_t n, int32_t mode,
   out->n_vars = nv;
   out->mode = mode;
   out->steps.clear();
+  out->steps.reserve(n + 1);  // at most one step per pattern, plus an intersection
   if (mode == GSMAT_PLAN_ADAPTIVE) mode = GSMAT_PLAN_DEFAULT;  // same static order
 
-  std::vector<int> order(n);
-  std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(),
-                   [&](int a, int b) { return st[a].stat < st[b].stat; });
-  std::vector<int> rem = order;  // remaining, in sorted order
+  // stable insertion sort by the statistic (n <= kMaxPats)
+  int order[kMaxPats];
+  for (int i = 0; i < n; ++i) {
+    int j = i;
+    for (; j > 0 && st[i].stat < st[order[j - 1]].stat; --j) order[j] = order[j - 1];
+    order[j] = i;
+  }
+  int rem_buf[kMaxPats];  // remaining, in sorted order
+  int n_rem = n;
+  std::copy(order, order + n, rem_buf);
+  const int* const rem = rem_buf;
   uint64_t bound = 0;
   int64_t est = 1;
 
@@ -113,7 +119,12 @@ gsmat_status build_plan(const gsmat_pattern* pats, int32_t n, int32_t mode,
     if (is_var(pats[t].s)) bound |= 1ull << var_of(pats[t].s);
     if (is_var(pats[t].o)) bound |= 1ull << var_of(pats[t].o);
   };
-  auto erase = [&](int t) { rem.erase(std::find(rem.begin(), rem.end(), t)); };
+  auto erase = [&](int t) {
+    int i = 0;
+    while (rem_buf[i] != t) ++i;
+    std::copy(rem_buf + i + 1, rem_buf + n_rem, rem_buf + i);
+    --n_rem;
+  };
   auto push = [&](int kind, int tp, int orient, int var, uint32_t members) {
     gsmat_step_info s;
     std::memset(&s, 0, sizeof(s));
@@ -128,19 +139,20 @@ gsmat_status build_plan(const gsmat_pattern* pats, int32_t n, int32_t mode,
 
   if (mode == GSMAT_PLAN_DEFAULT) {
     // constant-only patterns are a yes/no test; do them first
-    for (int t : order)
-      if (all_const(t)) {
-        est = std::min<int64_t>(est, st[t].stat);
-        push(GSMAT_STEP_FILTER, t, -1, -1, 0);
-        erase(t);
-      }
+    for (int i = 0; i < n; ++i) {
+      const int t = order[i];
+      if (!all_const(t)) continue;
+      est = std::min<int64_t>(est, st[t].stat);
+      push(GSMAT_STEP_FILTER, t, -1, -1, 0);
+      erase(t);
+    }
   }
 
   bool first = true;
-  while (!rem.empty()) {
+  while (n_rem > 0) {
     if (first) {
       first = false;
-      const int e1 = rem.front();
+      const int e1 = rem[0];
       if (mode == GSMAT_PLAN_DEFAULT && !all_const(e1)) {
         // star centre intersection on a variable endpoint of e1
         int best_v = -1;
@@ -152,7 +164,8 @@ gsmat_status build_plan(const gsmat_pattern* pats, int32_t n, int32_t mode,
           uint32_t mem = 0;
           int cnt = 0;
           int64_t e = INT64_MAX;
-          for (int t : rem) {
+          for (int i = 0; i < n_rem; ++i) {
+            const int t = rem[i];
             if (cnt >= kMaxLists) break;
             const bool vs = pats[t].s == term, vo = pats[t].o == term;
             if (vs == vo) continue;  // not incident, or a self loop on v
@@ -169,9 +182,9 @@ gsmat_status build_plan(const gsmat_pattern* pats, int32_t n, int32_t mode,
         if (best_v >= 0) {
           est = std::min(sat_mul(est, best_est), best_est);
           int first_member = -1;
-          for (int t : order)
-            if (best_mem >> t & 1) {
-              first_member = t;
+          for (int i = 0; i < n; ++i)
+            if (best_mem >> order[i] & 1) {
+              first_member = order[i];
               break;
             }
           push(GSMAT_STEP_INTERSECT, first_member, -1, best_v, best_mem);
@@ -190,20 +203,20 @@ gsmat_status build_plan(const gsmat_pattern* pats, int32_t n, int32_t mode,
     }
     int pick = -1;
     if (mode == GSMAT_PLAN_DEFAULT) {
-      for (int t : rem)
-        if (has_bound_var(t) && all_bound(t)) {
-          pick = t;
+      for (int i = 0; i < n_rem; ++i)
+        if (has_bound_var(rem[i]) && all_bound(rem[i])) {
+          pick = rem[i];
           break;
         }
     }
     if (pick < 0)
-      for (int t : rem)
-        if (has_bound_var(t)) {
-          pick = t;
+      for (int i = 0; i < n_rem; ++i)
+        if (has_bound_var(rem[i])) {
+          pick = rem[i];
           break;
         }
     if (pick < 0) {
-      pick = rem.front();
+      pick = rem[0];
       if (all_const(pick)) {
         est = std::min<int64_t>(est, st[pick].stat);
         push(GSMAT_STEP_FILTER, pick, -1, -1, 0);

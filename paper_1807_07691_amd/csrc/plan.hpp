@@ -44,6 +44,7 @@ struct gsmat_query_plan {
 };
 
 namespace gsmat {
-gsmat_status build_plan(const gsmat_pattern* pats, int32_t n, int32_t mode,
-                        const std::vector<TpStat>& st, gsmat_query_plan* out, std::string* err);
+// `st` holds one entry per pattern.
+gsmat_status build_plan(const gsmat_pattern* pats, int32_t n, int32_t mode, const TpStat* st,
+                        gsmat_query_plan* out, std::string* err);
 }  // namespace gsmat
