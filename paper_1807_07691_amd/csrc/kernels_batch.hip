@@ -69,53 +69,67 @@ __global__ __launch_bounds__(kBlock) void k_b_count(const CTask* __restrict__ ta
   }
 }
 
-// Sparse expansion, one count tile: the tile's output offsets (exclusive
-// scan of N from the tile's base), then the rows with output compacted in
-// order with their offsets and starts.
+// Sparse expansion, one count tile: the rows with output, compacted in
+// order, with their index, start and output offset (exclusive prefix of N
+// from the tile's base).  Thread t takes the tile's rows 8t..8t+7, so one
+// block scan of (outputs, rows with output) gives every kept row its offset
+// and place; the pair is packed into one int64, the row count in the low 12
+// bits (a tile has 2048 rows) and the outputs above it (at most 2048 rows of
+// fewer than 2^31 each: 2^42).
 __global__ __launch_bounds__(kBlock) void k_b_compact_rows(const WTask* __restrict__ tasks,
                                                            const GItem* __restrict__ items,
                                                            int nitems,
                                                            const int64_t* __restrict__ ts,
                                                            const int64_t* __restrict__ tsn) {
-  __shared__ int64_t s[kTile];
+  static_assert(kTile < (1 << 12), "row count must fit the low 12 bits");
   const GItem& it = items[find_item(items, nitems, blockIdx.x)];
   const WTask& T = tasks[it.task];
   const int64_t tile = (int64_t)blockIdx.x - it.w0;
-  const int64_t tile0 = tile * kTile;
-  const int64_t base = ts[T.t0 + tile] - ts[T.t0];
-  const int64_t cbase = tsn[T.t0 + tile] - tsn[T.t0];
   const int64_t n = T.n_in;
+  const int64_t i0 = tile * kTile + (int64_t)threadIdx.x * kItems;
+  const int32_t* __restrict__ N = T.N;
+  int32_t v[kItems];
+  if (i0 + kItems <= n && ((uintptr_t)(N + i0) & 15) == 0) {
+    const int4 a = *reinterpret_cast<const int4*>(N + i0);
+    const int4 b = *reinterpret_cast<const int4*>(N + i0 + 4);
+    v[0] = a.x;
+    v[1] = a.y;
+    v[2] = a.z;
+    v[3] = a.w;
+    v[4] = b.x;
+    v[5] = b.y;
+    v[6] = b.z;
+    v[7] = b.w;
+  } else {
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) v[j] = i0 + j < n ? N[i0 + j] : 0;
+  }
+  int64_t sum = 0;
+  int64_t cnt = 0;
 #pragma unroll
   for (int j = 0; j < kItems; ++j) {
-    const int64_t i = tile0 + (int64_t)j * kBlock + threadIdx.x;
-    s[j * kBlock + threadIdx.x] = i < n ? (int64_t)T.N[i] : 0;
+    sum += v[j];
+    cnt += v[j] > 0;
   }
-  __syncthreads();
-  int64_t loc = 0;
-#pragma unroll
-  for (int j = 0; j < kItems; ++j) loc += s[threadIdx.x * kItems + j];
   int64_t tot;
-  int64_t ex = block_excl_scan(loc, &tot) + base;
-#pragma unroll
-  for (int j = 0; j < kItems; ++j) {
-    const int64_t v = s[threadIdx.x * kItems + j];
-    s[threadIdx.x * kItems + j] = ex;
-    ex += v;
-  }
-  __syncthreads();
+  const int64_t ex = block_excl_scan(sum << 12 | cnt, &tot);
+  int64_t off = ts[T.t0 + tile] - ts[T.t0] + (ex >> 12);
+  int64_t pos = tsn[T.t0 + tile] - tsn[T.t0] + (ex & 0xFFF);
   int32_t* __restrict__ ridx = T.ridx;
   int32_t* __restrict__ cstart = T.cstart;
   int64_t* __restrict__ P = T.P;
-  const int32_t* __restrict__ N = T.N;
   const int32_t* __restrict__ st = T.start_in;
-  compact_tile(
-      tile, n, cbase, [&](int64_t i) { return N[i] > 0; },
-      [&](int64_t i, int64_t pos) {
-        ridx[pos] = (int32_t)i;
-        cstart[pos] = st[i];
-        P[pos] = s[i - tile0];
-      });
-  if (threadIdx.x == 0 && tile0 + kTile >= n) P[T.n] = T.m;
+#pragma unroll
+  for (int j = 0; j < kItems; ++j) {
+    if (v[j] > 0) {
+      ridx[pos] = (int32_t)(i0 + j);
+      cstart[pos] = st[i0 + j];
+      P[pos] = off;
+      ++pos;
+    }
+    off += v[j];
+  }
+  if (threadIdx.x == 0 && (tile + 1) * kTile >= n) P[T.n] = T.m;
 }
 
 // Output size of every task from the scanned tile sums (exclusive, with the
