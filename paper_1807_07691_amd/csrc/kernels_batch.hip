@@ -207,6 +207,11 @@ __global__ __launch_bounds__(kBlock) void k_b_write_idx(const WTask* __restrict_
   }
 }
 
+// Stable compaction of one tile of a filter or intersection task (rows
+// with a non-zero flag, K columns; K < 0: T.k columns).  Thread t takes the
+// tile's rows 8t..8t+7: one block scan of its kept-row count gives its first
+// output place, then a thread with kept rows reads its 8 values of each
+// column and writes the kept ones in row order.
 template <int K>
 __global__ __launch_bounds__(kBlock) void k_b_compact(const WTask* __restrict__ tasks,
                                                       const GItem* __restrict__ items, int nitems,
@@ -214,15 +219,49 @@ __global__ __launch_bounds__(kBlock) void k_b_compact(const WTask* __restrict__ 
   const GItem& it = items[find_item(items, nitems, blockIdx.x)];
   const WTask& T = tasks[it.task];
   const int64_t tile = (int64_t)blockIdx.x - it.w0;
-  const int64_t base = ts[T.t0 + tile] - ts[T.t0];
-  const OutStrided out{T.out0, T.ostride};
-  if constexpr (K >= 0) {
-    ColSet in;
+  const int64_t n = T.n;
+  const int64_t i0 = tile * kTile + (int64_t)threadIdx.x * kItems;
+  const bool full = i0 + kItems <= n;
+  const uint8_t* __restrict__ flags = T.flags;
+  uint32_t keep = 0;  // bit j: row i0 + j is kept
+  if (full && ((uintptr_t)(flags + i0) & 7) == 0) {
+    const uint64_t f = *reinterpret_cast<const uint64_t*>(flags + i0);
 #pragma unroll
-    for (int c = 0; c < K; ++c) in.c[c] = T.in.c[c];
-    compact_cols_tile<K>(tile, in, K, T.flags, T.n, base, out);
+    for (int j = 0; j < kItems; ++j) keep |= ((f >> (8 * j)) & 0xFF) ? 1u << j : 0u;
   } else {
-    compact_cols_tile<K>(tile, T.in, T.k, T.flags, T.n, base, out);
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) keep |= (i0 + j < n && flags[i0 + j] != 0) ? 1u << j : 0u;
+  }
+  int64_t tot;
+  const int64_t pos = ts[T.t0 + tile] - ts[T.t0] + block_excl_scan(__popc(keep), &tot);
+  if (keep == 0) return;  // no barrier follows
+  auto column = [&](const int32_t* __restrict__ src, int32_t* __restrict__ dst) {
+    int32_t x[kItems];
+    if (full && ((uintptr_t)(src + i0) & 15) == 0) {
+      const int4 a = *reinterpret_cast<const int4*>(src + i0);
+      const int4 b = *reinterpret_cast<const int4*>(src + i0 + 4);
+      x[0] = a.x;
+      x[1] = a.y;
+      x[2] = a.z;
+      x[3] = a.w;
+      x[4] = b.x;
+      x[5] = b.y;
+      x[6] = b.z;
+      x[7] = b.w;
+    } else {
+#pragma unroll
+      for (int j = 0; j < kItems; ++j) x[j] = (keep >> j & 1) ? src[i0 + j] : 0;
+    }
+    int64_t p = pos;
+#pragma unroll
+    for (int j = 0; j < kItems; ++j)
+      if (keep >> j & 1) dst[p++] = x[j];
+  };
+  if constexpr (K >= 0) {
+#pragma unroll
+    for (int c = 0; c < K; ++c) column(T.in.c[c], T.out0 + (int64_t)c * T.ostride);
+  } else {
+    for (int c = 0; c < T.k; ++c) column(T.in.c[c], T.out0 + (int64_t)c * T.ostride);
   }
 }
 
