@@ -166,10 +166,10 @@ struct Batch {
   DeviceMem* mem() { return st->mem.get(); }
 
   void add_in(BQ& b, int64_t n) {
-    if (b.si < (int)b.res->step_in.size()) b.res->step_in[b.si] += n;
+    if (b.si < b.res->n_steps) b.res->step_in[b.si] += n;
   }
   void add_out(BQ& b, int64_t m) {
-    if (b.si < (int)b.res->step_out.size()) b.res->step_out[b.si] += m;
+    if (b.si < b.res->n_steps) b.res->step_out[b.si] += m;
   }
 
   void fail(BQ& b, gsmat_status st_, const std::string& msg) {
@@ -638,7 +638,7 @@ void Batch::phase_write() {
     if (round_budget > 0 && round_bytes > 0 && round_bytes + (int64_t)bytes > round_budget) {
       if (defer) {
         // the round is full: this query repeats the step next round
-        if (b.si < (int)b.res->step_in.size()) b.res->step_in[b.si] -= b.t.n;
+        if (b.si < b.res->n_steps) b.res->step_in[b.si] -= b.t.n;
         continue;
       }
       b.state = kFallback;
@@ -962,8 +962,7 @@ struct gsmat_server {
       b.res->st = st;
       b.res->stream = s;
       b.res->n_vars = w.pl->n_vars;
-      b.res->step_in.assign(w.pl->steps.size(), 0);
-      b.res->step_out.assign(w.pl->steps.size(), 0);
+      b.res->reset_steps(w.pl->steps.size());
       b.t.n = 1;
       b.t.k = 0;
       b.rem = w.pl->pats.size() >= 32 ? 0xFFFFFFFFu : ((1u << w.pl->pats.size()) - 1);
@@ -994,8 +993,7 @@ struct gsmat_server {
         b.res->st = st;
         b.res->stream = s;
         b.res->n_vars = b.pl->n_vars;
-        b.res->step_in.assign(b.pl->steps.size(), 0);
-        b.res->step_out.assign(b.pl->steps.size(), 0);
+        b.res->reset_steps(b.pl->steps.size());
         gsmat_result* r = b.res.get();
         const gsmat_status rc = guarded([&]() -> gsmat_status {
           run_query(st, b.pl, bt.budget, bt.max_rows, s, r);
@@ -1102,8 +1100,7 @@ extern "C" gsmat_status gsmat_join_batch(gsmat_store* st, const gsmat_query_plan
       b.res->st = st;
       b.res->stream = s;
       b.res->n_vars = b.pl->n_vars;
-      b.res->step_in.assign(b.pl->steps.size(), 0);
-      b.res->step_out.assign(b.pl->steps.size(), 0);
+      b.res->reset_steps(b.pl->steps.size());
       b.t.n = 1;
       b.t.k = 0;
       b.rem = b.pl->pats.size() >= 32 ? 0xFFFFFFFFu : ((1u << b.pl->pats.size()) - 1);
@@ -1123,8 +1120,7 @@ extern "C" gsmat_status gsmat_join_batch(gsmat_store* st, const gsmat_query_plan
       b.res->st = st;
       b.res->stream = s;
       b.res->n_vars = b.pl->n_vars;
-      b.res->step_in.assign(b.pl->steps.size(), 0);
-      b.res->step_out.assign(b.pl->steps.size(), 0);
+      b.res->reset_steps(b.pl->steps.size());
       gsmat_result* r = b.res.get();
       const gsmat_status rc = guarded([&]() -> gsmat_status {
         run_query(st, b.pl, budget_bytes, max_rows, s, r);

@@ -263,7 +263,7 @@ struct Exec {
     const gsmat_step_info sp =
         (adaptive && !t.unit()) ? choose(t, rem) : pl->steps[std::min<size_t>(si, pl->steps.size() - 1)];
     const uint32_t next = rem & ~completes(sp);
-    if (si < (int)res->step_in.size()) res->step_in[si] += t.n;
+    if (si < res->n_steps) res->step_in[si] += t.n;
     switch (sp.kind) {
       case GSMAT_STEP_SCAN:
       case GSMAT_STEP_CARTESIAN: {
@@ -288,7 +288,7 @@ struct Exec {
   }
 
   void add_out(int si, int64_t m) {
-    if (si < (int)res->step_out.size()) res->step_out[si] += m;
+    if (si < res->n_steps) res->step_out[si] += m;
   }
 
   // t x r: r alone when t is the unit table, else the Cartesian product.
@@ -706,8 +706,7 @@ extern "C" gsmat_status gsmat_join(gsmat_store* st, const gsmat_query_plan* pl, 
     res->st = st;
     res->stream = s;
     res->n_vars = pl->n_vars;
-    res->step_in.assign(pl->steps.size(), 0);
-    res->step_out.assign(pl->steps.size(), 0);
+    res->reset_steps(pl->steps.size());
     run_query(st, pl, budget_bytes, max_rows, s, res.get());
     GS_HIP(hipStreamSynchronize(s));
     *out = res.release();
@@ -722,9 +721,9 @@ extern "C" gsmat_status gsmat_result_info(const gsmat_result* r, int64_t* n_rows
     if (!r) throw StatusFail{GSMAT_EINVAL, "result is NULL"};
     if (n_rows) *n_rows = r->rows;
     if (n_vars) *n_vars = r->n_vars;
-    if (n_steps) *n_steps = (int32_t)r->step_in.size();
-    if (step_rows_in) std::copy(r->step_in.begin(), r->step_in.end(), step_rows_in);
-    if (step_rows_out) std::copy(r->step_out.begin(), r->step_out.end(), step_rows_out);
+    if (n_steps) *n_steps = r->n_steps;
+    if (step_rows_in) std::copy(r->step_in, r->step_in + r->n_steps, step_rows_in);
+    if (step_rows_out) std::copy(r->step_out, r->step_out + r->n_steps, step_rows_out);
     return GSMAT_OK;
   });
 }

@@ -2,6 +2,7 @@
 // binding tables, result segments, and the adaptive step selection.
 #pragma once
 
+#include <algorithm>
 #include <memory>
 
 #include "store.hpp"
@@ -98,7 +99,18 @@ struct gsmat_result {
   int32_t n_vars = 0;
   int64_t rows = 0;
   std::vector<gsmat::Segment> segs;
-  std::vector<int64_t> step_in, step_out;
+  // rows into and out of each plan step (summed over chunks), kept inline: a
+  // plan has at most one step per pattern
+  static constexpr int kMaxSteps = gsmat::kMaxPats + 1;
+  int32_t n_steps = 0;
+  int64_t step_in[kMaxSteps], step_out[kMaxSteps];
+  // n counters, zeroed
+  void reset_steps(size_t n) {
+    if (n > (size_t)kMaxSteps) throw gsmat::StatusFail{GSMAT_EHIP, "internal: plan has too many steps"};
+    n_steps = (int32_t)n;
+    std::fill(step_in, step_in + n, 0);
+    std::fill(step_out, step_out + n, 0);
+  }
   ~gsmat_result() {
     for (auto& s : segs)
       if (s.owned) st->mem->free(s.owned, s.owned_bytes, stream);
