@@ -727,13 +727,22 @@ void Batch::phase_write() {
       bytes_comp[gk] += (1.0 + 4.0 * wt.k) * wt.n + 4.0 * wt.k * wt.m;
     }
   }
+  // the dense expansion writes go in one launch, grouped by column count
+  std::vector<GItem> g_wall;
+  int64_t n_wall = 0;
+  double bytes_wall = 0;
+  for (int k = 0; k < kMaxK + 2; ++k) {
+    for (const GItem& g : g_write[k]) g_wall.push_back(GItem{n_wall + g.w0, g.task, 0});
+    n_wall += n_write[k];
+    bytes_wall += bytes_write[k];
+  }
   // one upload: tasks, then every group's items
   const size_t o_w = LC.add(sizeof(WTask) * nt);
   auto put_group = [&](std::vector<GItem>& g) { return LC.add(sizeof(GItem) * std::max<size_t>(g.size(), 1)); };
   const size_t o_gscan = put_group(g_scan), o_gcrow = put_group(g_crow), o_gpart = put_group(g_part);
-  size_t o_gw[kMaxK + 2], o_gwi[kMaxK + 2], o_gc[kMaxK + 2];
+  const size_t o_gwall = put_group(g_wall);
+  size_t o_gwi[kMaxK + 2], o_gc[kMaxK + 2];
   for (int k = 0; k < kMaxK + 2; ++k) {
-    o_gw[k] = put_group(g_write[k]);
     o_gwi[k] = put_group(g_wi[k]);
     o_gc[k] = put_group(g_comp[k]);
   }
@@ -759,8 +768,8 @@ void Batch::phase_write() {
     copy_group(g_scan, o_gscan);
     copy_group(g_crow, o_gcrow);
     copy_group(g_part, o_gpart);
+    copy_group(g_wall, o_gwall);
     for (int k = 0; k < kMaxK + 2; ++k) {
-      copy_group(g_write[k], o_gw[k]);
       copy_group(g_wi[k], o_gwi[k]);
       copy_group(g_comp[k], o_gc[k]);
     }
@@ -777,10 +786,9 @@ void Batch::phase_write() {
   }
   if (!g_part.empty())
     launch_b_partition(dw, (const GItem*)(dc + o_gpart), (int)g_part.size(), n_part, s);
+  if (!g_wall.empty())
+    launch_b_write(dw, (const GItem*)(dc + o_gwall), (int)g_wall.size(), n_wall, bytes_wall, s);
   for (int k = 0; k < kMaxK + 2; ++k) {
-    if (!g_write[k].empty())
-      launch_b_write(k, dw, (const GItem*)(dc + o_gw[k]), (int)g_write[k].size(),
-              n_write[k], bytes_write[k], s);
     if (!g_wi[k].empty())
       launch_b_write_idx(k, dw, (const GItem*)(dc + o_gwi[k]), (int)g_wi[k].size(), n_wi[k],
                          bytes_wi[k], s);

@@ -82,10 +82,11 @@ void launch_b_scan_add(const WTask* tasks, const GItem* items, int nitems, const
                        int64_t tiles, double bytes, hipStream_t s);
 void launch_b_partition(const WTask* tasks, const GItem* items, int nitems, int64_t total,
                         hipStream_t s);
-// k > kMaxK selects the generic instantiation
-void launch_b_write(int k, const WTask* tasks, const GItem* items, int nitems, int64_t tiles,
+// every expansion write of a round (any column counts) in one launch
+void launch_b_write(const WTask* tasks, const GItem* items, int nitems, int64_t tiles,
                     double bytes, hipStream_t s);
-// the same over compacted rows (sparse expansions)
+// writes over compacted rows (sparse expansions), one launch per column
+// count; k > kMaxK selects the generic instantiation
 void launch_b_write_idx(int k, const WTask* tasks, const GItem* items, int nitems, int64_t tiles,
                         double bytes, hipStream_t s);
 void launch_b_compact(int k, const WTask* tasks, const GItem* items, int nitems,

@@ -580,20 +580,31 @@ __device__ inline void write_outputs(const ColSet& in, int kdyn, const int32_t* 
   }
 }
 
-// One path tile t of an expansion (all threads of the workgroup call it).
-// With ridx (kIdx), the rows are a compacted list: row i of P/start is the
-// input row ridx[i].
+// LDS staging of one path tile: each row's end offset and neighbour base
+// relative to the tile, the row of each output, and (compacted rows) each
+// row's input index.
+struct TileLds {
+  int32_t* sE;     // [kTile + 1]
+  int32_t* sRb;    // [kTile + 1]
+  uint16_t* sRow;  // [kTile]
+  int32_t* sIdx;   // [kTile + 1] with compacted rows, else unused
+};
+
+// One path tile t of an expansion (all threads of the workgroup call it),
+// staged in L.  With ridx (kIdx), the rows are a compacted list: row i of
+// P/start is the input row ridx[i].
 template <int K, class Out, bool kIdx = false>
-__device__ inline void write_expand_tile(int64_t t, const ColSet& in, int kdyn,
-                                         const int64_t* __restrict__ P,
-                                         const int32_t* __restrict__ start, int64_t n,
-                                         const int32_t* __restrict__ nbr, int64_t J0, int64_t J1,
-                                         const int64_t* __restrict__ split, const Out& out,
-                                         const int32_t* __restrict__ ridx = nullptr) {
-  __shared__ int32_t sE[kTile + 1];
-  __shared__ int32_t sRb[kTile + 1];
-  __shared__ uint16_t sRow[kTile];
-  __shared__ int32_t sIdx[kIdx ? kTile + 1 : 1];
+__device__ inline void write_expand_tile_in(const TileLds& L, int64_t t, const ColSet& in,
+                                            int kdyn, const int64_t* __restrict__ P,
+                                            const int32_t* __restrict__ start, int64_t n,
+                                            const int32_t* __restrict__ nbr, int64_t J0,
+                                            int64_t J1, const int64_t* __restrict__ split,
+                                            const Out& out,
+                                            const int32_t* __restrict__ ridx = nullptr) {
+  int32_t* const sE = L.sE;
+  int32_t* const sRb = L.sRb;
+  uint16_t* const sRow = L.sRow;
+  int32_t* const sIdx = L.sIdx;
   const int64_t nb = J1 - J0;
   const int64_t total = n + nb;
   const int64_t d0 = t * (int64_t)kTile;
@@ -633,6 +644,22 @@ __device__ inline void write_expand_tile(int64_t t, const ColSet& in, int kdyn,
   }
   __syncthreads();
   write_outputs<K, Out>(in, kdyn, nbr, sRow, sRb, kIdx ? sIdx : nullptr, a0, jb - J0, nbt, out);
+}
+
+// write_expand_tile_in with the workgroup's own staging.
+template <int K, class Out, bool kIdx = false>
+__device__ inline void write_expand_tile(int64_t t, const ColSet& in, int kdyn,
+                                         const int64_t* __restrict__ P,
+                                         const int32_t* __restrict__ start, int64_t n,
+                                         const int32_t* __restrict__ nbr, int64_t J0, int64_t J1,
+                                         const int64_t* __restrict__ split, const Out& out,
+                                         const int32_t* __restrict__ ridx = nullptr) {
+  __shared__ int32_t sE[kTile + 1];
+  __shared__ int32_t sRb[kTile + 1];
+  __shared__ uint16_t sRow[kTile];
+  __shared__ int32_t sIdx[kIdx ? kTile + 1 : 1];
+  write_expand_tile_in<K, Out, kIdx>(TileLds{sE, sRb, sRow, sIdx}, t, in, kdyn, P, start, n, nbr,
+                                     J0, J1, split, out, ridx);
 }
 
 }  // namespace dev

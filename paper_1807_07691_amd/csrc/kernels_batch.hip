@@ -170,20 +170,48 @@ __global__ void k_b_partition(const WTask* __restrict__ tasks, const GItem* __re
   T.split[t] = mp_split(T.P, T.n, 0, T.m, t);
 }
 
+// One tile of an expansion task with K parent columns (K < 0: T.k columns).
 template <int K>
-__global__ __launch_bounds__(kBlock) void k_b_write(const WTask* __restrict__ tasks,
-                                                    const GItem* __restrict__ items, int nitems) {
-  const GItem& it = items[find_item(items, nitems, blockIdx.x)];
-  const WTask& T = tasks[it.task];
-  const int64_t t = (int64_t)blockIdx.x - it.w0;
+__device__ inline void b_write_tile(const WTask& T, int64_t t, const TileLds& L) {
   const OutStrided out{T.out0, T.ostride};
   if constexpr (K >= 0) {
     ColSet in;
 #pragma unroll
     for (int c = 0; c < K; ++c) in.c[c] = T.in.c[c];
-    write_expand_tile<K>(t, in, K, T.P, T.start, T.n, T.nbr, 0, T.m, T.split, out);
+    write_expand_tile_in<K>(L, t, in, K, T.P, T.start, T.n, T.nbr, 0, T.m, T.split, out);
   } else {
-    write_expand_tile<K>(t, T.in, T.k, T.P, T.start, T.n, T.nbr, 0, T.m, T.split, out);
+    write_expand_tile_in<K>(L, t, T.in, T.k, T.P, T.start, T.n, T.nbr, 0, T.m, T.split, out);
+  }
+}
+
+// The expansion writes of a round, every column count in one launch: a
+// workgroup runs the variant of its task's count (uniform per workgroup).
+// The variants share one LDS staging area, so the launch has the
+// occupancy of a single variant and no launch waits for another's tail.
+__global__ __launch_bounds__(kBlock) void k_b_write(const WTask* __restrict__ tasks,
+                                                    const GItem* __restrict__ items, int nitems) {
+  __shared__ int32_t sE[kTile + 1];
+  __shared__ int32_t sRb[kTile + 1];
+  __shared__ uint16_t sRow[kTile];
+  const TileLds L{sE, sRb, sRow, nullptr};
+  const GItem& it = items[find_item(items, nitems, blockIdx.x)];
+  const WTask& T = tasks[it.task];
+  const int64_t t = (int64_t)blockIdx.x - it.w0;
+  static_assert(kMaxK == 11, "one case per specialised column count");
+  switch (T.k) {
+    case 0: return b_write_tile<0>(T, t, L);
+    case 1: return b_write_tile<1>(T, t, L);
+    case 2: return b_write_tile<2>(T, t, L);
+    case 3: return b_write_tile<3>(T, t, L);
+    case 4: return b_write_tile<4>(T, t, L);
+    case 5: return b_write_tile<5>(T, t, L);
+    case 6: return b_write_tile<6>(T, t, L);
+    case 7: return b_write_tile<7>(T, t, L);
+    case 8: return b_write_tile<8>(T, t, L);
+    case 9: return b_write_tile<9>(T, t, L);
+    case 10: return b_write_tile<10>(T, t, L);
+    case 11: return b_write_tile<11>(T, t, L);
+    default: return b_write_tile<-1>(T, t, L);
   }
 }
 
@@ -276,12 +304,6 @@ __global__ __launch_bounds__(kBlock) void k_b_compact(const WTask* __restrict__ 
   } while (0)
 
 template <int K>
-void b_write(const WTask* t, const GItem* g, int ng, int64_t tiles, double bytes, hipStream_t s) {
-  GS_BLAUNCH(GSMAT_K_WRITE, bytes,
-             hipLaunchKernelGGL(k_b_write<K>, dim3((unsigned)tiles), dim3(kBlock), 0, s, t, g,
-                                ng));
-}
-template <int K>
 void b_write_idx(const WTask* t, const GItem* g, int ng, int64_t tiles, double bytes,
                  hipStream_t s) {
   GS_BLAUNCH(GSMAT_K_WRITE, bytes,
@@ -348,23 +370,10 @@ void launch_b_partition(const WTask* tasks, const GItem* items, int nitems, int6
                                 dim3(kBlock), 0, s, tasks, items, nitems, total));
 }
 
-void launch_b_write(int k, const WTask* t, const GItem* g, int ng, int64_t tiles, double bytes,
+void launch_b_write(const WTask* t, const GItem* g, int ng, int64_t tiles, double bytes,
                     hipStream_t s) {
-  switch (k) {
-    case 0: return b_write<0>(t, g, ng, tiles, bytes, s);
-    case 1: return b_write<1>(t, g, ng, tiles, bytes, s);
-    case 2: return b_write<2>(t, g, ng, tiles, bytes, s);
-    case 3: return b_write<3>(t, g, ng, tiles, bytes, s);
-    case 4: return b_write<4>(t, g, ng, tiles, bytes, s);
-    case 5: return b_write<5>(t, g, ng, tiles, bytes, s);
-    case 6: return b_write<6>(t, g, ng, tiles, bytes, s);
-    case 7: return b_write<7>(t, g, ng, tiles, bytes, s);
-    case 8: return b_write<8>(t, g, ng, tiles, bytes, s);
-    case 9: return b_write<9>(t, g, ng, tiles, bytes, s);
-    case 10: return b_write<10>(t, g, ng, tiles, bytes, s);
-    case 11: return b_write<11>(t, g, ng, tiles, bytes, s);
-    default: return b_write<-1>(t, g, ng, tiles, bytes, s);
-  }
+  GS_BLAUNCH(GSMAT_K_WRITE, bytes,
+             hipLaunchKernelGGL(k_b_write, dim3((unsigned)tiles), dim3(kBlock), 0, s, t, g, ng));
 }
 
 void launch_b_write_idx(int k, const WTask* t, const GItem* g, int ng, int64_t tiles, double bytes,
