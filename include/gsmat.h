@@ -43,8 +43,9 @@
  *     tuning setting of the store and must not overlap other calls on it.
  *   - A result's (and a server's) memory is returned to the allocator on the
  *     stream it was made on: that stream must outlive them.
- *   - After a non-OK gsmat_server_step the server's state is unspecified:
- *     free it.
+ *   - A gsmat_server_step whose round fails (device allocation, HIP error)
+ *     returns that status; the queries the round carried finish as failed
+ *     with it (reported by gsmat_server_poll) and the server stays usable.
  */
 #ifndef GSMAT_H
 #define GSMAT_H
@@ -132,7 +133,8 @@ typedef struct {
 /* Copies n host triples (s[i], p[i], o[i]) to the device.  Duplicates are
  * allowed and removed by gsmat_build_index (D is a set).  EINVAL if any id is
  * out of range, n < 0, or a pointer is NULL while n > 0; EUNSUPPORTED if
- * bits(n_predicates-1) + 2*bits(n_vertices-1) > 64.  `alloc` may be NULL. */
+ * bits(n_predicates-1) + 2*bits(n_vertices-1) > 64 or n >= 2^32 (the device
+ * sort ranks keys with 32-bit positions).  `alloc` may be NULL. */
 gsmat_status gsmat_load_triples(const int32_t* s, const int32_t* p, const int32_t* o, int64_t n,
                                 int32_t n_vertices, int32_t n_predicates,
                                 const gsmat_allocator* alloc, void* stream, gsmat_store** out);
@@ -247,6 +249,14 @@ gsmat_status gsmat_result_rows_many(const gsmat_result* const* results, int32_t 
  * then walks only those in the merge-path write; the rows written and their
  * order do not change.  theta in [0, 1], 0 never; defaults 0.5 and 4096. */
 gsmat_status gsmat_set_sparse_expand(gsmat_store* st, double theta, int64_t min_rows);
+
+/* The write strategy the batched join takes for an expansion of n_in input
+ * rows of which n_nonempty have output, under the setting (theta, min_rows):
+ * 1 = sparse (compacted rows with output), 0 = merge path over every row.
+ * The compacted row list holds 32-bit row indices, so an expansion of 2^31
+ * or more input rows always takes the merge path over every row.  Host
+ * only, no device work. */
+int32_t gsmat_expand_strategy(double theta, int64_t min_rows, int64_t n_in, int64_t n_nonempty);
 
 /* Autotuner: runs gsmat_join_batch on the plans once untimed, then with each
  * candidate theta (0, 0.25, 0.5, 0.75, 1; the fastest of three runs each,

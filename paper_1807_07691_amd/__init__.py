@@ -40,7 +40,7 @@ EXPORTED = [
     "gsmat_server_poll", "gsmat_server_free", "gsmat_dict_new", "gsmat_dict_free",
     "gsmat_dict_load_text", "gsmat_dict_triples", "gsmat_dict_sizes", "gsmat_dict_lookup",
     "gsmat_dict_term", "gsmat_parse_bgp", "gsmat_set_hub_options", "gsmat_set_sparse_expand",
-    "gsmat_autotune_batch",
+    "gsmat_autotune_batch", "gsmat_expand_strategy",
 ]
 
 
@@ -81,6 +81,8 @@ def _load():
     L.gsmat_set_sparse_expand.argtypes = [vp, ctypes.c_double, i64]
     L.gsmat_autotune_batch.restype = i32
     L.gsmat_autotune_batch.argtypes = [vp, vp, i32, i64, vp, vp, vp]
+    L.gsmat_expand_strategy.restype = i32
+    L.gsmat_expand_strategy.argtypes = [ctypes.c_double, i64, i64, i64]
     L.gsmat_set_hub_options.restype = i32
     L.gsmat_set_hub_options.argtypes = [vp, i64, i64]
     L.gsmat_build_index.restype = i32
@@ -615,6 +617,13 @@ def gsmat_parse_bgp(d, text):
 
 def gsmat_set_sparse_expand(store, theta, min_rows=4096):
     _check(_lib.gsmat_set_sparse_expand(store.h, float(theta), int(min_rows)))
+
+
+def gsmat_expand_strategy(theta, min_rows, n_in, n_nonempty):
+    """1 when the batched join writes such an expansion over its compacted
+    rows with output, 0 when it walks every input row."""
+    return int(_lib.gsmat_expand_strategy(float(theta), int(min_rows), int(n_in),
+                                          int(n_nonempty)))
 
 
 SPARSE_CANDIDATES = (0.0, 0.25, 0.5, 0.75, 1.0)

@@ -678,8 +678,7 @@ void Batch::phase_write() {
       wt.N = c.N;
       const int gk = wt.k <= kMaxK ? wt.k : kMaxK + 1;
       // sparse: few input rows have output; the write walks only those
-      sparse[i] = sparse_theta > 0 && c.n >= sparse_min_rows &&
-                  (double)nonempty[i] < sparse_theta * (double)c.n;
+      sparse[i] = sparse_expand(sparse_theta, sparse_min_rows, c.n, nonempty[i]);
       if (sparse[i]) {
         const int64_t ne = nonempty[i];
         wt.n_in = c.n;
@@ -944,13 +943,16 @@ struct gsmat_server {
     for (Finished& f : done) delete f.res;
   }
 
-  // Bytes the admitted queries hold or are expected to need.
+  // Bytes the admitted queries hold or are expected to need, and those of
+  // finished results not yet polled.
   int64_t committed() const {
     int64_t c = 0;
     for (const BQ& b : bt.q) {
       const int64_t held = b.t.keep ? 4 * col_stride(b.t.n) * (int64_t)b.t.k : 0;
       c += std::max(held, b.est_bytes);
     }
+    for (const Finished& f : done)
+      if (f.res) c += 4 * col_stride(f.res->rows) * (int64_t)std::max(f.res->n_vars, 1);
     return c;
   }
 
@@ -1051,7 +1053,23 @@ extern "C" gsmat_status gsmat_server_step(gsmat_server* sv, int32_t* n_active, i
     sv->bt.sparse_min_rows = sv->st->sparse_min_rows;
     bool any = false;
     for (const BQ& b : sv->bt.q) any |= b.state == kActive;
-    if (any) sv->bt.round();
+    if (any) {
+      // a round that fails part-way (device allocation, HIP error) has
+      // already counted rows of its steps: the queries it carried fail with
+      // its status instead of repeating the step in the next round
+      const gsmat_status rc = guarded([&]() -> gsmat_status {
+        sv->bt.round();
+        return GSMAT_OK;
+      });
+      if (rc != GSMAT_OK) {
+        const std::string msg = gsmat_last_error();
+        for (BQ& b : sv->bt.q)
+          if (b.state == kActive) sv->bt.fail(b, rc, msg);
+        sv->bt.R = Batch::Round();
+        sv->collect();
+        throw StatusFail{rc, msg};
+      }
+    }
     sv->collect();
     if (n_active) *n_active = (int32_t)sv->bt.q.size();
     if (n_waiting) *n_waiting = (int32_t)sv->waiting.size();
@@ -1294,6 +1312,11 @@ extern "C" gsmat_status gsmat_set_sparse_expand(gsmat_store* st, double theta, i
     st->sparse_min_rows = min_rows;
     return GSMAT_OK;
   });
+}
+
+extern "C" int32_t gsmat_expand_strategy(double theta, int64_t min_rows, int64_t n_in,
+                                         int64_t n_nonempty) {
+  return sparse_expand(theta, min_rows, n_in, n_nonempty) ? 1 : 0;
 }
 
 extern "C" gsmat_status gsmat_autotune_batch(gsmat_store* st,

@@ -63,6 +63,16 @@ struct SCand {
 // Column counts with their own write / compaction instantiation.
 constexpr int kMaxK = 11;
 
+// Write strategy of a batched expansion of n input rows of which ne have
+// output: true = compact the rows with output and walk only those (the
+// compacted row list holds int32 input row indices, so n must stay below
+// 2^31); false = the merge path over every input row.
+__host__ __device__ inline bool sparse_expand(double theta, int64_t min_rows, int64_t n,
+                                              int64_t ne) {
+  return theta > 0 && n >= min_rows && n <= (int64_t)INT32_MAX &&
+         (double)ne < theta * (double)n;
+}
+
 void launch_lookup_many(const LookupReq* req, int32_t n, const PredDesc* dout, const PredDesc* din,
                         OriPtrs out, OriPtrs in, LookupRes* res, hipStream_t s);
 // fan-out samples: kSampleBlocks partial sums per candidate to part[c * kSampleBlocks + b]

@@ -303,6 +303,9 @@ extern "C" gsmat_status gsmat_load_triples(const int32_t* s, const int32_t* p, c
     if (!out) throw StatusFail{GSMAT_EINVAL, "out is NULL"};
     *out = nullptr;
     if (n < 0) throw StatusFail{GSMAT_EINVAL, "n < 0"};
+    // the device radix sort ranks keys with 32-bit bucket positions
+    if (n >= ((int64_t)1 << 32))
+      throw StatusFail{GSMAT_EUNSUPPORTED, "2^32 or more input triples"};
     if (n > 0 && (!s || !p || !o)) throw StatusFail{GSMAT_EINVAL, "NULL triple array"};
     if (n_vertices < 1 || n_predicates < 1)
       throw StatusFail{GSMAT_EINVAL, "n_vertices and n_predicates must be >= 1"};

@@ -57,6 +57,28 @@ def test_load_validation_before_device_work(G):
     assert e.value.status == G.GSMAT_EUNSUPPORTED
 
 
+def test_triple_count_guard_before_device_work(G):
+    # the device sort ranks keys with 32-bit positions: 2^32 triples or more
+    # are refused before any array is read or any device call is made
+    z = np.zeros(1, np.int32)
+    out = ctypes.c_void_p()
+    ptr = z.ctypes.data_as(ctypes.c_void_p)
+    rc = G._lib.gsmat_load_triples(ptr, ptr, ptr, 2**32, 8, 2, None, None, ctypes.byref(out))
+    assert rc == G.GSMAT_EUNSUPPORTED and not out.value
+    assert b"2^32" in G._lib.gsmat_last_error()
+
+
+def test_sparse_expansion_strategy_guard(G):
+    # compacted row lists hold int32 row indices: never for 2^31 input rows
+    assert G.gsmat_expand_strategy(0.5, 4096, 10**6, 10**5) == 1
+    assert G.gsmat_expand_strategy(0.5, 4096, 10**6, 6 * 10**5) == 0
+    assert G.gsmat_expand_strategy(0.5, 4096, 4095, 1) == 0      # below min_rows
+    assert G.gsmat_expand_strategy(0.0, 1, 10**6, 0) == 0        # off
+    assert G.gsmat_expand_strategy(1.0, 1, 2**31 - 1, 1) == 1
+    assert G.gsmat_expand_strategy(1.0, 1, 2**31, 1) == 0
+    assert G.gsmat_expand_strategy(1.0, 1, 2**40, 1) == 0
+
+
 def test_allocator_failure_is_enomem(G):
     calls = []
 
