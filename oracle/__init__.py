@@ -58,6 +58,11 @@ def lib():
         L.oracle_result_nvars.argtypes = [vp]
         L.oracle_result_copy.argtypes = [vp, vp]
         L.oracle_result_fingerprint.argtypes = [vp, vp]
+        L.oracle_fingerprint_rows.argtypes = [vp, i64, i32, vp]
+        L.oracle_mix64.restype = ctypes.c_uint64
+        L.oracle_mix64.argtypes = [ctypes.c_uint64]
+        L.oracle_result_partition.restype = i64
+        L.oracle_result_partition.argtypes = [vp, i32, i32, vp]
         L.oracle_result_free.argtypes = [vp]
         L.oracle_dataset_new.restype = vp
         L.oracle_dataset_new.argtypes = [vp, vp, vp, i64]
@@ -114,16 +119,26 @@ class Dataset:
     def __del__(self):
         self.close()
 
-    def join(self, tps, n_vars, cap_rows=-1, fingerprint=False):
+    def join(self, tps, n_vars, cap_rows=-1, fingerprint=False, partition=None):
         t = _i32(np.asarray(tps).reshape(-1, 3))
         h = lib().oracle_join_dataset(self.h, _p(t), len(t), n_vars, cap_rows)
-        return _collect(h, n_vars, fingerprint)
+        return _collect(h, n_vars, fingerprint, partition)
 
 
-def _collect(h, n_vars, fingerprint):
+def _collect(h, n_vars, fingerprint, partition=None):
     if not h:
         raise ValueError("oracle_join rejected the input (invalid BGP or row cap exceeded)")
     try:
+        if partition is not None:
+            # (fingerprint, sorted rows of the hash partition h1 mod m == r)
+            mod, res = partition
+            fp = np.zeros(3, np.uint64)
+            lib().oracle_result_fingerprint(h, _p(fp))
+            k = lib().oracle_result_partition(h, mod, res, None)
+            part = np.empty((k, n_vars), np.int32)
+            if k and n_vars:
+                lib().oracle_result_partition(h, mod, res, _p(part))
+            return tuple(int(x) for x in fp), part
         if fingerprint:
             out = np.zeros(3, np.uint64)
             lib().oracle_result_fingerprint(h, _p(out))
@@ -137,15 +152,32 @@ def _collect(h, n_vars, fingerprint):
         lib().oracle_result_free(h)
 
 
-def join(s, p, o, tps, n_vars, cap_rows=-1, fingerprint=False):
+def join(s, p, o, tps, n_vars, cap_rows=-1, fingerprint=False, partition=None):
     """Sorted result rows (rows x n_vars int32) of the BGP `tps` ((n,3) int32).
 
-    With fingerprint=True returns (rows, h1 sum, h2 sum) instead.
+    With fingerprint=True returns (rows, h1 sum, h2 sum) instead; with
+    partition=(m, r) returns (that fingerprint, the sorted rows whose h1 is r
+    modulo m).
     """
     s, p, o = _i32(s), _i32(p), _i32(o)
     t = _i32(np.asarray(tps).reshape(-1, 3))
     h = lib().oracle_join(_p(s), _p(p), _p(o), len(s), _p(t), len(t), n_vars, cap_rows)
-    return _collect(h, n_vars, fingerprint)
+    return _collect(h, n_vars, fingerprint, partition)
+
+
+def fingerprint_rows_c(rows):
+    """The C oracle's fingerprint of arbitrary rows (row-major int32)."""
+    rows = np.ascontiguousarray(rows, dtype=np.int32)
+    n = rows.shape[0]
+    nv = rows.shape[1] if rows.ndim == 2 else 0
+    out = np.zeros(3, np.uint64)
+    lib().oracle_fingerprint_rows(_p(rows) if rows.size else None, n, nv, _p(out))
+    return tuple(int(x) for x in out)
+
+
+def mix64(z):
+    """The SplitMix64 finaliser of the C oracle."""
+    return int(lib().oracle_mix64(int(z) & 0xFFFFFFFFFFFFFFFF))
 
 
 def brute_force(s, p, o, tps, n_vars, V):
@@ -196,6 +228,34 @@ def plan_order(tps, stat):
         order.append(e)
         N |= {x for x in (tps[e][0], tps[e][2]) if x < 0}
     return order
+
+
+def _h1(rows):
+    rows = np.asarray(rows)
+    with np.errstate(over="ignore"):
+        x = np.full(len(rows), 0x1234567, np.uint64)
+        for c in range(rows.shape[1] if rows.ndim == 2 else 0):
+            v = rows[:, c].astype(np.int64).astype(np.uint64) & np.uint64(0xFFFFFFFF)
+            z = x ^ v
+            z = z ^ (z >> np.uint64(30))
+            z = z * np.uint64(0xbf58476d1ce4e5b9)
+            z = z ^ (z >> np.uint64(27))
+            z = z * np.uint64(0x94d049bb133111eb)
+            x = z ^ (z >> np.uint64(31))
+    return x
+
+
+def partition_rows(rows, mod=64, residue=0):
+    """The rows whose h1 (the fingerprint's first row hash) is `residue`
+    modulo `mod`, sorted: the hash partition the oracle returns with
+    partition=(mod, residue), for rows fetched from the GPU library."""
+    rows = np.asarray(rows)
+    if len(rows) == 0:
+        return rows.reshape(0, rows.shape[1] if rows.ndim == 2 else 0).astype(np.int32)
+    keep = rows[(_h1(rows) % np.uint64(mod)) == np.uint64(residue)]
+    if keep.ndim == 2 and keep.shape[1] and len(keep):
+        keep = keep[np.lexsort(keep.T[::-1])]
+    return keep.astype(np.int32)
 
 
 def fingerprint_rows(rows: np.ndarray):

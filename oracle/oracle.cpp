@@ -269,25 +269,51 @@ void oracle_result_copy(void* h, int32_t* out) {
   if (!r->vals.empty()) std::memcpy(out, r->vals.data(), r->vals.size() * sizeof(int32_t));
 }
 
-// Order-independent fingerprint of the row multiset: (rows, sum of h1, sum of
-// h2) modulo 2^64, with h_k a SplitMix64 chain over the row's values in
-// variable order started from seed k.
-void oracle_result_fingerprint(void* h, uint64_t* out3) {
-  Result* r = static_cast<Result*>(h);
+// Order-independent fingerprint of a row multiset: (rows, sum of h1, sum of
+// h2) modulo 2^64, with h_k a chain of the SplitMix64 finaliser over the
+// row's values in variable order started from seed k.  Rows are row-major
+// [n][nvars].
+static uint64_t row_h1(const int32_t* row, int32_t nvars) {
+  uint64_t x = 0x1234567ULL;
+  for (int c = 0; c < nvars; ++c) x = mix64(x ^ (uint32_t)row[c]);
+  return x;
+}
+
+void oracle_fingerprint_rows(const int32_t* rows, int64_t n, int32_t nvars, uint64_t* out3) {
   uint64_t a = 0, b = 0;
-  for (int64_t i = 0; i < r->rows; ++i) {
-    uint64_t x = 0x1234567ULL, y = 0x89abcdefULL;
-    for (int c = 0; c < r->nvars; ++c) {
-      uint32_t v = (uint32_t)r->vals[i * r->nvars + c];
-      x = mix64(x ^ v);
-      y = mix64(y ^ v);
-    }
-    a += x;
+  for (int64_t i = 0; i < n; ++i) {
+    uint64_t y = 0x89abcdefULL;
+    for (int c = 0; c < nvars; ++c) y = mix64(y ^ (uint32_t)rows[i * nvars + c]);
+    a += row_h1(rows + i * nvars, nvars);
     b += y;
   }
-  out3[0] = (uint64_t)r->rows;
+  out3[0] = (uint64_t)n;
   out3[1] = a;
   out3[2] = b;
+}
+
+void oracle_result_fingerprint(void* h, uint64_t* out3) {
+  Result* r = static_cast<Result*>(h);
+  oracle_fingerprint_rows(r->vals.data(), r->rows, r->nvars, out3);
+}
+
+// The SplitMix64 finaliser itself (pinned by the tests to the generator's
+// published output sequence).
+uint64_t oracle_mix64(uint64_t z) { return mix64(z); }
+
+// Hash partition of the sorted rows: those with h1(row) mod `mod` ==
+// `residue`, in sorted order, copied to out (may be null to count).
+// Returns their number.
+int64_t oracle_result_partition(void* h, int32_t mod, int32_t residue, int32_t* out) {
+  Result* r = static_cast<Result*>(h);
+  int64_t k = 0;
+  for (int64_t i = 0; i < r->rows; ++i) {
+    const int32_t* row = r->vals.data() + i * r->nvars;
+    if ((int64_t)(row_h1(row, r->nvars) % (uint64_t)mod) != residue) continue;
+    if (out) std::memcpy(out + k * r->nvars, row, sizeof(int32_t) * r->nvars);
+    ++k;
+  }
+  return k;
 }
 
 void oracle_result_free(void* h) { delete static_cast<Result*>(h); }

@@ -267,3 +267,54 @@ def test_batch_medium_workload(G, O):
     for pl in plans:
         pl.close()
     assert checked >= 50
+
+
+# ------------------------------------------------------------------ wide tables
+def _wide_graph(seed, V=300):
+    """Two predicates giving most vertices one successor (a few two, some
+    none), so long chains keep tens to hundreds of rows and expansions have
+    input rows without output."""
+    rng = np.random.default_rng(seed)
+    s, p, o = [], [], []
+    for pred in (0, 1):
+        src = rng.choice(V, int(V * 0.9), replace=False)
+        dst = rng.integers(0, V, len(src))
+        extra = rng.choice(V, V // 5, replace=False)
+        s += [src, extra]
+        o += [dst, rng.integers(0, V, len(extra))]
+        p += [np.full(len(src) + len(extra), pred)]
+    return (np.concatenate(s).astype(np.int32), np.concatenate(p).astype(np.int32),
+            np.concatenate(o).astype(np.int32), V)
+
+
+def _chain(n, preds, const_start=None):
+    tps = []
+    for i in range(n):
+        a = -(i + 1) if (i > 0 or const_start is None) else const_start
+        tps.append([a, preds[i % len(preds)], -(i + 2)])
+    if const_start is not None:  # renumber: variables from 0
+        tps = [[x if x >= 0 else x + 1, q, y + 1] for x, q, y in tps]
+    return tps
+
+
+@pytest.mark.parametrize("sparse", [(0.0, 4096), (1.0, 1)])
+def test_batch_wide_tables(G, O, sparse):
+    """Chains of 7 to 14 patterns: every column count of the batched write and
+    compaction (8 to 15 columns, past the specialised ones), against the
+    plain join and the oracle, with the sparse write off and forced on."""
+    s, p, o, V = _wide_graph(21)
+    st = _store(G, s, p, o, V, 2)
+    queries = []
+    for n in range(7, 15):
+        queries.append(_chain(n, [0, 1]))
+        queries.append(_chain(n, [1, 1, 0], const_start=int(n * 7 % V)))
+    # a snowflake closing a cycle: a filter over a wide table
+    queries.append(_chain(11, [0]) + [[-12, 1, -1]])
+    nv = [int(-np.min(np.asarray(q))) for q in queries]
+    want = [O.join(s, p, o, q, k) for q, k in zip(queries, nv)]
+    assert max(len(w) for w in want) > 50
+    print(f"[gpu] batch wide tables sparse={sparse} rows={[len(w) for w in want]}", flush=True)
+    G.gsmat_set_sparse_expand(st, *sparse)
+    for mode in (0, 2):
+        _check_batch(G, st, queries, mode, oracle_rows=want)
+    st.close()

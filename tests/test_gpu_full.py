@@ -1,14 +1,25 @@
 """GPU parity at the workloads' full sizes, in the benchmark's launch
-configuration (adaptive plans, 64 GiB step budget).
+configuration (adaptive plans, 64 GiB step budget), plus chunked execution at
+the large graph's size.
 
-medium (2M vertices, 20M triples, 64 BGPs): every query against the oracle --
-sorted rows when at most 2e6 rows, else the row-multiset fingerprint.
+medium (2M vertices, 20M triples, 64 BGPs): every query's sorted rows against
+the oracle's (rows x variables stays below 2^31 for every query).
 
 large (40M vertices, 200M triples, 128 BGPs with up to 1e9 rows): every
-query's row count against the generator's independent tree count, and sampled
-outputs: for a spread of queries, the GPU rows whose first variable equals a
-sampled value are compared with the oracle's answer to the query with that
-variable bound to the value (a query the oracle finishes in seconds).
+query's row count against the generator's independent tree count; the sorted
+rows of a spread of queries of up to 1e7 rows against the oracle's; and
+sampled outputs of the larger ones: for a spread of queries, the GPU rows
+whose first variable equals a sampled value against the oracle's answer to
+the query with that variable bound to the value.  Under a 2 GiB step budget
+the queries whose steps exceed it run chunked: counts again against the tree
+counts, and sampled outputs across the first chunk boundary of the largest
+ones against the oracle.
+
+batch (the 4096 BGPs on the large graph in one gsmat_join_batch): every count
+against the tree counts, 48 sampled queries row for row against the plain
+join, a spread of 32 queries over every result-size decade against the
+oracle's sorted rows; under a 16 MiB budget the largest results leave the
+batch for the chunked single-query path, with the same counts and rows.
 """
 import numpy as np
 import pytest
@@ -16,6 +27,7 @@ import pytest
 pytestmark = pytest.mark.gpu
 
 BUDGET = 64 * 2**30
+PAGE = 1 << 24
 
 
 def _sorted(a):
@@ -33,6 +45,22 @@ def G():
     return G
 
 
+@pytest.fixture(scope="module")
+def large(G):
+    """The 200M-triple graph, its store, its 128 queries and the oracle's
+    triple set (shared by the large and batch tests)."""
+    import oracle as O
+    import workload as W
+    spec, (s, p, o), gi, qs = W.make_workload("large")
+    gi.close()
+    st = G.gsmat_load_triples(s, p, o, spec.V, spec.P)
+    G.gsmat_build_index(st)
+    ds = O.Dataset(s, p, o)
+    yield spec, s, p, o, qs, st, ds
+    ds.close()
+    st.close()
+
+
 def _bind_first_var(tps, n_vars, value):
     """The BGP with variable 0 replaced by the constant `value` (variables renumbered)."""
     out = []
@@ -46,7 +74,12 @@ def _bind_first_var(tps, n_vars, value):
     return np.array(out, np.int32), n_vars - 1
 
 
-@pytest.mark.timeout(600)
+def _fetch_all(G, r, rows):
+    return np.concatenate([G.gsmat_fetch_bindings(r, off, PAGE) for off in range(0, rows, PAGE)]) \
+        if rows > PAGE else G.gsmat_fetch_bindings(r)
+
+
+@pytest.mark.timeout(900)
 def test_medium_every_query(G):
     import oracle as O
     import workload as W
@@ -58,48 +91,54 @@ def test_medium_every_query(G):
     checked = 0
     for i, q in enumerate(qs):
         print(f"[gpu] medium q{i} rows={q.count}", flush=True)
+        assert q.count * max(q.n_vars, 1) < 2**31
         got = G.evaluate(st, q.tps, G.PLAN_ADAPTIVE, budget_bytes=BUDGET)
         assert len(got) == q.count
         try:
-            if q.count <= 2 * 10**6:
-                want = ds.join(q.tps, q.n_vars, cap_rows=5 * 10**7)
-                assert np.array_equal(_sorted(got), want)
-            else:
-                want = ds.join(q.tps, q.n_vars, cap_rows=5 * 10**7, fingerprint=True)
-                assert O.fingerprint_rows(got) == want
-            checked += 1
+            want = ds.join(q.tps, q.n_vars, cap_rows=5 * 10**7)
         except ValueError:
             # the oracle's query-order intermediate exceeded its cap: the
             # count above (an independent tree count) still pins the query
-            pass
+            continue
+        assert np.array_equal(_sorted(got), want), i
+        checked += 1
+    print(f"[gpu] medium: {checked}/{len(qs)} queries sort-compared with the oracle", flush=True)
     assert checked >= 50
+    ds.close()
+    st.close()
 
 
 @pytest.mark.timeout(900)
-def test_large_counts_and_sampled_rows(G):
-    import oracle as O
-    import workload as W
-    spec, (s, p, o), gi, qs = W.make_workload("large")
-    gi.close()
-    st = G.gsmat_load_triples(s, p, o, spec.V, spec.P)
-    G.gsmat_build_index(st)
-    ds = O.Dataset(s, p, o)
+def test_large_counts_and_rows(G, large):
+    spec, s, p, o, qs, st, ds = large
     order = sorted(range(len(qs)), key=lambda i: qs[i].count)
     sample = sorted(set(order[:: max(1, len(order) // 8)] + [order[-1]]))
-    sampled = 0
+    # full sorted compare for a spread of the queries of at most 1e7 rows
+    small = [i for i in order if qs[i].count <= 10**7]
+    full = sorted(set(small[:: max(1, len(small) // 6)] + [small[-1]]))
+    sampled = compared = 0
     for i, q in enumerate(qs):
         pl = G.gsmat_plan(st, q.tps, G.PLAN_ADAPTIVE)
         r = G.gsmat_join(st, pl, BUDGET)
         rows = G.gsmat_result_info(r)["rows"]
         assert rows == q.count, (i, rows, q.count)
+        if i in full:
+            print(f"[gpu] large q{i} rows={rows} full compare", flush=True)
+            got = _sorted(_fetch_all(G, r, rows))
+            try:
+                want = ds.join(q.tps, q.n_vars, cap_rows=5 * 10**7)
+            except ValueError:
+                want = None
+            if want is not None:
+                assert np.array_equal(got, want), i
+                compared += 1
         if i in sample and q.n_vars >= 2:
             first = G.gsmat_fetch_bindings(r, 0, 1)
             value = int(first[0, 0])
             print(f"[gpu] large q{i} rows={rows} sample x0={value}", flush=True)
             sub = []
-            page = 1 << 24
-            for off in range(0, rows, page):
-                part = G.gsmat_fetch_bindings(r, off, page)
+            for off in range(0, rows, PAGE):
+                part = G.gsmat_fetch_bindings(r, off, PAGE)
                 sub.append(part[part[:, 0] == value][:, 1:])
             got = _sorted(np.concatenate(sub))
             tps2, nv2 = _bind_first_var(q.tps, q.n_vars, value)
@@ -112,32 +151,84 @@ def test_large_counts_and_sampled_rows(G):
                 sampled += 1
         r.close()
         pl.close()
+    print(f"[gpu] large: {compared} full compares, {sampled} sampled slices", flush=True)
+    assert compared >= len(full) - 1
     assert sampled >= len(sample) // 2
 
 
 @pytest.mark.timeout(900)
-def test_batch_workload_full_size(G):
+def test_large_chunked(G, large):
+    """A 2 GiB step budget chunks the large steps (paper Sec. 7.3 block
+    transmission): same counts; for the largest chunked queries, the rows
+    whose first variable equals the value found at the first chunk boundary
+    equal the oracle's answer to the query with that variable bound.  (The
+    adaptive plan samples fan-outs per chunk, so a chunked run may order its
+    rows differently from an unchunked one; the multiset is the same.)"""
+    spec, s, p, o, qs, st, ds = large
+    small_budget = 2 * 2**30
+    chunked = []
+    for i, q in enumerate(qs):
+        pl = G.gsmat_plan(st, q.tps, G.PLAN_ADAPTIVE)
+        r = G.gsmat_join(st, pl, small_budget)
+        info = G.gsmat_result_info(r)
+        assert info["rows"] == q.count, (i, info["rows"], q.count)
+        # the last step's output is n_vars columns wide: above the budget it
+        # was cut into output ranges
+        if q.count * 4 * q.n_vars > small_budget:
+            chunked.append(i)
+        r.close()
+        pl.close()
+    print(f"[gpu] large: {len(chunked)} queries ran chunked under a 2 GiB budget", flush=True)
+    assert len(chunked) >= 3
+    checked = 0
+    for i in sorted(chunked, key=lambda i: -qs[i].count)[:4]:
+        q = qs[i]
+        pl = G.gsmat_plan(st, q.tps, G.PLAN_ADAPTIVE)
+        r = G.gsmat_join(st, pl, small_budget)
+        rpc = small_budget // (4 * q.n_vars)
+        value = int(G.gsmat_fetch_bindings(r, rpc, 1)[0, 0])
+        print(f"[gpu] large chunked q{i} rows={q.count} boundary {rpc} x0={value}", flush=True)
+        sub = []
+        for off in range(0, q.count, PAGE):
+            part = G.gsmat_fetch_bindings(r, off, PAGE)
+            sub.append(part[part[:, 0] == value][:, 1:])
+        got = _sorted(np.concatenate(sub))
+        r.close()
+        pl.close()
+        tps2, nv2 = _bind_first_var(q.tps, q.n_vars, value)
+        try:
+            want = ds.join(tps2, nv2, cap_rows=5 * 10**7)
+        except ValueError:
+            continue
+        assert np.array_equal(got, want), i
+        checked += 1
+    assert checked >= 2
+
+
+@pytest.fixture(scope="module")
+def batch(G, large):
+    import workload as W
+    spec, s, p, o, qs, st, ds = large
+    gi = W.GraphIndex(s, p, o, spec.V, spec.P)
+    bq = W.gen_batch_queries(gi, spec)
+    gi.close()
+    return bq
+
+
+@pytest.mark.timeout(900)
+def test_batch_workload_full_size(G, large, batch):
     """The 4096-query batch set on the 200M-triple graph in one gsmat_join_batch
     (the benchmark's launch configuration): every count against the
     generator's tree count; 48 sampled queries row for row against the plain
-    join, and the smallest of them against the oracle."""
-    import oracle as O
-    import workload as W
-    spec, _ = W.CONFIGS["large"]
-    s, p, o = W.gen_graph(spec)
-    gi = W.GraphIndex(s, p, o, spec.V, spec.P)
-    qs = W.gen_batch_queries(gi, spec)
-    gi.close()
-    st = G.gsmat_load_triples(s, p, o, spec.V, spec.P)
-    G.gsmat_build_index(st)
+    join; 32 queries spread over the result-size decades against the oracle."""
+    spec, s, p, o, _, st, ds = large
+    qs = batch
     print(f"[gpu] batch full size: {len(qs)} queries", flush=True)
     plans, _ = G.gsmat_plan_batch(st, [q.tps for q in qs], G.PLAN_ADAPTIVE, as_set=True)
     results, _ = G.gsmat_join_batch(st, plans, BUDGET, as_set=True)
     rows = results.rows()
     assert rows.tolist() == [q.count for q in qs]
     sample = list(range(0, len(qs), len(qs) // 48))[:48]
-    ds = O.Dataset(s, p, o)
-    oracle_checked = 0
     for i in sample:
         q = qs[i]
         got = G.gsmat_fetch_bindings(results[i])
@@ -146,14 +237,52 @@ def test_batch_workload_full_size(G):
         assert np.array_equal(got, G.gsmat_fetch_bindings(r)), i
         r.close()
         pl.close()
-        if q.count <= 10**4:
-            try:
-                want = ds.join(q.tps, q.n_vars, cap_rows=2 * 10**7)
-            except ValueError:  # the oracle's query-order intermediate is above its cap
-                continue
-            assert np.array_equal(_sorted(got), want), i
-            oracle_checked += 1
-    print(f"[gpu] batch full size: {oracle_checked} sampled queries against the oracle", flush=True)
-    assert oracle_checked >= 8
+    # oracle: 32 queries, an equal number from each of the six decades
+    by_decade = {}
+    for i, q in enumerate(qs):
+        d = min(5, len(str(max(q.count, 1))) - 1)
+        by_decade.setdefault(d, []).append(i)
+    pick = []
+    for d in sorted(by_decade):
+        ids = by_decade[d]
+        pick += ids[:: max(1, len(ids) // 6)][:6]
+    oracle_checked = 0
+    for i in pick[:36]:
+        q = qs[i]
+        try:
+            want = ds.join(q.tps, q.n_vars, cap_rows=2 * 10**7)
+        except ValueError:  # the oracle's query-order intermediate is above its cap
+            continue
+        got = G.gsmat_fetch_bindings(results[i])
+        assert np.array_equal(_sorted(got), want), i
+        oracle_checked += 1
+    print(f"[gpu] batch full size: {oracle_checked} queries over all decades against the oracle",
+          flush=True)
+    assert oracle_checked >= 28
+    results.close()
+    plans.close()
+
+
+@pytest.mark.timeout(900)
+def test_batch_full_size_small_budget(G, large, batch):
+    """Under a 16 MiB step budget the batch hands its largest steps to the
+    chunked single-query path: counts unchanged, rows equal to the plain
+    join under the same budget."""
+    spec, s, p, o, _, st, ds = large
+    qs = batch
+    budget = 16 * 2**20
+    plans, _ = G.gsmat_plan_batch(st, [q.tps for q in qs], G.PLAN_ADAPTIVE, as_set=True)
+    results, _ = G.gsmat_join_batch(st, plans, budget, as_set=True)
+    assert results.rows().tolist() == [q.count for q in qs]
+    big = sorted(range(len(qs)), key=lambda i: -qs[i].count)[:16]
+    for i in big:
+        q = qs[i]
+        pl = G.gsmat_plan(st, q.tps, G.PLAN_ADAPTIVE)
+        r = G.gsmat_join(st, pl, budget)
+        assert np.array_equal(G.gsmat_fetch_bindings(results[i]), G.gsmat_fetch_bindings(r)), i
+        r.close()
+        pl.close()
+    print(f"[gpu] batch full size under a 16 MiB budget: counts equal, {len(big)} largest "
+          f"queries equal to the plain join", flush=True)
     results.close()
     plans.close()

@@ -86,6 +86,30 @@ def test_worked_example_aux_arrays(ex):
         first["Row"], first["Num"], first["Rpos_1based"])
 
 
+def test_worked_example_column_compressed(ex):
+    # Sec. 6.3 prints the first entry of B(W), the likes matrix keyed by its
+    # object; the fixture holds both entries and the column-compressed
+    # M_1..M_3 derived by transposing the printed matrices
+    for h, want in ex["csc"].items():
+        keys, ptr, nbr = O.csr(ex["s"], ex["p"], ex["o"], int(h), 1)
+        assert keys.tolist() == want["col_ids"], h
+        assert ptr.tolist() == want["ptr"], h
+        assert nbr.tolist() == want["rows"], h
+    keys, ptr, nbr = O.csr(ex["s"], ex["p"], ex["o"], ex["predicates"]["likes"], 1)
+    bw = ex["aux_B_W"]
+    assert keys.tolist() == bw["Row"]
+    assert np.diff(ptr).tolist() == bw["Num"]
+    assert (ptr[:-1] + 1).tolist() == bw["Rpos_1based"]
+    assert (bw["Row"][0], bw["Num"][0], bw["Rpos_1based"][0]) == (
+        ex["aux_B_W_first"]["Row"], ex["aux_B_W_first"]["Num"], ex["aux_B_W_first"]["Rpos_1based"])
+    # the two orientations hold the same pairs
+    for h, pairs in ex["matrices"].items():
+        keys, ptr, nbr = O.csr(ex["s"], ex["p"], ex["o"], int(h), 1)
+        t = sorted([int(nbr[j]), int(keys[r])] for r in range(len(keys))
+                   for j in range(ptr[r], ptr[r + 1]))
+        assert t == sorted(pairs), h
+
+
 def test_worked_example_plan(ex):
     nnz = {int(h): len(v) for h, v in ex["matrices"].items()}
     stat = [nnz[t[1]] for t in ex["query_tps"]]
@@ -206,6 +230,66 @@ def test_fingerprint_matches_rows():
     assert O.join(s, p, o, tps, 3, fingerprint=True) == O.fingerprint_rows(rows)
     # fingerprint is order independent
     assert O.fingerprint_rows(rows[::-1]) == O.fingerprint_rows(rows)
+
+
+def test_fingerprint_finaliser_is_splitmix64():
+    # the row hashes chain the SplitMix64 finaliser: its outputs over the
+    # generator's state sequence are the published ones
+    g = _load("splitmix64.json")
+    gamma = int(g["gamma"], 16)
+    M = (1 << 64) - 1
+    for seed, want in ((0, [int(x, 16) for x in g["seed_0_hex"]]), (1234567, g["seed_1234567"])):
+        st = seed
+        got = []
+        for _ in want:
+            st = (st + gamma) & M
+            got.append(O.mix64(st))
+        assert got == want, seed
+
+
+def test_fingerprint_discriminates_row_multisets():
+    # the fingerprint must change under every plausible parity mistake: a
+    # changed value, two values swapped inside a row, a duplicated row, a
+    # dropped row, a row replaced by another answer (same count)
+    rng = np.random.default_rng(11)
+    s, p, o = _random_graph(rng, 60, 2, 1500)
+    rows = O.join(s, p, o, [[-1, 0, -2], [-2, 1, -3]], 3)
+    assert len(rows) > 100
+    base = O.fingerprint_rows_c(rows)
+    assert base == O.fingerprint_rows(rows) == O.join(s, p, o, [[-1, 0, -2], [-2, 1, -3]], 3,
+                                                       fingerprint=True)
+    variants = {}
+    r = rows.copy(); r[17, 1] += 1; variants["value"] = r
+    i = int(np.flatnonzero(rows[:, 0] != rows[:, 2])[0])
+    r = rows.copy(); r[i, [0, 2]] = r[i, [2, 0]]; variants["swap"] = r
+    variants["duplicate"] = np.concatenate([rows, rows[5:6]])
+    variants["drop"] = rows[1:]
+    r = rows.copy(); r[3] = r[4]; variants["replace"] = r
+    for name, v in variants.items():
+        assert O.fingerprint_rows_c(v) != base, name
+        assert O.fingerprint_rows(v) != base, name
+    # and must not change with the row order
+    perm = rng.permutation(len(rows))
+    assert O.fingerprint_rows_c(rows[perm]) == base
+
+
+def test_hash_partition_covers_rows_once():
+    # the 1/64 partition compare: the partitions over all residues are
+    # disjoint, cover every row, and the Python selection of GPU rows picks
+    # the rows the C oracle returns for the same residue
+    rng = np.random.default_rng(13)
+    s, p, o = _random_graph(rng, 80, 2, 3000)
+    tps = [[-1, 0, -2], [-2, 1, -3]]
+    rows = O.join(s, p, o, tps, 3)
+    parts = []
+    for res in range(64):
+        fp, part = O.join(s, p, o, tps, 3, partition=(64, res))
+        assert fp == O.fingerprint_rows_c(rows)
+        assert np.array_equal(part, O.partition_rows(rows[::-1], 64, res)), res
+        parts.append(part)
+    allp = np.concatenate(parts)
+    assert len(allp) == len(rows)
+    assert np.array_equal(allp[np.lexsort(allp.T[::-1])], rows)
 
 
 # ---------------------------------------------------------------- closed forms on a power-law graph
