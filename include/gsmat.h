@@ -234,6 +234,28 @@ gsmat_status gsmat_join_batch(gsmat_store* st, const gsmat_query_plan* const* pl
                               int32_t n_plans, int64_t budget_bytes, int64_t max_rows,
                               void* stream, gsmat_result** out, gsmat_status* status);
 
+/* How gsmat_join_batch runs its rounds (the rows and their order are the
+ * same either way):
+ *   1 (default) device-driven: every query's state stays in device memory; a
+ *     round is a fixed sequence of launches that choose each query's step,
+ *     count, scan, allocate (bump allocation from an output slab and a
+ *     scratch region) and write, with sizes read on the device, so the host
+ *     enqueues as many rounds as the longest plan needs and waits once.  A
+ *     task that does not fit the regions waits a round; at the wait the host
+ *     adds larger regions and runs the remaining rounds.  The batch's
+ *     intermediate tables stay in device memory until its results are freed.
+ *   0 host-driven: the host builds every round's tasks and allocations from
+ *     sizes read back twice per round (the serving loop always runs so).
+ * EINVAL for another value. */
+gsmat_status gsmat_set_batch_engine(gsmat_store* st, int32_t engine);
+
+/* Starting sizes, in bytes, of the device-driven batch's output slab and
+ * scratch region for the next gsmat_join_batch on the store (0: 256 MiB and
+ * 128 MiB).  After every batch the store keeps the sizes that batch needed
+ * (plus an eighth) as the next starting sizes.  Small regions only cost
+ * extra rounds; the rows do not change.  EINVAL for a negative size. */
+gsmat_status gsmat_set_batch_regions(gsmat_store* st, int64_t out_bytes, int64_t scratch_bytes);
+
 /* Frees n plans (NULL entries are skipped) and sets every entry to NULL. */
 void gsmat_plan_free_many(gsmat_query_plan** plans, int32_t n);
 

@@ -40,7 +40,8 @@ EXPORTED = [
     "gsmat_server_poll", "gsmat_server_free", "gsmat_dict_new", "gsmat_dict_free",
     "gsmat_dict_load_text", "gsmat_dict_triples", "gsmat_dict_sizes", "gsmat_dict_lookup",
     "gsmat_dict_term", "gsmat_parse_bgp", "gsmat_set_hub_options", "gsmat_set_sparse_expand",
-    "gsmat_autotune_batch", "gsmat_expand_strategy",
+    "gsmat_autotune_batch", "gsmat_expand_strategy", "gsmat_set_batch_engine",
+    "gsmat_set_batch_regions",
 ]
 
 
@@ -79,6 +80,10 @@ def _load():
     L.gsmat_load_triples.argtypes = [vp, vp, vp, i64, i32, i32, vp, vp, pp]
     L.gsmat_set_sparse_expand.restype = i32
     L.gsmat_set_sparse_expand.argtypes = [vp, ctypes.c_double, i64]
+    L.gsmat_set_batch_engine.restype = i32
+    L.gsmat_set_batch_engine.argtypes = [vp, i32]
+    L.gsmat_set_batch_regions.restype = i32
+    L.gsmat_set_batch_regions.argtypes = [vp, i64, i64]
     L.gsmat_autotune_batch.restype = i32
     L.gsmat_autotune_batch.argtypes = [vp, vp, i32, i64, vp, vp, vp]
     L.gsmat_expand_strategy.restype = i32
@@ -617,6 +622,21 @@ def gsmat_parse_bgp(d, text):
 
 def gsmat_set_sparse_expand(store, theta, min_rows=4096):
     _check(_lib.gsmat_set_sparse_expand(store.h, float(theta), int(min_rows)))
+
+
+ENGINE_HOST, ENGINE_DEVICE = 0, 1
+
+
+def gsmat_set_batch_engine(store, engine):
+    """gsmat_join_batch's rounds: ENGINE_DEVICE (default, device-driven) or
+    ENGINE_HOST (host-driven)."""
+    _check(_lib.gsmat_set_batch_engine(store.h, int(engine)))
+
+
+def gsmat_set_batch_regions(store, out_bytes=0, scratch_bytes=0):
+    """Starting sizes of the device-driven batch's output slab and scratch
+    region (0: the defaults); the store then keeps each batch's own sizes."""
+    _check(_lib.gsmat_set_batch_regions(store.h, int(out_bytes), int(scratch_bytes)))
 
 
 def gsmat_expand_strategy(theta, min_rows, n_in, n_nonempty):

@@ -278,6 +278,11 @@ void prof_end(hipStream_t s, int cls, double bytes) {
   if (g_prof_pending.size() > 4096) prof_drain_locked();
 }
 
+void prof_add_bytes(int cls, double bytes) {
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  if ((g_prof_mask >> cls) & 1) g_bytes[cls] += bytes;
+}
+
 }  // namespace gsmat
 
 using namespace gsmat;

@@ -1137,7 +1137,36 @@ extern "C" gsmat_status gsmat_join_batch(gsmat_store* st, const gsmat_query_plan
           b.t = Table();
         }
     }
-    bt.run();
+    if (st->batch_engine == 1) {
+      // device-driven rounds; the queries' host state only collects outcomes
+      std::vector<DevQueryOut> dq;
+      std::vector<const gsmat_query_plan*> live;
+      std::vector<int> at;
+      for (int i = 0; i < n_plans; ++i)
+        if (bt.q[i].state == kActive) {
+          live.push_back(bt.q[i].pl);
+          at.push_back(i);
+        }
+      run_batch_device(st, live.data(), (int32_t)live.size(), budget_bytes, max_rows, s, dq);
+      for (size_t j = 0; j < dq.size(); ++j) {
+        BQ& b = bt.q[at[j]];
+        if (dq[j].state == kDevDone) {
+          b.res.reset(dq[j].res);
+          b.state = kDone;
+        } else if (dq[j].state == kDevFailed) {
+          b.state = kFailed;
+          b.status = dq[j].status;
+          b.err = dq[j].status == GSMAT_ETOOBIG
+                      ? "result exceeds max_rows (" + std::to_string(max_rows) + ")"
+                      : "query failed";
+          b.res.reset();
+        } else {
+          b.state = kFallback;
+        }
+      }
+    } else {
+      bt.run();
+    }
     // queries that left the batch run alone, from the start
     for (int i = 0; i < n_plans; ++i) {
       BQ& b = bt.q[i];
@@ -1310,6 +1339,26 @@ extern "C" gsmat_status gsmat_set_sparse_expand(gsmat_store* st, double theta, i
     if (min_rows < 1) throw StatusFail{GSMAT_EINVAL, "min_rows must be at least 1"};
     st->sparse_theta = theta;
     st->sparse_min_rows = min_rows;
+    return GSMAT_OK;
+  });
+}
+
+extern "C" gsmat_status gsmat_set_batch_engine(gsmat_store* st, int32_t engine) {
+  return guarded([&]() -> gsmat_status {
+    if (!st) throw StatusFail{GSMAT_EINVAL, "store is NULL"};
+    if (engine != 0 && engine != 1) throw StatusFail{GSMAT_EINVAL, "engine must be 0 or 1"};
+    st->batch_engine = engine;
+    return GSMAT_OK;
+  });
+}
+
+extern "C" gsmat_status gsmat_set_batch_regions(gsmat_store* st, int64_t out_bytes,
+                                               int64_t scratch_bytes) {
+  return guarded([&]() -> gsmat_status {
+    if (!st) throw StatusFail{GSMAT_EINVAL, "store is NULL"};
+    if (out_bytes < 0 || scratch_bytes < 0) throw StatusFail{GSMAT_EINVAL, "negative size"};
+    st->dbatch_out_hint = out_bytes;
+    st->dbatch_scr_hint = scratch_bytes;
     return GSMAT_OK;
   });
 }

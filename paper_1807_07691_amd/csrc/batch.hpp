@@ -73,6 +73,20 @@ __host__ __device__ inline bool sparse_expand(double theta, int64_t min_rows, in
          (double)ne < theta * (double)n;
 }
 
+// Device-driven batched join (dbatch.hip): every plan evaluated with its
+// state on the device.  out[i]: state kDevDone with res set (owned by the
+// caller), kDevFallback (the query left the batch: run it alone), or
+// kDevFailed with status.
+enum : int32_t { kDevDone = 0, kDevFallback = 1, kDevFailed = 2 };
+struct DevQueryOut {
+  gsmat_result* res;
+  int32_t state;
+  gsmat_status status;
+};
+void run_batch_device(gsmat_store* st, const gsmat_query_plan* const* plans, int32_t n,
+                      int64_t budget, int64_t max_rows, hipStream_t s,
+                      std::vector<DevQueryOut>& out);
+
 void launch_lookup_many(const LookupReq* req, int32_t n, const PredDesc* dout, const PredDesc* din,
                         OriPtrs out, OriPtrs in, LookupRes* res, hipStream_t s);
 // fan-out samples: kSampleBlocks partial sums per candidate to part[c * kSampleBlocks + b]

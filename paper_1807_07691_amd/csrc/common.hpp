@@ -210,6 +210,9 @@ void host_sync(hipStream_t s);  // hipStreamSynchronize, timed for instrumentati
 void host_event_sync(hipEvent_t e);  // hipEventSynchronize, timed likewise
 void prof_end(hipStream_t s, int cls, double bytes);
 bool prof_on(int cls);
+// adds algorithmic bytes to a class whose launches were sized on the device
+// (their byte counts are known only after the stream has synchronised)
+void prof_add_bytes(int cls, double bytes);
 
 // -------------------------------------------------------------------------
 // kernel launchers (kernels.hip)

@@ -1,0 +1,1359 @@
+// Device-driven batched join.  Every query's state (its binding table, the
+// patterns left, its step) lives in device memory, and a round of the
+// batched join (paper Sec. 7.2: count, prefix sum, exact allocation and
+// write, for the next step of every query) is a fixed sequence of launches
+// whose sizes are read on the device:
+//
+//   choose    one thread per query: applies the previous round's outcome,
+//             then picks the next step (the plan's, or the adaptive rule's
+//             filter / candidate expansions)
+//   sample    fan-out samples of every query's candidate expansions
+//   task      one thread per query: the sampled choice, then the step either
+//             finishes at once (a view into the store, an all-constant
+//             filter, an empty intersection) or becomes a count-phase task
+//   layout    one workgroup: tiles and count-phase scratch of every task,
+//             bump-allocated from the round's scratch region
+//   count     count / flag tiles of every task (Algorithm "Pre-allocating
+//             result matrix space", first loop)
+//   scan      one workgroup: tile sums scanned (second loop)
+//   decide    one workgroup: every task's output size and outcome, its
+//             output table bump-allocated from the current output slab
+//   describe  one thread per query: write descriptors
+//   post      row offsets (dense expansions), rows with output (sparse
+//             expansions) and compactions (filters, intersections)
+//   partition merge-path splits of every expansion
+//   write     merge-path expansion writes
+//
+// The grid-stride kernels run a fixed grid and read their tile counts from
+// the device, so the host enqueues rounds without waiting for them; it waits
+// once per group of rounds (as many rounds as the longest plan can take) and
+// then only reads a small summary.  Allocation never waits for the host: a
+// task whose scratch or output does not fit the current regions is deferred
+// (it repeats its step in a later round), and at the wait the host adds a
+// larger output slab or scratch region and runs the remaining rounds.  Each
+// query takes exactly the steps it takes under the single-query executor
+// (same plan, same choice rule, same sampled fan-outs) and writes its rows in
+// the same order.  A query whose next step is a Cartesian product, a
+// (?x p ?x) scan or an output above the step budget leaves the batch and is
+// finished by the single-query executor.
+#include <algorithm>
+#include <cstring>
+#include <memory>
+#include <vector>
+
+#include "batch.hpp"
+#include "batch_tiles.hpp"
+#include "device.hpp"
+#include "exec.hpp"
+
+namespace gsmat {
+
+namespace {
+
+using namespace dev;
+
+constexpr int kQBlock = 256;  // threads per workgroup of the per-query kernels
+constexpr int kGrid = 2048;   // workgroups of the grid-stride kernels (8 per CU)
+
+enum : int32_t { kQActive = 0, kQDone = 1, kQFallback = 2, kQFailed = 3 };
+// outcome of a query's step in the current round
+enum : int32_t {
+  kONone = 0,   // nothing pending
+  kOTask,       // counted this round (decided by `decide`)
+  kODefer,      // did not fit the memory regions: repeat the step
+  kODone,       // empty output: the query is finished with no rows
+  kOPass,       // filter that removed nothing: the table goes on
+  kODriver,     // intersection whose driver ids all survive
+  kOWrite,      // output table written
+  kOFallback    // leaves the batch
+};
+
+struct DPat {
+  int32_t s, p, o;
+};
+struct DStep {
+  int8_t kind, tp, orient, var;
+  uint32_t members;
+};
+struct DPlanQ {
+  int32_t np, nsteps, nv, mode, absent, pad;
+};
+struct DLk {  // a planning lookup (valid = 0: look up on the device)
+  int32_t start, len, found, valid;
+};
+
+// A binding table: column c holds variable var[c]; slab = output slab
+// holding the columns (-1: store memory).
+struct DTab {
+  int64_t n;
+  int32_t k, slab;
+  const int32_t* col[kMaxCols];
+  int8_t var[kMaxCols];
+};
+
+struct DQ {
+  DTab t;
+  int32_t state, status;
+  int32_t si, new_var;
+  uint32_t rem, next;
+  int32_t cand0, nc;
+  int8_t cand_tp[kMaxPats], cand_or[kMaxPats];
+  DStep sp;
+  int32_t outcome, kind;
+  int32_t kout, sparse;
+  int32_t out_slab, pad;
+  int64_t n_in;      // rows entering the step
+  int64_t m, ne;     // task output rows, expansion rows with output
+  int64_t cnt_off;   // count-phase scratch (offset in the scratch region)
+  int64_t out_off;   // output table (offset in the output slab)
+  int64_t scr_off;   // write-phase scratch
+  int64_t rows;      // result rows once emitted
+};
+
+// Shared control block: the memory regions, this round's sizes, the summary
+// the host reads at its wait, and the algorithmic bytes of the pass.
+struct DCtl {
+  char* out_base;
+  int64_t out_cap, out_used;
+  char* scr_base;
+  int64_t scr_cap, scr_used, scr_peak;
+  int64_t* ts;
+  int64_t* tsn;
+  int64_t ntiles, n_post, n_part, n_write;
+  int64_t want_out, want_scr;
+  int64_t bytes_count, bytes_post, bytes_write;
+  int32_t out_slab, ncand, active, deferred, error, pad;
+};
+
+struct DRes {
+  int32_t state, status, slab, pad;
+  int64_t rows;
+};
+
+struct DArgs {
+  int32_t nq, mp, ms, mv;
+  int64_t budget, round_budget, max_rows;
+  double theta;
+  int64_t min_rows;
+  const PredDesc* dout;
+  const PredDesc* din;
+  OriPtrs out, in;
+  const int32_t* out_src;
+  const DPlanQ* pq;
+  const DPat* pats;
+  const DStep* steps;
+  const DLk* lkin;
+  LookupRes* lk;
+  DQ* q;
+  int64_t* sin;
+  int64_t* sout;
+  SCand* cands;
+  int64_t* part;
+  CTask* ct;
+  ListRef* lists;
+  WTask* wt;
+  int64_t* ne;
+  int64_t* w_cnt;  // [nq + 1] first count tile of each query's task
+  int64_t* w_post;
+  int64_t* w_part;
+  int64_t* w_write;
+  DCtl* ctl;
+  DRes* res;
+  const int32_t** res_col;  // [nq * mv]
+};
+
+__device__ inline bool d_isvar(int32_t t) { return t < 0; }
+__device__ inline int d_var(int32_t t) { return -t - 1; }
+__device__ inline int64_t d_a256(int64_t b) { return (b + 255) & ~(int64_t)255; }
+__device__ inline int64_t d_stride(int64_t n) { return ((n > 1 ? n : 1) + 63) / 64 * 64; }
+__device__ inline int64_t d_tiles(int64_t n) { return (n + kTile - 1) / kTile; }
+
+__device__ inline int tab_col(const DTab& t, int v) {
+  for (int c = 0; c < t.k; ++c)
+    if (t.var[c] == v) return c;
+  return -1;
+}
+
+__device__ inline PredView d_view(const DArgs& A, int orient, int32_t p) {
+  if (orient == 0) {
+    PredView pv = view_of(A.dout[p], A.out);
+    pv.src = A.out_src + A.dout[p].nbr_base;
+    return pv;
+  }
+  return view_of(A.din[p], A.in);
+}
+
+// Bitmap of row v of predicate p in one orientation, or null.
+__device__ inline const uint32_t* d_row_bitmap(const DArgs& A, int orient, int32_t p, int32_t v) {
+  const PredDesc& d = orient == 0 ? A.dout[p] : A.din[p];
+  const OriPtrs& o = orient == 0 ? A.out : A.in;
+  if (!d.hub_n) return nullptr;
+  const int32_t* a = o.hub_keys + d.hub_base;
+  const int32_t r = lower_bound_i32(a, d.hub_n, v);
+  if (r >= d.hub_n || a[r] != v) return nullptr;
+  return o.hub_bm + (d.hub_base + r) * o.hub_words;
+}
+
+__device__ inline void d_error(const DArgs& A, DQ& Q) {
+  atomicAdd(&A.ctl->error, 1);
+  Q.state = kQFallback;
+  Q.outcome = kONone;
+}
+
+// The patterns a step completes (its own; an intersection: the members whose
+// other endpoint is a constant).
+__device__ inline uint32_t d_completes(const DPat* pats, int np, const DStep& sp) {
+  if (sp.kind != GSMAT_STEP_INTERSECT) return 1u << sp.tp;
+  uint32_t m = 0;
+  const int32_t cterm = -(sp.var + 1);
+  for (int tp = 0; tp < np; ++tp) {
+    if (!(sp.members >> tp & 1)) continue;
+    const DPat q = pats[tp];
+    const int32_t other = q.s == cterm ? q.o : q.s;
+    if (!d_isvar(other)) m |= 1u << tp;
+  }
+  return m;
+}
+
+// Adaptive choice on a bound table: true with sp = a filter when a remaining
+// connected pattern has both endpoints bound; else Q.nc candidate
+// expansions, and sp = the Cartesian step over the smallest remaining
+// pattern for when there are none.
+__device__ inline bool d_candidates(const DArgs& A, const DPat* pats, int np, DQ& Q, DStep& sp) {
+  uint64_t bound = 0;
+  for (int c = 0; c < Q.t.k; ++c) bound |= 1ull << Q.t.var[c];
+  auto vb = [&](int32_t x) { return d_isvar(x) && ((bound >> d_var(x)) & 1); };
+  auto is_bound = [&](int32_t x) { return !d_isvar(x) || ((bound >> d_var(x)) & 1); };
+  for (int tp = 0; tp < np; ++tp) {
+    if (!(Q.rem >> tp & 1)) continue;
+    const DPat q = pats[tp];
+    const bool connected = vb(q.s) || vb(q.o);
+    const bool all_const = !d_isvar(q.s) && !d_isvar(q.o);
+    if ((connected || all_const) && is_bound(q.s) && is_bound(q.o)) {
+      sp = DStep{(int8_t)GSMAT_STEP_FILTER, (int8_t)tp, -1, -1, 0u};
+      return true;
+    }
+  }
+  int nc = 0;
+  for (int tp = 0; tp < np; ++tp) {
+    if (!(Q.rem >> tp & 1)) continue;
+    const DPat q = pats[tp];
+    const bool sb = vb(q.s), ob = vb(q.o);
+    if (sb == ob) continue;
+    const int32_t free_term = sb ? q.o : q.s;
+    if (!d_isvar(free_term)) continue;
+    Q.cand_tp[nc] = (int8_t)tp;
+    Q.cand_or[nc] = sb ? 0 : 1;
+    ++nc;
+  }
+  Q.nc = nc;
+  int pick = -1;
+  int64_t best = INT64_MAX;
+  for (int tp = 0; tp < np; ++tp) {
+    if (!(Q.rem >> tp & 1)) continue;
+    const int64_t z = A.dout[pats[tp].p].nnz;
+    if (z < best) {
+      best = z;
+      pick = tp;
+    }
+  }
+  sp = DStep{(int8_t)GSMAT_STEP_CARTESIAN, (int8_t)(pick < 0 ? 0 : pick), -1, -1, 0u};
+  return false;
+}
+
+// The candidate with the smallest sampled fan-out (the first on ties).
+__device__ inline DStep d_pick(const DPat* pats, const DQ& Q, const int64_t* sums) {
+  int best = 0;
+  if (sums)
+    for (int i = 1; i < Q.nc; ++i)
+      if (sums[i] < sums[best]) best = i;
+  const DPat q = pats[Q.cand_tp[best]];
+  const int o = Q.cand_or[best];
+  return DStep{(int8_t)GSMAT_STEP_EXPAND, Q.cand_tp[best], (int8_t)o,
+               (int8_t)(o == 0 ? d_var(q.o) : d_var(q.s)), 0u};
+}
+
+// The step is done: counters, then the query moves on with table r.
+__device__ inline void d_finish(const DArgs& A, int qi, DQ& Q, const DTab& r, int64_t m) {
+  const DPlanQ& pl = A.pq[qi];
+  if (Q.si < pl.nsteps) {
+    A.sin[(int64_t)qi * A.ms + Q.si] += Q.n_in;
+    A.sout[(int64_t)qi * A.ms + Q.si] += m;
+  }
+  Q.t = r;
+  Q.rem = Q.next;
+  Q.si += 1;
+  Q.outcome = kONone;
+  if (r.n == 0) {
+    Q.state = kQDone;
+    Q.rows = 0;
+  } else if (Q.rem == 0) {
+    Q.rows = r.n;
+    if (A.max_rows >= 0 && r.n > A.max_rows) {
+      Q.state = kQFailed;
+      Q.status = GSMAT_ETOOBIG;
+    } else {
+      Q.state = kQDone;
+    }
+  }
+}
+
+__device__ inline void d_done_empty(const DArgs& A, int qi, DQ& Q) {
+  DTab r;
+  r.n = 0;
+  r.k = 0;
+  r.slab = -1;
+  d_finish(A, qi, Q, r, 0);
+}
+
+// Relation of pattern tp as a view into the store (a scan step on the unit
+// table); false for the (?x p ?x) diagonal.
+__device__ inline bool d_scan_view(const DArgs& A, int qi, int tp, DTab& r) {
+  const DPat p = A.pats[(int64_t)qi * A.mp + tp];
+  const LookupRes& lk = A.lk[(int64_t)qi * A.mp + tp];
+  r.slab = -1;
+  if (d_isvar(p.s) && d_isvar(p.o)) {
+    if (p.s == p.o) return false;
+    const PredDesc& d = A.dout[p.p];
+    r.n = d.nnz;
+    r.k = 2;
+    r.col[0] = A.out_src + d.nbr_base;
+    r.var[0] = (int8_t)d_var(p.s);
+    r.col[1] = A.out.nbr + d.nbr_base;
+    r.var[1] = (int8_t)d_var(p.o);
+  } else if (!d_isvar(p.s) && d_isvar(p.o)) {
+    r.n = lk.len;
+    r.k = 1;
+    r.col[0] = A.out.nbr + A.dout[p.p].nbr_base + lk.start;
+    r.var[0] = (int8_t)d_var(p.o);
+  } else if (d_isvar(p.s) && !d_isvar(p.o)) {
+    r.n = lk.len;
+    r.k = 1;
+    r.col[0] = A.in.nbr + A.din[p.p].nbr_base + lk.start;
+    r.var[0] = (int8_t)d_var(p.s);
+  } else {
+    r.n = lk.found ? 1 : 0;
+    r.k = 0;
+  }
+  return true;
+}
+
+// Applies the outcome decided for the query's task in the last round.
+__device__ inline void d_apply(const DArgs& A, int qi, DQ& Q) {
+  if (Q.state != kQActive) return;
+  switch (Q.outcome) {
+    case kONone:
+      return;
+    case kODefer:
+      Q.outcome = kONone;
+      return;
+    case kOFallback:
+      Q.state = kQFallback;
+      Q.outcome = kONone;
+      return;
+    case kODone:
+      d_done_empty(A, qi, Q);
+      return;
+    case kOPass: {
+      const DTab r = Q.t;
+      d_finish(A, qi, Q, r, Q.m);
+      return;
+    }
+    case kODriver: {
+      DTab r;
+      r.n = Q.m;
+      r.k = 1;
+      r.slab = -1;
+      r.col[0] = A.ct[qi].col;
+      r.var[0] = (int8_t)Q.new_var;
+      d_finish(A, qi, Q, r, Q.m);
+      return;
+    }
+    case kOWrite: {
+      const WTask& w = A.wt[qi];
+      DTab r;
+      r.n = Q.m;
+      r.slab = Q.out_slab;
+      if (Q.kind == kTaskExpand) {
+        r.k = Q.t.k + 1;
+        for (int c = 0; c < Q.t.k; ++c) r.var[c] = Q.t.var[c];
+        r.var[Q.t.k] = (int8_t)Q.new_var;
+      } else if (Q.kind == kTaskFilter) {
+        r.k = Q.t.k;
+        for (int c = 0; c < Q.t.k; ++c) r.var[c] = Q.t.var[c];
+      } else {
+        r.k = 1;
+        r.var[0] = (int8_t)Q.new_var;
+      }
+      for (int c = 0; c < r.k; ++c) r.col[c] = w.out0 + (int64_t)c * w.ostride;
+      d_finish(A, qi, Q, r, Q.m);
+      return;
+    }
+    default:
+      d_error(A, Q);
+  }
+}
+
+// ------------------------------------------------------------------ kernels
+
+__global__ void k_d_init(DArgs A) {
+  const int qi = blockIdx.x * blockDim.x + threadIdx.x;
+  if (qi >= A.nq) return;
+  DQ& Q = A.q[qi];
+  const DPlanQ& pl = A.pq[qi];
+  Q.t.n = 1;
+  Q.t.k = 0;
+  Q.t.slab = -1;
+  Q.state = kQActive;
+  Q.status = 0;
+  Q.si = 0;
+  Q.new_var = -1;
+  Q.rem = pl.np >= 32 ? 0xFFFFFFFFu : ((1u << pl.np) - 1);
+  Q.next = Q.rem;
+  Q.cand0 = -1;
+  Q.nc = 0;
+  Q.outcome = kONone;
+  Q.n_in = 0;
+  Q.rows = 0;
+  for (int i = 0; i < A.ms; ++i) {
+    A.sin[(int64_t)qi * A.ms + i] = 0;
+    A.sout[(int64_t)qi * A.ms + i] = 0;
+  }
+  if (pl.absent) {  // a pattern over an absent predicate or vertex matches nothing
+    Q.state = kQDone;
+    return;
+  }
+  for (int tp = 0; tp < pl.np; ++tp) {
+    const DPat p = A.pats[(int64_t)qi * A.mp + tp];
+    const DLk& l = A.lkin[(int64_t)qi * A.mp + tp];
+    LookupRes& r = A.lk[(int64_t)qi * A.mp + tp];
+    r = LookupRes{0, 0, 0, 0};
+    const bool sc = !d_isvar(p.s), oc = !d_isvar(p.o);
+    if (!sc && !oc) continue;
+    if (l.valid) {
+      r = LookupRes{l.start, l.len, l.found, 0};
+      continue;
+    }
+    LookupReq q;
+    if (sc && oc) q = LookupReq{0, p.p, p.s, p.o};
+    else if (sc) q = LookupReq{0, p.p, p.s, -1};
+    else q = LookupReq{1, p.p, p.o, -1};
+    r = lookup_one(q, A.dout, A.din, A.out, A.in);
+  }
+}
+
+// Applies the last round's outcomes; with `choose`, picks every active
+// query's next step (adaptive candidates go to the round's list), else
+// writes the per-query summary the host reads at its wait.
+__global__ void k_d_choose(DArgs A, int choose) {
+  const int qi = blockIdx.x * blockDim.x + threadIdx.x;
+  if (qi >= A.nq) return;
+  DQ& Q = A.q[qi];
+  d_apply(A, qi, Q);
+  if (Q.state == kQActive) atomicAdd(&A.ctl->active, 1);
+  if (!choose) {
+    const DPlanQ& pl = A.pq[qi];
+    DRes& r = A.res[qi];
+    const bool rows = Q.state == kQDone && Q.rows > 0;
+    r.state = Q.state;
+    r.status = Q.status;
+    r.slab = rows ? Q.t.slab : -1;
+    r.pad = 0;
+    r.rows = Q.state == kQDone ? Q.rows : 0;
+    for (int v = 0; v < pl.nv; ++v) {
+      const int c = rows ? tab_col(Q.t, v) : -1;
+      if (rows && c < 0) atomicAdd(&A.ctl->error, 1);
+      A.res_col[(int64_t)qi * A.mv + v] = c >= 0 ? Q.t.col[c] : nullptr;
+    }
+    return;
+  }
+  if (Q.state != kQActive) return;
+  Q.cand0 = -1;
+  Q.nc = 0;
+  const DPlanQ& pl = A.pq[qi];
+  const DPat* pats = A.pats + (int64_t)qi * A.mp;
+  const bool unit = Q.t.n == 1 && Q.t.k == 0;
+  if (pl.mode == GSMAT_PLAN_ADAPTIVE && !unit) {
+    DStep sp;
+    if (d_candidates(A, pats, pl.np, Q, sp) || Q.nc == 0) {
+      Q.nc = 0;
+      Q.sp = sp;
+    } else if (Q.nc == 1) {
+      Q.sp = d_pick(pats, Q, nullptr);
+    } else {
+      const int c0 = atomicAdd(&A.ctl->ncand, Q.nc);
+      if (c0 + Q.nc > A.nq * A.mp) {
+        d_error(A, Q);
+        return;
+      }
+      Q.cand0 = c0;
+      for (int i = 0; i < Q.nc; ++i) {
+        const DPat q = pats[Q.cand_tp[i]];
+        const bool from_s = Q.cand_or[i] == 0;
+        const int c = tab_col(Q.t, d_var(from_s ? q.s : q.o));
+        if (c < 0) {
+          d_error(A, Q);
+          return;
+        }
+        SCand& sc = A.cands[c0 + i];
+        sc.col = Q.t.col[c];
+        sc.pv = d_view(A, from_s ? 0 : 1, q.p);
+        sc.n = Q.t.n;
+      }
+    }
+  } else {
+    if (pl.nsteps < 1) {
+      d_error(A, Q);
+      return;
+    }
+    const int i = Q.si < pl.nsteps ? Q.si : pl.nsteps - 1;
+    Q.sp = A.steps[(int64_t)qi * A.ms + i];
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_d_sample(DArgs A) {
+  const int64_t total = (int64_t)A.ctl->ncand * kSampleBlocks;
+  for (int64_t j = blockIdx.x; j < total; j += gridDim.x) {
+    const SCand& sc = A.cands[j / kSampleBlocks];
+    const int64_t t = sample_fanout_slice((int)(j % kSampleBlocks), sc.col, sc.n, sc.pv);
+    if (threadIdx.x == 0) A.part[j] = t;
+  }
+}
+
+// The step of every active query: finished at once, or a count-phase task.
+__global__ void k_d_task(DArgs A) {
+  const int qi = blockIdx.x * blockDim.x + threadIdx.x;
+  if (qi >= A.nq) return;
+  DQ& Q = A.q[qi];
+  if (Q.state != kQActive) return;
+  const DPlanQ& pl = A.pq[qi];
+  const DPat* pats = A.pats + (int64_t)qi * A.mp;
+  if (Q.cand0 >= 0) {
+    int64_t sums[kMaxPats];
+    for (int i = 0; i < Q.nc; ++i) {
+      int64_t s = 0;
+      for (int j = 0; j < kSampleBlocks; ++j)
+        s += A.part[(int64_t)(Q.cand0 + i) * kSampleBlocks + j];
+      sums[i] = s;
+    }
+    Q.sp = d_pick(pats, Q, sums);
+  }
+  const DStep sp = Q.sp;
+  Q.next = Q.rem & ~d_completes(pats, pl.np, sp);
+  Q.n_in = Q.t.n;
+  Q.outcome = kONone;
+  const DPat p = pats[sp.tp];
+  const bool unit = Q.t.n == 1 && Q.t.k == 0;
+  CTask c{};
+  switch (sp.kind) {
+    case GSMAT_STEP_SCAN:
+    case GSMAT_STEP_CARTESIAN: {
+      DTab r;
+      if (!unit || !d_scan_view(A, qi, sp.tp, r)) {
+        Q.state = kQFallback;
+        return;
+      }
+      d_finish(A, qi, Q, r, r.n);
+      return;
+    }
+    case GSMAT_STEP_INTERSECT: {
+      if (!unit) {
+        Q.state = kQFallback;
+        return;
+      }
+      const int32_t cterm = -(sp.var + 1);
+      ListRef* out = A.lists + (int64_t)qi * kMaxLists;
+      // the shortest list drives; the others are written after it
+      int nl = 0, d = -1;
+      const int32_t* dids = nullptr;
+      int64_t dlen = 0;
+      for (int pass = 0; pass < 2; ++pass) {
+        int j = 0, w = 0;
+        for (int tp = 0; tp < pl.np; ++tp) {
+          if (!(sp.members >> tp & 1)) continue;
+          if (j >= kMaxLists) {
+            d_error(A, Q);
+            return;
+          }
+          const DPat m = pats[tp];
+          ListRef l{};
+          const int32_t* ids;
+          if (m.s == cterm && d_isvar(m.o)) {
+            l.pv = d_view(A, 0, m.p);
+            l.is_keys = 1;
+            l.len = l.pv.nr;
+            ids = l.pv.keys;
+          } else if (m.o == cterm && d_isvar(m.s)) {
+            l.pv = d_view(A, 1, m.p);
+            l.is_keys = 1;
+            l.len = l.pv.nr;
+            ids = l.pv.keys;
+          } else if (m.s == cterm) {
+            const LookupRes& r = A.lk[(int64_t)qi * A.mp + tp];
+            l.seg = A.in.nbr + A.din[m.p].nbr_base + r.start;
+            l.bm = d_row_bitmap(A, 1, m.p, m.o);
+            l.len = r.len;
+            ids = l.seg;
+          } else {
+            const LookupRes& r = A.lk[(int64_t)qi * A.mp + tp];
+            l.seg = A.out.nbr + A.dout[m.p].nbr_base + r.start;
+            l.bm = d_row_bitmap(A, 0, m.p, m.s);
+            l.len = r.len;
+            ids = l.seg;
+          }
+          if (pass == 0) {
+            if (d < 0 || l.len < dlen) {
+              d = j;
+              dlen = l.len;
+              dids = ids;
+            }
+          } else if (j != d) {
+            out[w++] = l;
+          }
+          ++j;
+        }
+        nl = w;
+      }
+      if (d < 0 || dlen == 0) {
+        d_done_empty(A, qi, Q);
+        return;
+      }
+      c.kind = kTaskIntersect;
+      c.n = dlen;
+      c.col = dids;
+      c.l0 = qi * kMaxLists;
+      c.nl = nl;
+      Q.new_var = sp.var;
+      break;
+    }
+    case GSMAT_STEP_FILTER: {
+      if (!d_isvar(p.s) && !d_isvar(p.o)) {
+        if (A.lk[(int64_t)qi * A.mp + sp.tp].found) {
+          const DTab r = Q.t;
+          d_finish(A, qi, Q, r, r.n);
+        } else {
+          d_done_empty(A, qi, Q);
+        }
+        return;
+      }
+      c.kind = kTaskFilter;
+      c.n = Q.t.n;
+      if (d_isvar(p.s)) {
+        const int cs = tab_col(Q.t, d_var(p.s));
+        if (cs < 0) {
+          Q.state = kQFallback;
+          return;
+        }
+        c.pa.s_col = Q.t.col[cs];
+      } else {
+        c.pa.s_const = p.s;
+      }
+      if (d_isvar(p.o)) {
+        const int co = tab_col(Q.t, d_var(p.o));
+        if (co < 0) {
+          Q.state = kQFallback;
+          return;
+        }
+        c.pa.o_col = Q.t.col[co];
+      } else {
+        c.pa.o_const = p.o;
+      }
+      c.pv = d_view(A, 0, p.p);
+      break;
+    }
+    case GSMAT_STEP_EXPAND: {
+      const int bound_var = sp.orient == 0 ? d_var(p.s) : d_var(p.o);
+      const int bc = tab_col(Q.t, bound_var);
+      if (bc < 0 || Q.t.k + 1 > kMaxCols) {
+        Q.state = kQFallback;  // the single-query executor reports it
+        return;
+      }
+      c.kind = kTaskExpand;
+      c.n = Q.t.n;
+      c.col = Q.t.col[bc];
+      c.pv = d_view(A, sp.orient == 0 ? 0 : 1, p.p);
+      Q.new_var = sp.orient == 0 ? d_var(p.o) : d_var(p.s);
+      break;
+    }
+    default:
+      Q.state = kQFallback;
+      return;
+  }
+  Q.kind = c.kind;
+  Q.outcome = kOTask;
+  A.ct[qi] = c;
+}
+
+// Count-phase scratch of a task: N, start and offsets P of an expansion, or
+// the keep flags of a filter or intersection.
+__device__ inline int64_t d_cnt_bytes(int kind, int64_t n) {
+  if (kind == kTaskExpand) return 2 * d_a256(4 * n) + d_a256(8 * (n + 1));
+  return d_a256(n);
+}
+
+// Algorithmic bytes of a count task: a lookup of every input row's bound
+// value (4 read + 8 row extent) and its count and start written (expansion);
+// two values, one probe word and a flag (filter); the driver id, one probe
+// per other list and a flag (intersection).
+__device__ inline int64_t d_count_alg(const CTask& c) {
+  if (c.kind == kTaskExpand) return 20 * c.n;
+  if (c.kind == kTaskFilter) return 13 * c.n;
+  return (5 + 4 * (int64_t)c.nl) * c.n;
+}
+
+// Tiles and count-phase scratch of every task (one workgroup of kScanBlock
+// threads; thread t takes a contiguous range of queries).  A task whose
+// scratch (with its share of the tile-sum arrays) does not fit the scratch
+// region is deferred; fitting is a prefix property, so the tasks that run
+// are the first ones in query order.
+__global__ __launch_bounds__(kScanBlock) void k_d_layout(DArgs A) {
+  DCtl& C = *A.ctl;
+  const int per = (A.nq + kScanBlock - 1) / kScanBlock;
+  const int q0 = min(A.nq, (int)threadIdx.x * per), q1 = min(A.nq, q0 + per);
+  const int64_t cap = C.scr_cap;
+  int64_t v1[1] = {0}, e1[1], t1[1];
+  for (int q = q0; q < q1; ++q) {
+    const DQ& Q = A.q[q];
+    if (Q.state == kQActive && Q.outcome == kOTask)
+      v1[0] += d_cnt_bytes(Q.kind, A.ct[q].n) + 16 * d_tiles(A.ct[q].n);
+  }
+  block_excl_scan_n<1>(v1, e1, t1);
+  int64_t v2[3] = {0, 0, 0}, e2[3], t2[3];  // tiles, scratch bytes, algorithmic bytes
+  int64_t run = e1[0];
+  int defer = 0;
+  int64_t want = 0;
+  for (int q = q0; q < q1; ++q) {
+    DQ& Q = A.q[q];
+    if (Q.state != kQActive || Q.outcome != kOTask) continue;
+    const int64_t n = A.ct[q].n;
+    const int64_t cb = d_cnt_bytes(Q.kind, n), cost = cb + 16 * d_tiles(n);
+    run += cost;
+    if (run + 1024 > cap) {
+      Q.outcome = kODefer;
+      ++defer;
+      want = max(want, cost + 1024);
+      continue;
+    }
+    v2[0] += d_tiles(n);
+    v2[1] += cb;
+    v2[2] += d_count_alg(A.ct[q]);
+  }
+  block_excl_scan_n<3>(v2, e2, t2);
+  int64_t w = e2[0], off = e2[1];
+  char* base = C.scr_base;
+  for (int q = q0; q < q1; ++q) {
+    A.w_cnt[q] = w;
+    DQ& Q = A.q[q];
+    if (Q.state != kQActive || Q.outcome != kOTask) continue;
+    CTask& c = A.ct[q];
+    const int64_t n = c.n;
+    Q.cnt_off = off;
+    if (Q.kind == kTaskExpand) {
+      c.N = (int32_t*)(base + off);
+      c.start = (int32_t*)(base + off + d_a256(4 * n));
+      c.nonempty = A.ne + q;
+      A.ne[q] = 0;
+    } else {
+      c.flags = (uint8_t*)(base + off);
+    }
+    w += d_tiles(n);
+    off += d_cnt_bytes(Q.kind, n);
+  }
+  __shared__ int s_defer;
+  __shared__ unsigned long long s_want;
+  if (threadIdx.x == 0) {
+    s_defer = 0;
+    s_want = 0;
+  }
+  __syncthreads();
+  if (defer) {
+    atomicAdd(&s_defer, defer);
+    atomicMax(&s_want, (unsigned long long)want);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int64_t nt = t2[0];
+    A.w_cnt[A.nq] = nt;
+    C.ntiles = nt;
+    C.ts = (int64_t*)(base + t2[1]);
+    C.tsn = (int64_t*)(base + t2[1] + d_a256(8 * (nt + 1)));
+    C.scr_used = t2[1] + 2 * d_a256(8 * (nt + 1));
+    C.bytes_count += t2[2];
+    C.ncand = 0;
+    C.active = 0;
+    C.deferred += s_defer;
+    C.want_scr = max(C.want_scr, (int64_t)s_want);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_d_count(DArgs A) {
+  const DCtl& C = *A.ctl;
+  const int64_t nt = C.ntiles;
+  int64_t* ts = C.ts;
+  int64_t* tsn = C.tsn;
+  for (int64_t b = blockIdx.x; b < nt; b += gridDim.x) {
+    const int qi = find_first_tile(A.w_cnt, A.nq, b);
+    int64_t ne;
+    const int64_t sum = b_count_tile(A.ct[qi], b - A.w_cnt[qi], A.lists, &ne);
+    if (threadIdx.x == 0) {
+      ts[b] = sum;
+      tsn[b] = ne;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_d_scan(DArgs A) {
+  const DCtl& C = *A.ctl;
+  scan_tile_sums2_block(C.ts, C.tsn, C.ntiles);
+}
+
+// Output bytes of a task's table.
+__device__ inline int64_t d_out_bytes(int64_t m, int kout) {
+  return 4 * d_stride(m) * (int64_t)(kout > 1 ? kout : 1);
+}
+
+// Write-phase sizes of an accepted task: scratch bytes (splits; compacted
+// rows), tiles of the post launch, split entries, write tiles, and the
+// algorithmic bytes of its post and write work.
+struct WSizes {
+  int64_t scr, post, part, write, alg_post, alg_write;
+};
+__device__ inline WSizes d_wsizes(const DQ& Q, const CTask& c) {
+  WSizes z{0, d_tiles(c.n), 0, 0, 0, 0};
+  const int64_t n = c.n, m = Q.m, ne = Q.ne;
+  const int64_t k = Q.t.k;
+  if (Q.kind == kTaskExpand) {
+    const int64_t nw = Q.sparse ? ne : n;
+    const int64_t pt = d_tiles(nw + m);
+    z.part = pt + 1;
+    z.write = pt;
+    z.scr = d_a256(8 * (pt + 1));
+    if (Q.sparse) {
+      z.scr += 2 * d_a256(4 * ne) + d_a256(8 * (ne + 1));
+      z.alg_post = 4 * n + 20 * ne;
+      z.alg_write = 4 * m * (k + 2) + 16 * ne + 4 * k * ne;
+    } else {
+      z.alg_post = 12 * n;
+      z.alg_write = 4 * m * (k + 2) + 12 * n + 4 * k * ne;
+    }
+  } else {
+    const int64_t kk = Q.kind == kTaskIntersect ? 1 : k;
+    z.alg_post = (1 + 4 * kk) * n + 4 * kk * m;
+  }
+  return z;
+}
+
+// Every task's output size and outcome; outputs and write scratch of the
+// accepted tasks bump-allocated; the launch groups' first tiles.  One
+// workgroup of kScanBlock threads.
+__global__ __launch_bounds__(kScanBlock) void k_d_decide(DArgs A) {
+  DCtl& C = *A.ctl;
+  const int per = (A.nq + kScanBlock - 1) / kScanBlock;
+  const int q0 = min(A.nq, (int)threadIdx.x * per), q1 = min(A.nq, q0 + per);
+  const int64_t* ts = C.ts;
+  // outcomes and output bytes
+  int64_t va[1] = {0}, ea[1], ta[1];
+  for (int q = q0; q < q1; ++q) {
+    DQ& Q = A.q[q];
+    if (Q.state != kQActive || Q.outcome != kOTask) continue;
+    const CTask& c = A.ct[q];
+    const int64_t m = ts[A.w_cnt[q + 1]] - ts[A.w_cnt[q]];
+    Q.m = m;
+    Q.ne = Q.kind == kTaskExpand ? A.ne[q] : 0;
+    int o;
+    if (Q.kind == kTaskExpand) {
+      o = m == 0 ? kODone : kOWrite;
+      Q.kout = Q.t.k + 1;
+    } else if (Q.kind == kTaskFilter) {
+      o = m == c.n ? kOPass : (m == 0 ? kODone : kOWrite);
+      Q.kout = Q.t.k;
+    } else {
+      o = m == c.n ? kODriver : (m == 0 ? kODone : kOWrite);
+      Q.kout = 1;
+    }
+    if (o == kOWrite && A.budget > 0 && m > A.budget / (4 * (int64_t)max(Q.kout, 1)))
+      o = kOFallback;  // above the step budget: chunked by the single-query executor
+    Q.outcome = o;
+    if (o == kOWrite) va[0] += d_out_bytes(m, Q.kout);
+  }
+  block_excl_scan_n<1>(va, ea, ta);
+  // the round's outputs above the budget: the later queries leave the batch
+  int64_t vb[2] = {0, 0}, eb[2], tb[2];
+  int64_t run = ea[0];
+  for (int q = q0; q < q1; ++q) {
+    DQ& Q = A.q[q];
+    if (Q.state != kQActive || Q.outcome != kOWrite) continue;
+    const int64_t ob = d_out_bytes(Q.m, Q.kout);
+    const bool over = A.round_budget > 0 && run > 0 && run + ob > A.round_budget;
+    run += ob;
+    if (over) {
+      Q.outcome = kOFallback;
+      continue;
+    }
+    Q.sparse = Q.kind == kTaskExpand && sparse_expand(A.theta, A.min_rows, A.ct[q].n, Q.ne);
+    vb[0] += ob;
+    vb[1] += d_wsizes(Q, A.ct[q]).scr;
+  }
+  block_excl_scan_n<2>(vb, eb, tb);
+  // memory: a task whose output or scratch does not fit is deferred
+  int64_t vc[7] = {0, 0, 0, 0, 0, 0, 0}, ec[7], tc[7];
+  int64_t ro = eb[0], rs = eb[1];
+  const int64_t out_used = C.out_used, scr_used = C.scr_used;
+  int defer = 0;
+  int64_t want_o = 0, want_s = 0;
+  for (int q = q0; q < q1; ++q) {
+    DQ& Q = A.q[q];
+    if (Q.state != kQActive || Q.outcome != kOWrite) continue;
+    const CTask& c = A.ct[q];
+    const int64_t ob = d_out_bytes(Q.m, Q.kout);
+    const WSizes z = d_wsizes(Q, c);
+    const bool fits = out_used + ro + ob <= C.out_cap && scr_used + rs + z.scr <= C.scr_cap;
+    if (fits) {
+      Q.out_off = out_used + ro;
+      Q.scr_off = scr_used + rs;
+      Q.out_slab = C.out_slab;
+      vc[0] += z.post;
+      vc[1] += z.part;
+      vc[2] += z.write;
+      vc[3] += ob;
+      vc[4] += z.scr;
+      vc[5] += z.alg_post;
+      vc[6] += z.alg_write;
+    } else {
+      Q.outcome = kODefer;
+      ++defer;
+      want_o = max(want_o, ob);
+      want_s = max(want_s, d_cnt_bytes(Q.kind, c.n) + 16 * d_tiles(c.n) + z.scr + 1024);
+    }
+    ro += ob;
+    rs += z.scr;
+  }
+  block_excl_scan_n<7>(vc, ec, tc);
+  int64_t wp = ec[0], wq = ec[1], ww = ec[2];
+  for (int q = q0; q < q1; ++q) {
+    A.w_post[q] = wp;
+    A.w_part[q] = wq;
+    A.w_write[q] = ww;
+    const DQ& Q = A.q[q];
+    if (Q.state != kQActive || Q.outcome != kOWrite) continue;
+    const WSizes z = d_wsizes(Q, A.ct[q]);
+    wp += z.post;
+    wq += z.part;
+    ww += z.write;
+  }
+  __shared__ int s_defer;
+  __shared__ unsigned long long s_wo, s_ws;
+  if (threadIdx.x == 0) {
+    s_defer = 0;
+    s_wo = s_ws = 0;
+  }
+  __syncthreads();
+  if (defer) {
+    atomicAdd(&s_defer, defer);
+    atomicMax(&s_wo, (unsigned long long)want_o);
+    atomicMax(&s_ws, (unsigned long long)want_s);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    A.w_post[A.nq] = tc[0];
+    A.w_part[A.nq] = tc[1];
+    A.w_write[A.nq] = tc[2];
+    C.n_post = tc[0];
+    C.n_part = tc[1];
+    C.n_write = tc[2];
+    C.out_used = out_used + tc[3];
+    C.scr_used = scr_used + tc[4];
+    C.scr_peak = max(C.scr_peak, C.scr_used);
+    C.bytes_post += tc[5];
+    C.bytes_write += tc[6];
+    C.deferred += s_defer;
+    C.want_out = max(C.want_out, (int64_t)s_wo);
+    C.want_scr = max(C.want_scr, (int64_t)s_ws);
+  }
+}
+
+// Write descriptors of the accepted tasks.
+__global__ void k_d_describe(DArgs A) {
+  const int qi = blockIdx.x * blockDim.x + threadIdx.x;
+  if (qi >= A.nq) return;
+  const DQ& Q = A.q[qi];
+  if (Q.state != kQActive || Q.outcome != kOWrite) return;
+  const DCtl& C = *A.ctl;
+  const CTask& c = A.ct[qi];
+  WTask w{};
+  const int64_t m = Q.m;
+  w.n = c.n;
+  w.m = m;
+  w.t0 = A.w_cnt[qi];
+  w.out0 = (int32_t*)(C.out_base + Q.out_off);
+  w.ostride = d_stride(m);
+  char* sb = C.scr_base + Q.scr_off;
+  char* cb = C.scr_base + Q.cnt_off;
+  if (Q.kind == kTaskExpand) {
+    w.k = Q.t.k;
+    for (int cc = 0; cc < Q.t.k; ++cc) w.in.c[cc] = Q.t.col[cc];
+    w.nbr = c.pv.nbr;
+    w.N = c.N;
+    if (Q.sparse) {
+      const int64_t ne = Q.ne;
+      w.n_in = c.n;
+      w.n = ne;
+      w.start_in = c.start;
+      w.ridx = (int32_t*)sb;
+      w.cstart = (int32_t*)(sb + d_a256(4 * ne));
+      w.P = (int64_t*)(sb + 2 * d_a256(4 * ne));
+      w.start = w.cstart;
+      w.split = (int64_t*)(sb + 2 * d_a256(4 * ne) + d_a256(8 * (ne + 1)));
+    } else {
+      w.start = c.start;
+      w.P = (int64_t*)(cb + 2 * d_a256(4 * c.n));
+      w.split = (int64_t*)sb;
+    }
+  } else if (Q.kind == kTaskFilter) {
+    w.k = Q.t.k;
+    for (int cc = 0; cc < Q.t.k; ++cc) w.in.c[cc] = Q.t.col[cc];
+    w.flags = c.flags;
+  } else {
+    w.k = 1;
+    w.in.c[0] = c.col;
+    w.flags = c.flags;
+  }
+  A.wt[qi] = w;
+}
+
+// Row offsets of the dense expansions, rows with output of the sparse ones,
+// compactions of the filters and intersections.
+__global__ __launch_bounds__(kBlock) void k_d_post(DArgs A) {
+  const DCtl& C = *A.ctl;
+  const int64_t nt = C.n_post;
+  const int64_t* ts = C.ts;
+  const int64_t* tsn = C.tsn;
+  for (int64_t b = blockIdx.x; b < nt; b += gridDim.x) {
+    const int qi = find_first_tile(A.w_post, A.nq, b);
+    const WTask& T = A.wt[qi];
+    const int64_t tile = b - A.w_post[qi];
+    if (T.flags) b_compact_tile_any(T, tile, ts);
+    else if (T.ridx) b_compact_rows_tile(T, tile, ts, tsn);
+    else b_scan_add_tile(T, tile, ts);
+    __syncthreads();  // the next tile reuses the LDS
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_d_partition(DArgs A) {
+  const int64_t total = A.ctl->n_part;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    const int qi = find_first_tile(A.w_part, A.nq, g);
+    const WTask& T = A.wt[qi];
+    T.split[g - A.w_part[qi]] = mp_split(T.P, T.n, 0, T.m, g - A.w_part[qi]);
+  }
+}
+
+// Every expansion write of the round, dense and compacted, any column count.
+__global__ __launch_bounds__(kBlock) void k_d_write(DArgs A) {
+  __shared__ int32_t sE[kTile + 1];
+  __shared__ int32_t sRb[kTile + 1];
+  __shared__ uint16_t sRow[kTile];
+  const TileLds L{sE, sRb, sRow, nullptr};
+  const int64_t nt = A.ctl->n_write;
+  for (int64_t b = blockIdx.x; b < nt; b += gridDim.x) {
+    const int qi = find_first_tile(A.w_write, A.nq, b);
+    const WTask& T = A.wt[qi];
+    const int64_t t = b - A.w_write[qi];
+    if (T.ridx) b_write_tile_any<true>(T, t, L);
+    else b_write_tile_any<false>(T, t, L);
+    __syncthreads();  // the next tile reuses the LDS
+  }
+}
+
+// ------------------------------------------------------------------ host
+
+// Growable pinned host buffer.
+struct PinnedBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  void* get(size_t want) {
+    if (want <= bytes) return p;
+    if (p) GS_HIP(hipHostFree(p));
+    p = nullptr;
+    bytes = 0;
+    size_t b = 1 << 16;
+    while (b < want) b <<= 1;
+    GS_HIP(hipHostMalloc(&p, b, hipHostMallocDefault));
+    bytes = b;
+    return p;
+  }
+  ~PinnedBuf() {
+    if (p) (void)hipHostFree(p);
+  }
+};
+PinnedBuf& pin_in() {
+  thread_local PinnedBuf b;
+  return b;
+}
+PinnedBuf& pin_out() {
+  thread_local PinnedBuf b;
+  return b;
+}
+PinnedBuf& pin_ctl() {
+  thread_local PinnedBuf b;
+  return b;
+}
+
+struct Lay {
+  size_t bytes = 0;
+  size_t add(size_t b) {
+    const size_t at = bytes;
+    bytes += (b + 255) / 256 * 256;
+    return at;
+  }
+};
+
+int64_t round_up(int64_t b, int64_t g) { return (b + g - 1) / g * g; }
+
+#define GS_DLAUNCH(cls, kern, grid, block, ...)                               \
+  do {                                                                       \
+    const bool _prof = prof_on(cls);                                         \
+    if (_prof) prof_begin(s, cls);                                           \
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, s, __VA_ARGS__);    \
+    GS_HIP(hipGetLastError());                                               \
+    if (_prof) prof_end(s, cls, 0.0);                                        \
+  } while (0)
+
+}  // namespace
+
+void run_batch_device(gsmat_store* st, const gsmat_query_plan* const* plans, int32_t nq,
+                      int64_t budget, int64_t max_rows, hipStream_t s,
+                      std::vector<DevQueryOut>& out) {
+  out.assign(nq, DevQueryOut{nullptr, kDevDone, GSMAT_OK});
+  if (nq == 0) return;
+  DeviceMem* mem = st->mem.get();
+  int mp = 1, ms = 1, mv = 1;
+  for (int i = 0; i < nq; ++i) {
+    mp = std::max(mp, (int)plans[i]->pats.size());
+    ms = std::max(ms, (int)plans[i]->steps.size());
+    mv = std::max(mv, (int)plans[i]->n_vars);
+  }
+  const size_t n = (size_t)nq;
+  // ---- device layout: uploaded inputs first, then the state
+  Lay L;
+  const size_t o_pq = L.add(sizeof(DPlanQ) * n), o_pats = L.add(sizeof(DPat) * n * mp),
+               o_steps = L.add(sizeof(DStep) * n * ms), o_lkin = L.add(sizeof(DLk) * n * mp),
+               o_ctl = L.add(sizeof(DCtl));
+  const size_t up_bytes = L.bytes;
+  const size_t o_lk = L.add(sizeof(LookupRes) * n * mp), o_q = L.add(sizeof(DQ) * n),
+               o_cands = L.add(sizeof(SCand) * n * mp),
+               o_part = L.add(sizeof(int64_t) * n * mp * kSampleBlocks),
+               o_ct = L.add(sizeof(CTask) * n), o_lists = L.add(sizeof(ListRef) * n * kMaxLists),
+               o_wt = L.add(sizeof(WTask) * n), o_ne = L.add(sizeof(int64_t) * n),
+               o_wc = L.add(sizeof(int64_t) * (n + 1)), o_wpo = L.add(sizeof(int64_t) * (n + 1)),
+               o_wpa = L.add(sizeof(int64_t) * (n + 1)), o_ww = L.add(sizeof(int64_t) * (n + 1));
+  // read back at the end, contiguous: results, their columns, step counters
+  const size_t o_res = L.add(sizeof(DRes) * n), o_rcol = L.add(sizeof(int32_t*) * n * mv),
+               o_sin = L.add(sizeof(int64_t) * n * ms), o_sout = L.add(sizeof(int64_t) * n * ms);
+  const size_t back_bytes = L.bytes - o_res;
+  Arena state(mem, L.bytes, s);
+  char* dv = (char*)state.p;
+
+  // ---- memory regions: the output slab and the round scratch
+  const int64_t g = (int64_t)1 << 20;  // sizes are kept in whole MiB
+  int64_t out_cap = st->dbatch_out_hint > 0 ? st->dbatch_out_hint : (int64_t)256 << 20;
+  int64_t scr_cap = st->dbatch_scr_hint > 0 ? st->dbatch_scr_hint : (int64_t)128 << 20;
+  scr_cap = std::max<int64_t>(scr_cap, 4096);  // the tile-sum arrays of an empty round
+  std::vector<std::shared_ptr<Arena>> slabs;
+  slabs.push_back(std::make_shared<Arena>(mem, (size_t)out_cap, s));
+  std::unique_ptr<Arena> scr(new Arena(mem, (size_t)scr_cap, s));
+
+  // ---- pack the plans
+  char* h = (char*)pin_in().get(up_bytes);
+  DPlanQ* hpq = (DPlanQ*)(h + o_pq);
+  DPat* hpats = (DPat*)(h + o_pats);
+  DStep* hsteps = (DStep*)(h + o_steps);
+  DLk* hlk = (DLk*)(h + o_lkin);
+  for (int i = 0; i < nq; ++i) {
+    const gsmat_query_plan* pl = plans[i];
+    const int np = (int)pl->pats.size();
+    const bool have = pl->lk_store == st->uid && pl->lk.size() == pl->pats.size();
+    DPlanQ& q = hpq[i];
+    q.np = np;
+    q.nsteps = (int)pl->steps.size();
+    q.nv = pl->n_vars;
+    q.mode = pl->mode;
+    q.absent = 0;
+    q.pad = 0;
+    for (int j = 0; j < mp; ++j) {
+      DPat& d = hpats[(size_t)i * mp + j];
+      DLk& l = hlk[(size_t)i * mp + j];
+      if (j < np) {
+        const gsmat_pattern& p = pl->pats[j];
+        d = DPat{p.s, p.p, p.o};
+        if (p.p >= st->P || (p.s >= 0 && p.s >= st->V) || (p.o >= 0 && p.o >= st->V))
+          q.absent = 1;
+        l = have && pl->lk[j].valid
+                ? DLk{pl->lk[j].start, pl->lk[j].len, pl->lk[j].found, 1}
+                : DLk{0, 0, 0, 0};
+      } else {
+        d = DPat{0, 0, 0};
+        l = DLk{0, 0, 0, 0};
+      }
+    }
+    for (int j = 0; j < ms; ++j) {
+      DStep& d = hsteps[(size_t)i * ms + j];
+      if (j < q.nsteps) {
+        const gsmat_step_info& sp = pl->steps[j];
+        d = DStep{(int8_t)sp.kind, (int8_t)sp.tp, (int8_t)sp.orient, (int8_t)sp.var, sp.members};
+      } else {
+        d = DStep{0, 0, 0, 0, 0u};
+      }
+    }
+  }
+  DCtl* hctl = (DCtl*)(h + o_ctl);
+  std::memset(hctl, 0, sizeof(DCtl));
+  hctl->out_base = (char*)slabs[0]->p;
+  hctl->out_cap = out_cap;
+  hctl->scr_base = (char*)scr->p;
+  hctl->scr_cap = scr_cap;
+  GS_HIP(hipMemcpyAsync(dv, h, up_bytes, hipMemcpyHostToDevice, s));
+
+  DArgs A{};
+  A.nq = nq;
+  A.mp = mp;
+  A.ms = ms;
+  A.mv = mv;
+  A.budget = budget;
+  A.round_budget = budget;
+  A.max_rows = max_rows;
+  A.theta = st->sparse_theta;
+  A.min_rows = st->sparse_min_rows;
+  A.dout = st->out.d_desc;
+  A.din = st->in.d_desc;
+  A.out = st->out.ptrs();
+  A.in = st->in.ptrs();
+  A.out_src = st->out.src;
+  A.pq = (const DPlanQ*)(dv + o_pq);
+  A.pats = (const DPat*)(dv + o_pats);
+  A.steps = (const DStep*)(dv + o_steps);
+  A.lkin = (const DLk*)(dv + o_lkin);
+  A.lk = (LookupRes*)(dv + o_lk);
+  A.q = (DQ*)(dv + o_q);
+  A.sin = (int64_t*)(dv + o_sin);
+  A.sout = (int64_t*)(dv + o_sout);
+  A.cands = (SCand*)(dv + o_cands);
+  A.part = (int64_t*)(dv + o_part);
+  A.ct = (CTask*)(dv + o_ct);
+  A.lists = (ListRef*)(dv + o_lists);
+  A.wt = (WTask*)(dv + o_wt);
+  A.ne = (int64_t*)(dv + o_ne);
+  A.w_cnt = (int64_t*)(dv + o_wc);
+  A.w_post = (int64_t*)(dv + o_wpo);
+  A.w_part = (int64_t*)(dv + o_wpa);
+  A.w_write = (int64_t*)(dv + o_ww);
+  A.ctl = (DCtl*)(dv + o_ctl);
+  A.res = (DRes*)(dv + o_res);
+  A.res_col = (const int32_t**)(dv + o_rcol);
+
+  const unsigned qgrid = (unsigned)ceil_div(nq, kQBlock);
+  GS_DLAUNCH(GSMAT_K_OTHER, k_d_init, qgrid, kQBlock, A);
+  DCtl* hc = (DCtl*)pin_ctl().get(sizeof(DCtl));
+  // every round completes at least one pattern of each query that is not
+  // deferred (an intersection first step: none), so mp + 1 rounds finish
+  // every query unless memory ran short
+  const int rounds = mp + 1;
+  int64_t out_total = 0;
+  for (int iter = 0;; ++iter) {
+    for (int r = 0; r < rounds; ++r) {
+      GS_DLAUNCH(GSMAT_K_OTHER, k_d_choose, qgrid, kQBlock, A, 1);
+      GS_DLAUNCH(GSMAT_K_OTHER, k_d_sample, kGrid, kBlock, A);
+      GS_DLAUNCH(GSMAT_K_OTHER, k_d_task, qgrid, kQBlock, A);
+      GS_DLAUNCH(GSMAT_K_SCAN, k_d_layout, 1, kScanBlock, A);
+      GS_DLAUNCH(GSMAT_K_COUNT, k_d_count, kGrid, kBlock, A);
+      GS_DLAUNCH(GSMAT_K_SCAN, k_d_scan, 1, kScanBlock, A);
+      GS_DLAUNCH(GSMAT_K_SCAN, k_d_decide, 1, kScanBlock, A);
+      GS_DLAUNCH(GSMAT_K_OTHER, k_d_describe, qgrid, kQBlock, A);
+      GS_DLAUNCH(GSMAT_K_COMPACT, k_d_post, kGrid, kBlock, A);
+      GS_DLAUNCH(GSMAT_K_OTHER, k_d_partition, kGrid, kBlock, A);
+      GS_DLAUNCH(GSMAT_K_WRITE, k_d_write, kGrid, kBlock, A);
+    }
+    GS_DLAUNCH(GSMAT_K_OTHER, k_d_choose, qgrid, kQBlock, A, 0);
+    GS_HIP(hipMemcpyAsync(hc, A.ctl, sizeof(DCtl), hipMemcpyDeviceToHost, s));
+    host_sync(s);
+    if (hc->error) throw StatusFail{GSMAT_EHIP, "internal: batched join state inconsistent"};
+    if (hc->active == 0 || iter >= 16) break;
+    if (hc->deferred == 0)  // cannot happen: a query needs more rounds only after a deferral
+      throw StatusFail{GSMAT_EHIP, "internal: batched join made no progress"};
+    // the regions were too small: a larger output slab and scratch region
+    if (hc->want_out > 0) {
+      out_total += hc->out_used;
+      const int64_t cap = round_up(std::max(2 * hc->out_cap, 2 * hc->want_out), g);
+      slabs.push_back(std::make_shared<Arena>(mem, (size_t)cap, s));
+      hc->out_base = (char*)slabs.back()->p;
+      hc->out_cap = cap;
+      hc->out_used = 0;
+      hc->out_slab = (int32_t)slabs.size() - 1;
+    }
+    if (hc->want_scr > 0) {
+      const int64_t cap = round_up(std::max(2 * hc->scr_cap, hc->want_scr), g);
+      scr.reset(new Arena(mem, (size_t)cap, s));
+      hc->scr_base = (char*)scr->p;
+      hc->scr_cap = cap;
+    }
+    hc->deferred = 0;
+    hc->want_out = hc->want_scr = 0;
+    GS_HIP(hipMemcpyAsync(A.ctl, hc, sizeof(DCtl), hipMemcpyHostToDevice, s));
+  }
+  out_total += hc->out_used;
+  // the pass's sizes are the next pass's starting regions
+  st->dbatch_out_hint = std::max<int64_t>(round_up(out_total + out_total / 8, g), g);
+  st->dbatch_scr_hint = std::max<int64_t>(round_up(hc->scr_peak + hc->scr_peak / 8, g), g);
+  prof_add_bytes(GSMAT_K_COUNT, (double)hc->bytes_count);
+  prof_add_bytes(GSMAT_K_COMPACT, (double)hc->bytes_post);
+  prof_add_bytes(GSMAT_K_WRITE, (double)hc->bytes_write);
+
+  // ---- results
+  char* hb = (char*)pin_out().get(back_bytes);
+  GS_HIP(hipMemcpyAsync(hb, dv + o_res, back_bytes, hipMemcpyDeviceToHost, s));
+  host_sync(s);
+  const DRes* hr = (const DRes*)hb;
+  const int32_t* const* hcol = (const int32_t* const*)(hb + (o_rcol - o_res));
+  const int64_t* hsin = (const int64_t*)(hb + (o_sin - o_res));
+  const int64_t* hsout = (const int64_t*)(hb + (o_sout - o_res));
+  for (int i = 0; i < nq; ++i) {
+    const DRes& r = hr[i];
+    DevQueryOut& o = out[i];
+    if (r.state == kQFailed) {
+      o.state = kDevFailed;
+      o.status = r.status;
+      continue;
+    }
+    if (r.state != kQDone) {  // left the batch (or unfinished): run alone
+      o.state = kDevFallback;
+      continue;
+    }
+    const gsmat_query_plan* pl = plans[i];
+    std::unique_ptr<gsmat_result> res(new gsmat_result);
+    res->st = st;
+    res->stream = s;
+    res->n_vars = pl->n_vars;
+    res->reset_steps(pl->steps.size());
+    for (size_t j = 0; j < pl->steps.size(); ++j) {
+      res->step_in[j] = hsin[(size_t)i * ms + j];
+      res->step_out[j] = hsout[(size_t)i * ms + j];
+    }
+    if (r.rows > 0) {
+      Segment seg;
+      seg.rows = r.rows;
+      for (int v = 0; v < pl->n_vars; ++v) seg.col[v] = hcol[(size_t)i * mv + v];
+      if (r.slab >= 0) {
+        if (r.slab >= (int)slabs.size())
+          throw StatusFail{GSMAT_EHIP, "internal: result in an unknown slab"};
+        seg.keep = slabs[r.slab];
+      }
+      res->rows = r.rows;
+      res->segs.push_back(seg);
+    }
+    o.res = res.release();
+    o.state = kDevDone;
+  }
+}
+
+}  // namespace gsmat

@@ -54,6 +54,36 @@ __device__ inline int64_t block_excl_scan(int64_t v, int64_t* total) {
   return off + inc - v;
 }
 
+// Exclusive scans of F values per thread over the whole workgroup (any
+// multiple of 64 threads up to 1024); tot receives the workgroup totals.
+// Contains barriers: every thread of the block must call it.
+template <int F>
+__device__ inline void block_excl_scan_n(const int64_t (&v)[F], int64_t (&ex)[F],
+                                         int64_t (&tot)[F]) {
+  __shared__ int64_t ws[F][16];
+  const int nw = (int)(blockDim.x >> 6);
+  int64_t inc[F];
+#pragma unroll
+  for (int f = 0; f < F; ++f) inc[f] = wave_incl_scan(v[f]);
+  if (lane_id() == 63) {
+#pragma unroll
+    for (int f = 0; f < F; ++f) ws[f][wave_id()] = inc[f];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int f = 0; f < F; ++f) {
+    int64_t off = 0, t = 0;
+    for (int q = 0; q < nw; ++q) {
+      const int64_t a = ws[f][q];
+      if (q < wave_id()) off += a;
+      t += a;
+    }
+    ex[f] = off + inc[f] - v[f];
+    tot[f] = t;
+  }
+  __syncthreads();
+}
+
 __device__ inline int64_t block_sum(int64_t v) {
   __shared__ int64_t ws[kWaves];
   v = wave_sum(v);
@@ -64,6 +94,69 @@ __device__ inline int64_t block_sum(int64_t v) {
   for (int i = 0; i < kWaves; ++i) tot += ws[i];
   __syncthreads();
   return tot;
+}
+
+// Two tile-sum arrays (neither null) scanned in one pass by one workgroup of kScanBlock
+// threads: exclusive prefix
+// sums in place, the totals at [nt].  One workgroup of 1024 threads walks the
+// arrays in chunks of 8192 sums (8 consecutive per thread); both scans share
+// each chunk's pair of barriers.
+constexpr int kScanBlock = 1024;
+__device__ inline void scan_tile_sums2_block(int64_t* ts, int64_t* ts2, int64_t nt) {
+  constexpr int W = kScanBlock / 64;
+  __shared__ int64_t ws[2][W];
+  const int lane = lane_id();
+  const int wid = wave_id();
+  int64_t carry = 0, carry2 = 0;
+  for (int64_t c0 = 0; c0 < nt; c0 += (int64_t)kScanBlock * kItems) {
+    int64_t v[kItems], w[kItems];
+    int64_t loc = 0, loc2 = 0;
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+      const int64_t i = c0 + (int64_t)threadIdx.x * kItems + j;
+      v[j] = i < nt ? ts[i] : 0;
+      w[j] = i < nt ? ts2[i] : 0;
+      loc += v[j];
+      loc2 += w[j];
+    }
+    const int64_t inc = wave_incl_scan(loc);
+    const int64_t inc2 = wave_incl_scan(loc2);
+    if (lane == 63) {
+      ws[0][wid] = inc;
+      ws[1][wid] = inc2;
+    }
+    __syncthreads();
+    int64_t off = 0, off2 = 0, tot = 0, tot2 = 0;
+#pragma unroll
+    for (int q = 0; q < W; ++q) {
+      const int64_t a = ws[0][q], b = ws[1][q];
+      if (q < wid) {
+        off += a;
+        off2 += b;
+      }
+      tot += a;
+      tot2 += b;
+    }
+    __syncthreads();
+    int64_t ex = carry + off + inc - loc;
+    int64_t ex2 = carry2 + off2 + inc2 - loc2;
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+      const int64_t i = c0 + (int64_t)threadIdx.x * kItems + j;
+      if (i < nt) {
+        ts[i] = ex;
+        ts2[i] = ex2;
+      }
+      ex += v[j];
+      ex2 += w[j];
+    }
+    carry += tot;
+    carry2 += tot2;
+  }
+  if (threadIdx.x == 0) {
+    ts[nt] = carry;
+    ts2[nt] = carry2;
+  }
 }
 
 __device__ inline int32_t lower_bound_i32(const int32_t* __restrict__ a, int32_t n, int32_t v) {
@@ -587,7 +680,7 @@ struct TileLds {
   int32_t* sE;     // [kTile + 1]
   int32_t* sRb;    // [kTile + 1]
   uint16_t* sRow;  // [kTile]
-  int32_t* sIdx;   // [kTile + 1] with compacted rows, else unused
+  int32_t* sIdx;   // [kTile + 1] with compacted rows (null: staged in sE after the walk)
 };
 
 // One path tile t of an expansion (all threads of the workgroup call it),
@@ -621,7 +714,7 @@ __device__ inline void write_expand_tile_in(const TileLds& L, int64_t t, const C
     const int64_t er = pe - jb;
     sE[i] = er > (int64_t)kTile + 1 ? kTile + 1 : (er < -1 ? -1 : (int32_t)er);
     sRb[i] = (int32_t)((int64_t)start[a0 + i] + (jb - pb));
-    if (kIdx) sIdx[i] = ridx[a0 + i];
+    if (kIdx && sIdx) sIdx[i] = ridx[a0 + i];
   }
   __syncthreads();
   const int dl = min((int)threadIdx.x * kItems, nat + nbt);
@@ -643,7 +736,14 @@ __device__ inline void write_expand_tile_in(const TileLds& L, int64_t t, const C
     }
   }
   __syncthreads();
-  write_outputs<K, Out>(in, kdyn, nbr, sRow, sRb, kIdx ? sIdx : nullptr, a0, jb - J0, nbt, out);
+  if (kIdx && !sIdx) {
+    // without an area of its own the row indices take the place of the row
+    // ends, which the walk no longer needs
+    for (int i = threadIdx.x; i < nr; i += kBlock) sE[i] = ridx[a0 + i];
+    __syncthreads();
+  }
+  write_outputs<K, Out>(in, kdyn, nbr, sRow, sRb, kIdx ? (sIdx ? sIdx : sE) : nullptr, a0,
+                        jb - J0, nbt, out);
 }
 
 // write_expand_tile_in with the workgroup's own staging.

@@ -47,67 +47,10 @@ __global__ __launch_bounds__(kBlock) void k_scan_tile_sums(int64_t* ts, int64_t 
   }
 }
 
-// Two tile-sum arrays (neither null) scanned in one pass: exclusive prefix
-// sums in place, the totals at [nt].  One workgroup of 1024 threads walks the
-// arrays in chunks of 8192 sums (8 consecutive per thread); both scans share
-// each chunk's pair of barriers.
-constexpr int kScanBlock = 1024;
+// Two tile-sum arrays (neither null) scanned in one pass (device.hpp).
 __global__ __launch_bounds__(kScanBlock) void k_scan_tile_sums2(int64_t* ts, int64_t* ts2,
                                                                 int64_t nt) {
-  constexpr int W = kScanBlock / 64;
-  __shared__ int64_t ws[2][W];
-  const int lane = lane_id();
-  const int wid = wave_id();
-  int64_t carry = 0, carry2 = 0;
-  for (int64_t c0 = 0; c0 < nt; c0 += (int64_t)kScanBlock * kItems) {
-    int64_t v[kItems], w[kItems];
-    int64_t loc = 0, loc2 = 0;
-#pragma unroll
-    for (int j = 0; j < kItems; ++j) {
-      const int64_t i = c0 + (int64_t)threadIdx.x * kItems + j;
-      v[j] = i < nt ? ts[i] : 0;
-      w[j] = i < nt ? ts2[i] : 0;
-      loc += v[j];
-      loc2 += w[j];
-    }
-    const int64_t inc = wave_incl_scan(loc);
-    const int64_t inc2 = wave_incl_scan(loc2);
-    if (lane == 63) {
-      ws[0][wid] = inc;
-      ws[1][wid] = inc2;
-    }
-    __syncthreads();
-    int64_t off = 0, off2 = 0, tot = 0, tot2 = 0;
-#pragma unroll
-    for (int q = 0; q < W; ++q) {
-      const int64_t a = ws[0][q], b = ws[1][q];
-      if (q < wid) {
-        off += a;
-        off2 += b;
-      }
-      tot += a;
-      tot2 += b;
-    }
-    __syncthreads();
-    int64_t ex = carry + off + inc - loc;
-    int64_t ex2 = carry2 + off2 + inc2 - loc2;
-#pragma unroll
-    for (int j = 0; j < kItems; ++j) {
-      const int64_t i = c0 + (int64_t)threadIdx.x * kItems + j;
-      if (i < nt) {
-        ts[i] = ex;
-        ts2[i] = ex2;
-      }
-      ex += v[j];
-      ex2 += w[j];
-    }
-    carry += tot;
-    carry2 += tot2;
-  }
-  if (threadIdx.x == 0) {
-    ts[nt] = carry;
-    ts2[nt] = carry2;
-  }
+  scan_tile_sums2_block(ts, ts2, nt);
 }
 
 template <class Tin, class Tout>

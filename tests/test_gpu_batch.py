@@ -92,17 +92,55 @@ def tiny(G, O):
 SPARSE = [(0.0, 4096), (0.5, 4096), (1.0, 1)]
 
 
+@pytest.mark.parametrize("engine", [1, 0])
 @pytest.mark.parametrize("sparse", SPARSE)
 @pytest.mark.parametrize("mode", [0, 1, 2])
-def test_batch_tiny_workload(G, tiny, mode, sparse):
+def test_batch_tiny_workload(G, tiny, mode, sparse, engine):
     spec, s, p, o, qs, st, want = tiny
-    print(f"[gpu] batch tiny mode={mode} sparse={sparse}", flush=True)
+    print(f"[gpu] batch tiny mode={mode} sparse={sparse} engine={engine}", flush=True)
     G.gsmat_set_sparse_expand(st, *sparse)
+    G.gsmat_set_batch_engine(st, engine)
     try:
         queries = [q.tps for q in qs] * 8  # each query 8 times in one batch
         _check_batch(G, st, queries, mode, oracle_rows=want * 8)
     finally:
         G.gsmat_set_sparse_expand(st, 0.5, 4096)
+        G.gsmat_set_batch_engine(st, 1)
+
+
+# starting output slab and scratch region of the device-driven rounds: the
+# defaults, and sizes far below one round's needs (tasks wait for space, the
+# host adds larger regions between groups of rounds)
+REGIONS = [(0, 0), (64 << 10, 8 << 10), (8 << 10, 256 << 10), (1 << 20, 4 << 10)]
+
+
+@pytest.mark.parametrize("regions", REGIONS)
+@pytest.mark.parametrize("mode", [0, 2])
+def test_batch_device_regions(G, tiny, mode, regions):
+    spec, s, p, o, qs, st, want = tiny
+    print(f"[gpu] batch tiny regions={regions} mode={mode}", flush=True)
+    G.gsmat_set_sparse_expand(st, 1.0, 1)
+    try:
+        for rep in range(2):  # the second batch starts from the first one's sizes
+            if rep == 0:
+                G.gsmat_set_batch_regions(st, *regions)
+            queries = [q.tps for q in qs] * 4
+            _check_batch(G, st, queries, mode, oracle_rows=want * 4)
+    finally:
+        G.gsmat_set_sparse_expand(st, 0.5, 4096)
+        G.gsmat_set_batch_regions(st, 0, 0)
+
+
+def _join_all(G, st, plans, budget=0, engine=1):
+    G.gsmat_set_batch_engine(st, engine)
+    try:
+        results, stat = G.gsmat_join_batch(st, plans, budget)
+    finally:
+        G.gsmat_set_batch_engine(st, 1)
+    out = [(G.gsmat_fetch_bindings(r), G.gsmat_result_info(r)) for r in results]
+    for r in results:
+        r.close()
+    return out, stat
 
 
 def test_batch_autotune(G, tiny):
@@ -231,6 +269,16 @@ def test_batch_random_graphs(G, O, seed):
     print(f"[gpu] batch random seed={seed} V={V} P={P} n={n}", flush=True)
     for mode in (0, 1, 2):
         _check_batch(G, st, queries, mode, oracle_rows=want)
+    # the host-driven and device-driven rounds give the same rows, in the
+    # same order, and the same step counts
+    plans, _ = G.gsmat_plan_batch(st, queries, 2)
+    a, sa = _join_all(G, st, plans, engine=0)
+    b, sb = _join_all(G, st, plans, engine=1)
+    assert sa == sb == [0] * len(queries)
+    for i, ((ra, ia), (rb, ib)) in enumerate(zip(a, b)):
+        assert np.array_equal(ra, rb) and ia == ib, i
+    for pl in plans:
+        pl.close()
 
 
 # ------------------------------------------------------------------ medium graph
