@@ -34,7 +34,9 @@ CSRC = os.path.join(ROOT, "paper_1807_07691_amd", "csrc")
 # committed counter summaries: workload -> (file, kernel sources it depends on)
 PMC_SUMMARY = {
     "large": ("write_expand_large_pmc.md", ["kernels.hip", "device.hpp"]),
-    "batch": ("write_batch_pmc.md", ["kernels_batch.hip", "device.hpp"]),
+    "batch": ("write_batch_pmc.md", ["dbatch.hip", "batch_tiles.hpp", "device.hpp"]),
+    "batch-host": ("write_batch_host_pmc.md", ["kernels_batch.hip", "batch_tiles.hpp",
+                                               "device.hpp"]),
 }
 
 
@@ -115,6 +117,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sparse-theta", type=float, default=-1.0,
                     help="batch workload: sparse-expansion threshold (< 0: autotune)")
+    ap.add_argument("--engine", type=int, default=1,
+                    help="batch workload: 1 device-driven rounds, 0 host-driven rounds")
     ap.add_argument("--no-plain", action="store_true",
                     help="batch workload: skip the plain one-query-at-a-time comparison")
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
@@ -421,6 +425,7 @@ def bench_batch(args, G, W, spec, qspec, queries, st, sh, budget, mode, stats, l
     done_at = np.cumsum(lat)  # completion times when all queries arrive together
 
     packed = G.pack_queries(tps)
+    G.gsmat_set_batch_engine(st, args.engine)
 
     def batch_pass(phase=None):
         a = time.perf_counter()
@@ -467,6 +472,9 @@ def bench_batch(args, G, W, spec, qspec, queries, st, sh, budget, mode, stats, l
     for k_, v_ in wprof.items():
         log(f"  warmup class {k_:8s}: {v_['launches']:6d} launches {v_['ms']:10.2f} ms "
             f"{v_['bytes'] / 1e9:10.2f} GB alg")
+    rounds = G.gsmat_batch_round_stats(st) if args.engine == 1 else []
+    for i_, r_ in enumerate(rounds):
+        log(f"  round {i_}: " + " ".join(f"{k_}={v_}" for k_, v_ in r_.items()))
     want = [q.count for q in queries]
     ok_plain = sum(int(a == b) for a, b in zip(want, plain_counts)) if plain_counts else None
     ok_batch = sum(int(a == b) for a, b in zip(want, batch_counts))
@@ -479,6 +487,7 @@ def bench_batch(args, G, W, spec, qspec, queries, st, sh, budget, mode, stats, l
     step_s = []
     phase = []
     total_rows = 0
+    host0 = G.gsmat_prof_host()
     t0 = time.perf_counter()
     for k in range(args.steps):
         a = time.perf_counter()
@@ -495,24 +504,42 @@ def bench_batch(args, G, W, spec, qspec, queries, st, sh, budget, mode, stats, l
             f"in {h1['syncs'] - h0['syncs']})")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    host1 = G.gsmat_prof_host()
     total_cells = sum(q.count * q.n_vars for q in queries) * args.steps
     prof = G.gsmat_prof_read()
     G.gsmat_prof_enable(0)
     value = total_rows / wall
     wr = prof["write"]
     achieved = (wr["bytes"] / (wr["ms"] / 1e3) / 1e9) if wr["ms"] > 0 else 0.0
+    kernel = ("k_d_write (per-kernel figure: every expansion write of a device-driven round, "
+              "dense and compacted rows, any column count)" if args.engine == 1 else
+              "write class (per-kernel figure: k_b_write + k_b_write_idx<K>, host-driven rounds)")
     roofline = {
         "bound": "hbm",
         "achieved": round(achieved, 1),
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": counter_traffic("batch", theta),
+        "traffic": counter_traffic("batch" if args.engine == 1 else "batch-host", theta),
         "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-        "kernel": "k_b_write (batched expansion write, all column counts)",
+        "kernel": kernel,
         "launches": wr["launches"],
         "avg_launch_ms": round(wr["ms"] / max(1, wr["launches"]), 4),
         "alg_bytes_per_launch": round(wr["bytes"] / max(1, wr["launches"]), 1),
+    }
+    # the whole pass: every kernel class's algorithmic bytes of one pass (from
+    # the warmup's per-class counters) over the timed wall time per step
+    pass_bytes = sum(v["bytes"] for v in wprof.values())
+    pass_kernel_ms = sum(v["ms"] for v in wprof.values())
+    step_ms = wall / args.steps * 1e3
+    pass_roofline = {
+        "alg_bytes_per_step": round(pass_bytes, 1),
+        "achieved": round(pass_bytes / (step_ms / 1e3) / 1e9, 1),
+        "unit": "GB/s",
+        "frac": round(pass_bytes / (step_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+        "kernel_ms_per_step": round(pass_kernel_ms, 3),
+        "note": "algorithmic bytes of all kernel classes per pass / ms_per_step; kernel ms "
+                "from the warmup's per-launch events",
     }
     cpu = None if args.no_cpu_baseline else cpu_baseline(queries, s, p, o, args.cpu_sample_s)
     ms = lambda x: round(x * 1e3, 3)  # noqa: E731
@@ -534,6 +561,7 @@ def bench_batch(args, G, W, spec, qspec, queries, st, sh, budget, mode, stats, l
                         f"{spec.T} triples; {nq} random-walk BGPs of 1-6 patterns, result "
                         f"sizes log-uniform over 1..1e6 rows",
             "mode": "batched (gsmat_plan_batch + gsmat_join_batch over all queries per step)",
+            "engine": "device-driven rounds" if args.engine == 1 else "host-driven rounds",
             "plan_mode": mode,
             "budget_bytes": budget,
             "parallelism": "single-gpu",
@@ -541,6 +569,9 @@ def bench_batch(args, G, W, spec, qspec, queries, st, sh, budget, mode, stats, l
         # every query of a step is submitted together and completes with the batch
         "p50_ms": ms(percentile(step_s, 0.5)),
         "p99_ms": ms(percentile(step_s, 0.99)),
+        "latency_kind": "pass completion: all queries of a pass are submitted together and "
+                        "every one completes with the pass (not a single query's latency)",
+        "host_waits_per_step": round((host1["syncs"] - host0["syncs"]) / args.steps, 2),
         "autotune": {"sparse_theta": theta,
                      "candidate_ms": {str(k): round(v, 3) for k, v in tune_ms.items()}},
         "plan_batch_ms": ms(sum(x for x, _ in phase) / len(phase)),
@@ -567,6 +598,8 @@ def bench_batch(args, G, W, spec, qspec, queries, st, sh, budget, mode, stats, l
         "build_s": round(build_s, 3),
         "index_bytes": stats["device_bytes"],
         "roofline": roofline,
+        "pass_roofline": pass_roofline,
+        "rounds": len(rounds) if rounds else None,
         "cpu_baseline": cpu,
     }
 

@@ -405,6 +405,15 @@ gsmat_status gsmat_release_pools(void);
 
 /* ---- instrumentation ----------------------------------------------------- */
 
+/* Rounds of the store's last device-driven gsmat_join_batch (at most 64
+ * recorded): *n_rounds receives their number and out[8 * i + f] (for i <
+ * cap) round i's f-th figure: tasks counted, count tiles, post tiles
+ * (row offsets, compacted rows, filter and intersection compactions), write
+ * tiles, split entries, output bytes allocated, candidate expansions
+ * sampled, tasks deferred for lack of memory.  Host only. */
+gsmat_status gsmat_batch_round_stats(const gsmat_store* st, int64_t* out, int32_t cap,
+                                     int32_t* n_rounds);
+
 /* Kernel classes timed when profiling is on. */
 enum {
   GSMAT_K_COUNT = 0,    /* per-row output counts (+ tile sums) */

@@ -41,7 +41,7 @@ EXPORTED = [
     "gsmat_dict_load_text", "gsmat_dict_triples", "gsmat_dict_sizes", "gsmat_dict_lookup",
     "gsmat_dict_term", "gsmat_parse_bgp", "gsmat_set_hub_options", "gsmat_set_sparse_expand",
     "gsmat_autotune_batch", "gsmat_expand_strategy", "gsmat_set_batch_engine",
-    "gsmat_set_batch_regions",
+    "gsmat_set_batch_regions", "gsmat_batch_round_stats",
 ]
 
 
@@ -84,6 +84,8 @@ def _load():
     L.gsmat_set_batch_engine.argtypes = [vp, i32]
     L.gsmat_set_batch_regions.restype = i32
     L.gsmat_set_batch_regions.argtypes = [vp, i64, i64]
+    L.gsmat_batch_round_stats.restype = i32
+    L.gsmat_batch_round_stats.argtypes = [vp, vp, i32, vp]
     L.gsmat_autotune_batch.restype = i32
     L.gsmat_autotune_batch.argtypes = [vp, vp, i32, i64, vp, vp, vp]
     L.gsmat_expand_strategy.restype = i32
@@ -637,6 +639,19 @@ def gsmat_set_batch_regions(store, out_bytes=0, scratch_bytes=0):
     """Starting sizes of the device-driven batch's output slab and scratch
     region (0: the defaults); the store then keeps each batch's own sizes."""
     _check(_lib.gsmat_set_batch_regions(store.h, int(out_bytes), int(scratch_bytes)))
+
+
+ROUND_STAT_FIELDS = ("tasks", "count_tiles", "post_tiles", "write_tiles", "split_entries",
+                     "out_bytes", "candidates", "deferred")
+
+
+def gsmat_batch_round_stats(store):
+    """Per round of the store's last device-driven batch: a dict of the
+    ROUND_STAT_FIELDS figures."""
+    out = np.zeros((64, len(ROUND_STAT_FIELDS)), np.int64)
+    n = ctypes.c_int32(0)
+    _check(_lib.gsmat_batch_round_stats(store.h, _p(out), 64, ctypes.byref(n)))
+    return [dict(zip(ROUND_STAT_FIELDS, map(int, row))) for row in out[: min(n.value, 64)]]
 
 
 def gsmat_expand_strategy(theta, min_rows, n_in, n_nonempty):

@@ -1168,9 +1168,11 @@ extern "C" gsmat_status gsmat_join_batch(gsmat_store* st, const gsmat_query_plan
       bt.run();
     }
     // queries that left the batch run alone, from the start
+    bool alone = false;
     for (int i = 0; i < n_plans; ++i) {
       BQ& b = bt.q[i];
       if (b.state != kFallback) continue;
+      alone = true;
       b.res.reset(new gsmat_result);
       b.res->st = st;
       b.res->stream = s;
@@ -1190,7 +1192,8 @@ extern "C" gsmat_status gsmat_join_batch(gsmat_store* st, const gsmat_query_plan
         b.state = kDone;
       }
     }
-    GS_HIP(hipStreamSynchronize(s));
+    // the batch's own work was waited for; what ran alone is waited for here
+    if (alone || st->batch_engine != 1) host_sync(s);
     gsmat_status first = GSMAT_OK;
     std::string first_err;
     for (int i = 0; i < n_plans; ++i) {
@@ -1359,6 +1362,20 @@ extern "C" gsmat_status gsmat_set_batch_regions(gsmat_store* st, int64_t out_byt
     if (out_bytes < 0 || scratch_bytes < 0) throw StatusFail{GSMAT_EINVAL, "negative size"};
     st->dbatch_out_hint = out_bytes;
     st->dbatch_scr_hint = scratch_bytes;
+    return GSMAT_OK;
+  });
+}
+
+extern "C" gsmat_status gsmat_batch_round_stats(const gsmat_store* st, int64_t* out,
+                                               int32_t cap, int32_t* n_rounds) {
+  return guarded([&]() -> gsmat_status {
+    if (!st || !n_rounds) throw StatusFail{GSMAT_EINVAL, "store or n_rounds is NULL"};
+    if (cap < 0 || (cap > 0 && !out)) throw StatusFail{GSMAT_EINVAL, "bad output array"};
+    const int32_t n = (int32_t)(st->dbatch_stats.size() / kStatFields);
+    *n_rounds = n;
+    for (int32_t i = 0; i < std::min(n, cap); ++i)
+      for (int f = 0; f < kStatFields; ++f)
+        out[(size_t)i * kStatFields + f] = st->dbatch_stats[(size_t)i * kStatFields + f];
     return GSMAT_OK;
   });
 }

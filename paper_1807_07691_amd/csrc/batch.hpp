@@ -78,6 +78,8 @@ __host__ __device__ inline bool sparse_expand(double theta, int64_t min_rows, in
 // caller), kDevFallback (the query left the batch: run it alone), or
 // kDevFailed with status.
 enum : int32_t { kDevDone = 0, kDevFallback = 1, kDevFailed = 2 };
+constexpr int kStatRounds = 64;  // rounds recorded per device-driven batch
+constexpr int kStatFields = 8;
 struct DevQueryOut {
   gsmat_result* res;
   int32_t state;

@@ -16,16 +16,22 @@
 //   count     count / flag tiles of every task (Algorithm "Pre-allocating
 //             result matrix space", first loop)
 //   scan      one workgroup: tile sums scanned (second loop)
-//   decide    one workgroup: every task's output size and outcome, its
-//             output table bump-allocated from the current output slab
+//   outcome   one thread per query: the task's output size and outcome
+//   alloc     one workgroup: output tables bump-allocated from the current
+//             output slab, write scratch from the round's scratch region
 //   describe  one thread per query: write descriptors
 //   post      row offsets (dense expansions), rows with output (sparse
 //             expansions) and compactions (filters, intersections)
 //   partition merge-path splits of every expansion
 //   write     merge-path expansion writes
 //
-// The grid-stride kernels run a fixed grid and read their tile counts from
-// the device, so the host enqueues rounds without waiting for them; it waits
+// The tile kernels run as many workgroups as the device holds at once, each
+// striding over the round's tiles (their count is read on the device), so
+// the host enqueues rounds without waiting for them.  (Taking tiles from a
+// shared counter instead was measured slower: one atomic per tile on one
+// address costs more than the uneven tiles it balances.)  The
+// single-workgroup kernels only scan per-query arrays laid out one value per
+// query.  The host waits
 // once per group of rounds (as many rounds as the longest plan can take) and
 // then only reads a small summary.  Allocation never waits for the host: a
 // task whose scratch or output does not fit the current regions is deferred
@@ -53,7 +59,7 @@ namespace {
 using namespace dev;
 
 constexpr int kQBlock = 256;  // threads per workgroup of the per-query kernels
-constexpr int kGrid = 2048;   // workgroups of the grid-stride kernels (8 per CU)
+constexpr int kPartGrid = 1024;  // workgroups of the split kernel (one thread per split)
 
 enum : int32_t { kQActive = 0, kQDone = 1, kQFallback = 2, kQFailed = 3 };
 // outcome of a query's step in the current round
@@ -99,14 +105,10 @@ struct DQ {
   int32_t cand0, nc;
   int8_t cand_tp[kMaxPats], cand_or[kMaxPats];
   DStep sp;
-  int32_t outcome, kind;
-  int32_t kout, sparse;
-  int32_t out_slab, pad;
+  int32_t kind;      // task kind of the current step
+  int32_t kout, sparse, pad;
   int64_t n_in;      // rows entering the step
   int64_t m, ne;     // task output rows, expansion rows with output
-  int64_t cnt_off;   // count-phase scratch (offset in the scratch region)
-  int64_t out_off;   // output table (offset in the output slab)
-  int64_t scr_off;   // write-phase scratch
   int64_t rows;      // result rows once emitted
 };
 
@@ -122,7 +124,11 @@ struct DCtl {
   int64_t ntiles, n_post, n_part, n_write;
   int64_t want_out, want_scr;
   int64_t bytes_count, bytes_post, bytes_write;
-  int32_t out_slab, ncand, active, deferred, error, pad;
+  int64_t scr_need;  // largest scratch a round asked for (deferred tasks included)
+  // per round: tasks counted, count tiles, post tiles, write tiles, tables
+  // written, output bytes, candidates sampled, deferred tasks
+  int64_t stats[kStatRounds][kStatFields];
+  int32_t out_slab, ncand, active, deferred, error, round;
 };
 
 struct DRes {
@@ -157,6 +163,13 @@ struct DArgs {
   int64_t* w_post;
   int64_t* w_part;
   int64_t* w_write;
+  // per query, one value each: this round's outcome (kO*), the task's
+  // count-phase cost, tiles, scratch and algorithmic bytes, its scratch
+  // offset; the write-phase sizes; the output and write scratch offsets
+  int32_t* oc;
+  int64_t *tk_cost, *tk_tiles, *tk_cb, *tk_alg, *cnt_off;
+  int64_t *wz_ob, *wz_sb, *wz_post, *wz_part, *wz_write, *wz_alg_post, *wz_alg_write;
+  int64_t *out_off, *scr_off;
   DCtl* ctl;
   DRes* res;
   const int32_t** res_col;  // [nq * mv]
@@ -194,10 +207,10 @@ __device__ inline const uint32_t* d_row_bitmap(const DArgs& A, int orient, int32
   return o.hub_bm + (d.hub_base + r) * o.hub_words;
 }
 
-__device__ inline void d_error(const DArgs& A, DQ& Q) {
+__device__ inline void d_error(const DArgs& A, int qi, DQ& Q) {
   atomicAdd(&A.ctl->error, 1);
   Q.state = kQFallback;
-  Q.outcome = kONone;
+  A.oc[qi] = kONone;
 }
 
 // The patterns a step completes (its own; an intersection: the members whose
@@ -283,7 +296,7 @@ __device__ inline void d_finish(const DArgs& A, int qi, DQ& Q, const DTab& r, in
   Q.t = r;
   Q.rem = Q.next;
   Q.si += 1;
-  Q.outcome = kONone;
+  A.oc[qi] = kONone;
   if (r.n == 0) {
     Q.state = kQDone;
     Q.rows = 0;
@@ -341,15 +354,15 @@ __device__ inline bool d_scan_view(const DArgs& A, int qi, int tp, DTab& r) {
 // Applies the outcome decided for the query's task in the last round.
 __device__ inline void d_apply(const DArgs& A, int qi, DQ& Q) {
   if (Q.state != kQActive) return;
-  switch (Q.outcome) {
+  switch (A.oc[qi]) {
     case kONone:
       return;
     case kODefer:
-      Q.outcome = kONone;
+      A.oc[qi] = kONone;
       return;
     case kOFallback:
       Q.state = kQFallback;
-      Q.outcome = kONone;
+      A.oc[qi] = kONone;
       return;
     case kODone:
       d_done_empty(A, qi, Q);
@@ -373,7 +386,7 @@ __device__ inline void d_apply(const DArgs& A, int qi, DQ& Q) {
       const WTask& w = A.wt[qi];
       DTab r;
       r.n = Q.m;
-      r.slab = Q.out_slab;
+      r.slab = A.ctl->out_slab;  // the host changes it only between groups of rounds
       if (Q.kind == kTaskExpand) {
         r.k = Q.t.k + 1;
         for (int c = 0; c < Q.t.k; ++c) r.var[c] = Q.t.var[c];
@@ -390,7 +403,7 @@ __device__ inline void d_apply(const DArgs& A, int qi, DQ& Q) {
       return;
     }
     default:
-      d_error(A, Q);
+      d_error(A, qi, Q);
   }
 }
 
@@ -412,9 +425,9 @@ __global__ void k_d_init(DArgs A) {
   Q.next = Q.rem;
   Q.cand0 = -1;
   Q.nc = 0;
-  Q.outcome = kONone;
   Q.n_in = 0;
   Q.rows = 0;
+  A.oc[qi] = kONone;
   for (int i = 0; i < A.ms; ++i) {
     A.sin[(int64_t)qi * A.ms + i] = 0;
     A.sout[(int64_t)qi * A.ms + i] = 0;
@@ -483,7 +496,7 @@ __global__ void k_d_choose(DArgs A, int choose) {
     } else {
       const int c0 = atomicAdd(&A.ctl->ncand, Q.nc);
       if (c0 + Q.nc > A.nq * A.mp) {
-        d_error(A, Q);
+        d_error(A, qi, Q);
         return;
       }
       Q.cand0 = c0;
@@ -492,7 +505,7 @@ __global__ void k_d_choose(DArgs A, int choose) {
         const bool from_s = Q.cand_or[i] == 0;
         const int c = tab_col(Q.t, d_var(from_s ? q.s : q.o));
         if (c < 0) {
-          d_error(A, Q);
+          d_error(A, qi, Q);
           return;
         }
         SCand& sc = A.cands[c0 + i];
@@ -503,7 +516,7 @@ __global__ void k_d_choose(DArgs A, int choose) {
     }
   } else {
     if (pl.nsteps < 1) {
-      d_error(A, Q);
+      d_error(A, qi, Q);
       return;
     }
     const int i = Q.si < pl.nsteps ? Q.si : pl.nsteps - 1;
@@ -511,13 +524,36 @@ __global__ void k_d_choose(DArgs A, int choose) {
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_d_sample(DArgs A) {
-  const int64_t total = (int64_t)A.ctl->ncand * kSampleBlocks;
+// Fan-out sample slices of every candidate (kSampleBlocks per candidate).
+// The tile kernels take their arrays as separate read-only, non-aliased
+// parameters, so that the descriptors are fetched with scalar loads.
+__global__ __launch_bounds__(kBlock) void k_d_sample(const SCand* __restrict__ cands,
+                                                     int64_t* __restrict__ part,
+                                                     const DCtl* __restrict__ ctl) {
+  const int64_t total = (int64_t)ctl->ncand * kSampleBlocks;
   for (int64_t j = blockIdx.x; j < total; j += gridDim.x) {
-    const SCand& sc = A.cands[j / kSampleBlocks];
+    const SCand& sc = cands[j / kSampleBlocks];
     const int64_t t = sample_fanout_slice((int)(j % kSampleBlocks), sc.col, sc.n, sc.pv);
-    if (threadIdx.x == 0) A.part[j] = t;
+    if (threadIdx.x == 0) part[j] = t;
+    __syncthreads();
   }
+}
+
+// Count-phase scratch of a task: N, start and offsets P of an expansion, or
+// the keep flags of a filter or intersection.
+__device__ inline int64_t d_cnt_bytes(int kind, int64_t n) {
+  if (kind == kTaskExpand) return 2 * d_a256(4 * n) + d_a256(8 * (n + 1));
+  return d_a256(n);
+}
+
+// Algorithmic bytes of a count task: a lookup of every input row's bound
+// value (4 read + 8 row extent) and its count and start written (expansion);
+// two values, one probe word and a flag (filter); the driver id, one probe
+// per other list and a flag (intersection).
+__device__ inline int64_t d_count_alg(const CTask& c) {
+  if (c.kind == kTaskExpand) return 20 * c.n;
+  if (c.kind == kTaskFilter) return 13 * c.n;
+  return (5 + 4 * (int64_t)c.nl) * c.n;
 }
 
 // The step of every active query: finished at once, or a count-phase task.
@@ -541,7 +577,7 @@ __global__ void k_d_task(DArgs A) {
   const DStep sp = Q.sp;
   Q.next = Q.rem & ~d_completes(pats, pl.np, sp);
   Q.n_in = Q.t.n;
-  Q.outcome = kONone;
+  A.oc[qi] = kONone;
   const DPat p = pats[sp.tp];
   const bool unit = Q.t.n == 1 && Q.t.k == 0;
   CTask c{};
@@ -563,7 +599,7 @@ __global__ void k_d_task(DArgs A) {
       }
       const int32_t cterm = -(sp.var + 1);
       ListRef* out = A.lists + (int64_t)qi * kMaxLists;
-      // the shortest list drives; the others are written after it
+      // the shortest list (the first on ties) drives; the others follow it
       int nl = 0, d = -1;
       const int32_t* dids = nullptr;
       int64_t dlen = 0;
@@ -572,7 +608,7 @@ __global__ void k_d_task(DArgs A) {
         for (int tp = 0; tp < pl.np; ++tp) {
           if (!(sp.members >> tp & 1)) continue;
           if (j >= kMaxLists) {
-            d_error(A, Q);
+            d_error(A, qi, Q);
             return;
           }
           const DPat m = pats[tp];
@@ -680,25 +716,13 @@ __global__ void k_d_task(DArgs A) {
       return;
   }
   Q.kind = c.kind;
-  Q.outcome = kOTask;
   A.ct[qi] = c;
-}
-
-// Count-phase scratch of a task: N, start and offsets P of an expansion, or
-// the keep flags of a filter or intersection.
-__device__ inline int64_t d_cnt_bytes(int kind, int64_t n) {
-  if (kind == kTaskExpand) return 2 * d_a256(4 * n) + d_a256(8 * (n + 1));
-  return d_a256(n);
-}
-
-// Algorithmic bytes of a count task: a lookup of every input row's bound
-// value (4 read + 8 row extent) and its count and start written (expansion);
-// two values, one probe word and a flag (filter); the driver id, one probe
-// per other list and a flag (intersection).
-__device__ inline int64_t d_count_alg(const CTask& c) {
-  if (c.kind == kTaskExpand) return 20 * c.n;
-  if (c.kind == kTaskFilter) return 13 * c.n;
-  return (5 + 4 * (int64_t)c.nl) * c.n;
+  const int64_t cb = d_cnt_bytes(c.kind, c.n), tiles = d_tiles(c.n);
+  A.tk_cb[qi] = cb;
+  A.tk_tiles[qi] = tiles;
+  A.tk_cost[qi] = cb + 16 * tiles;  // with its share of the two tile-sum arrays
+  A.tk_alg[qi] = d_count_alg(c);
+  A.oc[qi] = kOTask;
 }
 
 // Tiles and count-phase scratch of every task (one workgroup of kScanBlock
@@ -712,52 +736,36 @@ __global__ __launch_bounds__(kScanBlock) void k_d_layout(DArgs A) {
   const int q0 = min(A.nq, (int)threadIdx.x * per), q1 = min(A.nq, q0 + per);
   const int64_t cap = C.scr_cap;
   int64_t v1[1] = {0}, e1[1], t1[1];
-  for (int q = q0; q < q1; ++q) {
-    const DQ& Q = A.q[q];
-    if (Q.state == kQActive && Q.outcome == kOTask)
-      v1[0] += d_cnt_bytes(Q.kind, A.ct[q].n) + 16 * d_tiles(A.ct[q].n);
-  }
+  for (int q = q0; q < q1; ++q)
+    if (A.oc[q] == kOTask) v1[0] += A.tk_cost[q];
   block_excl_scan_n<1>(v1, e1, t1);
   int64_t v2[3] = {0, 0, 0}, e2[3], t2[3];  // tiles, scratch bytes, algorithmic bytes
   int64_t run = e1[0];
   int defer = 0;
   int64_t want = 0;
   for (int q = q0; q < q1; ++q) {
-    DQ& Q = A.q[q];
-    if (Q.state != kQActive || Q.outcome != kOTask) continue;
-    const int64_t n = A.ct[q].n;
-    const int64_t cb = d_cnt_bytes(Q.kind, n), cost = cb + 16 * d_tiles(n);
+    if (A.oc[q] != kOTask) continue;
+    const int64_t cost = A.tk_cost[q];
     run += cost;
     if (run + 1024 > cap) {
-      Q.outcome = kODefer;
+      A.oc[q] = kODefer;
       ++defer;
       want = max(want, cost + 1024);
       continue;
     }
-    v2[0] += d_tiles(n);
-    v2[1] += cb;
-    v2[2] += d_count_alg(A.ct[q]);
+    v2[0] += A.tk_tiles[q];
+    v2[1] += A.tk_cb[q];
+    v2[2] += A.tk_alg[q];
   }
   block_excl_scan_n<3>(v2, e2, t2);
   int64_t w = e2[0], off = e2[1];
-  char* base = C.scr_base;
   for (int q = q0; q < q1; ++q) {
     A.w_cnt[q] = w;
-    DQ& Q = A.q[q];
-    if (Q.state != kQActive || Q.outcome != kOTask) continue;
-    CTask& c = A.ct[q];
-    const int64_t n = c.n;
-    Q.cnt_off = off;
-    if (Q.kind == kTaskExpand) {
-      c.N = (int32_t*)(base + off);
-      c.start = (int32_t*)(base + off + d_a256(4 * n));
-      c.nonempty = A.ne + q;
-      A.ne[q] = 0;
-    } else {
-      c.flags = (uint8_t*)(base + off);
-    }
-    w += d_tiles(n);
-    off += d_cnt_bytes(Q.kind, n);
+    if (A.oc[q] != kOTask) continue;
+    A.cnt_off[q] = off;
+    A.ne[q] = 0;
+    w += A.tk_tiles[q];
+    off += A.tk_cb[q];
   }
   __shared__ int s_defer;
   __shared__ unsigned long long s_want;
@@ -771,8 +779,21 @@ __global__ __launch_bounds__(kScanBlock) void k_d_layout(DArgs A) {
     atomicMax(&s_want, (unsigned long long)want);
   }
   __syncthreads();
+  // tasks counted this round
+  int64_t vt[1] = {0}, et[1], tt[1];
+  for (int q = q0; q < q1; ++q) vt[0] += A.oc[q] == kOTask;
+  block_excl_scan_n<1>(vt, et, tt);
   if (threadIdx.x == 0) {
     const int64_t nt = t2[0];
+    char* base = C.scr_base;
+    C.scr_need = max(C.scr_need, t1[0] + 1024);
+    if (C.round < kStatRounds) {
+      int64_t* st = C.stats[C.round];
+      st[0] = tt[0];
+      st[1] = nt;
+      st[6] = C.ncand;
+      st[7] = s_defer;
+    }
     A.w_cnt[A.nq] = nt;
     C.ntiles = nt;
     C.ts = (int64_t*)(base + t2[1]);
@@ -786,19 +807,29 @@ __global__ __launch_bounds__(kScanBlock) void k_d_layout(DArgs A) {
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_d_count(DArgs A) {
-  const DCtl& C = *A.ctl;
-  const int64_t nt = C.ntiles;
-  int64_t* ts = C.ts;
-  int64_t* tsn = C.tsn;
+__global__ __launch_bounds__(kBlock) void k_d_count(const CTask* __restrict__ ct,
+                                                    const ListRef* __restrict__ lists,
+                                                    const int64_t* __restrict__ w_cnt,
+                                                    const int64_t* __restrict__ cnt_off,
+                                                    int64_t* __restrict__ ne, int nq,
+                                                    const DCtl* __restrict__ ctl) {
+  const int64_t nt = ctl->ntiles;
+  int64_t* ts = ctl->ts;
+  int64_t* tsn = ctl->tsn;
+  char* base = ctl->scr_base;
   for (int64_t b = blockIdx.x; b < nt; b += gridDim.x) {
-    const int qi = find_first_tile(A.w_cnt, A.nq, b);
-    int64_t ne;
-    const int64_t sum = b_count_tile(A.ct[qi], b - A.w_cnt[qi], A.lists, &ne);
+    const int qi = find_first_tile(w_cnt, nq, b);
+    const CTask& T = ct[qi];
+    char* cb = base + cnt_off[qi];
+    int64_t k;
+    const int64_t sum =
+        b_count_tile(T, b - w_cnt[qi], lists, (int32_t*)cb, (int32_t*)(cb + d_a256(4 * T.n)),
+                     (uint8_t*)cb, ne + qi, &k);
     if (threadIdx.x == 0) {
       ts[b] = sum;
-      tsn[b] = ne;
+      tsn[b] = k;
     }
+    __syncthreads();
   }
 }
 
@@ -812,121 +843,120 @@ __device__ inline int64_t d_out_bytes(int64_t m, int kout) {
   return 4 * d_stride(m) * (int64_t)(kout > 1 ? kout : 1);
 }
 
-// Write-phase sizes of an accepted task: scratch bytes (splits; compacted
-// rows), tiles of the post launch, split entries, write tiles, and the
-// algorithmic bytes of its post and write work.
-struct WSizes {
-  int64_t scr, post, part, write, alg_post, alg_write;
-};
-__device__ inline WSizes d_wsizes(const DQ& Q, const CTask& c) {
-  WSizes z{0, d_tiles(c.n), 0, 0, 0, 0};
-  const int64_t n = c.n, m = Q.m, ne = Q.ne;
-  const int64_t k = Q.t.k;
+// Every counted task's output size and outcome; for a table to write, its
+// output bytes, write scratch, tiles of the post launch, split entries,
+// write tiles and algorithmic bytes.
+__global__ void k_d_outcome(DArgs A) {
+  const int qi = blockIdx.x * blockDim.x + threadIdx.x;
+  if (qi >= A.nq || A.oc[qi] != kOTask) return;
+  DQ& Q = A.q[qi];
+  const DCtl& C = *A.ctl;
+  const CTask& c = A.ct[qi];
+  const int64_t m = C.ts[A.w_cnt[qi + 1]] - C.ts[A.w_cnt[qi]];
+  const int64_t n = c.n;
+  const int64_t ne = Q.kind == kTaskExpand ? A.ne[qi] : 0;
+  Q.m = m;
+  Q.ne = ne;
+  int o;
   if (Q.kind == kTaskExpand) {
-    const int64_t nw = Q.sparse ? ne : n;
-    const int64_t pt = d_tiles(nw + m);
-    z.part = pt + 1;
-    z.write = pt;
-    z.scr = d_a256(8 * (pt + 1));
+    o = m == 0 ? kODone : kOWrite;
+    Q.kout = Q.t.k + 1;
+  } else if (Q.kind == kTaskFilter) {
+    o = m == n ? kOPass : (m == 0 ? kODone : kOWrite);
+    Q.kout = Q.t.k;
+  } else {
+    o = m == n ? kODriver : (m == 0 ? kODone : kOWrite);
+    Q.kout = 1;
+  }
+  if (o == kOWrite && A.budget > 0 && m > A.budget / (4 * (int64_t)max(Q.kout, 1)))
+    o = kOFallback;  // above the step budget: chunked by the single-query executor
+  A.oc[qi] = o;
+  if (o != kOWrite) return;
+  const int64_t k = Q.t.k;
+  int64_t sb = 0, post = d_tiles(n), part = 0, write = 0, alg_post, alg_write = 0;
+  Q.sparse = Q.kind == kTaskExpand && sparse_expand(A.theta, A.min_rows, n, ne);
+  if (Q.kind == kTaskExpand) {
+    const int64_t pt = d_tiles((Q.sparse ? ne : n) + m);
+    part = pt + 1;
+    write = pt;
+    sb = d_a256(8 * (pt + 1));
     if (Q.sparse) {
-      z.scr += 2 * d_a256(4 * ne) + d_a256(8 * (ne + 1));
-      z.alg_post = 4 * n + 20 * ne;
-      z.alg_write = 4 * m * (k + 2) + 16 * ne + 4 * k * ne;
+      sb += 2 * d_a256(4 * ne) + d_a256(8 * (ne + 1));
+      alg_post = 4 * n + 20 * ne;
+      alg_write = 4 * m * (k + 2) + 16 * ne + 4 * k * ne;
     } else {
-      z.alg_post = 12 * n;
-      z.alg_write = 4 * m * (k + 2) + 12 * n + 4 * k * ne;
+      alg_post = 12 * n;
+      alg_write = 4 * m * (k + 2) + 12 * n + 4 * k * ne;
     }
   } else {
     const int64_t kk = Q.kind == kTaskIntersect ? 1 : k;
-    z.alg_post = (1 + 4 * kk) * n + 4 * kk * m;
+    alg_post = (1 + 4 * kk) * n + 4 * kk * m;
   }
-  return z;
+  A.wz_ob[qi] = d_out_bytes(m, Q.kout);
+  A.wz_sb[qi] = sb;
+  A.wz_post[qi] = post;
+  A.wz_part[qi] = part;
+  A.wz_write[qi] = write;
+  A.wz_alg_post[qi] = alg_post;
+  A.wz_alg_write[qi] = alg_write;
 }
 
-// Every task's output size and outcome; outputs and write scratch of the
-// accepted tasks bump-allocated; the launch groups' first tiles.  One
-// workgroup of kScanBlock threads.
-__global__ __launch_bounds__(kScanBlock) void k_d_decide(DArgs A) {
+// Output tables and write scratch of the tables to write, bump-allocated;
+// the launch groups' first tiles.  One workgroup of kScanBlock threads.
+// The round's outputs above the round budget send the later queries to the
+// single-query executor; a table or scratch that does not fit the current
+// regions waits for a later round.  Both rules keep a prefix of the tasks in
+// query order.
+__global__ __launch_bounds__(kScanBlock) void k_d_alloc(DArgs A) {
   DCtl& C = *A.ctl;
   const int per = (A.nq + kScanBlock - 1) / kScanBlock;
   const int q0 = min(A.nq, (int)threadIdx.x * per), q1 = min(A.nq, q0 + per);
-  const int64_t* ts = C.ts;
-  // outcomes and output bytes
   int64_t va[1] = {0}, ea[1], ta[1];
-  for (int q = q0; q < q1; ++q) {
-    DQ& Q = A.q[q];
-    if (Q.state != kQActive || Q.outcome != kOTask) continue;
-    const CTask& c = A.ct[q];
-    const int64_t m = ts[A.w_cnt[q + 1]] - ts[A.w_cnt[q]];
-    Q.m = m;
-    Q.ne = Q.kind == kTaskExpand ? A.ne[q] : 0;
-    int o;
-    if (Q.kind == kTaskExpand) {
-      o = m == 0 ? kODone : kOWrite;
-      Q.kout = Q.t.k + 1;
-    } else if (Q.kind == kTaskFilter) {
-      o = m == c.n ? kOPass : (m == 0 ? kODone : kOWrite);
-      Q.kout = Q.t.k;
-    } else {
-      o = m == c.n ? kODriver : (m == 0 ? kODone : kOWrite);
-      Q.kout = 1;
-    }
-    if (o == kOWrite && A.budget > 0 && m > A.budget / (4 * (int64_t)max(Q.kout, 1)))
-      o = kOFallback;  // above the step budget: chunked by the single-query executor
-    Q.outcome = o;
-    if (o == kOWrite) va[0] += d_out_bytes(m, Q.kout);
-  }
+  for (int q = q0; q < q1; ++q)
+    if (A.oc[q] == kOWrite) va[0] += A.wz_ob[q];
   block_excl_scan_n<1>(va, ea, ta);
-  // the round's outputs above the budget: the later queries leave the batch
   int64_t vb[2] = {0, 0}, eb[2], tb[2];
   int64_t run = ea[0];
   for (int q = q0; q < q1; ++q) {
-    DQ& Q = A.q[q];
-    if (Q.state != kQActive || Q.outcome != kOWrite) continue;
-    const int64_t ob = d_out_bytes(Q.m, Q.kout);
+    if (A.oc[q] != kOWrite) continue;
+    const int64_t ob = A.wz_ob[q];
     const bool over = A.round_budget > 0 && run > 0 && run + ob > A.round_budget;
     run += ob;
     if (over) {
-      Q.outcome = kOFallback;
+      A.oc[q] = kOFallback;
       continue;
     }
-    Q.sparse = Q.kind == kTaskExpand && sparse_expand(A.theta, A.min_rows, A.ct[q].n, Q.ne);
     vb[0] += ob;
-    vb[1] += d_wsizes(Q, A.ct[q]).scr;
+    vb[1] += A.wz_sb[q];
   }
   block_excl_scan_n<2>(vb, eb, tb);
-  // memory: a task whose output or scratch does not fit is deferred
   int64_t vc[7] = {0, 0, 0, 0, 0, 0, 0}, ec[7], tc[7];
   int64_t ro = eb[0], rs = eb[1];
   const int64_t out_used = C.out_used, scr_used = C.scr_used;
+  const int64_t out_cap = C.out_cap, scr_cap = C.scr_cap;
   int defer = 0;
   int64_t want_o = 0, want_s = 0;
   for (int q = q0; q < q1; ++q) {
-    DQ& Q = A.q[q];
-    if (Q.state != kQActive || Q.outcome != kOWrite) continue;
-    const CTask& c = A.ct[q];
-    const int64_t ob = d_out_bytes(Q.m, Q.kout);
-    const WSizes z = d_wsizes(Q, c);
-    const bool fits = out_used + ro + ob <= C.out_cap && scr_used + rs + z.scr <= C.scr_cap;
-    if (fits) {
-      Q.out_off = out_used + ro;
-      Q.scr_off = scr_used + rs;
-      Q.out_slab = C.out_slab;
-      vc[0] += z.post;
-      vc[1] += z.part;
-      vc[2] += z.write;
+    if (A.oc[q] != kOWrite) continue;
+    const int64_t ob = A.wz_ob[q], sb = A.wz_sb[q];
+    if (out_used + ro + ob <= out_cap && scr_used + rs + sb <= scr_cap) {
+      A.out_off[q] = out_used + ro;
+      A.scr_off[q] = scr_used + rs;
+      vc[0] += A.wz_post[q];
+      vc[1] += A.wz_part[q];
+      vc[2] += A.wz_write[q];
       vc[3] += ob;
-      vc[4] += z.scr;
-      vc[5] += z.alg_post;
-      vc[6] += z.alg_write;
+      vc[4] += sb;
+      vc[5] += A.wz_alg_post[q];
+      vc[6] += A.wz_alg_write[q];
     } else {
-      Q.outcome = kODefer;
+      A.oc[q] = kODefer;
       ++defer;
       want_o = max(want_o, ob);
-      want_s = max(want_s, d_cnt_bytes(Q.kind, c.n) + 16 * d_tiles(c.n) + z.scr + 1024);
+      want_s = max(want_s, A.tk_cost[q] + sb + 1024);
     }
     ro += ob;
-    rs += z.scr;
+    rs += sb;
   }
   block_excl_scan_n<7>(vc, ec, tc);
   int64_t wp = ec[0], wq = ec[1], ww = ec[2];
@@ -934,12 +964,10 @@ __global__ __launch_bounds__(kScanBlock) void k_d_decide(DArgs A) {
     A.w_post[q] = wp;
     A.w_part[q] = wq;
     A.w_write[q] = ww;
-    const DQ& Q = A.q[q];
-    if (Q.state != kQActive || Q.outcome != kOWrite) continue;
-    const WSizes z = d_wsizes(Q, A.ct[q]);
-    wp += z.post;
-    wq += z.part;
-    ww += z.write;
+    if (A.oc[q] != kOWrite) continue;
+    wp += A.wz_post[q];
+    wq += A.wz_part[q];
+    ww += A.wz_write[q];
   }
   __shared__ int s_defer;
   __shared__ unsigned long long s_wo, s_ws;
@@ -964,6 +992,16 @@ __global__ __launch_bounds__(kScanBlock) void k_d_decide(DArgs A) {
     C.out_used = out_used + tc[3];
     C.scr_used = scr_used + tc[4];
     C.scr_peak = max(C.scr_peak, C.scr_used);
+    C.scr_need = max(C.scr_need, scr_used + tb[1]);
+    if (C.round < kStatRounds) {
+      int64_t* st = C.stats[C.round];
+      st[2] = tc[0];
+      st[3] = tc[2];
+      st[4] = tc[1];  // split entries: tables written + path tiles
+      st[5] = tc[3];
+      st[7] += s_defer;
+    }
+    C.round += 1;
     C.bytes_post += tc[5];
     C.bytes_write += tc[6];
     C.deferred += s_defer;
@@ -972,12 +1010,11 @@ __global__ __launch_bounds__(kScanBlock) void k_d_decide(DArgs A) {
   }
 }
 
-// Write descriptors of the accepted tasks.
+// Write descriptors of the tables to write.
 __global__ void k_d_describe(DArgs A) {
   const int qi = blockIdx.x * blockDim.x + threadIdx.x;
-  if (qi >= A.nq) return;
+  if (qi >= A.nq || A.oc[qi] != kOWrite) return;
   const DQ& Q = A.q[qi];
-  if (Q.state != kQActive || Q.outcome != kOWrite) return;
   const DCtl& C = *A.ctl;
   const CTask& c = A.ct[qi];
   WTask w{};
@@ -985,53 +1022,56 @@ __global__ void k_d_describe(DArgs A) {
   w.n = c.n;
   w.m = m;
   w.t0 = A.w_cnt[qi];
-  w.out0 = (int32_t*)(C.out_base + Q.out_off);
+  w.out0 = (int32_t*)(C.out_base + A.out_off[qi]);
   w.ostride = d_stride(m);
-  char* sb = C.scr_base + Q.scr_off;
-  char* cb = C.scr_base + Q.cnt_off;
+  char* sb = C.scr_base + A.scr_off[qi];
+  char* cb = C.scr_base + A.cnt_off[qi];
   if (Q.kind == kTaskExpand) {
     w.k = Q.t.k;
     for (int cc = 0; cc < Q.t.k; ++cc) w.in.c[cc] = Q.t.col[cc];
     w.nbr = c.pv.nbr;
-    w.N = c.N;
+    w.N = (const int32_t*)cb;
+    const int32_t* start = (const int32_t*)(cb + d_a256(4 * c.n));
     if (Q.sparse) {
       const int64_t ne = Q.ne;
       w.n_in = c.n;
       w.n = ne;
-      w.start_in = c.start;
+      w.start_in = start;
       w.ridx = (int32_t*)sb;
       w.cstart = (int32_t*)(sb + d_a256(4 * ne));
       w.P = (int64_t*)(sb + 2 * d_a256(4 * ne));
       w.start = w.cstart;
       w.split = (int64_t*)(sb + 2 * d_a256(4 * ne) + d_a256(8 * (ne + 1)));
     } else {
-      w.start = c.start;
+      w.start = start;
       w.P = (int64_t*)(cb + 2 * d_a256(4 * c.n));
       w.split = (int64_t*)sb;
     }
-  } else if (Q.kind == kTaskFilter) {
-    w.k = Q.t.k;
-    for (int cc = 0; cc < Q.t.k; ++cc) w.in.c[cc] = Q.t.col[cc];
-    w.flags = c.flags;
   } else {
-    w.k = 1;
-    w.in.c[0] = c.col;
-    w.flags = c.flags;
+    if (Q.kind == kTaskFilter) {
+      w.k = Q.t.k;
+      for (int cc = 0; cc < Q.t.k; ++cc) w.in.c[cc] = Q.t.col[cc];
+    } else {
+      w.k = 1;
+      w.in.c[0] = c.col;
+    }
+    w.flags = (const uint8_t*)cb;
   }
   A.wt[qi] = w;
 }
 
 // Row offsets of the dense expansions, rows with output of the sparse ones,
 // compactions of the filters and intersections.
-__global__ __launch_bounds__(kBlock) void k_d_post(DArgs A) {
-  const DCtl& C = *A.ctl;
-  const int64_t nt = C.n_post;
-  const int64_t* ts = C.ts;
-  const int64_t* tsn = C.tsn;
+__global__ __launch_bounds__(kBlock) void k_d_post(const WTask* __restrict__ wt,
+                                                   const int64_t* __restrict__ w_post, int nq,
+                                                   const DCtl* __restrict__ ctl) {
+  const int64_t nt = ctl->n_post;
+  const int64_t* ts = ctl->ts;
+  const int64_t* tsn = ctl->tsn;
   for (int64_t b = blockIdx.x; b < nt; b += gridDim.x) {
-    const int qi = find_first_tile(A.w_post, A.nq, b);
-    const WTask& T = A.wt[qi];
-    const int64_t tile = b - A.w_post[qi];
+    const int qi = find_first_tile(w_post, nq, b);
+    const WTask& T = wt[qi];
+    const int64_t tile = b - w_post[qi];
     if (T.flags) b_compact_tile_any(T, tile, ts);
     else if (T.ridx) b_compact_rows_tile(T, tile, ts, tsn);
     else b_scan_add_tile(T, tile, ts);
@@ -1039,27 +1079,31 @@ __global__ __launch_bounds__(kBlock) void k_d_post(DArgs A) {
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_d_partition(DArgs A) {
-  const int64_t total = A.ctl->n_part;
+__global__ __launch_bounds__(kBlock) void k_d_partition(const WTask* __restrict__ wt,
+                                                        const int64_t* __restrict__ w_part,
+                                                        int nq, const DCtl* __restrict__ ctl) {
+  const int64_t total = ctl->n_part;
   for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total;
        g += (int64_t)gridDim.x * blockDim.x) {
-    const int qi = find_first_tile(A.w_part, A.nq, g);
-    const WTask& T = A.wt[qi];
-    T.split[g - A.w_part[qi]] = mp_split(T.P, T.n, 0, T.m, g - A.w_part[qi]);
+    const int qi = find_first_tile(w_part, nq, g);
+    const WTask& T = wt[qi];
+    T.split[g - w_part[qi]] = mp_split(T.P, T.n, 0, T.m, g - w_part[qi]);
   }
 }
 
 // Every expansion write of the round, dense and compacted, any column count.
-__global__ __launch_bounds__(kBlock) void k_d_write(DArgs A) {
+__global__ __launch_bounds__(kBlock) void k_d_write(const WTask* __restrict__ wt,
+                                                    const int64_t* __restrict__ w_write, int nq,
+                                                    const DCtl* __restrict__ ctl) {
   __shared__ int32_t sE[kTile + 1];
   __shared__ int32_t sRb[kTile + 1];
   __shared__ uint16_t sRow[kTile];
   const TileLds L{sE, sRb, sRow, nullptr};
-  const int64_t nt = A.ctl->n_write;
+  const int64_t nt = ctl->n_write;
   for (int64_t b = blockIdx.x; b < nt; b += gridDim.x) {
-    const int qi = find_first_tile(A.w_write, A.nq, b);
-    const WTask& T = A.wt[qi];
-    const int64_t t = b - A.w_write[qi];
+    const int qi = find_first_tile(w_write, nq, b);
+    const WTask& T = wt[qi];
+    const int64_t t = b - w_write[qi];
     if (T.ridx) b_write_tile_any<true>(T, t, L);
     else b_write_tile_any<false>(T, t, L);
     __syncthreads();  // the next tile reuses the LDS
@@ -1111,6 +1155,27 @@ struct Lay {
 
 int64_t round_up(int64_t b, int64_t g) { return (b + g - 1) / g * g; }
 
+// Workgroups of each tile kernel: as many as the device holds at once (the
+// kernels take tiles from a counter, so more would only wait for a slot).
+struct Grids {
+  unsigned sample, count, post, write;
+};
+const Grids& resident_grids() {
+  static Grids g = [] {
+    int dev = 0, cus = 0;
+    GS_HIP(hipGetDevice(&dev));
+    GS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    auto res = [&](const void* k) {
+      int per = 0;
+      GS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, kBlock, 0));
+      return (unsigned)std::max(1, per * std::max(cus, 1));
+    };
+    return Grids{res((const void*)k_d_sample), res((const void*)k_d_count),
+                 res((const void*)k_d_post), res((const void*)k_d_write)};
+  }();
+  return g;
+}
+
 #define GS_DLAUNCH(cls, kern, grid, block, ...)                               \
   do {                                                                       \
     const bool _prof = prof_on(cls);                                         \
@@ -1147,7 +1212,11 @@ void run_batch_device(gsmat_store* st, const gsmat_query_plan* const* plans, int
                o_ct = L.add(sizeof(CTask) * n), o_lists = L.add(sizeof(ListRef) * n * kMaxLists),
                o_wt = L.add(sizeof(WTask) * n), o_ne = L.add(sizeof(int64_t) * n),
                o_wc = L.add(sizeof(int64_t) * (n + 1)), o_wpo = L.add(sizeof(int64_t) * (n + 1)),
-               o_wpa = L.add(sizeof(int64_t) * (n + 1)), o_ww = L.add(sizeof(int64_t) * (n + 1));
+               o_wpa = L.add(sizeof(int64_t) * (n + 1)), o_ww = L.add(sizeof(int64_t) * (n + 1)),
+               o_oc = L.add(sizeof(int32_t) * n);
+  constexpr int kSoa = 14;  // per-query int64 arrays
+  size_t o_soa[kSoa];
+  for (int i = 0; i < kSoa; ++i) o_soa[i] = L.add(sizeof(int64_t) * n);
   // read back at the end, contiguous: results, their columns, step counters
   const size_t o_res = L.add(sizeof(DRes) * n), o_rcol = L.add(sizeof(int32_t*) * n * mv),
                o_sin = L.add(sizeof(int64_t) * n * ms), o_sout = L.add(sizeof(int64_t) * n * ms);
@@ -1248,34 +1317,58 @@ void run_batch_device(gsmat_store* st, const gsmat_query_plan* const* plans, int
   A.w_post = (int64_t*)(dv + o_wpo);
   A.w_part = (int64_t*)(dv + o_wpa);
   A.w_write = (int64_t*)(dv + o_ww);
+  A.oc = (int32_t*)(dv + o_oc);
+  int64_t** soa[kSoa] = {&A.tk_cost, &A.tk_tiles, &A.tk_cb, &A.tk_alg, &A.cnt_off,
+                         &A.wz_ob, &A.wz_sb, &A.wz_post, &A.wz_part, &A.wz_write,
+                         &A.wz_alg_post, &A.wz_alg_write, &A.out_off, &A.scr_off};
+  for (int i = 0; i < kSoa; ++i) *soa[i] = (int64_t*)(dv + o_soa[i]);
   A.ctl = (DCtl*)(dv + o_ctl);
   A.res = (DRes*)(dv + o_res);
   A.res_col = (const int32_t**)(dv + o_rcol);
 
   const unsigned qgrid = (unsigned)ceil_div(nq, kQBlock);
+  const Grids& grids = resident_grids();
   GS_DLAUNCH(GSMAT_K_OTHER, k_d_init, qgrid, kQBlock, A);
   DCtl* hc = (DCtl*)pin_ctl().get(sizeof(DCtl));
+  char* hb = (char*)pin_out().get(back_bytes);
   // every round completes at least one pattern of each query that is not
   // deferred (an intersection first step: none), so mp + 1 rounds finish
   // every query unless memory ran short
   const int rounds = mp + 1;
+  // Launch sizes: a tile kernel whose round had T tiles in the store's last
+  // batch gets a grid of T (plus an eighth) workgroups, one tile each when
+  // the round repeats; otherwise, or when there are more tiles, the
+  // workgroups stride over the tiles, and never fewer than the device holds.
+  const std::vector<int64_t> prev = st->dbatch_stats;
+  auto hinted = [&](int gr, int f, unsigned floor_) -> unsigned {
+    if ((size_t)(gr + 1) * kStatFields > prev.size()) return floor_;
+    const int64_t t = prev[(size_t)gr * kStatFields + f];
+    return (unsigned)std::min<int64_t>(std::max<int64_t>(t + t / 8, floor_), 1 << 22);
+  };
   int64_t out_total = 0;
+  int gr = 0;  // rounds launched so far
   for (int iter = 0;; ++iter) {
-    for (int r = 0; r < rounds; ++r) {
+    for (int r = 0; r < rounds; ++r, ++gr) {
       GS_DLAUNCH(GSMAT_K_OTHER, k_d_choose, qgrid, kQBlock, A, 1);
-      GS_DLAUNCH(GSMAT_K_OTHER, k_d_sample, kGrid, kBlock, A);
+      GS_DLAUNCH(GSMAT_K_OTHER, k_d_sample, grids.sample, kBlock, A.cands, A.part, A.ctl);
       GS_DLAUNCH(GSMAT_K_OTHER, k_d_task, qgrid, kQBlock, A);
       GS_DLAUNCH(GSMAT_K_SCAN, k_d_layout, 1, kScanBlock, A);
-      GS_DLAUNCH(GSMAT_K_COUNT, k_d_count, kGrid, kBlock, A);
+      GS_DLAUNCH(GSMAT_K_COUNT, k_d_count, hinted(gr, 1, grids.count), kBlock, A.ct, A.lists,
+                 A.w_cnt, A.cnt_off, A.ne, nq, A.ctl);
       GS_DLAUNCH(GSMAT_K_SCAN, k_d_scan, 1, kScanBlock, A);
-      GS_DLAUNCH(GSMAT_K_SCAN, k_d_decide, 1, kScanBlock, A);
+      GS_DLAUNCH(GSMAT_K_OTHER, k_d_outcome, qgrid, kQBlock, A);
+      GS_DLAUNCH(GSMAT_K_SCAN, k_d_alloc, 1, kScanBlock, A);
       GS_DLAUNCH(GSMAT_K_OTHER, k_d_describe, qgrid, kQBlock, A);
-      GS_DLAUNCH(GSMAT_K_COMPACT, k_d_post, kGrid, kBlock, A);
-      GS_DLAUNCH(GSMAT_K_OTHER, k_d_partition, kGrid, kBlock, A);
-      GS_DLAUNCH(GSMAT_K_WRITE, k_d_write, kGrid, kBlock, A);
+      GS_DLAUNCH(GSMAT_K_COMPACT, k_d_post, hinted(gr, 2, grids.post), kBlock, A.wt, A.w_post,
+                 nq, A.ctl);
+      GS_DLAUNCH(GSMAT_K_OTHER, k_d_partition, kPartGrid, kBlock, A.wt, A.w_part, nq, A.ctl);
+      GS_DLAUNCH(GSMAT_K_WRITE, k_d_write, hinted(gr, 3, grids.write), kBlock, A.wt, A.w_write,
+                 nq, A.ctl);
     }
     GS_DLAUNCH(GSMAT_K_OTHER, k_d_choose, qgrid, kQBlock, A, 0);
+    // the summary, and the results in case every query has finished
     GS_HIP(hipMemcpyAsync(hc, A.ctl, sizeof(DCtl), hipMemcpyDeviceToHost, s));
+    GS_HIP(hipMemcpyAsync(hb, dv + o_res, back_bytes, hipMemcpyDeviceToHost, s));
     host_sync(s);
     if (hc->error) throw StatusFail{GSMAT_EHIP, "internal: batched join state inconsistent"};
     if (hc->active == 0 || iter >= 16) break;
@@ -1304,15 +1397,14 @@ void run_batch_device(gsmat_store* st, const gsmat_query_plan* const* plans, int
   out_total += hc->out_used;
   // the pass's sizes are the next pass's starting regions
   st->dbatch_out_hint = std::max<int64_t>(round_up(out_total + out_total / 8, g), g);
-  st->dbatch_scr_hint = std::max<int64_t>(round_up(hc->scr_peak + hc->scr_peak / 8, g), g);
+  st->dbatch_scr_hint = std::max<int64_t>(round_up(hc->scr_need + hc->scr_need / 8, g), g);
+  st->dbatch_stats.assign(&hc->stats[0][0],
+                          &hc->stats[0][0] + (size_t)std::min(hc->round, kStatRounds) * kStatFields);
   prof_add_bytes(GSMAT_K_COUNT, (double)hc->bytes_count);
   prof_add_bytes(GSMAT_K_COMPACT, (double)hc->bytes_post);
   prof_add_bytes(GSMAT_K_WRITE, (double)hc->bytes_write);
 
-  // ---- results
-  char* hb = (char*)pin_out().get(back_bytes);
-  GS_HIP(hipMemcpyAsync(hb, dv + o_res, back_bytes, hipMemcpyDeviceToHost, s));
-  host_sync(s);
+  // ---- results (read back with the last summary)
   const DRes* hr = (const DRes*)hb;
   const int32_t* const* hcol = (const int32_t* const*)(hb + (o_rcol - o_res));
   const int64_t* hsin = (const int64_t*)(hb + (o_sin - o_res));

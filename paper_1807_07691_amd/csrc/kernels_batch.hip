@@ -40,7 +40,7 @@ __global__ __launch_bounds__(kBlock) void k_b_count(const CTask* __restrict__ ta
   const CTask& T = tasks[it.task];
   const int64_t tile = (int64_t)blockIdx.x - it.w0;
   int64_t ne;
-  const int64_t sum = b_count_tile(T, tile, lists, &ne);
+  const int64_t sum = b_count_tile(T, tile, lists, T.N, T.start, T.flags, T.nonempty, &ne);
   if (threadIdx.x == 0) {
     ts[blockIdx.x] = sum;
     tsn[blockIdx.x] = ne;

@@ -55,6 +55,7 @@ struct gsmat_store {
   int32_t batch_engine = 1;       // gsmat_join_batch: 1 device-driven rounds, 0 host-driven
   int64_t dbatch_out_hint = 0;    // device-driven rounds: output slab and scratch sizes of
   int64_t dbatch_scr_hint = 0;    // the last batch (the next one starts with them)
+  std::vector<int64_t> dbatch_stats;  // the last device-driven batch's rounds
   int64_t hub_min_len = 1 << 14;  // rows this long get a bitmap ...
   int64_t hub_max_bytes = 0;      // ... within this many bytes per orientation (0: none)
   uint64_t uid = 0;        // distinct for every index build in the process
