@@ -117,6 +117,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sparse-theta", type=float, default=-1.0,
                     help="batch workload: sparse-expansion threshold (< 0: autotune)")
+    ap.add_argument("--dense-div", type=int, default=256,
+                    help="index build: predicates with at least V/dense_div non-empty rows get a "
+                         "dense row pointer (0: the library default, 32)")
     ap.add_argument("--engine", type=int, default=1,
                     help="batch workload: 1 device-driven rounds, 0 host-driven rounds")
     ap.add_argument("--no-plain", action="store_true",
@@ -165,7 +168,7 @@ def main():
     st = G.gsmat_load_triples(s, p, o, spec.V, spec.P, stream=sh)
     load_s = time.perf_counter() - t0
     t0 = time.perf_counter()
-    G.gsmat_build_index(st, stream=sh)
+    G.gsmat_build_index(st, dense_div=args.dense_div, stream=sh)
     torch.cuda.synchronize()
     build_s = time.perf_counter() - t0
     stats = G.gsmat_store_stats(st)
@@ -449,12 +452,16 @@ def bench_batch(args, G, W, spec, qspec, queries, st, sh, budget, mode, stats, l
 
     # ---- batched: warmup (diagnostics, count and row checks), then timed
     log(f"batched warmup x{max(1, args.warmup)}")
-    G.gsmat_prof_enable(0x1F)
-    for w in range(max(1, args.warmup)):
+    nwarm = max(1, args.warmup)
+    for w in range(nwarm):
+        if w == nwarm - 1:  # per-class counters of the last warmup pass (regions and grids settled)
+            G.gsmat_prof_enable(0x1F)
         plans, results = batch_pass()
-        if w == 0:
+        if w == nwarm - 1:
             wprof = G.gsmat_prof_read()
             whost = G.gsmat_prof_host()
+            G.gsmat_prof_enable(0)
+        if w == 0:
             batch_counts = results.rows().tolist()
             sample = [] if args.no_plain else list(range(0, nq, max(1, nq // 64)))
             same = 0
@@ -562,6 +569,7 @@ def bench_batch(args, G, W, spec, qspec, queries, st, sh, budget, mode, stats, l
                         f"sizes log-uniform over 1..1e6 rows",
             "mode": "batched (gsmat_plan_batch + gsmat_join_batch over all queries per step)",
             "engine": "device-driven rounds" if args.engine == 1 else "host-driven rounds",
+            "dense_div": args.dense_div or 32,
             "plan_mode": mode,
             "budget_bytes": budget,
             "parallelism": "single-gpu",

@@ -1103,6 +1103,55 @@ extern "C" gsmat_status gsmat_server_poll(gsmat_server* sv, int32_t cap, int64_t
 
 extern "C" void gsmat_server_free(gsmat_server* sv) { delete sv; }
 
+namespace {
+
+// gsmat_join_batch with device-driven rounds: the queries that leave the
+// batch run alone afterwards, from the start.
+gsmat_status join_batch_device(gsmat_store* st, const gsmat_query_plan* const* plans,
+                               int32_t n_plans, int64_t budget_bytes, int64_t max_rows,
+                               hipStream_t s, gsmat_result** out, gsmat_status* status) {
+  std::vector<DevQueryOut> dq;
+  run_batch_device(st, plans, n_plans, budget_bytes, max_rows, s, dq);
+  bool alone = false;
+  gsmat_status first = GSMAT_OK;
+  std::string first_err;
+  for (int i = 0; i < n_plans; ++i) {
+    gsmat_status rc = dq[i].status;
+    std::string err;
+    if (dq[i].state == kDevFallback) {
+      alone = true;
+      std::unique_ptr<gsmat_result> r(new gsmat_result);
+      r->st = st;
+      r->stream = s;
+      r->n_vars = plans[i]->n_vars;
+      r->reset_steps(plans[i]->steps.size());
+      rc = guarded([&]() -> gsmat_status {
+        run_query(st, plans[i], budget_bytes, max_rows, s, r.get());
+        return GSMAT_OK;
+      });
+      if (rc == GSMAT_OK) out[i] = r.release();
+      else err = gsmat_last_error();
+    } else if (dq[i].state == kDevDone) {
+      out[i] = dq[i].res;
+    } else if (rc == GSMAT_ETOOBIG) {
+      err = "result exceeds max_rows (" + std::to_string(max_rows) + ")";
+    } else {
+      err = "query failed";
+    }
+    if (status) status[i] = rc;
+    if (rc != GSMAT_OK && first == GSMAT_OK) {
+      first = rc;
+      first_err = "query " + std::to_string(i) + ": " + err;
+    }
+  }
+  // the batch's own work was waited for; what ran alone is waited for here
+  if (alone) host_sync(s);
+  if (first != GSMAT_OK) throw StatusFail{first, first_err};
+  return GSMAT_OK;
+}
+
+}  // namespace
+
 extern "C" gsmat_status gsmat_join_batch(gsmat_store* st, const gsmat_query_plan* const* plans,
                                          int32_t n_plans, int64_t budget_bytes, int64_t max_rows,
                                          void* stream, gsmat_result** out, gsmat_status* status) {
@@ -1115,6 +1164,8 @@ extern "C" gsmat_status gsmat_join_batch(gsmat_store* st, const gsmat_query_plan
     for (int i = 0; i < n_plans; ++i)
       if (!plans[i]) throw StatusFail{GSMAT_EINVAL, "plan " + std::to_string(i) + " is NULL"};
     hipStream_t s = (hipStream_t)stream;
+    if (st->batch_engine == 1) return join_batch_device(st, plans, n_plans, budget_bytes, max_rows,
+                                                        s, out, status);
     Batch bt{st, s, budget_bytes, max_rows, {}, budget_bytes, false};
     bt.sparse_theta = st->sparse_theta;
     bt.sparse_min_rows = st->sparse_min_rows;
@@ -1137,42 +1188,11 @@ extern "C" gsmat_status gsmat_join_batch(gsmat_store* st, const gsmat_query_plan
           b.t = Table();
         }
     }
-    if (st->batch_engine == 1) {
-      // device-driven rounds; the queries' host state only collects outcomes
-      std::vector<DevQueryOut> dq;
-      std::vector<const gsmat_query_plan*> live;
-      std::vector<int> at;
-      for (int i = 0; i < n_plans; ++i)
-        if (bt.q[i].state == kActive) {
-          live.push_back(bt.q[i].pl);
-          at.push_back(i);
-        }
-      run_batch_device(st, live.data(), (int32_t)live.size(), budget_bytes, max_rows, s, dq);
-      for (size_t j = 0; j < dq.size(); ++j) {
-        BQ& b = bt.q[at[j]];
-        if (dq[j].state == kDevDone) {
-          b.res.reset(dq[j].res);
-          b.state = kDone;
-        } else if (dq[j].state == kDevFailed) {
-          b.state = kFailed;
-          b.status = dq[j].status;
-          b.err = dq[j].status == GSMAT_ETOOBIG
-                      ? "result exceeds max_rows (" + std::to_string(max_rows) + ")"
-                      : "query failed";
-          b.res.reset();
-        } else {
-          b.state = kFallback;
-        }
-      }
-    } else {
-      bt.run();
-    }
+    bt.run();
     // queries that left the batch run alone, from the start
-    bool alone = false;
     for (int i = 0; i < n_plans; ++i) {
       BQ& b = bt.q[i];
       if (b.state != kFallback) continue;
-      alone = true;
       b.res.reset(new gsmat_result);
       b.res->st = st;
       b.res->stream = s;
@@ -1192,8 +1212,7 @@ extern "C" gsmat_status gsmat_join_batch(gsmat_store* st, const gsmat_query_plan
         b.state = kDone;
       }
     }
-    // the batch's own work was waited for; what ran alone is waited for here
-    if (alone || st->batch_engine != 1) host_sync(s);
+    host_sync(s);
     gsmat_status first = GSMAT_OK;
     std::string first_err;
     for (int i = 0; i < n_plans; ++i) {

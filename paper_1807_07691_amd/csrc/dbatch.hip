@@ -274,35 +274,32 @@ __device__ inline bool d_candidates(const DArgs& A, const DPat* pats, int np, DQ
   return false;
 }
 
-// The candidate with the smallest sampled fan-out (the first on ties).
-__device__ inline DStep d_pick(const DPat* pats, const DQ& Q, const int64_t* sums) {
-  int best = 0;
-  if (sums)
-    for (int i = 1; i < Q.nc; ++i)
-      if (sums[i] < sums[best]) best = i;
+// Expansion step of candidate `best`.
+__device__ inline DStep d_pick(const DPat* pats, const DQ& Q, int best) {
   const DPat q = pats[Q.cand_tp[best]];
   const int o = Q.cand_or[best];
   return DStep{(int8_t)GSMAT_STEP_EXPAND, Q.cand_tp[best], (int8_t)o,
                (int8_t)(o == 0 ? d_var(q.o) : d_var(q.s)), 0u};
 }
 
-// The step is done: counters, then the query moves on with table r.
-__device__ inline void d_finish(const DArgs& A, int qi, DQ& Q, const DTab& r, int64_t m) {
+// The step is done and Q.t already holds the query's new table (tables are
+// updated in place: a copy of the column pointers would go through
+// private memory): counters, then the query moves on.
+__device__ inline void d_step_done(const DArgs& A, int qi, DQ& Q, int64_t m) {
   const DPlanQ& pl = A.pq[qi];
   if (Q.si < pl.nsteps) {
     A.sin[(int64_t)qi * A.ms + Q.si] += Q.n_in;
     A.sout[(int64_t)qi * A.ms + Q.si] += m;
   }
-  Q.t = r;
   Q.rem = Q.next;
   Q.si += 1;
   A.oc[qi] = kONone;
-  if (r.n == 0) {
+  if (Q.t.n == 0) {
     Q.state = kQDone;
     Q.rows = 0;
   } else if (Q.rem == 0) {
-    Q.rows = r.n;
-    if (A.max_rows >= 0 && r.n > A.max_rows) {
+    Q.rows = Q.t.n;
+    if (A.max_rows >= 0 && Q.t.n > A.max_rows) {
       Q.state = kQFailed;
       Q.status = GSMAT_ETOOBIG;
     } else {
@@ -312,19 +309,18 @@ __device__ inline void d_finish(const DArgs& A, int qi, DQ& Q, const DTab& r, in
 }
 
 __device__ inline void d_done_empty(const DArgs& A, int qi, DQ& Q) {
-  DTab r;
-  r.n = 0;
-  r.k = 0;
-  r.slab = -1;
-  d_finish(A, qi, Q, r, 0);
+  Q.t.n = 0;
+  Q.t.k = 0;
+  Q.t.slab = -1;
+  d_step_done(A, qi, Q, 0);
 }
 
-// Relation of pattern tp as a view into the store (a scan step on the unit
-// table); false for the (?x p ?x) diagonal.
+// Relation of pattern tp as a view into the store, written over the query's
+// unit table (a scan step); false, with the table untouched, for the
+// (?x p ?x) diagonal.
 __device__ inline bool d_scan_view(const DArgs& A, int qi, int tp, DTab& r) {
   const DPat p = A.pats[(int64_t)qi * A.mp + tp];
   const LookupRes& lk = A.lk[(int64_t)qi * A.mp + tp];
-  r.slab = -1;
   if (d_isvar(p.s) && d_isvar(p.o)) {
     if (p.s == p.o) return false;
     const PredDesc& d = A.dout[p.p];
@@ -348,6 +344,7 @@ __device__ inline bool d_scan_view(const DArgs& A, int qi, int tp, DTab& r) {
     r.n = lk.found ? 1 : 0;
     r.k = 0;
   }
+  r.slab = -1;
   return true;
 }
 
@@ -367,39 +364,30 @@ __device__ inline void d_apply(const DArgs& A, int qi, DQ& Q) {
     case kODone:
       d_done_empty(A, qi, Q);
       return;
-    case kOPass: {
-      const DTab r = Q.t;
-      d_finish(A, qi, Q, r, Q.m);
+    case kOPass:
+      d_step_done(A, qi, Q, Q.m);
       return;
-    }
-    case kODriver: {
-      DTab r;
-      r.n = Q.m;
-      r.k = 1;
-      r.slab = -1;
-      r.col[0] = A.ct[qi].col;
-      r.var[0] = (int8_t)Q.new_var;
-      d_finish(A, qi, Q, r, Q.m);
+    case kODriver:
+      Q.t.n = Q.m;
+      Q.t.k = 1;
+      Q.t.slab = -1;
+      Q.t.col[0] = A.ct[qi].col;
+      Q.t.var[0] = (int8_t)Q.new_var;
+      d_step_done(A, qi, Q, Q.m);
       return;
-    }
     case kOWrite: {
       const WTask& w = A.wt[qi];
-      DTab r;
-      r.n = Q.m;
-      r.slab = A.ctl->out_slab;  // the host changes it only between groups of rounds
       if (Q.kind == kTaskExpand) {
-        r.k = Q.t.k + 1;
-        for (int c = 0; c < Q.t.k; ++c) r.var[c] = Q.t.var[c];
-        r.var[Q.t.k] = (int8_t)Q.new_var;
-      } else if (Q.kind == kTaskFilter) {
-        r.k = Q.t.k;
-        for (int c = 0; c < Q.t.k; ++c) r.var[c] = Q.t.var[c];
-      } else {
-        r.k = 1;
-        r.var[0] = (int8_t)Q.new_var;
+        Q.t.var[Q.t.k] = (int8_t)Q.new_var;
+        Q.t.k += 1;
+      } else if (Q.kind == kTaskIntersect) {
+        Q.t.k = 1;
+        Q.t.var[0] = (int8_t)Q.new_var;
       }
-      for (int c = 0; c < r.k; ++c) r.col[c] = w.out0 + (int64_t)c * w.ostride;
-      d_finish(A, qi, Q, r, Q.m);
+      Q.t.n = Q.m;
+      Q.t.slab = A.ctl->out_slab;  // the host changes it only between groups of rounds
+      for (int c = 0; c < Q.t.k; ++c) Q.t.col[c] = w.out0 + (int64_t)c * w.ostride;
+      d_step_done(A, qi, Q, Q.m);
       return;
     }
     default:
@@ -492,7 +480,7 @@ __global__ void k_d_choose(DArgs A, int choose) {
       Q.nc = 0;
       Q.sp = sp;
     } else if (Q.nc == 1) {
-      Q.sp = d_pick(pats, Q, nullptr);
+      Q.sp = d_pick(pats, Q, 0);
     } else {
       const int c0 = atomicAdd(&A.ctl->ncand, Q.nc);
       if (c0 + Q.nc > A.nq * A.mp) {
@@ -565,14 +553,19 @@ __global__ void k_d_task(DArgs A) {
   const DPlanQ& pl = A.pq[qi];
   const DPat* pats = A.pats + (int64_t)qi * A.mp;
   if (Q.cand0 >= 0) {
-    int64_t sums[kMaxPats];
+    // the candidate with the smallest sampled fan-out (the first on ties)
+    int best = 0;
+    int64_t best_sum = 0;
     for (int i = 0; i < Q.nc; ++i) {
-      int64_t s = 0;
+      int64_t sum = 0;
       for (int j = 0; j < kSampleBlocks; ++j)
-        s += A.part[(int64_t)(Q.cand0 + i) * kSampleBlocks + j];
-      sums[i] = s;
+        sum += A.part[(int64_t)(Q.cand0 + i) * kSampleBlocks + j];
+      if (i == 0 || sum < best_sum) {
+        best = i;
+        best_sum = sum;
+      }
     }
-    Q.sp = d_pick(pats, Q, sums);
+    Q.sp = d_pick(pats, Q, best);
   }
   const DStep sp = Q.sp;
   Q.next = Q.rem & ~d_completes(pats, pl.np, sp);
@@ -584,12 +577,11 @@ __global__ void k_d_task(DArgs A) {
   switch (sp.kind) {
     case GSMAT_STEP_SCAN:
     case GSMAT_STEP_CARTESIAN: {
-      DTab r;
-      if (!unit || !d_scan_view(A, qi, sp.tp, r)) {
+      if (!unit || !d_scan_view(A, qi, sp.tp, Q.t)) {
         Q.state = kQFallback;
         return;
       }
-      d_finish(A, qi, Q, r, r.n);
+      d_step_done(A, qi, Q, Q.t.n);
       return;
     }
     case GSMAT_STEP_INTERSECT: {
@@ -665,8 +657,7 @@ __global__ void k_d_task(DArgs A) {
     case GSMAT_STEP_FILTER: {
       if (!d_isvar(p.s) && !d_isvar(p.o)) {
         if (A.lk[(int64_t)qi * A.mp + sp.tp].found) {
-          const DTab r = Q.t;
-          d_finish(A, qi, Q, r, r.n);
+          d_step_done(A, qi, Q, Q.t.n);
         } else {
           d_done_empty(A, qi, Q);
         }
@@ -835,7 +826,7 @@ __global__ __launch_bounds__(kBlock) void k_d_count(const CTask* __restrict__ ct
 
 __global__ __launch_bounds__(kScanBlock) void k_d_scan(DArgs A) {
   const DCtl& C = *A.ctl;
-  scan_tile_sums2_block(C.ts, C.tsn, C.ntiles);
+  scan_tile_sums2_block<16>(C.ts, C.tsn, C.ntiles);
 }
 
 // Output bytes of a task's table.
@@ -1017,8 +1008,19 @@ __global__ void k_d_describe(DArgs A) {
   const DQ& Q = A.q[qi];
   const DCtl& C = *A.ctl;
   const CTask& c = A.ct[qi];
-  WTask w{};
+  // fields written one by one (a local descriptor would go through private memory)
+  WTask& w = A.wt[qi];
   const int64_t m = Q.m;
+  w.nbr = nullptr;
+  w.N = nullptr;
+  w.start = nullptr;
+  w.P = nullptr;
+  w.split = nullptr;
+  w.flags = nullptr;
+  w.ridx = nullptr;
+  w.cstart = nullptr;
+  w.start_in = nullptr;
+  w.n_in = 0;
   w.n = c.n;
   w.m = m;
   w.t0 = A.w_cnt[qi];
@@ -1057,7 +1059,6 @@ __global__ void k_d_describe(DArgs A) {
     }
     w.flags = (const uint8_t*)cb;
   }
-  A.wt[qi] = w;
 }
 
 // Row offsets of the dense expansions, rows with output of the sparse ones,

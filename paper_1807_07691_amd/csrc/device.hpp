@@ -99,21 +99,22 @@ __device__ inline int64_t block_sum(int64_t v) {
 // Two tile-sum arrays (neither null) scanned in one pass by one workgroup of kScanBlock
 // threads: exclusive prefix
 // sums in place, the totals at [nt].  One workgroup of 1024 threads walks the
-// arrays in chunks of 8192 sums (8 consecutive per thread); both scans share
+// arrays in chunks of kScanBlock * kPer sums (kPer consecutive per thread); both scans share
 // each chunk's pair of barriers.
 constexpr int kScanBlock = 1024;
+template <int kPer = kItems>
 __device__ inline void scan_tile_sums2_block(int64_t* ts, int64_t* ts2, int64_t nt) {
   constexpr int W = kScanBlock / 64;
   __shared__ int64_t ws[2][W];
   const int lane = lane_id();
   const int wid = wave_id();
   int64_t carry = 0, carry2 = 0;
-  for (int64_t c0 = 0; c0 < nt; c0 += (int64_t)kScanBlock * kItems) {
-    int64_t v[kItems], w[kItems];
+  for (int64_t c0 = 0; c0 < nt; c0 += (int64_t)kScanBlock * kPer) {
+    int64_t v[kPer], w[kPer];
     int64_t loc = 0, loc2 = 0;
 #pragma unroll
-    for (int j = 0; j < kItems; ++j) {
-      const int64_t i = c0 + (int64_t)threadIdx.x * kItems + j;
+    for (int j = 0; j < kPer; ++j) {
+      const int64_t i = c0 + (int64_t)threadIdx.x * kPer + j;
       v[j] = i < nt ? ts[i] : 0;
       w[j] = i < nt ? ts2[i] : 0;
       loc += v[j];
@@ -141,8 +142,8 @@ __device__ inline void scan_tile_sums2_block(int64_t* ts, int64_t* ts2, int64_t 
     int64_t ex = carry + off + inc - loc;
     int64_t ex2 = carry2 + off2 + inc2 - loc2;
 #pragma unroll
-    for (int j = 0; j < kItems; ++j) {
-      const int64_t i = c0 + (int64_t)threadIdx.x * kItems + j;
+    for (int j = 0; j < kPer; ++j) {
+      const int64_t i = c0 + (int64_t)threadIdx.x * kPer + j;
       if (i < nt) {
         ts[i] = ex;
         ts2[i] = ex2;
