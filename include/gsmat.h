@@ -218,6 +218,24 @@ gsmat_status gsmat_plan_batch(const gsmat_store* st, const gsmat_pattern* pats,
 gsmat_status gsmat_join(gsmat_store* st, const gsmat_query_plan* pl, int64_t budget_bytes,
                         int64_t max_rows, void* stream, gsmat_result** out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the
+ * evaluation of gsmat_join (no step budget, no max_rows), with every
+ * intermediate table and every step's scratch kept in a fixed 64 MiB device
+ * array of the library (one per GPU, held until the process ends), and the
+ * result copied into the caller's device buffer: variable v's column at
+ * out + v * out_stride, rows [0, *n_rows), in the row order gsmat_join gives.
+ * No device memory is allocated or freed.  *n_rows always receives the row
+ * count when it is known.  EINVAL for a NULL store, plan or n_rows, a NULL
+ * out with out_cap > 0, out_cap < 0 or out_stride < out_cap; ENOMEM (message
+ * names the limit) when the intermediates and the result do not fit the
+ * 64 MiB array; ETOOBIG when the result has more than out_cap rows.  Calls on
+ * one GPU share its array: they are serialised by a lock, and each call's
+ * device work has ended when it returns. */
+gsmat_status gsmat_join_noalloc(gsmat_store* st, const gsmat_query_plan* pl, int32_t* out,
+                                int64_t out_stride, int64_t out_cap, int64_t* n_rows,
+                                void* stream);
+
 /* Evaluates n_plans plans together (Sec. 7.2's count, prefix sum, exact
  * allocation and write, run as one launch per phase for every query in the
  * batch).  Each query takes the same steps as under gsmat_join and yields

@@ -41,7 +41,7 @@ EXPORTED = [
     "gsmat_dict_load_text", "gsmat_dict_triples", "gsmat_dict_sizes", "gsmat_dict_lookup",
     "gsmat_dict_term", "gsmat_parse_bgp", "gsmat_set_hub_options", "gsmat_set_sparse_expand",
     "gsmat_autotune_batch", "gsmat_expand_strategy", "gsmat_set_batch_engine",
-    "gsmat_set_batch_regions", "gsmat_batch_round_stats",
+    "gsmat_set_batch_regions", "gsmat_batch_round_stats", "gsmat_join_noalloc",
 ]
 
 
@@ -85,6 +85,8 @@ def _load():
     L.gsmat_set_batch_regions.restype = i32
     L.gsmat_set_batch_regions.argtypes = [vp, i64, i64]
     L.gsmat_batch_round_stats.restype = i32
+    L.gsmat_join_noalloc.restype = i32
+    L.gsmat_join_noalloc.argtypes = [vp, vp, vp, i64, i64, vp, vp]
     L.gsmat_batch_round_stats.argtypes = [vp, vp, i32, vp]
     L.gsmat_autotune_batch.restype = i32
     L.gsmat_autotune_batch.argtypes = [vp, vp, i32, i64, vp, vp, vp]
@@ -370,6 +372,21 @@ def gsmat_join(store, plan, budget_bytes=0, max_rows=-1, stream=None):
     _check(_lib.gsmat_join(store.h, plan.h, budget_bytes, max_rows, _stream(stream),
                            ctypes.byref(h)))
     return Result(h, store)
+
+
+def gsmat_join_noalloc(store, plan, out_ptr, out_stride, out_cap, stream=None):
+    """gsmat_join into the caller's device buffer (variable v's column at
+    out_ptr + 4 * v * out_stride bytes) with no device allocation; returns the
+    row count.  Raises GsmatError (its `n_rows` attribute holds the row count
+    when it is known)."""
+    n = ctypes.c_int64(0)
+    rc = _lib.gsmat_join_noalloc(store.h, plan.h, ctypes.c_void_p(int(out_ptr)), int(out_stride),
+                                 int(out_cap), ctypes.byref(n), _stream(stream))
+    if rc != GSMAT_OK:
+        e = GsmatError(rc, _lib.gsmat_last_error().decode(errors="replace"))
+        e.n_rows = int(n.value)
+        raise e
+    return int(n.value)
 
 
 class _Handle:

@@ -13,7 +13,9 @@
 // (chunked expansion); the final table may therefore consist of segments.
 #include <algorithm>
 #include <cstring>
+#include <map>
 #include <memory>
+#include <mutex>
 
 #include "exec.hpp"
 
@@ -47,18 +49,12 @@ struct PinnedArea {
   int64_t part[kMaxPats * kSampleBlocks];
 };
 
+static_assert(sizeof(PinnedArea) <= kStageBytes, "staged results must fit the staging area");
+
 PinnedArea* pinned() {
   thread_local PinnedArea* a = nullptr;
   if (!a) GS_HIP(hipHostMalloc((void**)&a, sizeof(PinnedArea), hipHostMallocDefault));
   return a;
-}
-
-// Scans the tile sums in place and returns the grand total.
-int64_t scan_total(int64_t* ts, int64_t nt, hipStream_t s) {
-  PinnedArea* h = pinned();
-  launch_scan_tile_sums(ts, nt, ts + nt, s, &h->total[0]);
-  host_sync(s);
-  return h->total[0];
 }
 
 struct Exec {
@@ -75,7 +71,35 @@ struct Exec {
   // table allocations not yet released or handed to the result
   std::vector<std::pair<void*, size_t>> live;
 
-  DeviceMem* mem() { return st->mem.get(); }
+  // Device memory of the tables and step scratch (null: the store's), and
+  // where kernels leave small results for the host: null means pinned host
+  // memory; otherwise this device area, copied to the host after the stream
+  // synchronises (the allocation-free entry point uses both).
+  DeviceMem* dm = nullptr;
+  PinnedArea* dev_area = nullptr;
+
+  DeviceMem* mem() { return dm ? dm : st->mem.get(); }
+
+  // Copies `bytes` of the device area at `p` to host memory at `h` (staged
+  // small results) and waits for the stream.
+  void stage_back(void* h, const void* p, size_t bytes) {
+    GS_HIP(hipMemcpyAsync(h, p, bytes, hipMemcpyDeviceToHost, s));
+    host_sync(s);
+  }
+
+  // Scans the tile sums in place and returns the grand total.
+  int64_t scan_total(int64_t* ts, int64_t nt, hipStream_t st_) {
+    if (dev_area) {
+      launch_scan_tile_sums(ts, nt, ts + nt, st_, nullptr);
+      int64_t v = 0;
+      stage_back(&v, ts + nt, sizeof(v));
+      return v;
+    }
+    PinnedArea* h = pinned();
+    launch_scan_tile_sums(ts, nt, ts + nt, st_, &h->total[0]);
+    host_sync(st_);
+    return h->total[0];
+  }
 
   void forget(void* p) {
     for (size_t i = 0; i < live.size(); ++i)
@@ -136,6 +160,13 @@ struct Exec {
     LookupBatch b{};
     b.req[0] = LookupReq{orient, p, v, member};
     b.n = 1;
+    if (dev_area) {
+      launch_lookup(b, st->out.d_desc, st->in.d_desc, st->out.ptrs(), st->in.ptrs(),
+                    dev_area->res, s);
+      LookupRes r;
+      stage_back(&r, dev_area->res, sizeof(r));
+      return r;
+    }
     PinnedArea* h = pinned();
     launch_lookup(b, st->out.d_desc, st->in.d_desc, st->out.ptrs(), st->in.ptrs(), h->res, s);
     host_sync(s);
@@ -240,13 +271,20 @@ struct Exec {
     for (int i = 0; i < c.nc; ++i) candidate_view(st, pl, t, c, i, &ss.col[i], &ss.pv[i]);
     ss.n = t.n;
     ss.ncand = c.nc;
-    PinnedArea* h = pinned();
-    launch_sample_fanout(ss, h->part, s);
-    sync_stream();
+    int64_t part[kMaxPats * kSampleBlocks];
+    if (dev_area) {
+      launch_sample_fanout(ss, dev_area->part, s);
+      stage_back(part, dev_area->part, sizeof(int64_t) * c.nc * kSampleBlocks);
+    } else {
+      PinnedArea* h = pinned();
+      launch_sample_fanout(ss, h->part, s);
+      sync_stream();
+      std::copy(h->part, h->part + c.nc * kSampleBlocks, part);
+    }
     int64_t sum[kMaxPats];
     for (int i = 0; i < c.nc; ++i) {
       sum[i] = 0;
-      for (int b = 0; b < kSampleBlocks; ++b) sum[i] += h->part[i * kSampleBlocks + b];
+      for (int b = 0; b < kSampleBlocks; ++b) sum[i] += part[i * kSampleBlocks + b];
     }
     return step_pick(pl, c, sum);
   }
@@ -591,14 +629,16 @@ gsmat_step_info step_pick(const gsmat_query_plan* pl, const StepChoice& c, const
 }
 
 void run_query(gsmat_store* st, const gsmat_query_plan* pl, int64_t budget_bytes,
-               int64_t max_rows, hipStream_t s, gsmat_result* res) {
+               int64_t max_rows, hipStream_t s, gsmat_result* res, DeviceMem* mem,
+               void* dev_area) {
   // a pattern over an absent predicate or vertex matches nothing
   for (const gsmat_pattern& q : pl->pats) {
     if (q.p >= st->P) return;
     if (!is_var(q.s) && q.s >= st->V) return;
     if (!is_var(q.o) && q.o >= st->V) return;
   }
-  Exec ex{st, pl, s, budget_bytes, max_rows, res, pl->mode == GSMAT_PLAN_ADAPTIVE, {}};
+  Exec ex{st, pl, s, budget_bytes, max_rows, res, pl->mode == GSMAT_PLAN_ADAPTIVE, {},
+          mem, (PinnedArea*)dev_area};
   Table unit;
   unit.n = 1;
   unit.k = 0;
@@ -710,6 +750,155 @@ extern "C" gsmat_status gsmat_join(gsmat_store* st, const gsmat_query_plan* pl, 
     run_query(st, pl, budget_bytes, max_rows, s, res.get());
     GS_HIP(hipStreamSynchronize(s));
     *out = res.release();
+    return GSMAT_OK;
+  });
+}
+
+// ---------------------------------------------------------- allocation-free join
+//
+// gsmat_join_noalloc keeps every intermediate table and every step's scratch
+// in one file-scope device array of kNoAllocBytes (each GPU the library runs
+// on has its own copy, held until the process ends).  Host code never uses
+// the array's name as a device address: the address comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+
+namespace {
+
+constexpr size_t kNoAllocBytes = (size_t)64 << 20;
+static __device__ __align__(256) char scratch[kNoAllocBytes];
+
+struct NoAllocDevice {
+  std::mutex mu;          // serialises the calls on this device
+  char* base = nullptr;   // the array's device address
+};
+
+NoAllocDevice* noalloc_device(int dev) {
+  static std::mutex mu;
+  static std::map<int, NoAllocDevice*> devs;
+  std::lock_guard<std::mutex> g(mu);
+  NoAllocDevice*& d = devs[dev];
+  if (!d) {
+    std::unique_ptr<NoAllocDevice> nd(new NoAllocDevice);
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      throw StatusFail{GSMAT_EHIP, std::string("no-alloc scratch: hipGetSymbolAddress failed: ") +
+                                       hipGetErrorString(e)};
+    nd->base = (char*)p;
+    d = nd.release();
+  }
+  return d;
+}
+
+// Stack allocator over the array: blocks come off the top; a free marks its
+// block, and the top drops past every freed block at the top (the executor
+// frees in nearly reverse order).  The first kStageBytes hold the staged
+// small results.
+struct ScratchStack {
+  char* base = nullptr;
+  size_t top = kStageBytes;
+  size_t want = 0;  // largest request that did not fit
+  std::vector<size_t> off, len;
+  std::vector<char> freed;
+
+  void* alloc(size_t bytes) {
+    const size_t b = (std::max<size_t>(bytes, 1) + 255) / 256 * 256;
+    if (b > kNoAllocBytes - top) {
+      want = std::max(want, b);
+      return nullptr;
+    }
+    off.push_back(top);
+    len.push_back(b);
+    freed.push_back(0);
+    void* p = base + top;
+    top += b;
+    return p;
+  }
+  void free(void* p) {
+    const size_t o = (size_t)((char*)p - base);
+    for (size_t i = off.size(); i-- > 0;)
+      if (off[i] == o && !freed[i]) {
+        freed[i] = 1;
+        break;
+      }
+    while (!off.empty() && freed.back()) {
+      top = off.back();
+      off.pop_back();
+      len.pop_back();
+      freed.pop_back();
+    }
+  }
+  static void* alloc_cb(size_t bytes, void* stream, void* ctx) {
+    (void)stream;
+    return ((ScratchStack*)ctx)->alloc(bytes);
+  }
+  static void free_cb(void* p, size_t bytes, void* stream, void* ctx) {
+    (void)bytes;
+    (void)stream;
+    ((ScratchStack*)ctx)->free(p);
+  }
+};
+
+}  // namespace
+
+extern "C" gsmat_status gsmat_join_noalloc(gsmat_store* st, const gsmat_query_plan* pl,
+                                           int32_t* out, int64_t out_stride, int64_t out_cap,
+                                           int64_t* n_rows, void* stream) {
+  return guarded([&]() -> gsmat_status {
+    if (!st || !pl || !n_rows) throw StatusFail{GSMAT_EINVAL, "store, plan or n_rows is NULL"};
+    *n_rows = 0;
+    if (!st->built) throw StatusFail{GSMAT_ESTATE, "index not built"};
+    if (out_cap < 0 || out_stride < out_cap)
+      throw StatusFail{GSMAT_EINVAL, "out_cap must be >= 0 and out_stride >= out_cap"};
+    if (!out && out_cap > 0 && pl->n_vars > 0) throw StatusFail{GSMAT_EINVAL, "out is NULL"};
+    hipStream_t s = (hipStream_t)stream;
+    int dev = 0;
+    GS_HIP(hipGetDevice(&dev));
+    NoAllocDevice* nd = noalloc_device(dev);
+    std::lock_guard<std::mutex> lock(nd->mu);
+    ScratchStack stack;
+    stack.base = nd->base;
+    const gsmat_allocator a{&ScratchStack::alloc_cb, &ScratchStack::free_cb, &stack};
+    DeviceMem mem(&a);
+    gsmat_result res;
+    res.st = st;
+    res.stream = s;
+    res.n_vars = pl->n_vars;
+    res.reset_steps(pl->steps.size());
+    struct Drop {  // the segments live in the array: nothing to free
+      gsmat_result& r;
+      ~Drop() {
+        for (Segment& g : r.segs) g.owned = nullptr;
+      }
+    } drop{res};
+    try {
+      run_query(st, pl, 0, -1, s, &res, &mem, nd->base);
+    } catch (const OomFail&) {
+      (void)hipStreamSynchronize(s);  // nothing may still use the array
+      throw StatusFail{GSMAT_ENOMEM,
+                       "the join needs more than the " + std::to_string(kNoAllocBytes >> 20) +
+                           " MiB of the allocation-free scratch (a block of " +
+                           std::to_string(stack.want) + " bytes did not fit)"};
+    } catch (...) {
+      (void)hipStreamSynchronize(s);
+      throw;
+    }
+    *n_rows = res.rows;
+    if (res.rows > out_cap) {
+      host_sync(s);
+      throw StatusFail{GSMAT_ETOOBIG, "result has " + std::to_string(res.rows) +
+                                          " rows, more than out_cap (" + std::to_string(out_cap) +
+                                          ")"};
+    }
+    int64_t at = 0;
+    for (const Segment& g : res.segs) {
+      for (int v = 0; v < pl->n_vars && g.rows > 0; ++v)
+        GS_HIP(hipMemcpyAsync(out + (int64_t)v * out_stride + at, g.col[v],
+                              sizeof(int32_t) * (size_t)g.rows, hipMemcpyDeviceToDevice, s));
+      at += g.rows;
+    }
+    // the array is reused by the next call: its work ends before this returns
+    host_sync(s);
     return GSMAT_OK;
   });
 }

@@ -81,9 +81,14 @@ void candidate_view(const gsmat_store* st, const gsmat_query_plan* pl, const Tab
 // on ties); sums may be null when nc == 1.
 gsmat_step_info step_pick(const gsmat_query_plan* pl, const StepChoice& c, const int64_t* sums);
 
-// Runs one plan with the single-query executor, adding to res.
+// Runs one plan with the single-query executor, adding to res.  mem (null:
+// the store's allocator) provides the tables and step scratch; dev_area
+// (null: pinned host memory) is a device area of at least kStageBytes where
+// kernels leave the small results the host reads.
+constexpr size_t kStageBytes = 4096;
 void run_query(gsmat_store* st, const gsmat_query_plan* pl, int64_t budget_bytes,
-               int64_t max_rows, hipStream_t s, gsmat_result* res);
+               int64_t max_rows, hipStream_t s, gsmat_result* res, DeviceMem* mem = nullptr,
+               void* dev_area = nullptr);
 
 // Per-pattern statistics for the planner; lookups of constant endpoints go
 // to the device in one batch.
