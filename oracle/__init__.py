@@ -31,7 +31,8 @@ _SRC = os.path.join(_HERE, "oracle.cpp")
 def build(force: bool = True) -> str:
     if force or not os.path.exists(_SO):
         tmp = _SO + ".tmp"
-        subprocess.check_call(["g++", "-O2", "-std=c++17", "-shared", "-fPIC", _SRC, "-o", tmp])
+        subprocess.check_call(["g++", "-O2", "-std=c++17", "-fopenmp", "-shared", "-fPIC", _SRC,
+                               "-o", tmp])
         os.replace(tmp, _SO)
     return _SO
 
@@ -69,6 +70,8 @@ def lib():
         L.oracle_dataset_free.argtypes = [vp]
         L.oracle_join_dataset.restype = vp
         L.oracle_join_dataset.argtypes = [vp, vp, i32, i32, i64]
+        L.oracle_join_dataset_omp.restype = vp
+        L.oracle_join_dataset_omp.argtypes = [vp, vp, i32, i32, i64, i32]
         _lib = L
     return _lib
 
@@ -123,6 +126,13 @@ class Dataset:
         t = _i32(np.asarray(tps).reshape(-1, 3))
         h = lib().oracle_join_dataset(self.h, _p(t), len(t), n_vars, cap_rows)
         return _collect(h, n_vars, fingerprint, partition)
+
+    def join_omp(self, tps, n_vars, threads, cap_rows=-1, fingerprint=False):
+        """The same answer evaluated on `threads` host threads (the CPU
+        baseline's multi-core form)."""
+        t = _i32(np.asarray(tps).reshape(-1, 3))
+        h = lib().oracle_join_dataset_omp(self.h, _p(t), len(t), n_vars, cap_rows, int(threads))
+        return _collect(h, n_vars, fingerprint)
 
 
 def _collect(h, n_vars, fingerprint, partition=None):

@@ -30,9 +30,23 @@
 // Pattern encoding: endpoint >= 0 is a vertex constant; endpoint < 0 is the
 // variable -(x+1).  The predicate is always a constant (Sec. 6.3 assumes a
 // known predicate).
+//
+// A second evaluation of the same definition runs on every host core
+// (OpenMP), for the benchmark's CPU baseline: the same join order, each
+// pattern's relation gathered by a parallel scan of D, each later relation
+// keyed on its shared variables once (pairs of key and row, sorted in
+// parallel, probed by binary search), the first relation's rows split into
+// one contiguous range per thread, each range carried through all later
+// joins, and a parallel sort of the rows.  Its output equals the
+// single-threaded evaluation's (tested).
+#include <omp.h>
+
 #include <algorithm>
+#include <atomic>
 #include <cstdint>
 #include <cstring>
+#include <memory>
+#include <parallel/algorithm>
 #include <unordered_map>
 #include <vector>
 
@@ -162,6 +176,47 @@ inline uint64_t mix64(uint64_t z) {
   return z;
 }
 
+// R_i gathered by a parallel scan of D: threads take contiguous ranges of D
+// and their rows are concatenated in range order, so the relation equals
+// tp_relation's.
+Relation tp_relation_par(const std::vector<Triple>& D, int32_t ts, int32_t tp, int32_t to,
+                         int threads) {
+  Relation r;
+  const bool sv = ts < 0, ov = to < 0;
+  const int32_t xs = sv ? -ts - 1 : -1, xo = ov ? -to - 1 : -1;
+  const bool two = ov && !(sv && xo == xs);
+  if (sv) r.vars.push_back(xs);
+  if (two) r.vars.push_back(xo);
+  const int64_t n = (int64_t)D.size();
+  std::vector<std::vector<int32_t>> part(threads);
+#pragma omp parallel num_threads(threads)
+  {
+    const int t = omp_get_thread_num();
+    const int64_t a = n * t / threads, b = n * (t + 1) / threads;
+    std::vector<int32_t>& v = part[t];
+    for (int64_t i = a; i < b; ++i) {
+      const Triple& x = D[i];
+      if (x.p != tp) continue;
+      if (!sv && x.s != ts) continue;
+      if (!ov && x.o != to) continue;
+      if (sv && ov && xs == xo && x.s != x.o) continue;
+      if (sv) v.push_back(x.s);
+      if (two) v.push_back(x.o);
+    }
+  }
+  const size_t w = r.vars.size();
+  for (auto& v : part) {
+    r.vals.insert(r.vals.end(), v.begin(), v.end());
+    r.rows += w ? (int64_t)(v.size() / w) : 0;
+  }
+  if (w == 0) {  // all-constant pattern: one empty row per matching triple
+    int64_t m = 0;
+    for (const Triple& x : D) m += x.p == tp && x.s == ts && x.o == to;
+    r.rows = m;
+  }
+  return r;
+}
+
 }  // namespace
 
 extern "C" {
@@ -226,6 +281,123 @@ void* oracle_join_dataset(void* ds, const int32_t* tps, int32_t ntp, int32_t nva
                           int64_t cap_rows) {
   if (!ds || ntp < 0 || nvars < 0) return nullptr;
   return join_impl(*static_cast<std::vector<Triple>*>(ds), tps, ntp, nvars, cap_rows);
+}
+
+// The same evaluation on `threads` host threads (see the file comment).
+void* oracle_join_dataset_omp(void* ds, const int32_t* tps, int32_t ntp, int32_t nvars,
+                              int64_t cap_rows, int32_t threads) {
+  if (!ds || ntp <= 0 || nvars < 0 || threads < 1) return nullptr;
+  const std::vector<Triple>& D = *static_cast<std::vector<Triple>*>(ds);
+  std::vector<int> order = join_order(tps, ntp, nvars);
+  std::vector<Relation> rel(ntp);
+  for (int j = 0; j < ntp; ++j) {
+    const int t = order[j];
+    rel[j] = tp_relation_par(D, tps[3 * t], tps[3 * t + 1], tps[3 * t + 2], threads);
+  }
+  // the schema after each join, and per later relation its shared and new
+  // columns and a hash table on the shared ones
+  std::vector<std::vector<int>> a_shared(ntp), b_shared(ntp), b_new(ntp);
+  std::vector<int32_t> vars = rel[0].vars;
+  // per later relation: (key of its shared columns, row), sorted in parallel
+  std::vector<std::vector<std::pair<uint64_t, int64_t>>> keyed(ntp);
+  for (int j = 1; j < ntp; ++j) {
+    const Relation& b = rel[j];
+    for (size_t c = 0; c < b.vars.size(); ++c) {
+      auto it = std::find(vars.begin(), vars.end(), b.vars[c]);
+      if (it != vars.end()) {
+        a_shared[j].push_back((int)(it - vars.begin()));
+        b_shared[j].push_back((int)c);
+      } else {
+        b_new[j].push_back((int)c);
+      }
+    }
+    for (int c : b_new[j]) vars.push_back(b.vars[c]);
+    if (!b_shared[j].empty()) {
+      const size_t wb = b.vars.size();
+      std::vector<std::pair<uint64_t, int64_t>>& kv = keyed[j];
+      kv.resize((size_t)b.rows);
+#pragma omp parallel for num_threads(threads)
+      for (int64_t r = 0; r < b.rows; ++r) kv[r] = {pack_key(&b.vals[r * wb], b_shared[j]), r};
+      __gnu_parallel::sort(kv.begin(), kv.end());
+    }
+  }
+  if ((int32_t)vars.size() != nvars) return nullptr;
+  // the first relation's rows in one contiguous range per thread, each
+  // carried through every later join
+  const int64_t n0 = rel[0].rows;
+  if (cap_rows >= 0 && n0 > cap_rows) return nullptr;
+  const size_t w0 = rel[0].vars.size();
+  std::vector<Relation> out(threads);
+  std::atomic<int64_t> total{0};
+  std::atomic<bool> over{false};
+  // rows after each join, summed over the threads (an intermediate above the
+  // cap stops the evaluation, as in the single-threaded one)
+  std::unique_ptr<std::atomic<int64_t>[]> step_rows(new std::atomic<int64_t>[ntp]);
+  for (int j = 0; j < ntp; ++j) step_rows[j] = 0;
+#pragma omp parallel num_threads(threads)
+  {
+    const int t = omp_get_thread_num();
+    Relation cur;
+    cur.vars = rel[0].vars;
+    const int64_t a = n0 * t / threads, b = n0 * (t + 1) / threads;
+    cur.rows = b - a;
+    if (w0) cur.vals.assign(rel[0].vals.begin() + a * w0, rel[0].vals.begin() + b * w0);
+    for (int j = 1; j < ntp && !over.load(); ++j) {
+      const Relation& r = rel[j];
+      const size_t wa = cur.vars.size(), wb = r.vars.size();
+      Relation nx;
+      nx.vars = cur.vars;
+      for (int c : b_new[j]) nx.vars.push_back(r.vars[c]);
+      int64_t counted = 0;  // rows of this step already added to step_rows[j]
+      for (int64_t i = 0; i < cur.rows && !over.load(); ++i) {
+        auto emit = [&](int64_t k) {
+          for (size_t c = 0; c < wa; ++c) nx.vals.push_back(cur.vals[i * wa + c]);
+          for (int c : b_new[j]) nx.vals.push_back(r.vals[k * wb + c]);
+          ++nx.rows;
+        };
+        if (b_shared[j].empty()) {
+          for (int64_t k = 0; k < r.rows; ++k) emit(k);
+        } else {
+          const uint64_t key = pack_key(&cur.vals[i * wa], a_shared[j]);
+          const auto& kv = keyed[j];
+          auto it = std::lower_bound(kv.begin(), kv.end(), std::make_pair(key, (int64_t)INT64_MIN));
+          for (; it != kv.end() && it->first == key; ++it) emit(it->second);
+        }
+        if (cap_rows >= 0 && nx.rows - counted >= 65536) {  // the threads' running total
+          if ((step_rows[j] += nx.rows - counted) > cap_rows) over.store(true);
+          counted = nx.rows;
+        }
+      }
+      if (cap_rows >= 0 && (step_rows[j] += nx.rows - counted) > cap_rows) over.store(true);
+      cur = std::move(nx);
+    }
+    total += cur.rows;
+    out[t] = std::move(cur);
+  }
+  const int64_t rows = total.load();
+  if (over.load() || (cap_rows >= 0 && rows > cap_rows)) return nullptr;
+  Result* res = new Result;
+  res->nvars = nvars;
+  res->rows = rows;
+  std::vector<int> col_of(nvars);
+  for (int c = 0; c < nvars; ++c) col_of[vars[c]] = c;
+  std::vector<int32_t> perm((size_t)rows * nvars);
+  int64_t at = 0;
+  for (const Relation& r : out) {
+    for (int64_t i = 0; i < r.rows; ++i, ++at)
+      for (int x = 0; x < nvars; ++x) perm[at * nvars + x] = r.vals[i * nvars + col_of[x]];
+  }
+  std::vector<int64_t> idx(rows);
+  for (int64_t i = 0; i < rows; ++i) idx[i] = i;
+  __gnu_parallel::sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) {
+    return std::lexicographical_compare(&perm[a * nvars], &perm[a * nvars] + nvars,
+                                        &perm[b * nvars], &perm[b * nvars] + nvars);
+  });
+  res->vals.resize((size_t)rows * nvars);
+#pragma omp parallel for num_threads(threads)
+  for (int64_t i = 0; i < rows; ++i)
+    for (int x = 0; x < nvars; ++x) res->vals[i * nvars + x] = perm[idx[i] * nvars + x];
+  return res;
 }
 
 static void* join_impl(const std::vector<Triple>& D, const int32_t* tps, int32_t ntp,

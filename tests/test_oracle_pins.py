@@ -202,6 +202,36 @@ def test_oracle_shapes_brute_force(shape):
         assert got.shape == (1, 0)
 
 
+@pytest.mark.parametrize("seed", range(12))
+def test_multicore_oracle_equals_single_thread(seed):
+    """The OpenMP evaluation (the CPU baseline's multi-core form) gives the
+    single-threaded oracle's rows, on brute-force-sized toys and on larger
+    random graphs, every shape, and any thread count; an intermediate above
+    the row cap is refused by both."""
+    rng = np.random.default_rng(3000 + seed)
+    if seed < 6:
+        V, P, n = int(rng.integers(3, 8)), int(rng.integers(1, 4)), int(rng.integers(5, 40))
+    else:
+        V, P, n = int(rng.integers(50, 400)), int(rng.integers(1, 5)), int(rng.integers(500, 8000))
+    s, p, o = _random_graph(rng, V, P, n)
+    ds = O.Dataset(s, p, o)
+    cases = [_random_bgp(rng, V, P, int(rng.integers(1, 5)), int(rng.integers(1, 5)))
+             for _ in range(6)] + list(SHAPES.values())
+    for tps, nv in cases:
+        try:
+            want = ds.join(tps, nv, cap_rows=200_000)
+        except ValueError:
+            want = None
+        for threads in (1, 2, 7):
+            if want is None:
+                with pytest.raises(ValueError):
+                    ds.join_omp(tps, nv, threads, cap_rows=200_000)
+            else:
+                got = ds.join_omp(tps, nv, threads, cap_rows=200_000)
+                assert got.tolist() == want.tolist(), (tps, nv, threads)
+    ds.close()
+
+
 def test_set_semantics_duplicates_removed():
     rng = np.random.default_rng(3)
     s, p, o = _random_graph(rng, 5, 2, 30)
