@@ -382,8 +382,11 @@ gsmat_status gsmat_parse_bgp(const gsmat_dict* d, const char* text, size_t len,
  * planning lookups, each later expansion multiplying it by the mean row
  * length of its predicate, capped by the Theorem 1 bound (Sec. 6.2).  Each
  * gsmat_server_step admits what fits and runs one step of every admitted
- * query as one batched round (as in gsmat_join_batch), so queries that
- * arrive while others run join them at the next round.  A round whose
+ * query as one batched round (as in gsmat_join_batch with host-driven
+ * rounds), so queries that arrive while others run join them at the next
+ * round; a query alone in the server that has not started, with nothing
+ * waiting, is instead run to completion by the single-query executor within
+ * that step (later arrivals are admitted together afterwards).  A round whose
  * outputs would exceed mem_budget_bytes defers the later queries' steps to
  * the next round (the first always runs).  step_budget_bytes and max_rows
  * apply per query as in gsmat_join (a step above step_budget_bytes finishes

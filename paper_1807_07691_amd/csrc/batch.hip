@@ -94,6 +94,16 @@ std::vector<LookupRes> lookup_many(const gsmat_store* st, const std::vector<Look
   std::vector<LookupRes> out(req.size());
   if (req.empty()) return out;
   const size_t n = req.size();
+  if (n <= (size_t)kMaxLookups) {  // few requests: passed by value, no upload
+    LookupBatch b{};
+    for (size_t i = 0; i < n; ++i) b.req[i] = req[i];
+    b.n = (int32_t)n;
+    LookupRes* hres = (LookupRes*)pins()[kPinTotals].get(sizeof(LookupRes) * n);
+    launch_lookup(b, st->out.d_desc, st->in.d_desc, st->out.ptrs(), st->in.ptrs(), hres, s);
+    host_sync(s);
+    std::memcpy(out.data(), hres, sizeof(LookupRes) * n);
+    return out;
+  }
   Layout L;
   const size_t o_req = L.add(sizeof(LookupReq) * n);
   Arena a(st->mem.get(), L.bytes, s);
@@ -1051,8 +1061,23 @@ extern "C" gsmat_status gsmat_server_step(gsmat_server* sv, int32_t* n_active, i
     sv->admit();
     sv->bt.sparse_theta = sv->st->sparse_theta;
     sv->bt.sparse_min_rows = sv->st->sparse_min_rows;
-    bool any = false;
-    for (const BQ& b : sv->bt.q) any |= b.state == kActive;
+    int active = 0;
+    BQ* only = nullptr;
+    for (BQ& b : sv->bt.q)
+      if (b.state == kActive) {
+        ++active;
+        only = &b;
+      }
+    // A query alone in the server (nothing else active or waiting, not
+    // started) runs to completion with the single-query executor: a round of
+    // the batch would only add its host bookkeeping and a second wait per
+    // step.  Queries arriving meanwhile are admitted together afterwards.
+    if (active == 1 && sv->waiting.empty() && only->si == 0 && only->t.unit()) {
+      only->state = kFallback;
+      only->t = Table();
+      active = 0;
+    }
+    const bool any = active > 0;
     if (any) {
       // a round that fails part-way (device allocation, HIP error) has
       // already counted rows of its steps: the queries it carried fail with
