@@ -826,7 +826,7 @@ __global__ __launch_bounds__(kBlock) void k_d_count(const CTask* __restrict__ ct
 
 __global__ __launch_bounds__(kScanBlock) void k_d_scan(DArgs A) {
   const DCtl& C = *A.ctl;
-  scan_tile_sums2_block<16>(C.ts, C.tsn, C.ntiles);
+  scan_tile_sums2_block(C.ts, C.tsn, C.ntiles);
 }
 
 // Output bytes of a task's table.
