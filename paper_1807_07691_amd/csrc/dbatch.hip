@@ -1347,6 +1347,7 @@ void run_batch_device(gsmat_store* st, const gsmat_query_plan* const* plans, int
     return (unsigned)std::min<int64_t>(std::max<int64_t>(t + t / 8, floor_), 1 << 22);
   };
   int64_t out_total = 0;
+  std::vector<std::unique_ptr<gsmat_result>> made;
   int gr = 0;  // rounds launched so far
   for (int iter = 0;; ++iter) {
     for (int r = 0; r < rounds; ++r, ++gr) {
@@ -1370,6 +1371,19 @@ void run_batch_device(gsmat_store* st, const gsmat_query_plan* const* plans, int
     // the summary, and the results in case every query has finished
     GS_HIP(hipMemcpyAsync(hc, A.ctl, sizeof(DCtl), hipMemcpyDeviceToHost, s));
     GS_HIP(hipMemcpyAsync(hb, dv + o_res, back_bytes, hipMemcpyDeviceToHost, s));
+    if (iter == 0) {
+      // while the device runs: the result objects, filled after the wait
+      made.resize(nq);
+      for (int i = 0; i < nq; ++i) {
+        gsmat_result* r = new gsmat_result;
+        made[i].reset(r);
+        r->st = st;
+        r->stream = s;
+        r->n_vars = plans[i]->n_vars;
+        r->reset_steps(plans[i]->steps.size());
+        r->segs.reserve(1);
+      }
+    }
     host_sync(s);
     if (hc->error) throw StatusFail{GSMAT_EHIP, "internal: batched join state inconsistent"};
     if (hc->active == 0 || iter >= 16) break;
@@ -1423,11 +1437,7 @@ void run_batch_device(gsmat_store* st, const gsmat_query_plan* const* plans, int
       continue;
     }
     const gsmat_query_plan* pl = plans[i];
-    std::unique_ptr<gsmat_result> res(new gsmat_result);
-    res->st = st;
-    res->stream = s;
-    res->n_vars = pl->n_vars;
-    res->reset_steps(pl->steps.size());
+    std::unique_ptr<gsmat_result>& res = made[i];
     for (size_t j = 0; j < pl->steps.size(); ++j) {
       res->step_in[j] = hsin[(size_t)i * ms + j];
       res->step_out[j] = hsout[(size_t)i * ms + j];

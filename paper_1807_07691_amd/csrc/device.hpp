@@ -619,58 +619,66 @@ __device__ inline int64_t mp_split(const int64_t* __restrict__ P, int64_t n, int
 // The write loop is laid out for the memory system: output columns start on
 // 256-byte boundaries and the loop is shifted by the tile's offset modulo 64,
 // so every wave store covers whole 128-byte lines (unaligned tile starts
-// halved the store bandwidth); each thread handles two outputs per iteration
-// and issues all their loads (neighbour ids, K parent values) before any
-// store.  K is a compile-time column count (-1: any count, in groups of 4).
+// halved the store bandwidth); each thread handles U outputs per iteration
+// (four for up to three parent columns, else two) and issues all their loads
+// (neighbour ids, K parent values) before any store.  K is a compile-time
+// column count (-1: any count, in groups of 4).
 template <int K, class Out>
 __device__ inline void write_outputs(const ColSet& in, int kdyn, const int32_t* __restrict__ nbr,
                                      const uint16_t* sRow, const int32_t* sRb,
                                      const int32_t* sIdx, int64_t a0, int64_t ob, int nbt,
                                      const Out& out) {
+  constexpr int U = (K >= 0 && K <= 3) ? 4 : 2;
   const int k = K >= 0 ? K : kdyn;
   const int al = (int)(ob & 63);
   const int span = nbt + al;
-  for (int q = threadIdx.x; q < span; q += 2 * kBlock) {
-    const int o1 = q - al, o2 = q + kBlock - al;
-    const bool ok1 = o1 >= 0 && o1 < nbt, ok2 = o2 >= 0 && o2 < nbt;
-    const int r1 = ok1 ? sRow[o1] : 0, r2 = ok2 ? sRow[o2] : 0;
-    const int32_t v1 = ok1 ? nbr[sRb[r1] + o1] : 0;
-    const int32_t v2 = ok2 ? nbr[sRb[r2] + o2] : 0;
-    // parent rows: consecutive, or (compacted rows) their original indices
-    const int64_t row1 = sIdx ? (int64_t)sIdx[r1] : a0 + r1;
-    const int64_t row2 = sIdx ? (int64_t)sIdx[r2] : a0 + r2;
+  for (int q = threadIdx.x; q < span; q += U * kBlock) {
+    int o[U];
+    bool ok[U];
+    int r[U];
+    int32_t v[U];
+    int64_t row[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      o[u] = q + u * kBlock - al;
+      ok[u] = o[u] >= 0 && o[u] < nbt;
+      r[u] = ok[u] ? sRow[o[u]] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      v[u] = ok[u] ? nbr[sRb[r[u]] + o[u]] : 0;
+      // parent rows: consecutive, or (compacted rows) their original indices
+      row[u] = sIdx ? (int64_t)sIdx[r[u]] : a0 + r[u];
+    }
     if (K >= 0) {
-      int32_t x1[K > 0 ? K : 1], x2[K > 0 ? K : 1];
+      int32_t x[U][K > 0 ? K : 1];
 #pragma unroll
-      for (int c = 0; c < K; ++c) {
-        x1[c] = ok1 ? in.c[c][row1] : 0;
-        x2[c] = ok2 ? in.c[c][row2] : 0;
-      }
-      if (ok1) {
+      for (int u = 0; u < U; ++u)
 #pragma unroll
-        for (int c = 0; c < K; ++c) __builtin_nontemporal_store(x1[c], &out(c)[ob + o1]);
-      }
-      if (ok2) {
+        for (int c = 0; c < K; ++c) x[u][c] = ok[u] ? in.c[c][row[u]] : 0;
 #pragma unroll
-        for (int c = 0; c < K; ++c) __builtin_nontemporal_store(x2[c], &out(c)[ob + o2]);
-      }
+      for (int u = 0; u < U; ++u)
+        if (ok[u]) {
+#pragma unroll
+          for (int c = 0; c < K; ++c) __builtin_nontemporal_store(x[u][c], &out(c)[ob + o[u]]);
+        }
     } else {
       for (int c0 = 0; c0 < k; c0 += 4) {
-        int32_t x1[4], x2[4];
+        int32_t x[U][4];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          x1[c] = (ok1 && c0 + c < k) ? in.c[c0 + c][row1] : 0;
-          x2[c] = (ok2 && c0 + c < k) ? in.c[c0 + c][row2] : 0;
-        }
+        for (int u = 0; u < U; ++u)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          if (ok1 && c0 + c < k) __builtin_nontemporal_store(x1[c], &out(c0 + c)[ob + o1]);
-          if (ok2 && c0 + c < k) __builtin_nontemporal_store(x2[c], &out(c0 + c)[ob + o2]);
-        }
+          for (int c = 0; c < 4; ++c) x[u][c] = (ok[u] && c0 + c < k) ? in.c[c0 + c][row[u]] : 0;
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+          for (int c = 0; c < 4; ++c)
+            if (ok[u] && c0 + c < k) __builtin_nontemporal_store(x[u][c], &out(c0 + c)[ob + o[u]]);
       }
     }
-    if (ok1) __builtin_nontemporal_store(v1, &out(k)[ob + o1]);
-    if (ok2) __builtin_nontemporal_store(v2, &out(k)[ob + o2]);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (ok[u]) __builtin_nontemporal_store(v[u], &out(k)[ob + o[u]]);
   }
 }
 
