@@ -117,6 +117,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sparse-theta", type=float, default=-1.0,
                     help="batch workload: sparse-expansion threshold (< 0: autotune)")
+    ap.add_argument("--count-items", type=int, choices=(4, 8, 16), default=0,
+                    help="batch workload: force the count rows per thread (after any autotuning)")
+    ap.add_argument("--intersect", choices=("search", "window", "merge"), default=None,
+                    help="batch workload: force the intersection strategy (after any autotuning)")
     ap.add_argument("--dense-div", type=int, default=256,
                     help="index build: predicates with at least V/dense_div non-empty rows get a "
                          "dense row pointer (0: the library default, 32)")
@@ -486,12 +490,19 @@ def bench_batch(args, G, W, spec, qspec, queries, st, sh, budget, mode, stats, l
     # ---- autotuning (setup, untimed): the sparse-expansion threshold
     if args.sparse_theta < 0:
         plans, _ = G.gsmat_plan_batch(st, packed, mode, stream=sh, as_set=True)
-        theta, tune_ms = G.gsmat_autotune_batch(st, plans, budget, stream=sh)
+        tune = G.gsmat_autotune_batch(st, plans, budget, stream=sh)
         plans.close()
-        log(f"autotune: theta={theta} ms per candidate {tune_ms}")
+        log(f"autotune: {tune}")
     else:
-        theta, tune_ms = args.sparse_theta, {}
-        G.gsmat_set_sparse_expand(st, theta)
+        G.gsmat_set_sparse_expand(st, args.sparse_theta)
+        tune = dict(G.gsmat_get_batch_tuning(st), candidate_ms=None)
+    if args.count_items or args.intersect:
+        cur = G.gsmat_get_batch_tuning(st)
+        G.gsmat_set_batch_tuning(st, args.count_items or cur["count_items"],
+                                 G.ISECT_NAMES.index(args.intersect or cur["intersect"]))
+        tune = dict(G.gsmat_get_batch_tuning(st), candidate_ms=tune["candidate_ms"],
+                    forced={"count_items": args.count_items, "intersect": args.intersect})
+    theta = tune["sparse_theta"]
 
     # ---- batched: warmup (diagnostics, count and row checks), then timed
     log(f"batched warmup x{max(1, args.warmup)}")
@@ -623,8 +634,7 @@ def bench_batch(args, G, W, spec, qspec, queries, st, sh, budget, mode, stats, l
         "latency_kind": "pass completion: all queries of a pass are submitted together and "
                         "every one completes with the pass (not a single query's latency)",
         "host_waits_per_step": round((host1["syncs"] - host0["syncs"]) / args.steps, 2),
-        "autotune": {"sparse_theta": theta,
-                     "candidate_ms": {str(k): round(v, 3) for k, v in tune_ms.items()}},
+        "autotune": tune,
         "plan_batch_ms": ms(sum(x for x, _ in phase) / len(phase)),
         "join_batch_ms": ms(sum(y for _, y in phase) / len(phase)),
         "plain": None if plain_wall is None else {

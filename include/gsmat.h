@@ -39,8 +39,9 @@
  *     unless an allocator is given to gsmat_load_triples.
  *   - The store's index is immutable after gsmat_build_index; concurrent
  *     gsmat_join calls on different streams (and different results) are
- *     allowed.  gsmat_set_sparse_expand and gsmat_autotune_batch change a
- *     tuning setting of the store and must not overlap other calls on it.
+ *     allowed.  gsmat_set_sparse_expand, gsmat_set_batch_tuning and
+ *     gsmat_autotune_batch change tuning settings of the store and must not
+ *     overlap other calls on it.
  *   - A result's (and a server's) memory is returned to the allocator on the
  *     stream it was made on: that stream must outlive them.
  *   - A gsmat_server_step whose round fails (device allocation, HIP error)
@@ -290,6 +291,35 @@ gsmat_status gsmat_result_rows_many(const gsmat_result* const* results, int32_t 
  * order do not change.  theta in [0, 1], 0 never; defaults 0.5 and 4096. */
 gsmat_status gsmat_set_sparse_expand(gsmat_store* st, double theta, int64_t min_rows);
 
+/* Count-phase tile shape and intersection strategy of the device-driven
+ * batched join (engine 1).  Every count tile covers 2048 input rows;
+ * count_items rows per thread (4, 8 or 16) sets its workgroup to 512, 256
+ * or 128 threads.  Sorted-list intersections (a star centre bound from
+ * several patterns with constant other endpoints, Sec. 6.3's first step)
+ * take one of:
+ *   GSMAT_ISECT_SEARCH (0, default): each driver id binary-searches every
+ *     other list in device memory;
+ *   GSMAT_ISECT_WINDOW (1): the ids a tile of the sorted driver can meet
+ *     form one window of each list; a window of up to 2048 ids is staged in
+ *     LDS (the paper keeps small operands in shared memory, Sec. 7.3) and
+ *     searched there, a longer one is searched in memory within its bounds;
+ *   GSMAT_ISECT_MERGE (2): a staged window is merged with the tile's driver
+ *     ids along the merge path (equal shares of the two sorted sequences
+ *     per thread); a longer one is searched as with WINDOW.
+ * Lists with a hub bitmap (gsmat_build_index's hub option) are tested one
+ * bit at a time and lists of row keys by row lookups under every strategy.
+ * The rows and their order do not depend on either setting; the single-query
+ * join and the host-driven rounds always search with 8 rows per thread.
+ * Defaults 8 and SEARCH; EINVAL for other values. */
+#define GSMAT_ISECT_SEARCH 0
+#define GSMAT_ISECT_WINDOW 1
+#define GSMAT_ISECT_MERGE 2
+gsmat_status gsmat_set_batch_tuning(gsmat_store* st, int32_t count_items, int32_t intersect);
+
+/* The store's batch tuning settings (any pointer may be NULL). */
+gsmat_status gsmat_get_batch_tuning(const gsmat_store* st, double* theta, int64_t* min_rows,
+                                    int32_t* count_items, int32_t* intersect);
+
 /* The write strategy the batched join takes for an expansion of n_in input
  * rows of which n_nonempty have output, under the setting (theta, min_rows):
  * 1 = sparse (compacted rows with output), 0 = merge path over every row.
@@ -298,16 +328,28 @@ gsmat_status gsmat_set_sparse_expand(gsmat_store* st, double theta, int64_t min_
  * only, no device work. */
 int32_t gsmat_expand_strategy(double theta, int64_t min_rows, int64_t n_in, int64_t n_nonempty);
 
-/* Autotuner: runs gsmat_join_batch on the plans once untimed, then with each
- * candidate theta (0, 0.25, 0.5, 0.75, 1; the fastest of three runs each,
- * results discarded), keeps the fastest for the store (the store's current
- * theta stays unless another candidate is faster by more than 3 %) and
- * returns the kept value in *theta; ms[5] (may be NULL) receives each
- * candidate's wall time in milliseconds.  The rows of any later join do not
- * depend on the choice. */
+/* What gsmat_autotune_batch chose and timed.  A candidate's time is the
+ * fastest of three gsmat_join_batch runs in milliseconds (host wall time,
+ * results discarded); -1 where a setting was not tuned. */
+typedef struct gsmat_tune_report {
+  double theta;            /* chosen sparse-expansion threshold */
+  int32_t count_items;     /* chosen count rows per thread */
+  int32_t intersect;       /* chosen GSMAT_ISECT_* */
+  double theta_ms[5];      /* theta 0, 0.25, 0.5, 0.75, 1 */
+  double items_ms[3];      /* count_items 4, 8, 16 */
+  double intersect_ms[3];  /* SEARCH, WINDOW, MERGE */
+} gsmat_tune_report;
+
+/* Autotuner over the batched join's settings, one at a time in the order
+ * theta, count_items, intersect: runs gsmat_join_batch on the plans once
+ * untimed, then times each candidate of the setting with the others fixed
+ * and keeps the fastest (the store's current value stays unless another is
+ * faster by more than 3 %) before tuning the next.  With the host-driven
+ * engine only theta is tuned.  The rows of any later join do not depend on
+ * the choices.  rep may be NULL. */
 gsmat_status gsmat_autotune_batch(gsmat_store* st, const gsmat_query_plan* const* plans,
                                   int32_t n_plans, int64_t budget_bytes, void* stream,
-                                  double* theta, double* ms);
+                                  gsmat_tune_report* rep);
 
 /* Result shape; per-step rows in/out (arrays of n_steps entries, may be NULL)
  * are summed over chunks. */

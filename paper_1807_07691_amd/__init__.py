@@ -42,6 +42,7 @@ EXPORTED = [
     "gsmat_dict_term", "gsmat_parse_bgp", "gsmat_set_hub_options", "gsmat_set_sparse_expand",
     "gsmat_autotune_batch", "gsmat_expand_strategy", "gsmat_set_batch_engine",
     "gsmat_set_batch_regions", "gsmat_batch_round_stats", "gsmat_join_noalloc",
+    "gsmat_set_batch_tuning", "gsmat_get_batch_tuning",
 ]
 
 
@@ -89,7 +90,11 @@ def _load():
     L.gsmat_join_noalloc.argtypes = [vp, vp, vp, i64, i64, vp, vp]
     L.gsmat_batch_round_stats.argtypes = [vp, vp, i32, vp]
     L.gsmat_autotune_batch.restype = i32
-    L.gsmat_autotune_batch.argtypes = [vp, vp, i32, i64, vp, vp, vp]
+    L.gsmat_autotune_batch.argtypes = [vp, vp, i32, i64, vp, vp]
+    L.gsmat_set_batch_tuning.restype = i32
+    L.gsmat_set_batch_tuning.argtypes = [vp, i32, i32]
+    L.gsmat_get_batch_tuning.restype = i32
+    L.gsmat_get_batch_tuning.argtypes = [vp, vp, vp, vp, vp]
     L.gsmat_expand_strategy.restype = i32
     L.gsmat_expand_strategy.argtypes = [ctypes.c_double, i64, i64, i64]
     L.gsmat_set_hub_options.restype = i32
@@ -679,21 +684,52 @@ def gsmat_expand_strategy(theta, min_rows, n_in, n_nonempty):
 
 
 SPARSE_CANDIDATES = (0.0, 0.25, 0.5, 0.75, 1.0)
+ITEMS_CANDIDATES = (4, 8, 16)
+ISECT_SEARCH, ISECT_WINDOW, ISECT_MERGE = 0, 1, 2
+ISECT_NAMES = ("search", "window", "merge")
+
+
+class TuneReport(ctypes.Structure):
+    _fields_ = [("theta", ctypes.c_double), ("count_items", ctypes.c_int32),
+                ("intersect", ctypes.c_int32), ("theta_ms", ctypes.c_double * 5),
+                ("items_ms", ctypes.c_double * 3), ("intersect_ms", ctypes.c_double * 3)]
+
+
+def gsmat_set_batch_tuning(store, count_items=8, intersect=ISECT_SEARCH):
+    """Count rows per thread (4, 8, 16) and sorted-list intersection strategy
+    (ISECT_*) of the device-driven batched join."""
+    _check(_lib.gsmat_set_batch_tuning(store.h, int(count_items), int(intersect)))
+
+
+def gsmat_get_batch_tuning(store):
+    theta, min_rows = ctypes.c_double(), ctypes.c_int64()
+    items, isect = ctypes.c_int32(), ctypes.c_int32()
+    _check(_lib.gsmat_get_batch_tuning(store.h, ctypes.byref(theta), ctypes.byref(min_rows),
+                                       ctypes.byref(items), ctypes.byref(isect)))
+    return {"sparse_theta": theta.value, "sparse_min_rows": min_rows.value,
+            "count_items": items.value, "intersect": ISECT_NAMES[isect.value]}
 
 
 def gsmat_autotune_batch(store, plans, budget_bytes=0, stream=None):
-    """Times the batch under each sparse-expansion threshold and keeps the
-    fastest for the store: (theta, {candidate: ms})."""
+    """Tunes the batch's sparse-expansion threshold, count rows per thread and
+    intersection strategy in turn, keeping the fastest of each for the store:
+    a dict of the choices and each candidate's time in ms (-1: not tuned)."""
     if isinstance(plans, PlanSet):
         nq, ph = plans.n, plans.arr
     else:
         nq = len(plans)
         ph = (ctypes.c_void_p * max(nq, 1))(*[pl.h for pl in plans])
-    theta = ctypes.c_double()
-    ms = (ctypes.c_double * len(SPARSE_CANDIDATES))()
+    r = TuneReport()
     _check(_lib.gsmat_autotune_batch(store.h, ph, nq, budget_bytes, _stream(stream),
-                                     ctypes.byref(theta), ms))
-    return theta.value, {c: ms[i] for i, c in enumerate(SPARSE_CANDIDATES)}
+                                     ctypes.byref(r)))
+    return {"sparse_theta": r.theta, "count_items": r.count_items,
+            "intersect": ISECT_NAMES[r.intersect],
+            "candidate_ms": {
+                "sparse_theta": {str(c): round(r.theta_ms[i], 3)
+                                 for i, c in enumerate(SPARSE_CANDIDATES)},
+                "count_items": {str(c): round(r.items_ms[i], 3)
+                                for i, c in enumerate(ITEMS_CANDIDATES)},
+                "intersect": {n: round(r.intersect_ms[i], 3) for i, n in enumerate(ISECT_NAMES)}}}
 
 
 def gsmat_result_info(result):

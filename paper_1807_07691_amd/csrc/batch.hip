@@ -1399,6 +1399,33 @@ extern "C" gsmat_status gsmat_set_batch_engine(gsmat_store* st, int32_t engine) 
   });
 }
 
+extern "C" gsmat_status gsmat_set_batch_tuning(gsmat_store* st, int32_t count_items,
+                                              int32_t intersect) {
+  return guarded([&]() -> gsmat_status {
+    if (!st) throw StatusFail{GSMAT_EINVAL, "store is NULL"};
+    if (count_items != 4 && count_items != 8 && count_items != 16)
+      throw StatusFail{GSMAT_EINVAL, "count_items must be 4, 8 or 16"};
+    if (intersect < GSMAT_ISECT_SEARCH || intersect > GSMAT_ISECT_MERGE)
+      throw StatusFail{GSMAT_EINVAL, "intersect must be 0, 1 or 2"};
+    st->count_items = count_items;
+    st->intersect = intersect;
+    return GSMAT_OK;
+  });
+}
+
+extern "C" gsmat_status gsmat_get_batch_tuning(const gsmat_store* st, double* theta,
+                                              int64_t* min_rows, int32_t* count_items,
+                                              int32_t* intersect) {
+  return guarded([&]() -> gsmat_status {
+    if (!st) throw StatusFail{GSMAT_EINVAL, "store is NULL"};
+    if (theta) *theta = st->sparse_theta;
+    if (min_rows) *min_rows = st->sparse_min_rows;
+    if (count_items) *count_items = st->count_items;
+    if (intersect) *intersect = st->intersect;
+    return GSMAT_OK;
+  });
+}
+
 extern "C" gsmat_status gsmat_set_batch_regions(gsmat_store* st, int64_t out_bytes,
                                                int64_t scratch_bytes) {
   return guarded([&]() -> gsmat_status {
@@ -1432,21 +1459,16 @@ extern "C" int32_t gsmat_expand_strategy(double theta, int64_t min_rows, int64_t
 extern "C" gsmat_status gsmat_autotune_batch(gsmat_store* st,
                                              const gsmat_query_plan* const* plans,
                                              int32_t n_plans, int64_t budget_bytes, void* stream,
-                                             double* theta, double* ms) {
+                                             gsmat_tune_report* rep) {
   return guarded([&]() -> gsmat_status {
-    if (!st || !theta) throw StatusFail{GSMAT_EINVAL, "store or theta is NULL"};
-    static const double kCand[kTuneCandidates] = {0.0, 0.25, 0.5, 0.75, 1.0};
-    const double current = st->sparse_theta;
+    if (!st) throw StatusFail{GSMAT_EINVAL, "store is NULL"};
+    if (n_plans < 0 || (n_plans > 0 && !plans)) throw StatusFail{GSMAT_EINVAL, "bad plan array"};
     hipStream_t s = (hipStream_t)stream;
-    double current_ms = -1.0;
     std::vector<gsmat_result*> res(std::max(n_plans, 1));
-    double best_ms = 0;
-    int best = -1;
-    for (int c = -1; c < kTuneCandidates; ++c) {
-      // c = -1: one untimed run first (allocator and caches warm)
-      st->sparse_theta = kCand[c < 0 ? 0 : c];
+    // the fastest of three runs (one untimed run first when warm is set)
+    auto time_batch = [&](bool warm) {
       double t_min = 0;
-      for (int rep = 0; rep < (c < 0 ? 1 : 3); ++rep) {  // the fastest of three runs
+      for (int rep_i = warm ? -1 : 0; rep_i < 3; ++rep_i) {
         GS_HIP(hipStreamSynchronize(s));
         const auto t0 = std::chrono::steady_clock::now();
         const gsmat_status rc =
@@ -1456,21 +1478,49 @@ extern "C" gsmat_status gsmat_autotune_batch(gsmat_store* st,
                              std::chrono::steady_clock::now() - t0).count();
         for (int i = 0; i < n_plans; ++i) gsmat_result_free(res[i]);
         if (rc != GSMAT_OK) throw StatusFail{rc, gsmat_last_error()};
-        t_min = rep == 0 ? t : std::min(t_min, t);
+        if (rep_i >= 0) t_min = rep_i == 0 ? t : std::min(t_min, t);
       }
-      if (c < 0) continue;
-      if (ms) ms[c] = t_min;
-      if (kCand[c] == current) current_ms = t_min;
-      if (best < 0 || t_min < best_ms) {
-        best = c;
-        best_ms = t_min;
+      return t_min;
+    };
+    // one setting: every candidate timed, the current value kept unless
+    // another is faster by a clear margin
+    auto tune = [&](auto set, auto get, const auto* cand, int nc, double* ms) {
+      const auto current = get();
+      double current_ms = -1.0, best_ms = 0;
+      int best = -1;
+      for (int c = 0; c < nc; ++c) {
+        set(cand[c]);
+        const double t = time_batch(false);
+        if (ms) ms[c] = t;
+        if (cand[c] == current) current_ms = t;
+        if (best < 0 || t < best_ms) {
+          best = c;
+          best_ms = t;
+        }
       }
+      set((current_ms > 0 && best_ms > kTuneMargin * current_ms) ? current : cand[best]);
+    };
+    gsmat_tune_report r{};
+    std::fill(r.theta_ms, r.theta_ms + 5, -1.0);
+    std::fill(r.items_ms, r.items_ms + 3, -1.0);
+    std::fill(r.intersect_ms, r.intersect_ms + 3, -1.0);
+    static const double kTheta[kTuneCandidates] = {0.0, 0.25, 0.5, 0.75, 1.0};
+    static const int32_t kItemsCand[3] = {4, 8, 16};
+    static const int32_t kIsectCand[3] = {GSMAT_ISECT_SEARCH, GSMAT_ISECT_WINDOW,
+                                          GSMAT_ISECT_MERGE};
+    time_batch(true);  // allocator, caches and round hints warm
+    tune([&](double v) { st->sparse_theta = v; }, [&] { return st->sparse_theta; }, kTheta,
+         kTuneCandidates, r.theta_ms);
+    if (st->batch_engine == 1) {
+      tune([&](int32_t v) { st->count_items = v; }, [&] { return st->count_items; }, kItemsCand, 3,
+           r.items_ms);
+      tune([&](int32_t v) { st->intersect = v; }, [&] { return st->intersect; }, kIsectCand, 3,
+           r.intersect_ms);
     }
-    // the current threshold stays unless another is faster by a clear margin
-    const double chosen =
-        (current_ms > 0 && best_ms > kTuneMargin * current_ms) ? current : kCand[best];
-    st->sparse_theta = chosen;
-    *theta = chosen;
+    r.theta = st->sparse_theta;
+    r.count_items = st->count_items;
+    r.intersect = st->intersect;
+    if (rep) *rep = r;
     return GSMAT_OK;
   });
 }

@@ -37,13 +37,14 @@ __device__ inline int find_first_tile(const int64_t* __restrict__ w0, int n, int
 // Count / flag tile of one count-phase task, writing to N/start
 // (expansions) or flags; the tile sum is returned, and for expansions the
 // rows with output go to ne and are added to *nonempty (one atomic per
-// workgroup).
+// workgroup).  kT threads per workgroup; kS: the intersection strategy.
+template <int kT = kBlock, int kS = kIsSearch>
 __device__ inline int64_t b_count_tile(const CTask& T, int64_t tile, const ListRef* lists,
                                        int32_t* N, int32_t* start, uint8_t* flags,
                                        int64_t* nonempty, int64_t* ne) {
   if (T.kind == kTaskExpand) {
     const PredView pv = T.pv;
-    const int64_t packed = count_expand_tile<true>(tile, T.col, T.n, pv, N, start);
+    const int64_t packed = count_expand_tile<true, kT>(tile, T.col, T.n, pv, N, start);
     const int64_t k = packed >> kNonEmptyShift;
     if (threadIdx.x == 0 && k > 0) atomicAdd((unsigned long long*)nonempty, (unsigned long long)k);
     *ne = k;
@@ -53,9 +54,9 @@ __device__ inline int64_t b_count_tile(const CTask& T, int64_t tile, const ListR
   if (T.kind == kTaskFilter) {
     const PredView pv = T.pv;
     const ProbeArgs pa = T.pa;
-    return flag_filter_tile(tile, pa, T.n, pv, flags);
+    return flag_filter_tile<kT>(tile, pa, T.n, pv, flags);
   }
-  return flag_intersect_tile(tile, T.col, T.n, lists + T.l0, T.nl, flags);
+  return flag_intersect_tile<kT, kS>(tile, T.col, T.n, lists + T.l0, T.nl, flags);
 }
 
 // Sparse expansion, one count tile: the rows with output, compacted in

@@ -44,6 +44,7 @@
 // finished by the single-query executor.
 #include <algorithm>
 #include <cstring>
+#include <functional>
 #include <memory>
 #include <vector>
 
@@ -798,7 +799,8 @@ __global__ __launch_bounds__(kScanBlock) void k_d_layout(DArgs A) {
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_d_count(const CTask* __restrict__ ct,
+template <int kT, int kS>
+__global__ __launch_bounds__(kT) void k_d_count(const CTask* __restrict__ ct,
                                                     const ListRef* __restrict__ lists,
                                                     const int64_t* __restrict__ w_cnt,
                                                     const int64_t* __restrict__ cnt_off,
@@ -814,7 +816,7 @@ __global__ __launch_bounds__(kBlock) void k_d_count(const CTask* __restrict__ ct
     char* cb = base + cnt_off[qi];
     int64_t k;
     const int64_t sum =
-        b_count_tile(T, b - w_cnt[qi], lists, (int32_t*)cb, (int32_t*)(cb + d_a256(4 * T.n)),
+        b_count_tile<kT, kS>(T, b - w_cnt[qi], lists, (int32_t*)cb, (int32_t*)(cb + d_a256(4 * T.n)),
                      (uint8_t*)cb, ne + qi, &k);
     if (threadIdx.x == 0) {
       ts[b] = sum;
@@ -1159,7 +1161,7 @@ int64_t round_up(int64_t b, int64_t g) { return (b + g - 1) / g * g; }
 // Workgroups of each tile kernel: as many as the device holds at once (the
 // kernels take tiles from a counter, so more would only wait for a slot).
 struct Grids {
-  unsigned sample, count, post, write;
+  unsigned sample, post, write;  // the count launch's: count_resident()
 };
 const Grids& resident_grids() {
   static Grids g = [] {
@@ -1171,8 +1173,8 @@ const Grids& resident_grids() {
       GS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, kBlock, 0));
       return (unsigned)std::max(1, per * std::max(cus, 1));
     };
-    return Grids{res((const void*)k_d_sample), res((const void*)k_d_count),
-                 res((const void*)k_d_post), res((const void*)k_d_write)};
+    return Grids{res((const void*)k_d_sample), res((const void*)k_d_post),
+                 res((const void*)k_d_write)};
   }();
   return g;
 }
@@ -1185,6 +1187,41 @@ const Grids& resident_grids() {
     GS_HIP(hipGetLastError());                                               \
     if (_prof) prof_end(s, cls, 0.0);                                        \
   } while (0)
+
+// The count launch for the store's tile shape (threads per workgroup) and
+// intersection strategy; every variant takes the same tiles, so the round's
+// scratch layout does not depend on the choice.
+template <int kT, int kS>
+unsigned count_resident() {
+  static const unsigned r = [] {
+    int dev = 0, cus = 0, per = 0;
+    GS_HIP(hipGetDevice(&dev));
+    GS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    GS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void*)k_d_count<kT, kS>, kT,
+                                                        0));
+    return (unsigned)std::max(1, per * std::max(cus, 1));
+  }();
+  return r;
+}
+template <int kT, int kS>
+void launch_count_as(hipStream_t s, const DArgs& A, int nq, const std::function<unsigned(unsigned)>& grid) {
+  auto k = k_d_count<kT, kS>;
+  GS_DLAUNCH(GSMAT_K_COUNT, k, grid(count_resident<kT, kS>()), kT, A.ct, A.lists, A.w_cnt,
+             A.cnt_off, A.ne, nq, A.ctl);
+}
+template <int kS>
+void launch_count_s(int items, hipStream_t s, const DArgs& A, int nq,
+                    const std::function<unsigned(unsigned)>& grid) {
+  if (items == 4) return launch_count_as<kTile / 4, kS>(s, A, nq, grid);
+  if (items == 16) return launch_count_as<kTile / 16, kS>(s, A, nq, grid);
+  return launch_count_as<kTile / 8, kS>(s, A, nq, grid);
+}
+void launch_count(int items, int strategy, hipStream_t s, const DArgs& A, int nq,
+                  const std::function<unsigned(unsigned)>& grid) {
+  if (strategy == kIsWindow) return launch_count_s<kIsWindow>(items, s, A, nq, grid);
+  if (strategy == kIsMerge) return launch_count_s<kIsMerge>(items, s, A, nq, grid);
+  return launch_count_s<kIsSearch>(items, s, A, nq, grid);
+}
 
 }  // namespace
 
@@ -1355,8 +1392,8 @@ void run_batch_device(gsmat_store* st, const gsmat_query_plan* const* plans, int
       GS_DLAUNCH(GSMAT_K_OTHER, k_d_sample, grids.sample, kBlock, A.cands, A.part, A.ctl);
       GS_DLAUNCH(GSMAT_K_OTHER, k_d_task, qgrid, kQBlock, A);
       GS_DLAUNCH(GSMAT_K_SCAN, k_d_layout, 1, kScanBlock, A);
-      GS_DLAUNCH(GSMAT_K_COUNT, k_d_count, hinted(gr, 1, grids.count), kBlock, A.ct, A.lists,
-                 A.w_cnt, A.cnt_off, A.ne, nq, A.ctl);
+      launch_count(st->count_items, st->intersect, s, A, nq,
+                   [&](unsigned floor_) { return hinted(gr, 1, floor_); });
       GS_DLAUNCH(GSMAT_K_SCAN, k_d_scan, 1, kScanBlock, A);
       GS_DLAUNCH(GSMAT_K_OTHER, k_d_outcome, qgrid, kQBlock, A);
       GS_DLAUNCH(GSMAT_K_SCAN, k_d_alloc, 1, kScanBlock, A);

@@ -84,14 +84,17 @@ __device__ inline void block_excl_scan_n(const int64_t (&v)[F], int64_t (&ex)[F]
   __syncthreads();
 }
 
+// Sum over a workgroup of kT threads.
+template <int kT = kBlock>
 __device__ inline int64_t block_sum(int64_t v) {
-  __shared__ int64_t ws[kWaves];
+  constexpr int kW = kT / 64;
+  __shared__ int64_t ws[kW];
   v = wave_sum(v);
   if (lane_id() == 0) ws[wave_id()] = v;
   __syncthreads();
   int64_t tot = 0;
 #pragma unroll
-  for (int i = 0; i < kWaves; ++i) tot += ws[i];
+  for (int i = 0; i < kW; ++i) tot += ws[i];
   __syncthreads();
   return tot;
 }
@@ -398,25 +401,29 @@ __device__ inline int64_t sample_fanout_slice(int slice, const int32_t* __restri
 // kNonEmpty the result also carries, above bit kNonEmptyShift, the number of
 // rows with N_i > 0 (a tile's length sum stays below 2^kNonEmptyShift).
 constexpr int kNonEmptyShift = 48;
-template <bool kNonEmpty = false>
+// The count-phase tiles take a tile of kTile rows with a workgroup of kT
+// threads (kT in {128, 256, 512}: 16, 8 or 4 rows per thread); row
+// tile0 + j * kT + t goes to thread t.
+template <bool kNonEmpty = false, int kT = kBlock>
 __device__ inline int64_t count_expand_tile(int64_t tile, const int32_t* __restrict__ col,
                                             int64_t n, const PredView& pv,
                                             int32_t* __restrict__ N,
                                             int32_t* __restrict__ start) {
+  constexpr int kI = kTile / kT;
   const int64_t tile0 = tile * kTile;
-  int32_t v[kItems], st[kItems], len[kItems];
-  bool ok[kItems];
+  int32_t v[kI], st[kI], len[kI];
+  bool ok[kI];
 #pragma unroll
-  for (int j = 0; j < kItems; ++j) {
-    const int64_t i = tile0 + (int64_t)j * kBlock + threadIdx.x;
+  for (int j = 0; j < kI; ++j) {
+    const int64_t i = tile0 + (int64_t)j * kT + threadIdx.x;
     ok[j] = i < n;
     v[j] = ok[j] ? col[i] : 0;
   }
-  row_lookup_n<kItems>(pv, v, ok, st, len);
+  row_lookup_n<kI>(pv, v, ok, st, len);
   int64_t loc = 0;
 #pragma unroll
-  for (int j = 0; j < kItems; ++j) {
-    const int64_t i = tile0 + (int64_t)j * kBlock + threadIdx.x;
+  for (int j = 0; j < kI; ++j) {
+    const int64_t i = tile0 + (int64_t)j * kT + threadIdx.x;
     if (ok[j]) {
       N[i] = len[j];
       start[i] = st[j];
@@ -424,50 +431,52 @@ __device__ inline int64_t count_expand_tile(int64_t tile, const int32_t* __restr
       if (kNonEmpty && len[j] > 0) loc += (int64_t)1 << kNonEmptyShift;
     }
   }
-  return block_sum(loc);
+  return block_sum<kT>(loc);
 }
 
 // Filter: keep row i when (s_i, o_i) is a pair of the predicate.
+template <int kT = kBlock>
 __device__ inline int64_t flag_filter_tile(int64_t tile, const ProbeArgs& pa, int64_t n,
                                            const PredView& pv, uint8_t* __restrict__ flags) {
+  constexpr int kI = kTile / kT;
   const int64_t tile0 = tile * kTile;
-  int32_t sv[kItems], ov[kItems], st[kItems], len[kItems];
-  bool ok[kItems];
+  int32_t sv[kI], ov[kI], st[kI], len[kI];
+  bool ok[kI];
 #pragma unroll
-  for (int j = 0; j < kItems; ++j) {
-    const int64_t i = tile0 + (int64_t)j * kBlock + threadIdx.x;
+  for (int j = 0; j < kI; ++j) {
+    const int64_t i = tile0 + (int64_t)j * kT + threadIdx.x;
     ok[j] = i < n;
     sv[j] = ok[j] ? (pa.s_col ? pa.s_col[i] : pa.s_const) : 0;
     ov[j] = ok[j] ? (pa.o_col ? pa.o_col[i] : pa.o_const) : 0;
   }
-  row_lookup_n<kItems>(pv, sv, ok, st, len);
+  row_lookup_n<kI>(pv, sv, ok, st, len);
   // rows with a bitmap answer with one bit; the others are searched
-  int32_t hub[kItems];
+  int32_t hub[kI];
 #pragma unroll
-  for (int j = 0; j < kItems; ++j) hub[j] = -1;
+  for (int j = 0; j < kI; ++j) hub[j] = -1;
   if (pv.hub_n > 0) {
-    int32_t hl[kItems], hn[kItems], hk[kItems];
+    int32_t hl[kI], hn[kI], hk[kI];
 #pragma unroll
-    for (int j = 0; j < kItems; ++j) {
+    for (int j = 0; j < kI; ++j) {
       hl[j] = 0;
       hn[j] = len[j] >= pv.hub_min ? pv.hub_n : 0;
     }
-    lower_bound_n<kItems>(pv.hub_keys, sv, hl, hn);
+    lower_bound_n<kI>(pv.hub_keys, sv, hl, hn);
 #pragma unroll
-    for (int j = 0; j < kItems; ++j) hk[j] = (len[j] >= pv.hub_min && hl[j] < pv.hub_n) ? pv.hub_keys[hl[j]] : -1;
+    for (int j = 0; j < kI; ++j) hk[j] = (len[j] >= pv.hub_min && hl[j] < pv.hub_n) ? pv.hub_keys[hl[j]] : -1;
 #pragma unroll
-    for (int j = 0; j < kItems; ++j) hub[j] = (len[j] > 0 && hk[j] == sv[j]) ? hl[j] : -1;
+    for (int j = 0; j < kI; ++j) hub[j] = (len[j] > 0 && hk[j] == sv[j]) ? hl[j] : -1;
   }
   // o_i among the members of row s_i
-  int32_t lo[kItems], cnt[kItems], k[kItems];
+  int32_t lo[kI], cnt[kI], k[kI];
 #pragma unroll
-  for (int j = 0; j < kItems; ++j) {
+  for (int j = 0; j < kI; ++j) {
     lo[j] = st[j];
     cnt[j] = hub[j] >= 0 ? 0 : len[j];
   }
-  lower_bound_n<kItems>(pv.nbr, ov, lo, cnt);
+  lower_bound_n<kI>(pv.nbr, ov, lo, cnt);
 #pragma unroll
-  for (int j = 0; j < kItems; ++j) {
+  for (int j = 0; j < kI; ++j) {
     if (hub[j] >= 0)
       k[j] = bit_set(pv.hub_bm + (int64_t)hub[j] * pv.hub_words, ov[j]) ? ov[j] : -1;
     else
@@ -475,64 +484,187 @@ __device__ inline int64_t flag_filter_tile(int64_t tile, const ProbeArgs& pa, in
   }
   int64_t loc = 0;
 #pragma unroll
-  for (int j = 0; j < kItems; ++j) {
-    const int64_t i = tile0 + (int64_t)j * kBlock + threadIdx.x;
+  for (int j = 0; j < kI; ++j) {
+    const int64_t i = tile0 + (int64_t)j * kT + threadIdx.x;
     if (ok[j]) {
       const uint8_t f = (len[j] > 0 && k[j] == ov[j]) ? 1 : 0;
       flags[i] = f;
       loc += f;
     }
   }
-  return block_sum(loc);
+  return block_sum<kT>(loc);
 }
 
 // Star-centre intersection: keep driver id x when it is in every list.
+// Lists of keys are answered by row lookups and lists with a row bitmap by
+// one bit; a sorted list (a row of a compressed matrix) by one of three
+// strategies, uniform over a launch:
+//   kIsSearch  every driver id binary-searches the whole list in memory;
+//   kIsWindow  the tile's driver ids are sorted, so the ids they can meet
+//              form one window of the list, found by two searches; a window
+//              of at most kWinCap ids is staged in LDS and searched there,
+//              a longer one is searched in memory within its bounds;
+//   kIsMerge   the window staged as above is merged with the tile's driver
+//              ids along the merge path (each thread walks an equal share
+//              of the two sorted sequences); a window longer than kWinCap
+//              is searched in memory as with kIsWindow.
+// kIsWindow and kIsMerge need the driver sorted ascending and distinct, as
+// every intersection driver is (a row of a compressed matrix, or a
+// predicate's sorted row keys).
+constexpr int kIsSearch = 0;
+constexpr int kIsWindow = 1;
+constexpr int kIsMerge = 2;
+constexpr int kWinCap = 2048;
+
+// First index in a[0, n) whose value exceeds v.
+__device__ inline int32_t upper_bound_i32(const int32_t* __restrict__ a, int32_t n, int32_t v) {
+  int32_t lo = 0, len = n;
+  while (len > 0) {
+    const int32_t half = len >> 1;
+    if (a[lo + half] <= v) {
+      lo += half + 1;
+      len -= half + 1;
+    } else {
+      len = half;
+    }
+  }
+  return lo;
+}
+
+// Membership of the driver ids x (tile rows, kT threads) in the sorted list
+// seg[0, len) under strategy kS (kIsWindow or kIsMerge); d points at the
+// tile's nd driver ids.  Called by the whole workgroup.
+template <int kT, int kS>
+__device__ inline void window_members(const int32_t* __restrict__ seg, int32_t len,
+                                      const int32_t* __restrict__ d, int nd,
+                                      const int32_t (&x)[kTile / kT], bool (&keep)[kTile / kT]) {
+  constexpr int kI = kTile / kT;
+  __shared__ int32_t sWin[2];
+  __shared__ int32_t sW[kWinCap];
+  if (threadIdx.x == 0) sWin[0] = lower_bound_i32(seg, len, d[0]);
+  if (threadIdx.x == 1) sWin[1] = upper_bound_i32(seg, len, d[nd - 1]);
+  __syncthreads();
+  const int32_t w0 = sWin[0];
+  const int32_t nw = sWin[1] - w0;
+  if (nw > kWinCap) {
+    // the window does not fit: search it in memory
+    int32_t lo[kI], cnt[kI], k[kI];
+#pragma unroll
+    for (int j = 0; j < kI; ++j) {
+      lo[j] = w0;
+      cnt[j] = keep[j] ? nw : 0;
+    }
+    lower_bound_n<kI>(seg, x, lo, cnt);
+#pragma unroll
+    for (int j = 0; j < kI; ++j) k[j] = (keep[j] && lo[j] < w0 + nw) ? seg[lo[j]] : -1;
+#pragma unroll
+    for (int j = 0; j < kI; ++j) keep[j] = keep[j] && k[j] == x[j];
+    __syncthreads();  // sWin is rewritten by the next list
+    return;
+  }
+  for (int i = threadIdx.x; i < nw; i += kT) sW[i] = seg[w0 + i];
+  if constexpr (kS == kIsWindow) {
+    __syncthreads();
+    int32_t lo[kI], cnt[kI], k[kI];
+#pragma unroll
+    for (int j = 0; j < kI; ++j) {
+      lo[j] = 0;
+      cnt[j] = keep[j] ? nw : 0;
+    }
+    lower_bound_n<kI>(sW, x, lo, cnt);
+#pragma unroll
+    for (int j = 0; j < kI; ++j) k[j] = (keep[j] && lo[j] < nw) ? sW[lo[j]] : -1;
+#pragma unroll
+    for (int j = 0; j < kI; ++j) keep[j] = keep[j] && k[j] == x[j];
+  } else {
+    __shared__ int32_t sD[kTile];
+    __shared__ uint8_t sF[kTile];
+#pragma unroll
+    for (int j = 0; j < kI; ++j) {
+      const int i = j * kT + threadIdx.x;
+      if (i < nd) sD[i] = x[j];
+    }
+    __syncthreads();
+    // thread t merges outputs [t * per, (t + 1) * per) of the merged
+    // sequence, a driver id taken before an equal list id; its first driver
+    // index is the merge-path split of its first diagonal
+    const int total = nd + nw;
+    const int per = (total + kT - 1) / kT;
+    const int g0 = min(total, (int)threadIdx.x * per);
+    const int g1 = min(total, g0 + per);
+    int lo = max(0, g0 - nw), hi = min(g0, nd);
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (sD[mid] <= sW[g0 - mid - 1]) lo = mid + 1;
+      else hi = mid;
+    }
+    int a = lo, b = g0 - lo;
+    for (int g = g0; g < g1; ++g) {
+      if (a < nd && (b >= nw || sD[a] <= sW[b])) {
+        sF[a] = (b < nw && sD[a] == sW[b]) ? 1 : 0;
+        ++a;
+      } else {
+        ++b;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kI; ++j) keep[j] = keep[j] && sF[j * kT + threadIdx.x] != 0;
+  }
+  __syncthreads();  // sWin, sW (and sD, sF) are rewritten by the next list
+}
+
+template <int kT = kBlock, int kS = kIsSearch>
 __device__ inline int64_t flag_intersect_tile(int64_t tile, const int32_t* __restrict__ driver,
                                               int64_t n, const ListRef* lists, int nl,
                                               uint8_t* __restrict__ flags) {
+  constexpr int kI = kTile / kT;
   const int64_t tile0 = tile * kTile;
-  int32_t x[kItems];
-  bool keep[kItems];
+  int32_t x[kI];
+  bool keep[kI];
 #pragma unroll
-  for (int j = 0; j < kItems; ++j) {
-    const int64_t i = tile0 + (int64_t)j * kBlock + threadIdx.x;
+  for (int j = 0; j < kI; ++j) {
+    const int64_t i = tile0 + (int64_t)j * kT + threadIdx.x;
     keep[j] = i < n;
     x[j] = keep[j] ? driver[i] : 0;
   }
   for (int l = 0; l < nl; ++l) {
     const ListRef& L = lists[l];
     if (L.is_keys) {
-      int32_t st[kItems], len[kItems];
-      row_lookup_n<kItems>(L.pv, x, keep, st, len);
+      int32_t st[kI], len[kI];
+      row_lookup_n<kI>(L.pv, x, keep, st, len);
 #pragma unroll
-      for (int j = 0; j < kItems; ++j) keep[j] = keep[j] && len[j] > 0;
+      for (int j = 0; j < kI; ++j) keep[j] = keep[j] && len[j] > 0;
     } else if (L.bm) {
 #pragma unroll
-      for (int j = 0; j < kItems; ++j) keep[j] = keep[j] && bit_set(L.bm, x[j]);
+      for (int j = 0; j < kI; ++j) keep[j] = keep[j] && bit_set(L.bm, x[j]);
+    } else if constexpr (kS != kIsSearch) {
+      const int nd = (int)(n - tile0 < kTile ? n - tile0 : kTile);
+      window_members<kT, kS>(L.seg, (int32_t)L.len, driver + tile0, nd, x, keep);
     } else {
-      int32_t lo[kItems], cnt[kItems], k[kItems];
+      int32_t lo[kI], cnt[kI], k[kI];
 #pragma unroll
-      for (int j = 0; j < kItems; ++j) {
+      for (int j = 0; j < kI; ++j) {
         lo[j] = 0;
         cnt[j] = keep[j] ? (int32_t)L.len : 0;
       }
-      lower_bound_n<kItems>(L.seg, x, lo, cnt);
+      lower_bound_n<kI>(L.seg, x, lo, cnt);
 #pragma unroll
-      for (int j = 0; j < kItems; ++j) k[j] = (keep[j] && lo[j] < (int32_t)L.len) ? L.seg[lo[j]] : -1;
+      for (int j = 0; j < kI; ++j) k[j] = (keep[j] && lo[j] < (int32_t)L.len) ? L.seg[lo[j]] : -1;
 #pragma unroll
-      for (int j = 0; j < kItems; ++j) keep[j] = keep[j] && k[j] == x[j];
+      for (int j = 0; j < kI; ++j) keep[j] = keep[j] && k[j] == x[j];
     }
   }
   int64_t loc = 0;
 #pragma unroll
-  for (int j = 0; j < kItems; ++j) {
-    const int64_t i = tile0 + (int64_t)j * kBlock + threadIdx.x;
+  for (int j = 0; j < kI; ++j) {
+    const int64_t i = tile0 + (int64_t)j * kT + threadIdx.x;
     if (i < n) {
       flags[i] = keep[j] ? 1 : 0;
       loc += keep[j] ? 1 : 0;
     }
   }
-  return block_sum(loc);
+  return block_sum<kT>(loc);
 }
 
 // Exclusive prefix sum of one tile of x, offset by base: out[i] for the

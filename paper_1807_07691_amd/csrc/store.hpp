@@ -53,6 +53,8 @@ struct gsmat_store {
   double sparse_theta = 0.5;       // batched expansions: compact rows below this fill ...
   int64_t sparse_min_rows = 4096;  // ... in expansions of at least this many rows
   int32_t batch_engine = 1;       // gsmat_join_batch: 1 device-driven rounds, 0 host-driven
+  int32_t count_items = 8;        // device-driven count tiles: rows per thread (4, 8 or 16)
+  int32_t intersect = 0;          // ... sorted-list intersections: 0 search, 1 window, 2 merge
   int64_t dbatch_out_hint = 0;    // device-driven rounds: output slab and scratch sizes of
   int64_t dbatch_scr_hint = 0;    // the last batch (the next one starts with them)
   std::vector<int64_t> dbatch_stats;  // the last device-driven batch's rounds

@@ -217,6 +217,6 @@ def test_server_entry_points_validate_before_device_work(G):
 def test_hub_and_sparse_options_validate(G):
     assert G.lib().gsmat_set_hub_options(None, 2, 1) == G.GSMAT_EINVAL
     assert G.lib().gsmat_set_sparse_expand(None, 0.5, 4096) == G.GSMAT_EINVAL
-    theta = ctypes.c_double()
-    assert G.lib().gsmat_autotune_batch(None, None, 0, 0, None, ctypes.byref(theta),
-                                        None) == G.GSMAT_EINVAL
+    assert G.lib().gsmat_autotune_batch(None, None, 0, 0, None, None) == G.GSMAT_EINVAL
+    assert G.lib().gsmat_set_batch_tuning(None, 8, 0) == G.GSMAT_EINVAL
+    assert G.lib().gsmat_get_batch_tuning(None, None, None, None, None) == G.GSMAT_EINVAL

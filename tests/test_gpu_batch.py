@@ -144,19 +144,110 @@ def _join_all(G, st, plans, budget=0, engine=1):
 
 
 def test_batch_autotune(G, tiny):
-    """The tuner keeps one of its candidates; results do not depend on it."""
+    """The tuner keeps one candidate of each setting; results do not depend on it."""
     spec, s, p, o, qs, st, want = tiny
     G.gsmat_set_sparse_expand(st, 0.5, 1)
     try:
         queries = [q.tps for q in qs] * 8
         plans, _ = G.gsmat_plan_batch(st, queries, G.PLAN_ADAPTIVE, as_set=True)
-        theta, ms = G.gsmat_autotune_batch(st, plans)
-        print(f"[gpu] autotune: theta={theta} ms={ms}", flush=True)
-        assert theta in G.SPARSE_CANDIDATES and len(ms) == 5 and all(v > 0 for v in ms.values())
+        rep = G.gsmat_autotune_batch(st, plans)
+        print(f"[gpu] autotune: {rep}", flush=True)
+        assert rep["sparse_theta"] in G.SPARSE_CANDIDATES
+        assert rep["count_items"] in G.ITEMS_CANDIDATES
+        assert rep["intersect"] in G.ISECT_NAMES
+        ms = rep["candidate_ms"]
+        assert len(ms["sparse_theta"]) == 5 and all(v > 0 for v in ms["sparse_theta"].values())
+        assert len(ms["count_items"]) == 3 and all(v > 0 for v in ms["count_items"].values())
+        assert len(ms["intersect"]) == 3 and all(v > 0 for v in ms["intersect"].values())
+        got = G.gsmat_get_batch_tuning(st)
+        assert got["count_items"] == rep["count_items"] and got["intersect"] == rep["intersect"]
         _check_batch(G, st, queries, G.PLAN_ADAPTIVE, oracle_rows=want * 8)
+        plans.close()
+        # with the host-driven rounds only theta is tuned
+        G.gsmat_set_batch_engine(st, 0)
+        plans, _ = G.gsmat_plan_batch(st, [q.tps for q in qs], G.PLAN_ADAPTIVE, as_set=True)
+        rep = G.gsmat_autotune_batch(st, plans)
+        assert all(v == -1 for v in rep["candidate_ms"]["intersect"].values())
         plans.close()
     finally:
         G.gsmat_set_sparse_expand(st, 0.5, 4096)
+        G.gsmat_set_batch_engine(st, 1)
+        G.gsmat_set_batch_tuning(st, 8, G.ISECT_SEARCH)
+
+
+# count-phase rows per thread and sorted-list intersection strategy of the
+# device-driven rounds
+TUNING = [(items, isect) for items in (4, 8, 16) for isect in (0, 1, 2)]
+
+
+@pytest.mark.parametrize("tuning", TUNING)
+def test_batch_tuning_tiny(G, tiny, tuning):
+    spec, s, p, o, qs, st, want = tiny
+    print(f"[gpu] batch tiny tuning={tuning}", flush=True)
+    G.gsmat_set_batch_tuning(st, *tuning)
+    G.gsmat_set_sparse_expand(st, 1.0, 1)
+    try:
+        queries = [q.tps for q in qs] * 4
+        for mode in (0, 1, 2):
+            _check_batch(G, st, queries, mode, oracle_rows=want * 4)
+    finally:
+        G.gsmat_set_batch_tuning(st, 8, G.ISECT_SEARCH)
+        G.gsmat_set_sparse_expand(st, 0.5, 4096)
+
+
+def _star_graph():
+    """Rows of constant objects made for the intersection strategies: a
+    dense run, sparse ids over the whole range, a run overlapping the first,
+    half of all ids, every id, and a predicate with variable objects (a list
+    of row keys).  Driver tiles then meet windows shorter and longer than the
+    2048 ids a workgroup stages."""
+    rng = np.random.default_rng(11)
+    V = 60_000
+    def take(ids, pred, obj):
+        return ids.astype(np.int32), np.full(len(ids), pred, np.int32), np.full(len(ids), obj, np.int32)
+    parts = [
+        take(np.flatnonzero(rng.random(6000) < 0.9), 0, 1),
+        take(np.flatnonzero(rng.random(V) < 0.05), 1, 2),
+        take(np.arange(3000, 9000), 2, 3),
+        take(rng.choice(V, V // 2, replace=False), 3, 4),
+        take(np.arange(V), 4, 5),
+    ]
+    ks = rng.choice(V, 20_000, replace=False)
+    parts.append((ks.astype(np.int32), np.full(len(ks), 5, np.int32),
+                  rng.integers(0, V, len(ks)).astype(np.int32)))
+    s = np.concatenate([a for a, _, _ in parts])
+    p = np.concatenate([b for _, b, _ in parts])
+    o = np.concatenate([c for _, _, c in parts])
+    return s, p, o, V
+
+
+STARS = [
+    [[-1, 0, 1], [-1, 2, 3]],                   # dense run against an overlapping run
+    [[-1, 0, 1], [-1, 3, 4], [-1, 4, 5]],       # dense driver, half and all ids
+    [[-1, 1, 2], [-1, 4, 5]],                   # sparse driver: windows past 2048 ids
+    [[-1, 1, 2], [-1, 3, 4], [-1, 5, -2]],      # sparse driver, half, row keys
+    [[-1, 2, 3], [-1, 3, 4], [-1, 4, 5], [-1, 0, 1]],
+    [[-1, 3, 4], [-1, 4, 5]],                   # a long driver (many tiles)
+    [[-1, 3, 4], [-1, 5, -2], [-2, 4, 5]],      # intersection, then an expansion
+    [[-1, 0, 1], [-1, 1, 2], [-1, 2, 3]],       # few common ids
+]
+
+
+@pytest.mark.parametrize("tuning", TUNING)
+def test_batch_tuning_star_intersections(G, O, tuning):
+    """Star-centre intersections of long sorted lists under every strategy
+    and tile shape: identical to the single-query join (which searches) and
+    to the oracle."""
+    s, p, o, V = _star_graph()
+    st = _store(G, s, p, o, V, 6)
+    want = [O.join(s, p, o, q, int(-np.min(np.asarray(q)))) for q in STARS]
+    assert min(len(w) for w in want) > 0 and max(len(w) for w in want) > 5000
+    print(f"[gpu] batch star intersections tuning={tuning} rows={[len(w) for w in want]}",
+          flush=True)
+    G.gsmat_set_batch_tuning(st, *tuning)
+    for mode in (1, 2):  # the planner's star intersections
+        _check_batch(G, st, STARS * 2, mode, oracle_rows=want * 2)
+    st.close()
 
 
 @pytest.mark.parametrize("mode", [1, 2])
@@ -247,6 +338,7 @@ def test_batch_random_graphs(G, O, seed):
         G.gsmat_set_hub_options(st, int(rng.integers(1, 8)), 1 << 26)
     G.gsmat_build_index(st, dense_div=int(rng.choice([1, 32, 10**6])))
     G.gsmat_set_sparse_expand(st, *SPARSE[seed % 3])
+    G.gsmat_set_batch_tuning(st, *TUNING[(seed * 4) % len(TUNING)])
     queries, want = [], []
     while len(queries) < 70:
         ntp = int(rng.integers(1, 5))
