@@ -364,6 +364,72 @@ gsmat_status gsmat_fetch_bindings(const gsmat_result* r, int64_t row_offset, int
 
 void gsmat_result_free(gsmat_result* r);
 
+/* ---- OPTIONAL, UNION and FILTER (Sec. 9) ---------------------------------
+ *
+ * The paper names these operators as future work without defining them.
+ * Here they take the SPARQL algebra's meaning over bags of solution mappings,
+ * and every BGP inside a query runs on the sparse-matrix join (Sec. 6-7).
+ *
+ * A query is the bag union of its branches, in ascending branch id.  A
+ * branch has three parts:
+ *   - its required BGP (the patterns of group 0; with none, the bag holding
+ *     one mapping that binds nothing);
+ *   - its OPTIONAL BGPs (groups 1, 2, ...), left-joined in ascending group id;
+ *   - the conjunction of its FILTER conditions, applied last.
+ * LeftJoin(A, B) keeps every merge of a row of A with a compatible row of B
+ * (equal on every variable bound in both).  A row of A that has no such row
+ * in B is kept alone.
+ *
+ * Patterns must be well designed: a variable that an OPTIONAL group shares
+ * with any other group of its branch must occur in the branch's required
+ * BGP.  Otherwise the call returns GSMAT_EUNSUPPORTED.  The required rows are
+ * numbered, B's patterns run from the required table itself (the adaptive
+ * step choice expands and filters off its bound columns), and the rows no
+ * match kept are compacted and returned with B's variables unbound.
+ *
+ * FILTER conditions compare term ids: a variable or a constant id on each
+ * side.  A comparison with an unbound operand is an error, and the row is
+ * dropped (for != as well).  BOUND and NOT_BOUND take a variable in a.
+ */
+typedef struct {
+  int32_t s, p, o;  /* as in gsmat_pattern; variables 0..n_vars-1 */
+  int32_t branch;   /* union branch (>= 0) */
+  int32_t group;    /* 0 required, > 0 an OPTIONAL group */
+} gsmat_ext_pattern;
+
+#define GSMAT_F_EQ 0
+#define GSMAT_F_NE 1
+#define GSMAT_F_LT 2
+#define GSMAT_F_LE 3
+#define GSMAT_F_GT 4
+#define GSMAT_F_GE 5
+#define GSMAT_F_BOUND 6
+#define GSMAT_F_NOT_BOUND 7
+typedef struct {
+  int32_t op;      /* GSMAT_F_* */
+  int32_t a, b;    /* terms: >= 0 an id, < 0 the variable -(x+1); b unused by BOUND ops */
+  int32_t branch;  /* the branch it filters (a branch may consist of filters only) */
+} gsmat_filter;
+
+/* Evaluates the query.  n_vars (0..31) is the number of result columns: each
+ * variable a term names must be below it, and a variable a row does not bind
+ * is fetched as -1.  Rows come in branch order.  Within a branch their order
+ * is unspecified but fixed for given inputs.  budget_bytes and max_rows act
+ * as in gsmat_join: the budget chunks each BGP step, and max_rows bounds the
+ * final row count (GSMAT_ETOOBIG).  The result has no per-step counters
+ * (n_steps 0).
+ * Errors:
+ *   - The query is checked before the store and before any device work.
+ *   - EINVAL: an empty query, a variable at or above n_vars, a negative branch
+ *     or group, an unknown op, or BOUND on a constant.
+ *   - EUNSUPPORTED: a variable predicate, a BGP of more than 32 patterns, more
+ *     than 16 conditions in a branch, n_vars above 31, a pattern that is not
+ *     well designed, or an OPTIONAL whose left side has 2^31 rows or more. */
+gsmat_status gsmat_join_ext(gsmat_store* st, const gsmat_ext_pattern* pats, int32_t n_pats,
+                            const gsmat_filter* filters, int32_t n_filters, int32_t n_vars,
+                            int64_t budget_bytes, int64_t max_rows, void* stream,
+                            gsmat_result** out);
+
 /* ---- text boundary: dictionary and BGP parser (Sec. 5.2, Sec. 6.3) -------- */
 
 /* A host dictionary: the bijections h_p (predicates) and h_so (subjects and

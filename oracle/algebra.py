@@ -64,10 +64,11 @@ def bgp_rows(s, p, o, tps, n_vars, cap_rows=-1):
     return out
 
 
-def left_join(A, B, b_vars):
+def left_join(A, B, b_vars, cap_rows=-1):
     """SPARQL LeftJoin of the row bags A and B; every row of B binds exactly
     b_vars.  Rows of B are indexed by their values on the variables of
-    b_vars that a row of A binds (one index per such subset)."""
+    b_vars that a row of A binds (one index per such subset).  ValueError
+    once the result holds more than cap_rows rows (cap_rows >= 0)."""
     n_vars = A.shape[1]
     index = {}
 
@@ -88,6 +89,8 @@ def left_join(A, B, b_vars):
                 out.append(np.where(a != UNBOUND, a, b))
         else:
             out.append(a)
+        if 0 <= cap_rows < len(out):
+            raise ValueError("left join result exceeds cap_rows")
     return np.array(out, np.int32).reshape(len(out), n_vars)
 
 
@@ -128,7 +131,8 @@ def filter_ok(row, conds):
 
 def join_ext(s, p, o, pats, filters, n_vars, cap_rows=-1, sort=True):
     """Rows (rows x n_vars int32, -1 unbound) of the query; sorted unless
-    sort=False (then in branch order)."""
+    sort=False (then in branch order).  ValueError when a BGP's intermediate
+    or a left join's result exceeds cap_rows (cap_rows >= 0)."""
     pats = np.asarray(pats, np.int32).reshape(-1, 5)
     filters = np.asarray(filters, np.int32).reshape(-1, 4)
     branches = sorted(set(pats[:, 3].tolist()) | set(filters[:, 3].tolist()))
@@ -139,7 +143,8 @@ def join_ext(s, p, o, pats, filters, n_vars, cap_rows=-1, sort=True):
         omega = bgp_rows(s, p, o, mine[mine[:, 4] == 0][:, :3], n_vars, cap_rows)
         for g in groups:
             tps = mine[mine[:, 4] == g][:, :3]
-            omega = left_join(omega, bgp_rows(s, p, o, tps, n_vars, cap_rows), _vars_of(tps))
+            omega = left_join(omega, bgp_rows(s, p, o, tps, n_vars, cap_rows), _vars_of(tps),
+                              cap_rows)
         conds = [tuple(map(int, f[:3])) for f in filters if f[3] == br]
         if conds:
             keep = [i for i, row in enumerate(omega) if filter_ok(row, conds)]

@@ -42,7 +42,7 @@ EXPORTED = [
     "gsmat_dict_term", "gsmat_parse_bgp", "gsmat_set_hub_options", "gsmat_set_sparse_expand",
     "gsmat_autotune_batch", "gsmat_expand_strategy", "gsmat_set_batch_engine",
     "gsmat_set_batch_regions", "gsmat_batch_round_stats", "gsmat_join_noalloc",
-    "gsmat_set_batch_tuning", "gsmat_get_batch_tuning",
+    "gsmat_set_batch_tuning", "gsmat_get_batch_tuning", "gsmat_join_ext",
 ]
 
 
@@ -119,6 +119,8 @@ def _load():
     L.gsmat_plan_free.argtypes = [vp]
     L.gsmat_join.restype = i32
     L.gsmat_join.argtypes = [vp, vp, i64, i64, vp, pp]
+    L.gsmat_join_ext.restype = i32
+    L.gsmat_join_ext.argtypes = [vp, vp, i32, vp, i32, i32, i64, i64, vp, pp]
     L.gsmat_result_info.restype = i32
     L.gsmat_result_info.argtypes = [vp, vp, vp, vp, vp, vp]
     L.gsmat_fetch_bindings.restype = i32
@@ -376,6 +378,26 @@ def gsmat_join(store, plan, budget_bytes=0, max_rows=-1, stream=None):
     h = ctypes.c_void_p()
     _check(_lib.gsmat_join(store.h, plan.h, budget_bytes, max_rows, _stream(stream),
                            ctypes.byref(h)))
+    return Result(h, store)
+
+
+F_EQ, F_NE, F_LT, F_LE, F_GT, F_GE, F_BOUND, F_NOT_BOUND = range(8)
+
+
+def gsmat_join_ext(store, pats, filters=(), n_vars=None, budget_bytes=0, max_rows=-1,
+                   stream=None):
+    """OPTIONAL / UNION / FILTER query: pats (n, 5) int32 rows (s, p, o, branch,
+    group), filters (m, 4) int32 rows (op, a, b, branch); n_vars defaults to
+    one past the largest variable named.  Returns a Result (unbound = -1)."""
+    pa = np.ascontiguousarray(np.asarray(pats, dtype=np.int32).reshape(-1, 5))
+    fa = np.ascontiguousarray(np.asarray(filters, dtype=np.int32).reshape(-1, 4))
+    if n_vars is None:
+        terms = np.concatenate([pa[:, [0, 2]].ravel(), fa[:, [1, 2]].ravel()])
+        n_vars = int(-terms.min()) if len(terms) and terms.min() < 0 else 0
+    h = ctypes.c_void_p()
+    _check(_lib.gsmat_join_ext(store.h, _p(pa) if pa.size else None, len(pa),
+                               _p(fa) if fa.size else None, len(fa), int(n_vars), budget_bytes,
+                               max_rows, _stream(stream), ctypes.byref(h)))
     return Result(h, store)
 
 

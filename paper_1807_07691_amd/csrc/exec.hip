@@ -77,6 +77,8 @@ struct Exec {
   // synchronises (the allocation-free entry point uses both).
   DeviceMem* dm = nullptr;
   PinnedArea* dev_area = nullptr;
+  // set: final tables are appended here rather than added to res
+  std::vector<Table>* collect = nullptr;
 
   DeviceMem* mem() { return dm ? dm : st->mem.get(); }
 
@@ -174,6 +176,12 @@ struct Exec {
   }
 
   void emit(Table& t) {
+    if (collect) {
+      if (t.owned) forget(t.owned);
+      collect->push_back(t);
+      t.owned = nullptr;
+      return;
+    }
     const int nv = pl->n_vars;
     Segment seg;
     seg.rows = t.n;
@@ -647,6 +655,38 @@ void run_query(gsmat_store* st, const gsmat_query_plan* pl, int64_t budget_bytes
     ex.run(0, unit, all);
   } catch (...) {
     ex.release_all();
+    throw;
+  }
+}
+
+void run_collect(gsmat_store* st, const gsmat_query_plan* pl, const Table* t0,
+                 int64_t budget_bytes, hipStream_t s, std::vector<Table>* out) {
+  for (const gsmat_pattern& q : pl->pats) {
+    if (q.p >= st->P) return;
+    if (!is_var(q.s) && q.s >= st->V) return;
+    if (!is_var(q.o) && q.o >= st->V) return;
+  }
+  gsmat_result counters;  // step counters only (no steps kept)
+  counters.st = st;
+  counters.stream = s;
+  Exec ex{st, pl, s, budget_bytes, -1, &counters, true, {}, nullptr, nullptr, out};
+  Table t;
+  if (t0) {
+    if (t0->owned) throw StatusFail{GSMAT_EHIP, "internal: a starting table must not own memory"};
+    t = *t0;
+  } else {
+    t.n = 1;
+    t.k = 0;
+  }
+  const size_t first = out->size();
+  const uint32_t all = pl->pats.size() >= 32 ? 0xFFFFFFFFu : ((1u << pl->pats.size()) - 1);
+  try {
+    ex.run(0, t, all);
+  } catch (...) {
+    ex.release_all();
+    for (size_t i = first; i < out->size(); ++i)
+      if ((*out)[i].owned) st->mem->free((*out)[i].owned, (*out)[i].owned_bytes, s);
+    out->resize(first);
     throw;
   }
 }

@@ -20,6 +20,8 @@ struct Arena {
   size_t bytes = 0;
   hipStream_t s = nullptr;
   Arena(DeviceMem* m, size_t b, hipStream_t st);
+  // takes over an allocation of b bytes at p made from m
+  Arena(DeviceMem* m, void* p_, size_t b, hipStream_t st) : mem(m), p(p_), bytes(b), s(st) {}
   ~Arena();
   Arena(const Arena&) = delete;
   Arena& operator=(const Arena&) = delete;
@@ -31,6 +33,7 @@ struct Segment {
   void* owned = nullptr;
   size_t owned_bytes = 0;
   std::shared_ptr<Arena> keep;        // arena holding the columns, if any
+  std::shared_ptr<void> hold;         // anything else the columns live in
 };
 
 // Columnar int32 binding table: column c holds variable var[c].  The columns
@@ -89,6 +92,14 @@ constexpr size_t kStageBytes = 4096;
 void run_query(gsmat_store* st, const gsmat_query_plan* pl, int64_t budget_bytes,
                int64_t max_rows, hipStream_t s, gsmat_result* res, DeviceMem* mem = nullptr,
                void* dev_area = nullptr);
+
+// Runs plan pl (adaptive step choice) from table t0, or from the unit table
+// when t0 is null, and appends the final tables to out instead of adding them
+// to a result: each table's owned allocation (if any) passes to the caller,
+// and its columns may also be views into t0 or the store.  t0's columns stay
+// the caller's (t0.owned must be null).
+void run_collect(gsmat_store* st, const gsmat_query_plan* pl, const Table* t0,
+                 int64_t budget_bytes, hipStream_t s, std::vector<Table>* out);
 
 // Per-pattern statistics for the planner; lookups of constant endpoints go
 // to the device in one batch.

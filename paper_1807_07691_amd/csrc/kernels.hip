@@ -390,7 +390,8 @@ __global__ void k_pack_rows(ColSet cols, int k, int64_t row0, int64_t rows,
        e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t r = e / k;
     const int c = (int)(e - r * k);
-    out[e] = cols.c[c][row0 + r];
+    const int32_t* col = cols.c[c];
+    out[e] = col ? col[row0 + r] : -1;  // no column: the variable is unbound
   }
 }
 

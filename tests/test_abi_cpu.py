@@ -220,3 +220,38 @@ def test_hub_and_sparse_options_validate(G):
     assert G.lib().gsmat_autotune_batch(None, None, 0, 0, None, None) == G.GSMAT_EINVAL
     assert G.lib().gsmat_set_batch_tuning(None, 8, 0) == G.GSMAT_EINVAL
     assert G.lib().gsmat_get_batch_tuning(None, None, None, None, None) == G.GSMAT_EINVAL
+
+
+def test_join_ext_validates_the_query_before_the_store(G):
+    """gsmat_join_ext checks the query first (no store, no device work)."""
+    lib = G.lib()
+    out = ctypes.c_void_p()
+
+    def rc(pats, filters=(), n_vars=3, out_p=ctypes.byref(out)):
+        pa = np.ascontiguousarray(np.asarray(pats, np.int32).reshape(-1, 5))
+        fa = np.ascontiguousarray(np.asarray(filters, np.int32).reshape(-1, 4))
+        return lib.gsmat_join_ext(None, pa.ctypes.data_as(ctypes.c_void_p) if pa.size else None,
+                                  len(pa), fa.ctypes.data_as(ctypes.c_void_p) if fa.size else None,
+                                  len(fa), n_vars, 0, -1, None, out_p)
+
+    req = [[-1, 0, -2, 0, 0]]
+    assert rc(req, out_p=None) == G.GSMAT_EINVAL
+    assert rc([]) == G.GSMAT_EINVAL                                   # empty query
+    assert rc([[-4, 0, -2, 0, 0]]) == G.GSMAT_EINVAL                  # variable beyond n_vars
+    assert rc(req, n_vars=32) == G.GSMAT_EUNSUPPORTED
+    assert rc([[-1, -1, -2, 0, 0]]) == G.GSMAT_EUNSUPPORTED           # variable predicate
+    assert rc([[-1, 0, -2, -1, 0]]) == G.GSMAT_EINVAL                 # negative branch
+    assert rc([[-1, 0, -2, 0, -2]]) == G.GSMAT_EINVAL                 # negative group
+    assert rc(req, [[9, -1, -2, 0]]) == G.GSMAT_EINVAL                # unknown op
+    assert rc(req, [[G.F_BOUND, 3, 0, 0]]) == G.GSMAT_EINVAL          # BOUND of a constant
+    assert rc(req, [[G.F_EQ, -1, -7, 0]]) == G.GSMAT_EINVAL           # filter variable too large
+    assert rc(req, [[G.F_EQ, -1, 1, 0]] * 17) == G.GSMAT_EUNSUPPORTED
+    assert rc([[-1, 0, -2, 0, 0]] * 33) == G.GSMAT_EUNSUPPORTED       # a BGP of 33 patterns
+    # not well designed: ?z is shared by two OPTIONAL groups but not required
+    assert rc(req + [[-2, 1, -3, 0, 1], [-3, 1, -1, 0, 2]]) == G.GSMAT_EUNSUPPORTED
+    # ... and the same query with ?z required is accepted (then the NULL store)
+    assert rc(req + [[-2, 1, -3, 0, 0], [-2, 1, -3, 0, 1], [-3, 1, -1, 0, 2]]) == G.GSMAT_EINVAL
+    assert "store" in lib.gsmat_last_error().decode()
+    # another branch may reuse the variable freely; filters may name any variable
+    assert rc(req + [[-2, 1, -3, 0, 1], [-3, 1, -1, 1, 0]], [[G.F_BOUND, -3, 0, 0]]) == G.GSMAT_EINVAL
+    assert "store" in lib.gsmat_last_error().decode()
