@@ -717,12 +717,58 @@ __global__ void k_d_task(DArgs A) {
   A.oc[qi] = kOTask;
 }
 
+// Queries per thread that the single-workgroup kernels hold in registers
+// (batches of up to kAllocRegs * kScanBlock queries).
+constexpr int kAllocRegs = 4;
+
+// The end of k_d_layout: deferrals, the round's tile-sum arrays, and its
+// statistics (t1: total scratch asked; t2: totals of tiles, scratch bytes
+// and algorithmic bytes; tasks: tasks counted this round).
+__device__ inline void d_layout_finish(DArgs& A, DCtl& C, const int64_t (&t1)[1],
+                                       const int64_t (&t2)[3], int64_t tasks, int defer,
+                                       int64_t want) {
+  __shared__ int s_defer;
+  __shared__ unsigned long long s_want;
+  if (threadIdx.x == 0) {
+    s_defer = 0;
+    s_want = 0;
+  }
+  __syncthreads();
+  if (defer) {
+    atomicAdd(&s_defer, defer);
+    atomicMax(&s_want, (unsigned long long)want);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int64_t nt = t2[0];
+    char* base = C.scr_base;
+    C.scr_need = max(C.scr_need, t1[0] + 1024);
+    if (C.round < kStatRounds) {
+      int64_t* st = C.stats[C.round];
+      st[0] = tasks;
+      st[1] = nt;
+      st[6] = C.ncand;
+      st[7] = s_defer;
+    }
+    A.w_cnt[A.nq] = nt;
+    C.ntiles = nt;
+    C.ts = (int64_t*)(base + t2[1]);
+    C.tsn = (int64_t*)(base + t2[1] + d_a256(8 * (nt + 1)));
+    C.scr_used = t2[1] + 2 * d_a256(8 * (nt + 1));
+    C.bytes_count += t2[2];
+    C.ncand = 0;
+    C.active = 0;
+    C.deferred += s_defer;
+    C.want_scr = max(C.want_scr, (int64_t)s_want);
+  }
+}
+
 // Tiles and count-phase scratch of every task (one workgroup of kScanBlock
 // threads; thread t takes a contiguous range of queries).  A task whose
 // scratch (with its share of the tile-sum arrays) does not fit the scratch
 // region is deferred; fitting is a prefix property, so the tasks that run
 // are the first ones in query order.
-__global__ __launch_bounds__(kScanBlock) void k_d_layout(DArgs A) {
+__global__ __launch_bounds__(kScanBlock) void k_d_layout_loop(DArgs A) {
   DCtl& C = *A.ctl;
   const int per = (A.nq + kScanBlock - 1) / kScanBlock;
   const int q0 = min(A.nq, (int)threadIdx.x * per), q1 = min(A.nq, q0 + per);
@@ -759,44 +805,73 @@ __global__ __launch_bounds__(kScanBlock) void k_d_layout(DArgs A) {
     w += A.tk_tiles[q];
     off += A.tk_cb[q];
   }
-  __shared__ int s_defer;
-  __shared__ unsigned long long s_want;
-  if (threadIdx.x == 0) {
-    s_defer = 0;
-    s_want = 0;
-  }
-  __syncthreads();
-  if (defer) {
-    atomicAdd(&s_defer, defer);
-    atomicMax(&s_want, (unsigned long long)want);
-  }
-  __syncthreads();
   // tasks counted this round
   int64_t vt[1] = {0}, et[1], tt[1];
   for (int q = q0; q < q1; ++q) vt[0] += A.oc[q] == kOTask;
   block_excl_scan_n<1>(vt, et, tt);
-  if (threadIdx.x == 0) {
-    const int64_t nt = t2[0];
-    char* base = C.scr_base;
-    C.scr_need = max(C.scr_need, t1[0] + 1024);
-    if (C.round < kStatRounds) {
-      int64_t* st = C.stats[C.round];
-      st[0] = tt[0];
-      st[1] = nt;
-      st[6] = C.ncand;
-      st[7] = s_defer;
-    }
-    A.w_cnt[A.nq] = nt;
-    C.ntiles = nt;
-    C.ts = (int64_t*)(base + t2[1]);
-    C.tsn = (int64_t*)(base + t2[1] + d_a256(8 * (nt + 1)));
-    C.scr_used = t2[1] + 2 * d_a256(8 * (nt + 1));
-    C.bytes_count += t2[2];
-    C.ncand = 0;
-    C.active = 0;
-    C.deferred += s_defer;
-    C.want_scr = max(C.want_scr, (int64_t)s_want);
+  d_layout_finish(A, C, t1, t2, tt[0], defer, want);
+}
+
+// The same with thread t's queries [t * kAP, (t + 1) * kAP) held in
+// registers (every field read once, all loads in flight together); up to
+// kAP * kScanBlock queries.
+template <int kAP>
+__global__ __launch_bounds__(kScanBlock) void k_d_layout(DArgs A) {
+  DCtl& C = *A.ctl;
+  const int q0 = (int)threadIdx.x * kAP;
+  const int64_t cap = C.scr_cap;
+  int32_t oc[kAP];
+  int64_t cost[kAP], tiles[kAP], cb[kAP], alg[kAP];
+#pragma unroll
+  for (int j = 0; j < kAP; ++j) {
+    const int q = q0 + j;
+    const bool in = q < A.nq;
+    oc[j] = in ? A.oc[q] : kONone;
+    cost[j] = in ? A.tk_cost[q] : 0;
+    tiles[j] = in ? A.tk_tiles[q] : 0;
+    cb[j] = in ? A.tk_cb[q] : 0;
+    alg[j] = in ? A.tk_alg[q] : 0;
   }
+  int64_t v1[1] = {0}, e1[1], t1[1];
+#pragma unroll
+  for (int j = 0; j < kAP; ++j)
+    if (oc[j] == kOTask) v1[0] += cost[j];
+  block_excl_scan_n<1>(v1, e1, t1);
+  int64_t v2[4] = {0, 0, 0, 0}, e2[4], t2x[4];  // tiles, scratch, algorithmic bytes, tasks
+  int64_t run = e1[0];
+  int defer = 0;
+  int64_t want = 0;
+#pragma unroll
+  for (int j = 0; j < kAP; ++j) {
+    if (oc[j] != kOTask) continue;
+    run += cost[j];
+    if (run + 1024 > cap) {
+      oc[j] = kODefer;
+      A.oc[q0 + j] = kODefer;
+      ++defer;
+      want = max(want, cost[j] + 1024);
+      continue;
+    }
+    v2[0] += tiles[j];
+    v2[1] += cb[j];
+    v2[2] += alg[j];
+    v2[3] += 1;
+  }
+  block_excl_scan_n<4>(v2, e2, t2x);
+  int64_t w = e2[0], off = e2[1];
+#pragma unroll
+  for (int j = 0; j < kAP; ++j) {
+    const int q = q0 + j;
+    if (q >= A.nq) break;
+    A.w_cnt[q] = w;
+    if (oc[j] != kOTask) continue;
+    A.cnt_off[q] = off;
+    A.ne[q] = 0;
+    w += tiles[j];
+    off += cb[j];
+  }
+  const int64_t t2[3] = {t2x[0], t2x[1], t2x[2]};
+  d_layout_finish(A, C, t1, t2, t2x[3], defer, want);
 }
 
 template <int kT, int kS>
@@ -894,13 +969,61 @@ __global__ void k_d_outcome(DArgs A) {
   A.wz_alg_write[qi] = alg_write;
 }
 
-// Output tables and write scratch of the tables to write, bump-allocated;
-// the launch groups' first tiles.  One workgroup of kScanBlock threads.
-// The round's outputs above the round budget send the later queries to the
-// single-query executor; a table or scratch that does not fit the current
-// regions waits for a later round.  Both rules keep a prefix of the tasks in
-// query order.
-__global__ __launch_bounds__(kScanBlock) void k_d_alloc(DArgs A) {
+// k_d_alloc: output tables and write scratch of the tables to write,
+// bump-allocated; the launch groups' first tiles.  One workgroup of
+// kScanBlock threads.  The round's outputs above the round budget send the
+// later queries to the single-query executor; a table or scratch that does
+// not fit the current regions waits for a later round.  Both rules keep a
+// prefix of the tasks in query order.
+//
+// Its end: the round's totals, deferrals and statistics (tc: totals of the
+// seven per-table sums; tb: of the two table sizes).
+__device__ inline void d_alloc_finish(DArgs& A, DCtl& C, const int64_t (&tc)[7],
+                                      const int64_t (&tb)[2], int defer, int64_t want_o,
+                                      int64_t want_s, int64_t out_used, int64_t scr_used) {
+  __shared__ int s_defer;
+  __shared__ unsigned long long s_wo, s_ws;
+  if (threadIdx.x == 0) {
+    s_defer = 0;
+    s_wo = s_ws = 0;
+  }
+  __syncthreads();
+  if (defer) {
+    atomicAdd(&s_defer, defer);
+    atomicMax(&s_wo, (unsigned long long)want_o);
+    atomicMax(&s_ws, (unsigned long long)want_s);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    A.w_post[A.nq] = tc[0];
+    A.w_part[A.nq] = tc[1];
+    A.w_write[A.nq] = tc[2];
+    C.n_post = tc[0];
+    C.n_part = tc[1];
+    C.n_write = tc[2];
+    C.out_used = out_used + tc[3];
+    C.scr_used = scr_used + tc[4];
+    C.scr_peak = max(C.scr_peak, C.scr_used);
+    C.scr_need = max(C.scr_need, scr_used + tb[1]);
+    if (C.round < kStatRounds) {
+      int64_t* st = C.stats[C.round];
+      st[2] = tc[0];
+      st[3] = tc[2];
+      st[4] = tc[1];  // split entries: tables written + path tiles
+      st[5] = tc[3];
+      st[7] += s_defer;
+    }
+    C.round += 1;
+    C.bytes_post += tc[5];
+    C.bytes_write += tc[6];
+    C.deferred += s_defer;
+    C.want_out = max(C.want_out, (int64_t)s_wo);
+    C.want_scr = max(C.want_scr, (int64_t)s_ws);
+  }
+}
+
+// Any number of queries: thread t takes queries [t * per, (t + 1) * per).
+__global__ __launch_bounds__(kScanBlock) void k_d_alloc_loop(DArgs A) {
   DCtl& C = *A.ctl;
   const int per = (A.nq + kScanBlock - 1) / kScanBlock;
   const int q0 = min(A.nq, (int)threadIdx.x * per), q1 = min(A.nq, q0 + per);
@@ -962,45 +1085,101 @@ __global__ __launch_bounds__(kScanBlock) void k_d_alloc(DArgs A) {
     wq += A.wz_part[q];
     ww += A.wz_write[q];
   }
-  __shared__ int s_defer;
-  __shared__ unsigned long long s_wo, s_ws;
-  if (threadIdx.x == 0) {
-    s_defer = 0;
-    s_wo = s_ws = 0;
+  d_alloc_finish(A, C, tc, tb, defer, want_o, want_s, out_used, scr_used);
+}
+
+// Up to kAP * kScanBlock queries: thread t holds queries [t * kAP, (t + 1) *
+// kAP) in registers, every field read once with all loads in flight together
+// (the loop above waits for each query's loads in turn).  Same rules, same
+// results.
+template <int kAP>
+__global__ __launch_bounds__(kScanBlock) void k_d_alloc(DArgs A) {
+  DCtl& C = *A.ctl;
+  const int q0 = (int)threadIdx.x * kAP;
+  int32_t oc[kAP];
+  int64_t ob[kAP], sb[kAP], zp[kAP], zq[kAP], zw[kAP], ap[kAP], aw[kAP], cost[kAP];
+#pragma unroll
+  for (int j = 0; j < kAP; ++j) {
+    const int q = q0 + j;
+    const bool in = q < A.nq;
+    oc[j] = in ? A.oc[q] : kONone;
+    ob[j] = in ? A.wz_ob[q] : 0;
+    sb[j] = in ? A.wz_sb[q] : 0;
+    zp[j] = in ? A.wz_post[q] : 0;
+    zq[j] = in ? A.wz_part[q] : 0;
+    zw[j] = in ? A.wz_write[q] : 0;
+    ap[j] = in ? A.wz_alg_post[q] : 0;
+    aw[j] = in ? A.wz_alg_write[q] : 0;
+    cost[j] = in ? A.tk_cost[q] : 0;
   }
-  __syncthreads();
-  if (defer) {
-    atomicAdd(&s_defer, defer);
-    atomicMax(&s_wo, (unsigned long long)want_o);
-    atomicMax(&s_ws, (unsigned long long)want_s);
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    A.w_post[A.nq] = tc[0];
-    A.w_part[A.nq] = tc[1];
-    A.w_write[A.nq] = tc[2];
-    C.n_post = tc[0];
-    C.n_part = tc[1];
-    C.n_write = tc[2];
-    C.out_used = out_used + tc[3];
-    C.scr_used = scr_used + tc[4];
-    C.scr_peak = max(C.scr_peak, C.scr_used);
-    C.scr_need = max(C.scr_need, scr_used + tb[1]);
-    if (C.round < kStatRounds) {
-      int64_t* st = C.stats[C.round];
-      st[2] = tc[0];
-      st[3] = tc[2];
-      st[4] = tc[1];  // split entries: tables written + path tiles
-      st[5] = tc[3];
-      st[7] += s_defer;
+  int64_t va[1] = {0}, ea[1], ta[1];
+#pragma unroll
+  for (int j = 0; j < kAP; ++j)
+    if (oc[j] == kOWrite) va[0] += ob[j];
+  block_excl_scan_n<1>(va, ea, ta);
+  int64_t vb[2] = {0, 0}, eb[2], tb[2];
+  int64_t run = ea[0];
+  bool changed[kAP];
+#pragma unroll
+  for (int j = 0; j < kAP; ++j) {
+    changed[j] = false;
+    if (oc[j] != kOWrite) continue;
+    const bool over = A.round_budget > 0 && run > 0 && run + ob[j] > A.round_budget;
+    run += ob[j];
+    if (over) {
+      oc[j] = kOFallback;
+      changed[j] = true;
+      continue;
     }
-    C.round += 1;
-    C.bytes_post += tc[5];
-    C.bytes_write += tc[6];
-    C.deferred += s_defer;
-    C.want_out = max(C.want_out, (int64_t)s_wo);
-    C.want_scr = max(C.want_scr, (int64_t)s_ws);
+    vb[0] += ob[j];
+    vb[1] += sb[j];
   }
+  block_excl_scan_n<2>(vb, eb, tb);
+  int64_t vc[7] = {0, 0, 0, 0, 0, 0, 0}, ec[7], tc[7];
+  int64_t ro = eb[0], rs = eb[1];
+  const int64_t out_used = C.out_used, scr_used = C.scr_used;
+  const int64_t out_cap = C.out_cap, scr_cap = C.scr_cap;
+  int defer = 0;
+  int64_t want_o = 0, want_s = 0;
+#pragma unroll
+  for (int j = 0; j < kAP; ++j) {
+    if (oc[j] != kOWrite) continue;
+    if (out_used + ro + ob[j] <= out_cap && scr_used + rs + sb[j] <= scr_cap) {
+      A.out_off[q0 + j] = out_used + ro;
+      A.scr_off[q0 + j] = scr_used + rs;
+      vc[0] += zp[j];
+      vc[1] += zq[j];
+      vc[2] += zw[j];
+      vc[3] += ob[j];
+      vc[4] += sb[j];
+      vc[5] += ap[j];
+      vc[6] += aw[j];
+    } else {
+      oc[j] = kODefer;
+      changed[j] = true;
+      ++defer;
+      want_o = max(want_o, ob[j]);
+      want_s = max(want_s, cost[j] + sb[j] + 1024);
+    }
+    ro += ob[j];
+    rs += sb[j];
+  }
+  block_excl_scan_n<7>(vc, ec, tc);
+  int64_t wp = ec[0], wq = ec[1], ww = ec[2];
+#pragma unroll
+  for (int j = 0; j < kAP; ++j) {
+    const int q = q0 + j;
+    if (q >= A.nq) break;
+    A.w_post[q] = wp;
+    A.w_part[q] = wq;
+    A.w_write[q] = ww;
+    if (changed[j]) A.oc[q] = oc[j];
+    if (oc[j] != kOWrite) continue;
+    wp += zp[j];
+    wq += zq[j];
+    ww += zw[j];
+  }
+  d_alloc_finish(A, C, tc, tb, defer, want_o, want_s, out_used, scr_used);
 }
 
 // Write descriptors of the tables to write.
@@ -1391,12 +1570,20 @@ void run_batch_device(gsmat_store* st, const gsmat_query_plan* const* plans, int
       GS_DLAUNCH(GSMAT_K_OTHER, k_d_choose, qgrid, kQBlock, A, 1);
       GS_DLAUNCH(GSMAT_K_OTHER, k_d_sample, grids.sample, kBlock, A.cands, A.part, A.ctl);
       GS_DLAUNCH(GSMAT_K_OTHER, k_d_task, qgrid, kQBlock, A);
-      GS_DLAUNCH(GSMAT_K_SCAN, k_d_layout, 1, kScanBlock, A);
+      if (nq <= kAllocRegs * kScanBlock) {
+        GS_DLAUNCH(GSMAT_K_SCAN, k_d_layout<kAllocRegs>, 1, kScanBlock, A);
+      } else {
+        GS_DLAUNCH(GSMAT_K_SCAN, k_d_layout_loop, 1, kScanBlock, A);
+      }
       launch_count(st->count_items, st->intersect, s, A, nq,
                    [&](unsigned floor_) { return hinted(gr, 1, floor_); });
       GS_DLAUNCH(GSMAT_K_SCAN, k_d_scan, 1, kScanBlock, A);
       GS_DLAUNCH(GSMAT_K_OTHER, k_d_outcome, qgrid, kQBlock, A);
-      GS_DLAUNCH(GSMAT_K_SCAN, k_d_alloc, 1, kScanBlock, A);
+      if (nq <= kAllocRegs * kScanBlock) {
+        GS_DLAUNCH(GSMAT_K_SCAN, k_d_alloc<kAllocRegs>, 1, kScanBlock, A);
+      } else {
+        GS_DLAUNCH(GSMAT_K_SCAN, k_d_alloc_loop, 1, kScanBlock, A);
+      }
       GS_DLAUNCH(GSMAT_K_OTHER, k_d_describe, qgrid, kQBlock, A);
       GS_DLAUNCH(GSMAT_K_COMPACT, k_d_post, hinted(gr, 2, grids.post), kBlock, A.wt, A.w_post,
                  nq, A.ctl);

@@ -325,6 +325,26 @@ def test_batch_shapes(G, O, mode):
     _check_batch(G, st, [t for t, _ in SHAPES], mode, oracle_rows=want)
 
 
+@pytest.mark.parametrize("regions", [(0, 0), (64 << 10, 8 << 10)])
+def test_batch_past_register_kernels(G, O, regions):
+    """More than 4096 queries in one batch (the shapes, a few rows each): the
+    single-workgroup kernels that hold four queries per thread in registers
+    give way to their looping versions, also with tasks deferred for want of
+    space."""
+    rng = np.random.default_rng(7)
+    s, p, o = (rng.integers(0, 12, 150).astype(np.int32), rng.integers(0, 3, 150).astype(np.int32),
+               rng.integers(0, 12, 150).astype(np.int32))
+    st = _store(G, s, p, o, 100, 8)
+    want = [O.join(s, p, o, t, nv) for t, nv in SHAPES]
+    reps = 4200 // len(SHAPES) + 1
+    queries = [t for t, _ in SHAPES] * reps
+    assert len(queries) > 4096 and sum(len(w) for w in want) * reps < 10**6
+    print(f"[gpu] batch of {len(queries)} queries, regions={regions}", flush=True)
+    G.gsmat_set_batch_regions(st, *regions)
+    _check_batch(G, st, queries, G.PLAN_ADAPTIVE, oracle_rows=want * reps)
+    st.close()
+
+
 @pytest.mark.parametrize("seed", range(8))
 def test_batch_random_graphs(G, O, seed):
     rng = np.random.default_rng(900 + seed)
