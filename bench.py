@@ -128,6 +128,8 @@ def main():
                     help="batch workload: 1 device-driven rounds, 0 host-driven rounds")
     ap.add_argument("--no-serve", action="store_true",
                     help="batch workload: skip the served-vs-plain comparison at --rates")
+    ap.add_argument("--serve-detail", action="store_true",
+                    help="serving comparison: log each mode's slowest queries (kind, arrival, ms)")
     ap.add_argument("--no-ext", action="store_true",
                     help="batch workload: skip the OPTIONAL / FILTER pass")
     ap.add_argument("--no-plain", action="store_true",
@@ -784,7 +786,10 @@ def serve_rates(args, G, light, heavy, st, sh, mode):
             k = nxt
             while k < n and t_arr[k] <= now:
                 k += 1
-            if k > nxt:
+            if k == nxt + 1:  # one arrival: planned alone
+                G.gsmat_server_submit(sv, G.gsmat_plan(st, qs[nxt].tps, mode, stream=sh), nxt)
+                nxt = k
+            elif k > nxt:
                 plans, _ = G.gsmat_plan_batch(st, [q.tps for q in qs[nxt:k]], mode, stream=sh,
                                               as_set=True)
                 for i in range(k - nxt):
@@ -799,7 +804,7 @@ def serve_rates(args, G, light, heavy, st, sh, mode):
             steps += 1
             rounds_active += a
             if d:
-                fin = G.gsmat_server_poll(sv)
+                fin = G.gsmat_server_poll(sv, cap=d)
                 tf = time.perf_counter() - t0
                 for tag, r, status in fin:
                     lat[tag] = tf - t_arr[tag]
@@ -842,10 +847,13 @@ def serve_rates(args, G, light, heavy, st, sh, mode):
             gc_pauses.append((info.get("generation"), round((time.perf_counter() - _t[0]) * 1e3, 2)))
     gc.callbacks.append(gc_cb)
     ms = lambda x: round(float(x) * 1e3, 3)  # noqa: E731
-    # warm both paths (allocator, pinned buffers, code objects)
+    # warm both paths (allocator, pinned buffers, code objects); every heavy
+    # query once, so that neither timed loop meets a result size the device
+    # allocator has not cached yet (the loop run first would pay for it)
     t_w, q_w, _ = arrivals(2000, 0.25, 99)
     run_served(t_w, q_w)
     run_plain(t_w, q_w)
+    run_plain(np.zeros(len(heavy)), list(heavy))
     # the driver loops are Python: objects made before timing are frozen and
     # the collector is off while requests run (a full collection paused the
     # loop for ~47 ms), for the served and the plain loop alike
@@ -882,6 +890,13 @@ def serve_rates(args, G, light, heavy, st, sh, mode):
                       "p99_ms": ms(np.percentile(lat_p, 99)),
                       "makespan_s": round(wall_p, 3)},
         }
+        if args.serve_detail:
+            heavy_ids = {id(q) for q in heavy}
+            for name, lat in (("served", lat_s), ("plain", lat_p)):
+                worst = np.argsort(-lat)[:14]
+                log(f"  {name} slowest: " + ", ".join(
+                    f"{'H' if id(qs[i]) in heavy_ids else 'L'}@{t_arr[i] * 1e3:.1f}:"
+                    f"{lat[i] * 1e3:.2f}" for i in worst))
         log(f"  served p50 {r['served']['p50_ms']} ms p99 {r['served']['p99_ms']} ms "
             f"{r['served']['bindings_per_s']:.3g} b/s ({steps} steps, {mean_active:.1f} active); "
             f"plain p50 {r['plain']['p50_ms']} ms p99 {r['plain']['p99_ms']} ms "

@@ -492,9 +492,10 @@ gsmat_status gsmat_parse_bgp(const gsmat_dict* d, const char* text, size_t len,
  * gsmat_server_step admits what fits and runs one step of every admitted
  * query as one batched round (as in gsmat_join_batch with host-driven
  * rounds), so queries that arrive while others run join them at the next
- * round; a query alone in the server that has not started, with nothing
- * waiting, is instead run to completion by the single-query executor within
- * that step (later arrivals are admitted together afterwards).  A round whose
+ * round; when the server holds at most two queries, none started and none
+ * waiting, the step instead runs the oldest to completion with the
+ * single-query executor (the other waits for the next step; later arrivals
+ * are admitted at the next step).  A round whose
  * outputs would exceed mem_budget_bytes defers the later queries' steps to
  * the next round (the first always runs).  step_budget_bytes and max_rows
  * apply per query as in gsmat_join (a step above step_budget_bytes finishes

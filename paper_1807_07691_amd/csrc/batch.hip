@@ -1054,6 +1054,10 @@ extern "C" gsmat_status gsmat_server_submit(gsmat_server* sv, const gsmat_query_
   });
 }
 
+// Queries the server runs one after another instead of batching them (see
+// gsmat_server_step).
+constexpr int kAloneMax = 2;
+
 extern "C" gsmat_status gsmat_server_step(gsmat_server* sv, int32_t* n_active, int32_t* n_waiting,
                                           int32_t* n_done) {
   return guarded([&]() -> gsmat_status {
@@ -1061,20 +1065,25 @@ extern "C" gsmat_status gsmat_server_step(gsmat_server* sv, int32_t* n_active, i
     sv->admit();
     sv->bt.sparse_theta = sv->st->sparse_theta;
     sv->bt.sparse_min_rows = sv->st->sparse_min_rows;
-    int active = 0;
-    BQ* only = nullptr;
+    int active = 0, fresh = 0;
     for (BQ& b : sv->bt.q)
       if (b.state == kActive) {
         ++active;
-        only = &b;
+        fresh += b.si == 0 && b.t.unit();
       }
-    // A query alone in the server (nothing else active or waiting, not
-    // started) runs to completion with the single-query executor: a round of
-    // the batch would only add its host bookkeeping and a second wait per
-    // step.  Queries arriving meanwhile are admitted together afterwards.
-    if (active == 1 && sv->waiting.empty() && only->si == 0 && only->t.unit()) {
-      only->state = kFallback;
-      only->t = Table();
+    // At most kAloneMax queries in the server, none started and none waiting:
+    // the oldest runs to completion with the single-query executor and the
+    // step returns, so its result can be polled before the next one runs.
+    // For so few queries the batch's rounds cost more than running them one
+    // after another (each round adds its host bookkeeping and a second wait
+    // per step).  Queries arriving meanwhile are admitted at the next step.
+    if (active > 0 && active <= kAloneMax && fresh == active && sv->waiting.empty()) {
+      for (BQ& b : sv->bt.q)
+        if (b.state == kActive) {
+          b.state = kFallback;
+          b.t = Table();
+          break;
+        }
       active = 0;
     }
     const bool any = active > 0;
