@@ -43,10 +43,11 @@ def _vars_of(tps):
     return sorted({-t - 1 for tp in tps for t in (tp[0], tp[2]) if t < 0})
 
 
-def bgp_rows(s, p, o, tps, n_vars, cap_rows=-1):
+def bgp_rows(s, p, o, tps, n_vars, cap_rows=-1, bgp=None):
     """Solutions of one BGP as rows over all n_vars variables (-1 where the
     BGP has no such variable); no pattern: one row with every variable
-    unbound."""
+    unbound.  bgp(local_tps, n_local, cap_rows) replaces the oracle join over
+    (s, p, o) when given (for instance a prebuilt Dataset's join)."""
     tps = [list(map(int, t)) for t in tps]
     if not tps:
         return np.full((1, n_vars), UNBOUND, np.int32)
@@ -57,7 +58,10 @@ def bgp_rows(s, p, o, tps, n_vars, cap_rows=-1):
         return -loc[-t - 1] - 1 if t < 0 else t
 
     local = np.array([[rn(a), b, rn(c)] for a, b, c in tps], np.int32)
-    r = join(s, p, o, local, len(used), cap_rows=cap_rows)
+    if bgp is not None:
+        r = bgp(local, len(used), cap_rows)
+    else:
+        r = join(s, p, o, local, len(used), cap_rows=cap_rows)
     out = np.full((len(r), n_vars), UNBOUND, np.int32)
     for v, i in loc.items():
         out[:, v] = r[:, i]
@@ -152,5 +156,50 @@ def join_ext(s, p, o, pats, filters, n_vars, cap_rows=-1, sort=True):
         parts.append(omega)
     out = (np.concatenate(parts) if parts else np.zeros((0, n_vars), np.int32)).astype(np.int32)
     if sort and len(out) and n_vars:
+        out = out[np.lexsort(out.T[::-1])]
+    return out
+
+
+def join_ext_wd(bgp, pats, filters, n_vars, cap_rows=-1):
+    """The answer of join_ext for well-designed queries (every variable an
+    OPTIONAL group shares with the rest of its branch occurs in the required
+    BGP), computed from inner joins: for each OPTIONAL group g, the BGP
+    required + g is joined by bgp(local_tps, n_local, cap_rows) and its rows
+    are grouped by their required values; a required row r then takes, group
+    after group, every merge with its extensions, or stays as it is when it
+    has none (what LeftJoin keeps when the shared variables are all bound).
+    Suited to large triple sets, where a group's own relation is too big for
+    the left join's index."""
+    pats = np.asarray(pats, np.int32).reshape(-1, 5)
+    filters = np.asarray(filters, np.int32).reshape(-1, 4)
+    branches = sorted(set(pats[:, 3].tolist()) | set(filters[:, 3].tolist()))
+    parts = []
+    for br in branches:
+        mine = pats[pats[:, 3] == br]
+        req = [list(map(int, t)) for t in mine[mine[:, 4] == 0][:, :3]]
+        req_vars = _vars_of(req)
+        base = bgp_rows(None, None, None, req, n_vars, cap_rows, bgp=bgp)
+        ext = []
+        for g in sorted(set(mine[:, 4].tolist()) - {0}):
+            both = req + [list(map(int, t)) for t in mine[mine[:, 4] == g][:, :3]]
+            index = {}
+            for row in bgp_rows(None, None, None, both, n_vars, cap_rows, bgp=bgp):
+                index.setdefault(tuple(int(row[v]) for v in req_vars), []).append(row)
+            ext.append(index)
+        conds = [tuple(map(int, f[:3])) for f in filters if f[3] == br]
+        out = []
+        for r in base:
+            key = tuple(int(r[v]) for v in req_vars)
+            rows = [r]
+            for index in ext:
+                e = index.get(key)
+                if e:
+                    rows = [np.where(a != UNBOUND, a, b) for a in rows for b in e]
+                if 0 <= cap_rows < len(out) + len(rows):
+                    raise ValueError("result exceeds cap_rows")
+            out += [x for x in rows if not conds or filter_ok(x, conds)]
+        parts.append(np.array(out, np.int32).reshape(len(out), n_vars))
+    out = np.concatenate(parts) if parts else np.zeros((0, n_vars), np.int32)
+    if len(out) and n_vars:
         out = out[np.lexsort(out.T[::-1])]
     return out

@@ -20,6 +20,9 @@ against the tree counts, 48 sampled queries row for row against the plain
 join, a spread of 32 queries over every result-size decade against the
 oracle's sorted rows; under a 16 MiB budget the largest results leave the
 batch for the chunked single-query path, with the same counts and rows.
+
+OPTIONAL / FILTER / UNION queries built on batch BGPs (the benchmark's shape):
+sorted rows against the oracle.
 """
 import numpy as np
 import pytest
@@ -301,3 +304,39 @@ def test_batch_full_size_small_budget(G, large, batch):
           f"queries equal to the plain join", flush=True)
     results.close()
     plans.close()
+
+
+@pytest.mark.timeout(900)
+def test_ext_full_size(G, large, batch):
+    """OPTIONAL / FILTER / UNION queries on the 200M-triple graph in the shape
+    the benchmark times (a batch BGP as the required group, an OPTIONAL
+    expansion of its last variable along its first predicate, FILTER(?v0 !=
+    ?v1); every fourth query also a second branch with the BGP alone under
+    FILTER(BOUND(?v0))), against the oracle's inner-join form of the well-
+    designed left join on the prebuilt triple set."""
+    from oracle import algebra as A
+    spec, s, p, o, _, st, ds = large
+    bgp = lambda t, nv, cap: ds.join(t, nv, cap_rows=cap)  # noqa: E731
+    picked = [q for q in batch[::8] if 2 <= q.n_vars <= 30 and 10 <= q.count <= 20_000][:16]
+    checked = rows = 0
+    for i, q in enumerate(picked):
+        tps = np.asarray(q.tps, np.int32).reshape(-1, 3)
+        nv = q.n_vars
+        pats = [[int(a), int(b), int(c), 0, 0] for a, b, c in tps]
+        pats.append([-nv, int(tps[0, 1]), -(nv + 1), 0, 1])
+        filt = [[G.F_NE, -1, -2, 0]]
+        if i % 4 == 3:
+            pats += [[int(a), int(b), int(c), 1, 0] for a, b, c in tps]
+            filt.append([G.F_BOUND, -1, 0, 1])
+        try:
+            want = A.join_ext_wd(bgp, pats, filt, nv + 1, cap_rows=2_000_000)
+        except ValueError:  # an intermediate above the oracle's cap
+            continue
+        r = G.gsmat_join_ext(st, pats, filt, nv + 1, BUDGET)
+        got = G.gsmat_fetch_bindings(r)
+        r.close()
+        assert np.array_equal(_sorted(got), want), i
+        checked += 1
+        rows += len(want)
+    print(f"[gpu] ext full size: {checked} queries, {rows} rows against the oracle", flush=True)
+    assert checked >= 10

@@ -164,3 +164,29 @@ def test_filter_comparisons_by_hand():
     for op in (A.F_EQ, A.F_NE, A.F_LT, A.F_LE, A.F_GT, A.F_GE):
         assert not A.filter_ok(row, [(op, -2, 5)])
     assert A.filter_ok(row, [(A.F_NOT_BOUND, -2, 0), (A.F_BOUND, -3, 0)])
+
+
+@pytest.mark.parametrize("seed", range(150))
+def test_inner_join_form_equals_left_join(seed):
+    """join_ext_wd (inner joins of required + each OPTIONAL group, grouped by
+    the required values) gives join_ext's answer on well-designed queries."""
+    rng = np.random.default_rng(9000 + seed)
+    V, P = int(rng.integers(2, 7)), int(rng.integers(1, 3))
+    s, p, o = _triples(rng, V, P, int(rng.integers(3, 25)))
+    n_vars = int(rng.integers(1, 5))
+    while True:
+        pats, filters = _random_query(rng, V, P, n_vars, well_designed=True)
+        ok = True
+        for br in set(pats[:, 3].tolist()):
+            mine = pats[pats[:, 3] == br]
+            req = set(A._vars_of(mine[mine[:, 4] == 0][:, :3]))
+            groups = sorted(set(mine[:, 4].tolist()) - {0})
+            for g in groups:
+                mv = set(A._vars_of(mine[mine[:, 4] == g][:, :3]))
+                rest = req.union(*[A._vars_of(mine[mine[:, 4] == h][:, :3]) for h in groups if h != g])
+                ok &= not (mv & rest - req)
+        if ok:
+            break
+    bgp = lambda t, nv, cap: O.join(s, p, o, t, nv, cap_rows=cap)  # noqa: E731
+    assert np.array_equal(A.join_ext_wd(bgp, pats, filters, n_vars),
+                          A.join_ext(s, p, o, pats, filters, n_vars)), (pats.tolist(), filters.tolist())
