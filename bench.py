@@ -130,6 +130,10 @@ def main():
                     help="batch workload: skip the served-vs-plain comparison at --rates")
     ap.add_argument("--serve-detail", action="store_true",
                     help="serving comparison: log each mode's slowest queries (kind, arrival, ms)")
+    ap.add_argument("--pipeline", action="store_true",
+                    help="batch workload: plan the next pass on a second host thread and "
+                         "stream while the current one joins (default: each pass is planned "
+                         "after the previous one's join)")
     ap.add_argument("--no-ext", action="store_true",
                     help="batch workload: skip the OPTIONAL / FILTER pass")
     ap.add_argument("--no-plain", action="store_true",
@@ -515,10 +519,11 @@ def bench_batch(args, G, W, spec, qspec, queries, st, sh, budget, mode, stats, l
     # ---- batched: warmup (diagnostics, count and row checks), then timed
     log(f"batched warmup x{max(1, args.warmup)}")
     nwarm = max(1, args.warmup)
+    warm_phase = []
     for w in range(nwarm):
         if w == nwarm - 1:  # per-class counters of the last warmup pass (regions and grids settled)
             G.gsmat_prof_enable(0x1F)
-        plans, results = batch_pass()
+        plans, results = batch_pass(warm_phase)
         if w == nwarm - 1:
             wprof = G.gsmat_prof_read()
             whost = G.gsmat_prof_host()
@@ -558,19 +563,52 @@ def bench_batch(args, G, W, spec, qspec, queries, st, sh, budget, mode, stats, l
     total_rows = 0
     host0 = G.gsmat_prof_host()
     t0 = time.perf_counter()
-    for k in range(args.steps):
-        a = time.perf_counter()
-        h0 = G.gsmat_prof_host()
-        plans, results = batch_pass(phase)
-        total_rows += int(results.rows().sum())
-        results.close()
-        plans.close()
-        step_s.append(time.perf_counter() - a)
-        h1 = G.gsmat_prof_host()
-        log(f"step {k + 1}/{args.steps}: {step_s[-1] * 1e3:.1f} ms (plan {phase[-1][0] * 1e3:.1f}, "
-            f"join {phase[-1][1] * 1e3:.1f}; host alloc {h1['alloc_ms'] - h0['alloc_ms']:.1f} ms "
-            f"in {h1['allocs'] - h0['allocs']}, sync {h1['sync_ms'] - h0['sync_ms']:.1f} ms "
-            f"in {h1['syncs'] - h0['syncs']})")
+    if not args.pipeline:
+        for k in range(args.steps):
+            a = time.perf_counter()
+            h0 = G.gsmat_prof_host()
+            plans, results = batch_pass(phase)
+            total_rows += int(results.rows().sum())
+            results.close()
+            plans.close()
+            step_s.append(time.perf_counter() - a)
+            h1 = G.gsmat_prof_host()
+            log(f"step {k + 1}/{args.steps}: {step_s[-1] * 1e3:.1f} ms (plan "
+                f"{phase[-1][0] * 1e3:.1f}, join {phase[-1][1] * 1e3:.1f}; host alloc "
+                f"{h1['alloc_ms'] - h0['alloc_ms']:.1f} ms in {h1['allocs'] - h0['allocs']}, "
+                f"sync {h1['sync_ms'] - h0['sync_ms']:.1f} ms in {h1['syncs'] - h0['syncs']})")
+    else:
+        # pass k + 1 is planned on a second host thread and stream while pass
+        # k joins (ctypes calls release the GIL), starting with the join: its
+        # planning lookup then runs before the join's kernels fill the device
+        # (started later, it waits behind them).  Every plan and join of the
+        # K passes is inside the timed region, and a pass's latency runs from
+        # the start of its planning to the end of its join.
+        import concurrent.futures as cf
+        plan_stream = torch.cuda.Stream()
+        psh = int(plan_stream.cuda_stream)
+
+        def plan_next():
+            a_ = time.perf_counter()
+            pl_, _ = G.gsmat_plan_batch(st, packed, mode, stream=psh, as_set=True)
+            return a_, time.perf_counter(), pl_
+
+        with cf.ThreadPoolExecutor(1) as pool:
+            fut = pool.submit(plan_next)
+            for k in range(args.steps):
+                a, b, plans = fut.result()
+                bj = time.perf_counter()
+                if k + 1 < args.steps:
+                    fut = pool.submit(plan_next)
+                results, _ = G.gsmat_join_batch(st, plans, budget, -1, stream=sh, as_set=True)
+                c = time.perf_counter()
+                total_rows += int(results.rows().sum())
+                results.close()
+                plans.close()
+                phase.append((b - a, c - bj))
+                step_s.append(c - a)
+                log(f"pass {k + 1}/{args.steps}: planned {(b - a) * 1e3:.1f} ms, joined "
+                    f"{(c - bj) * 1e3:.1f} ms, {(c - a) * 1e3:.1f} ms from planning to results")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     host1 = G.gsmat_prof_host()
@@ -630,6 +668,9 @@ def bench_batch(args, G, W, spec, qspec, queries, st, sh, budget, mode, stats, l
                         f"{spec.T} triples; {nq} random-walk BGPs of 1-6 patterns, result "
                         f"sizes log-uniform over 1..1e6 rows",
             "mode": "batched (gsmat_plan_batch + gsmat_join_batch over all queries per step)",
+            "pipeline": None if not args.pipeline else
+            "the next pass is planned on a second host thread and stream while the current "
+            "pass joins; all plans and joins of the timed passes are inside the timed region",
             "engine": "device-driven rounds" if args.engine == 1 else "host-driven rounds",
             "dense_div": args.dense_div or 32,
             "plan_mode": mode,
@@ -640,7 +681,8 @@ def bench_batch(args, G, W, spec, qspec, queries, st, sh, budget, mode, stats, l
         "p50_ms": ms(percentile(step_s, 0.5)),
         "p99_ms": ms(percentile(step_s, 0.99)),
         "latency_kind": "pass completion: all queries of a pass are submitted together and "
-                        "every one completes with the pass (not a single query's latency)",
+                        "every one completes with the pass (not a single query's latency); "
+                        "from the start of the pass's planning to the end of its join",
         "host_waits_per_step": round((host1["syncs"] - host0["syncs"]) / args.steps, 2),
         "autotune": tune,
         "plan_batch_ms": ms(sum(x for x, _ in phase) / len(phase)),
