@@ -568,13 +568,17 @@ def bench_batch(args, G, W, spec, qspec, queries, st, sh, budget, mode, stats, l
             a = time.perf_counter()
             h0 = G.gsmat_prof_host()
             plans, results = batch_pass(phase)
+            c0 = time.perf_counter()
             total_rows += int(results.rows().sum())
             results.close()
+            c1 = time.perf_counter()
             plans.close()
             step_s.append(time.perf_counter() - a)
+            c2 = time.perf_counter()
             h1 = G.gsmat_prof_host()
             log(f"step {k + 1}/{args.steps}: {step_s[-1] * 1e3:.1f} ms (plan "
-                f"{phase[-1][0] * 1e3:.1f}, join {phase[-1][1] * 1e3:.1f}; host alloc "
+                f"{phase[-1][0] * 1e3:.1f}, join {phase[-1][1] * 1e3:.1f}, results freed "
+                f"{(c1 - c0) * 1e3:.2f}, plans freed {(c2 - c1) * 1e3:.2f}; host alloc "
                 f"{h1['alloc_ms'] - h0['alloc_ms']:.1f} ms in {h1['allocs'] - h0['allocs']}, "
                 f"sync {h1['sync_ms'] - h0['sync_ms']:.1f} ms in {h1['syncs'] - h0['syncs']})")
     else:

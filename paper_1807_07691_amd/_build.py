@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 SO = os.path.join(HERE, "libgsmat.so")
-SOURCES = ["api.cpp", "plan.cpp", "dict.cpp", "kernels.hip", "store.hip", "exec.hip", "kernels_batch.hip", "batch.hip", "dbatch.hip", "ext.hip"]
+SOURCES = ["api.cpp", "plan.cpp", "dict.cpp", "kernels.hip", "store.hip", "exec.hip", "kernels_batch.hip", "batch.hip", "dbatch.hip", "ext.hip", "host_pool.cpp"]
 ARCH = os.environ.get("GSMAT_OFFLOAD_ARCH", "gfx950")
 
 

@@ -32,6 +32,7 @@
 
 #include "batch.hpp"
 #include "exec.hpp"
+#include "host_pool.hpp"
 
 using namespace gsmat;
 
@@ -1325,32 +1326,41 @@ extern "C" gsmat_status gsmat_plan_batch(const gsmat_store* st, const gsmat_patt
       }
     }
     const std::vector<LookupRes> res = lookup_many(st, req, s);
+    // the plans are independent: built on the host pool's threads
+    host_parallel_for(n_queries, 256, [&](int64_t lo, int64_t hi) {
+      for (int64_t i = lo; i < hi; ++i) {
+        if (rc[i] != GSMAT_OK) continue;
+        try {
+          const gsmat_pattern* pq = pats + off[i];
+          TpStat* ts = stats.data() + so[i];
+          const int* ro = req_of.data() + so[i];
+          for (int j = 0; j < n_pats[i]; ++j) {
+            const int r = ro[j];
+            if (r < 0) continue;
+            const bool both = !is_var(pq[j].s) && !is_var(pq[j].o);
+            const int64_t v = both ? res[r].found : res[r].len;
+            ts[j].stat = ts[j].rows_s = ts[j].rows_o = v;
+          }
+          std::unique_ptr<gsmat_query_plan> pl(new gsmat_query_plan);
+          rc[i] = build_plan(pq, n_pats[i], mode, ts, pl.get(), &msg[i]);
+          if (rc[i] == GSMAT_OK && mode != GSMAT_PLAN_PAPER) {
+            pl->lk.assign(n_pats[i], gsmat_pat_lookup{});
+            for (int j = 0; j < n_pats[i]; ++j) {
+              const int r = ro[j];
+              if (r >= 0) pl->lk[j] = gsmat_pat_lookup{res[r].start, res[r].len, res[r].found, 1};
+            }
+            pl->lk_store = st->uid;
+          }
+          if (rc[i] == GSMAT_OK) out[i] = pl.release();
+        } catch (...) {
+          rc[i] = GSMAT_ENOMEM;
+          msg[i] = "host memory exhausted while planning";
+        }
+      }
+    });
     gsmat_status first = GSMAT_OK;
     std::string first_err;
     for (int i = 0; i < n_queries; ++i) {
-      if (rc[i] == GSMAT_OK) {
-        const gsmat_pattern* pq = pats + off[i];
-        TpStat* ts = stats.data() + so[i];
-        const int* ro = req_of.data() + so[i];
-        for (int j = 0; j < n_pats[i]; ++j) {
-          const int r = ro[j];
-          if (r < 0) continue;
-          const bool both = !is_var(pq[j].s) && !is_var(pq[j].o);
-          const int64_t v = both ? res[r].found : res[r].len;
-          ts[j].stat = ts[j].rows_s = ts[j].rows_o = v;
-        }
-        std::unique_ptr<gsmat_query_plan> pl(new gsmat_query_plan);
-        rc[i] = build_plan(pq, n_pats[i], mode, ts, pl.get(), &msg[i]);
-        if (rc[i] == GSMAT_OK && mode != GSMAT_PLAN_PAPER) {
-          pl->lk.assign(n_pats[i], gsmat_pat_lookup{});
-          for (int j = 0; j < n_pats[i]; ++j) {
-            const int r = ro[j];
-            if (r >= 0) pl->lk[j] = gsmat_pat_lookup{res[r].start, res[r].len, res[r].found, 1};
-          }
-          pl->lk_store = st->uid;
-        }
-        if (rc[i] == GSMAT_OK) out[i] = pl.release();
-      }
       if (status) status[i] = rc[i];
       if (rc[i] != GSMAT_OK && first == GSMAT_OK) {
         first = rc[i];
