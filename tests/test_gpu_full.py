@@ -23,6 +23,10 @@ batch for the chunked single-query path, with the same counts and rows.
 
 OPTIONAL / FILTER / UNION queries built on batch BGPs (the benchmark's shape):
 sorted rows against the oracle.
+
+served (640 batch BGPs and 4 heavy ones through gsmat_server in uneven
+waves): every count against the tree counts, rows against the plain join and
+the oracle.
 """
 import numpy as np
 import pytest
@@ -340,3 +344,65 @@ def test_ext_full_size(G, large, batch):
         rows += len(want)
     print(f"[gpu] ext full size: {checked} queries, {rows} rows against the oracle", flush=True)
     assert checked >= 10
+
+
+@pytest.mark.timeout(900)
+def test_served_full_size(G, large, batch):
+    """The serving configuration on the 200M-triple graph: 640 batch BGPs
+    (every sixth of the set) and 4 heavy BGPs of 5e7-2e8 rows submitted to
+    gsmat_server in uneven waves (queries join rounds already under way):
+    every row count against the generator's tree count, every 20th light
+    result row for row against the plain join, and the light results of up to
+    1e4 rows over the whole set against the oracle's sorted rows."""
+    import workload as W
+    spec, s, p, o, _, st, ds = large
+    gi = W.GraphIndex(s, p, o, spec.V, spec.P)
+    heavy = W.gen_heavy_queries(gi, spec)[:4]
+    gi.close()
+    light = batch[::6][:640]
+    qs = light[:300] + heavy[:2] + light[300:] + heavy[2:]
+    waves = [1, 3, 17, 2, 64, 1, 1, 40, 128, 5, 9, 200, 2, 7, 33, 1, 150] + [20] * 20
+    sv = G.gsmat_server_new(st, 200 * 10**9, BUDGET, -1, 1 << 20)
+    got, nxt, steps = {}, 0, 0
+    try:
+        for w in waves + [0] * 100_000:
+            for _ in range(w):
+                if nxt < len(qs):
+                    G.gsmat_server_submit(sv, G.gsmat_plan(st, qs[nxt].tps, G.PLAN_ADAPTIVE), nxt)
+                    nxt += 1
+            G.gsmat_server_step(sv)
+            steps += 1
+            for tag, r, status in G.gsmat_server_poll(sv):
+                assert status == 0 and r is not None, (tag, status)
+                info = G.gsmat_result_info(r)
+                rows = G.gsmat_fetch_bindings(r) if qs[tag].count <= 2 * 10**6 else None
+                got[tag] = (info["rows"], rows)
+                r.close()
+            if nxt == len(qs) and len(got) == len(qs):
+                break
+    finally:
+        sv.close()
+    assert [got[i][0] for i in range(len(qs))] == [q.count for q in qs]
+    plain = oracle_checked = 0
+    heavy_ids = {id(h) for h in heavy}
+    for i, q in enumerate(qs):
+        if id(q) in heavy_ids:
+            continue
+        if i % 20 == 0:
+            pl = G.gsmat_plan(st, q.tps, G.PLAN_ADAPTIVE)
+            r = G.gsmat_join(st, pl, BUDGET)
+            assert np.array_equal(got[i][1], G.gsmat_fetch_bindings(r)), i
+            r.close()
+            pl.close()
+            plain += 1
+        if q.count <= 10**4 and i % 7 == 0:
+            try:
+                want = ds.join(q.tps, q.n_vars, cap_rows=2 * 10**7)
+            except ValueError:
+                continue
+            assert np.array_equal(_sorted(got[i][1]), want), i
+            oracle_checked += 1
+    print(f"[gpu] served full size: {len(qs)} queries in {steps} steps, counts equal, "
+          f"{plain} row for row against the plain join, {oracle_checked} against the oracle",
+          flush=True)
+    assert plain >= 30 and oracle_checked >= 20
