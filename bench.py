@@ -121,7 +121,7 @@ def main():
                     help="batch workload: force the count rows per thread (after any autotuning)")
     ap.add_argument("--intersect", choices=("search", "window", "merge"), default=None,
                     help="batch workload: force the intersection strategy (after any autotuning)")
-    ap.add_argument("--dense-div", type=int, default=256,
+    ap.add_argument("--dense-div", type=int, default=1024,
                     help="index build: predicates with at least V/dense_div non-empty rows get a "
                          "dense row pointer (0: the library default, 32)")
     ap.add_argument("--engine", type=int, default=1,
