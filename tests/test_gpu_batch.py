@@ -187,9 +187,9 @@ def test_batch_tuning_tiny(G, tiny, tuning):
     G.gsmat_set_batch_tuning(st, *tuning)
     G.gsmat_set_sparse_expand(st, 1.0, 1)
     try:
-        queries = [q.tps for q in qs] * 4
-        for mode in (0, 1, 2):
-            _check_batch(G, st, queries, mode, oracle_rows=want * 4)
+        queries = [q.tps for q in qs] * 2
+        for mode in (1, 2):  # the modes that plan star intersections
+            _check_batch(G, st, queries, mode, oracle_rows=want * 2)
     finally:
         G.gsmat_set_batch_tuning(st, 8, G.ISECT_SEARCH)
         G.gsmat_set_sparse_expand(st, 0.5, 4096)
