@@ -103,7 +103,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="batch",
-                    choices=["tiny", "medium", "large", "batch", "serve"])
+                    choices=["tiny", "medium", "large", "batch", "serve", "ext"])
     ap.add_argument("--rates", default="500,2000,8000",
                     help="serve workload: Poisson arrival rates (queries/s)")
     ap.add_argument("--serve-seconds", type=float, default=2.0,
@@ -157,7 +157,7 @@ def main():
     torch.cuda.set_device(0)
     import paper_1807_07691_amd as G
 
-    batch = args.workload in ("batch", "serve")
+    batch = args.workload in ("batch", "serve", "ext")
     spec, qspec = W.CONFIGS["large" if batch else args.workload]
     if batch:
         qspec = W.BATCH
@@ -191,6 +191,30 @@ def main():
 
     budget = int(args.budget_gb * 2**30)
     mode = args.plan_mode
+    if args.workload == "ext":
+        # the OPTIONAL / FILTER pass alone, as its own line
+        ext = ext_pass(args, G, queries, st, sh, budget, mode)
+        out = {
+            "metric": "OPTIONAL / FILTER result rows/sec (one query at a time)",
+            "value": ext["rows_per_s"],
+            "unit": "rows/s",
+            "n_gpus": 1,
+            "steps": 3,
+            "warmup": 1,
+            "ms_per_step": ext["pass_ms"],
+            "higher_is_better": True,
+            "scaling": "weak",
+            "vs_baseline": None,
+            "dtype": "int32",
+            "data": "synthetic",
+            "config": {"workload": f"ext: {ext['queries']} OPTIONAL / FILTER queries on the batch "
+                                   f"BGPs of the {spec.T}-triple graph", "plan_mode": mode,
+                       "parallelism": "single-gpu"},
+            "ext": ext,
+        }
+        print(json.dumps(out), flush=True)
+        st.close()
+        return
     if args.workload == "serve":
         gi = W.GraphIndex(s, p, o, spec.V, spec.P)
         heavy = W.gen_heavy_queries(gi, spec)
