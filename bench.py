@@ -710,7 +710,9 @@ def bench_batch(args, G, W, spec, qspec, queries, st, sh, budget, mode, stats, l
         "p99_ms": ms(percentile(step_s, 0.99)),
         "latency_kind": "pass completion: all queries of a pass are submitted together and "
                         "every one completes with the pass (not a single query's latency); "
-                        "from the start of the pass's planning to the end of its join",
+                        + ("from the start of the pass's planning to the end of its join"
+                           if args.pipeline else
+                           "the pass's planning, join and the freeing of its results and plans"),
         "host_waits_per_step": round((host1["syncs"] - host0["syncs"]) / args.steps, 2),
         "autotune": tune,
         "plan_batch_ms": ms(sum(x for x, _ in phase) / len(phase)),
