@@ -10,7 +10,8 @@
 //     match come out already merged with their T row; a kernel marks the ids
 //     that survived, and the rows of T never marked are compacted out and
 //     kept with B's variables unbound;
-//   * FILTER evaluates its conditions per row and compacts;
+//   * FILTER evaluates its conditions per row and compacts; conditions on the
+//     required variables and constants alone run before the left joins;
 //   * UNION is the concatenation of the branches' tables.
 // A query's result is a list of column tables ("parts"), each binding a
 // subset of the variables; a variable a part lacks is unbound (fetched as -1).
@@ -458,9 +459,21 @@ extern "C" gsmat_status gsmat_join_ext(gsmat_store* st, const gsmat_ext_pattern*
     res->reset_steps(0);
     XRun x{st, s, budget_bytes};
     for (const XBranch& br : branches) {
+      // conditions on required variables and constants only hold or fail the
+      // same before the left joins (those variables are bound in every row and
+      // a left join never changes them): applied first, on the smaller table
+      const uint64_t req = vars_of(br.req);
+      std::vector<XCond> early, late;
+      for (const XCond& c : br.conds) {
+        const bool cmp = c.op != GSMAT_F_BOUND && c.op != GSMAT_F_NOT_BOUND;
+        bool on_req = !is_var(c.a) || (req >> var_of(c.a) & 1);
+        if (cmp) on_req = on_req && (!is_var(c.b) || (req >> var_of(c.b) & 1));
+        (on_req ? early : late).push_back(c);
+      }
       std::vector<XPart> parts = x.bgp(br.req);
+      if (!early.empty()) parts = x.filter(std::move(parts), early);
       for (const auto& g : br.opt) parts = x.left_join(std::move(parts), g);
-      if (!br.conds.empty()) parts = x.filter(std::move(parts), br.conds);
+      if (!late.empty()) parts = x.filter(std::move(parts), late);
       for (XPart& p : parts) {
         if (p.n == 0) continue;
         Segment seg;
