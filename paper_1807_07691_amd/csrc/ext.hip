@@ -22,6 +22,7 @@
 // T, so the match is an equi-join on bound columns.
 
 #include <algorithm>
+#include <cstdint>
 #include <memory>
 #include <string>
 #include <vector>
@@ -282,11 +283,13 @@ struct XRun {
       p.col[p.k] = t.col[c];
       p.var[p.k] = map[c];
       ++p.k;
-      const char* a = (const char*)t.col[c];
-      for (const auto& h : from)
-        if (a >= (const char*)h->p && a < (const char*)h->p + h->bytes &&
+      const uintptr_t a = (uintptr_t)t.col[c];
+      for (const auto& h : from) {
+        const uintptr_t lo = (uintptr_t)h->p;
+        if (a >= lo && a < lo + h->bytes &&
             std::find(p.keep.begin(), p.keep.end(), h) == p.keep.end())
           p.keep.push_back(h);
+      }
     }
     return p;
   }
