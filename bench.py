@@ -130,6 +130,9 @@ def main():
                     help="batch workload: skip the served-vs-plain comparison at --rates")
     ap.add_argument("--serve-detail", action="store_true",
                     help="serving comparison: log each mode's slowest queries (kind, arrival, ms)")
+    ap.add_argument("--two-call", action="store_true",
+                    help="batch workload: gsmat_plan_batch + gsmat_join_batch per pass instead "
+                         "of the fused gsmat_join_batch_bgp")
     ap.add_argument("--pipeline", action="store_true",
                     help="batch workload: plan the next pass on a second host thread and "
                          "stream while the current one joins (default: each pass is planned "
@@ -513,8 +516,21 @@ def bench_batch(args, G, W, spec, qspec, queries, st, sh, budget, mode, stats, l
     packed = G.pack_queries(tps)
     G.gsmat_set_batch_engine(st, args.engine)
 
+    fused = args.engine == 1 and not args.two_call and not args.pipeline
+
+    class _NoPlans:
+        def close(self):
+            pass
+
     def batch_pass(phase=None):
         a = time.perf_counter()
+        if fused:  # planning inside the one call
+            results, _ = G.gsmat_join_batch_bgp(st, packed, mode, budget, -1, stream=sh,
+                                                as_set=True)
+            c = time.perf_counter()
+            if phase is not None:
+                phase.append((0.0, c - a))
+            return _NoPlans(), results
         plans, _ = G.gsmat_plan_batch(st, packed, mode, stream=sh, as_set=True)
         b = time.perf_counter()
         results, _ = G.gsmat_join_batch(st, plans, budget, -1, stream=sh, as_set=True)
@@ -695,7 +711,9 @@ def bench_batch(args, G, W, spec, qspec, queries, st, sh, budget, mode, stats, l
             "workload": f"batch: {spec.V} vertices, {spec.P} predicates Zipf({spec.zipf_s}), "
                         f"{spec.T} triples; {nq} random-walk BGPs of 1-6 patterns, result "
                         f"sizes log-uniform over 1..1e6 rows",
-            "mode": "batched (gsmat_plan_batch + gsmat_join_batch over all queries per step)",
+            "mode": ("batched (gsmat_join_batch_bgp: planning and the device-driven join of all "
+                     "queries in one call per step)") if fused else
+                    "batched (gsmat_plan_batch + gsmat_join_batch over all queries per step)",
             "pipeline": None if not args.pipeline else
             "the next pass is planned on a second host thread and stream while the current "
             "pass joins; all plans and joins of the timed passes are inside the timed region",

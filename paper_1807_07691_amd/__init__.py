@@ -43,6 +43,7 @@ EXPORTED = [
     "gsmat_autotune_batch", "gsmat_expand_strategy", "gsmat_set_batch_engine",
     "gsmat_set_batch_regions", "gsmat_batch_round_stats", "gsmat_join_noalloc",
     "gsmat_set_batch_tuning", "gsmat_get_batch_tuning", "gsmat_join_ext",
+    "gsmat_join_batch_bgp",
 ]
 
 
@@ -119,6 +120,8 @@ def _load():
     L.gsmat_plan_free.argtypes = [vp]
     L.gsmat_join.restype = i32
     L.gsmat_join.argtypes = [vp, vp, i64, i64, vp, pp]
+    L.gsmat_join_batch_bgp.restype = i32
+    L.gsmat_join_batch_bgp.argtypes = [vp, vp, vp, i32, i32, i64, i64, vp, vp, vp]
     L.gsmat_join_ext.restype = i32
     L.gsmat_join_ext.argtypes = [vp, vp, i32, vp, i32, i32, i64, i64, vp, pp]
     L.gsmat_result_info.restype = i32
@@ -525,6 +528,27 @@ def gsmat_join_batch(store, plans, budget_bytes=0, max_rows=-1, stream=None,
     st = np.zeros(max(nq, 1), np.int32)
     rc = _lib.gsmat_join_batch(store.h, ph, nq, budget_bytes, max_rows, _stream(stream), hs,
                                _p(st))
+    msg = _lib.gsmat_last_error().decode(errors="replace") if rc != GSMAT_OK else ""
+    if rc != GSMAT_OK and raise_on_error:
+        _lib.gsmat_result_free_many(hs, nq)
+        raise GsmatError(rc, msg)
+    statuses = st[:nq].tolist()
+    if as_set:
+        return ResultSet(hs, nq, store), statuses
+    return [Result(ctypes.c_void_p(hs[i]), store) if hs[i] else None for i in range(nq)], statuses
+
+
+def gsmat_join_batch_bgp(store, queries, mode=PLAN_ADAPTIVE, budget_bytes=0, max_rows=-1,
+                         stream=None, raise_on_error=True, as_set=False):
+    """Plans and joins several BGPs in one call (no plan objects): queries is a
+    list of (n, 3) pattern arrays or the (flat, n_pats) pair of pack_queries.
+    Returns (results, statuses) as gsmat_join_batch does."""
+    flat, n_pats = queries if isinstance(queries, tuple) else pack_queries(queries)
+    nq = len(n_pats)
+    hs = (ctypes.c_void_p * max(nq, 1))()
+    st = np.zeros(max(nq, 1), np.int32)
+    rc = _lib.gsmat_join_batch_bgp(store.h, _p(flat), _p(n_pats), nq, mode, budget_bytes,
+                                   max_rows, _stream(stream), hs, _p(st))
     msg = _lib.gsmat_last_error().decode(errors="replace") if rc != GSMAT_OK else ""
     if rc != GSMAT_OK and raise_on_error:
         _lib.gsmat_result_free_many(hs, nq)

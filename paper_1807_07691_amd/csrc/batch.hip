@@ -1187,6 +1187,68 @@ gsmat_status join_batch_device(gsmat_store* st, const gsmat_query_plan* const* p
 
 }  // namespace
 
+extern "C" gsmat_status gsmat_join_batch_bgp(gsmat_store* st, const gsmat_pattern* pats,
+                                             const int32_t* n_pats, int32_t n_queries,
+                                             int32_t mode, int64_t budget_bytes, int64_t max_rows,
+                                             void* stream, gsmat_result** out,
+                                             gsmat_status* status) {
+  return guarded([&]() -> gsmat_status {
+    if (n_queries < 0) throw StatusFail{GSMAT_EINVAL, "negative query count"};
+    if (n_queries > 0 && (!out || !n_pats || !pats))
+      throw StatusFail{GSMAT_EINVAL, "pats, n_pats or out is NULL"};
+    for (int i = 0; i < n_queries; ++i) out[i] = nullptr;
+    if (!st) throw StatusFail{GSMAT_EINVAL, "store is NULL"};
+    if (!st->built) throw StatusFail{GSMAT_ESTATE, "index not built"};
+    if (mode != GSMAT_PLAN_PAPER && mode != GSMAT_PLAN_DEFAULT && mode != GSMAT_PLAN_ADAPTIVE)
+      throw StatusFail{GSMAT_EINVAL, "unknown plan mode " + std::to_string(mode)};
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<DevQueryOut> dq;
+    std::vector<gsmat_status> prc;
+    std::vector<std::string> pmsg;
+    std::vector<std::unique_ptr<gsmat_query_plan>> fb;
+    run_batch_device_bgp(st, pats, n_pats, n_queries, mode, budget_bytes, max_rows, s, dq, prc,
+                         pmsg, fb);
+    bool alone = false;
+    gsmat_status first = GSMAT_OK;
+    std::string first_err;
+    for (int i = 0; i < n_queries; ++i) {
+      gsmat_status rc = prc[i];
+      std::string err = rc != GSMAT_OK ? pmsg[i] : std::string();
+      if (rc == GSMAT_OK) {
+        rc = dq[i].status;
+        if (dq[i].state == kDevFallback) {
+          alone = true;
+          std::unique_ptr<gsmat_result> r(new gsmat_result);
+          r->st = st;
+          r->stream = s;
+          r->n_vars = fb[i]->n_vars;
+          r->reset_steps(fb[i]->steps.size());
+          rc = guarded([&]() -> gsmat_status {
+            run_query(st, fb[i].get(), budget_bytes, max_rows, s, r.get());
+            return GSMAT_OK;
+          });
+          if (rc == GSMAT_OK) out[i] = r.release();
+          else err = gsmat_last_error();
+        } else if (dq[i].state == kDevDone) {
+          out[i] = dq[i].res;
+        } else if (rc == GSMAT_ETOOBIG) {
+          err = "result exceeds max_rows (" + std::to_string(max_rows) + ")";
+        } else {
+          err = "query failed";
+        }
+      }
+      if (status) status[i] = rc;
+      if (rc != GSMAT_OK && first == GSMAT_OK) {
+        first = rc;
+        first_err = "query " + std::to_string(i) + ": " + err;
+      }
+    }
+    if (alone) host_sync(s);
+    if (first != GSMAT_OK) throw StatusFail{first, first_err};
+    return GSMAT_OK;
+  });
+}
+
 extern "C" gsmat_status gsmat_join_batch(gsmat_store* st, const gsmat_query_plan* const* plans,
                                          int32_t n_plans, int64_t budget_bytes, int64_t max_rows,
                                          void* stream, gsmat_result** out, gsmat_status* status) {
@@ -1267,6 +1329,87 @@ extern "C" gsmat_status gsmat_join_batch(gsmat_store* st, const gsmat_query_plan
   });
 }
 
+namespace gsmat {
+
+void plan_prepare(const gsmat_store* st, const gsmat_pattern* pats, const int32_t* n_pats,
+                  int32_t nq, int32_t mode, hipStream_t s, PlanPrep* pp) {
+  PlanPrep& P = *pp;
+  // off: first pattern of each query; so: its first statistics slot (a query
+  // over the pattern limit fails validation and takes none)
+  P.off.assign(nq + 1, 0);
+  P.so.assign(nq + 1, 0);
+  for (int i = 0; i < nq; ++i) {
+    if (n_pats[i] < 0) throw StatusFail{GSMAT_EINVAL, "negative pattern count"};
+    P.off[i + 1] = P.off[i] + n_pats[i];
+    P.so[i + 1] = P.so[i] + (n_pats[i] <= kMaxPats ? n_pats[i] : 0);
+  }
+  P.rc.assign(nq, GSMAT_OK);
+  P.msg.assign(nq, std::string());
+  P.nv.assign(nq, 0);
+  P.stats.assign(P.so[nq], TpStat{});
+  P.req_of.assign(P.so[nq], -1);
+  std::vector<LookupReq> req;
+  req.reserve(P.so[nq]);
+  for (int i = 0; i < nq; ++i) {
+    const gsmat_pattern* pq = pats + P.off[i];
+    const int n = n_pats[i];
+    P.rc[i] = validate_patterns(pq, n, &P.nv[i], &P.msg[i]);
+    if (P.rc[i] != GSMAT_OK) continue;
+    // the statistics pattern_stats gathers, with the lookups pooled
+    TpStat* ts = P.stats.data() + P.so[i];
+    int* ro = P.req_of.data() + P.so[i];
+    for (int j = 0; j < n; ++j) {
+      const gsmat_pattern& p = pq[j];
+      TpStat& t = ts[j];
+      if (p.p < 0 || p.p >= st->P) continue;
+      t.stat = st->out.desc[p.p].nnz;
+      t.rows_s = st->out.desc[p.p].nr;
+      t.rows_o = st->in.desc[p.p].nr;
+      if (mode == GSMAT_PLAN_PAPER) continue;
+      const bool sc = !is_var(p.s), oc = !is_var(p.o);
+      if ((sc && p.s >= st->V) || (oc && p.o >= st->V)) {
+        t.stat = t.rows_s = t.rows_o = 0;
+        continue;
+      }
+      if (!sc && !oc) continue;
+      ro[j] = (int)req.size();
+      if (sc && oc) req.push_back({0, p.p, p.s, p.o});
+      else if (sc) req.push_back({0, p.p, p.s, -1});
+      else req.push_back({1, p.p, p.o, -1});
+    }
+  }
+  P.res = lookup_many(st, req, s);
+}
+
+gsmat_status plan_build(const gsmat_store* st, const gsmat_pattern* pats, const int32_t* n_pats,
+                        int32_t mode, PlanPrep& P, int64_t i, gsmat_query_plan* pl) {
+  const gsmat_pattern* pq = pats + P.off[i];
+  TpStat* ts = P.stats.data() + P.so[i];
+  const int* ro = P.req_of.data() + P.so[i];
+  for (int j = 0; j < n_pats[i]; ++j) {
+    const int r = ro[j];
+    if (r < 0) continue;
+    const bool both = !is_var(pq[j].s) && !is_var(pq[j].o);
+    const int64_t v = both ? P.res[r].found : P.res[r].len;
+    ts[j].stat = ts[j].rows_s = ts[j].rows_o = v;
+  }
+  const gsmat_status rc = build_plan(pq, n_pats[i], mode, ts, pl, &P.msg[i]);
+  if (rc == GSMAT_OK && mode != GSMAT_PLAN_PAPER) {
+    pl->lk.assign(n_pats[i], gsmat_pat_lookup{});
+    for (int j = 0; j < n_pats[i]; ++j) {
+      const int r = ro[j];
+      if (r >= 0) pl->lk[j] = gsmat_pat_lookup{P.res[r].start, P.res[r].len, P.res[r].found, 1};
+    }
+    pl->lk_store = st->uid;
+  } else {
+    pl->lk.clear();
+    pl->lk_store = 0;
+  }
+  return rc;
+}
+
+}  // namespace gsmat
+
 extern "C" gsmat_status gsmat_plan_batch(const gsmat_store* st, const gsmat_pattern* pats,
                                          const int32_t* n_pats, int32_t n_queries, int32_t mode,
                                          void* stream, gsmat_query_plan** out,
@@ -1280,91 +1423,29 @@ extern "C" gsmat_status gsmat_plan_batch(const gsmat_store* st, const gsmat_patt
     if (!st->built) throw StatusFail{GSMAT_ESTATE, "index not built"};
     if (mode != GSMAT_PLAN_PAPER && mode != GSMAT_PLAN_DEFAULT && mode != GSMAT_PLAN_ADAPTIVE)
       throw StatusFail{GSMAT_EINVAL, "unknown plan mode " + std::to_string(mode)};
-    hipStream_t s = (hipStream_t)stream;
-    // off: first pattern of each query; so: its first statistics slot (a
-    // query over the pattern limit fails validation and takes none)
-    std::vector<int64_t> off(n_queries + 1, 0), so(n_queries + 1, 0);
-    for (int i = 0; i < n_queries; ++i) {
-      if (n_pats[i] < 0) throw StatusFail{GSMAT_EINVAL, "negative pattern count"};
-      off[i + 1] = off[i] + n_pats[i];
-      so[i + 1] = so[i] + (n_pats[i] <= kMaxPats ? n_pats[i] : 0);
-    }
-    std::vector<gsmat_status> rc(n_queries, GSMAT_OK);
-    std::vector<std::string> msg(n_queries);
-    // per pattern, flat over the batch: statistics and lookup request index
-    std::vector<TpStat> stats(so[n_queries]);
-    std::vector<int> req_of(so[n_queries], -1);
-    std::vector<LookupReq> req;
-    req.reserve(so[n_queries]);
-    for (int i = 0; i < n_queries; ++i) {
-      const gsmat_pattern* pq = pats + off[i];
-      const int n = n_pats[i];
-      int32_t nv = 0;
-      rc[i] = validate_patterns(pq, n, &nv, &msg[i]);
-      if (rc[i] != GSMAT_OK) continue;
-      // the statistics pattern_stats gathers, with the lookups pooled
-      TpStat* ts = stats.data() + so[i];
-      int* ro = req_of.data() + so[i];
-      for (int j = 0; j < n; ++j) {
-        const gsmat_pattern& p = pq[j];
-        TpStat& t = ts[j];
-        if (p.p < 0 || p.p >= st->P) continue;
-        t.stat = st->out.desc[p.p].nnz;
-        t.rows_s = st->out.desc[p.p].nr;
-        t.rows_o = st->in.desc[p.p].nr;
-        if (mode == GSMAT_PLAN_PAPER) continue;
-        const bool sc = !is_var(p.s), oc = !is_var(p.o);
-        if ((sc && p.s >= st->V) || (oc && p.o >= st->V)) {
-          t.stat = t.rows_s = t.rows_o = 0;
-          continue;
-        }
-        if (!sc && !oc) continue;
-        ro[j] = (int)req.size();
-        if (sc && oc) req.push_back({0, p.p, p.s, p.o});
-        else if (sc) req.push_back({0, p.p, p.s, -1});
-        else req.push_back({1, p.p, p.o, -1});
-      }
-    }
-    const std::vector<LookupRes> res = lookup_many(st, req, s);
+    PlanPrep P;
+    plan_prepare(st, pats, n_pats, n_queries, mode, (hipStream_t)stream, &P);
     // the plans are independent: built on the host pool's threads
     host_parallel_for(n_queries, 256, [&](int64_t lo, int64_t hi) {
       for (int64_t i = lo; i < hi; ++i) {
-        if (rc[i] != GSMAT_OK) continue;
+        if (P.rc[i] != GSMAT_OK) continue;
         try {
-          const gsmat_pattern* pq = pats + off[i];
-          TpStat* ts = stats.data() + so[i];
-          const int* ro = req_of.data() + so[i];
-          for (int j = 0; j < n_pats[i]; ++j) {
-            const int r = ro[j];
-            if (r < 0) continue;
-            const bool both = !is_var(pq[j].s) && !is_var(pq[j].o);
-            const int64_t v = both ? res[r].found : res[r].len;
-            ts[j].stat = ts[j].rows_s = ts[j].rows_o = v;
-          }
           std::unique_ptr<gsmat_query_plan> pl(new gsmat_query_plan);
-          rc[i] = build_plan(pq, n_pats[i], mode, ts, pl.get(), &msg[i]);
-          if (rc[i] == GSMAT_OK && mode != GSMAT_PLAN_PAPER) {
-            pl->lk.assign(n_pats[i], gsmat_pat_lookup{});
-            for (int j = 0; j < n_pats[i]; ++j) {
-              const int r = ro[j];
-              if (r >= 0) pl->lk[j] = gsmat_pat_lookup{res[r].start, res[r].len, res[r].found, 1};
-            }
-            pl->lk_store = st->uid;
-          }
-          if (rc[i] == GSMAT_OK) out[i] = pl.release();
+          P.rc[i] = plan_build(st, pats, n_pats, mode, P, i, pl.get());
+          if (P.rc[i] == GSMAT_OK) out[i] = pl.release();
         } catch (...) {
-          rc[i] = GSMAT_ENOMEM;
-          msg[i] = "host memory exhausted while planning";
+          P.rc[i] = GSMAT_ENOMEM;
+          P.msg[i] = "host memory exhausted while planning";
         }
       }
     });
     gsmat_status first = GSMAT_OK;
     std::string first_err;
     for (int i = 0; i < n_queries; ++i) {
-      if (status) status[i] = rc[i];
-      if (rc[i] != GSMAT_OK && first == GSMAT_OK) {
-        first = rc[i];
-        first_err = "query " + std::to_string(i) + ": " + msg[i];
+      if (status) status[i] = P.rc[i];
+      if (P.rc[i] != GSMAT_OK && first == GSMAT_OK) {
+        first = P.rc[i];
+        first_err = "query " + std::to_string(i) + ": " + P.msg[i];
       }
     }
     if (first != GSMAT_OK) throw StatusFail{first, first_err};

@@ -2,7 +2,12 @@
 // and the batched kernels (kernels_batch.hip), and the launchers.
 #pragma once
 
+#include <memory>
+#include <string>
+#include <vector>
+
 #include "common.hpp"
+#include "plan.hpp"
 
 namespace gsmat {
 
@@ -88,6 +93,34 @@ struct DevQueryOut {
 void run_batch_device(gsmat_store* st, const gsmat_query_plan* const* plans, int32_t n,
                       int64_t budget, int64_t max_rows, hipStream_t s,
                       std::vector<DevQueryOut>& out);
+
+// Planning of a batch of BGPs, shared by gsmat_plan_batch and the fused
+// gsmat_join_batch_bgp: prepare validates every query, takes each pattern's
+// statistics and does every constant's row lookup in one device launch;
+// build then plans query i (rc[i] == GSMAT_OK) into pl, as gsmat_plan would.
+struct PlanPrep {
+  std::vector<int64_t> off, so;     // first pattern / first statistics slot per query
+  std::vector<gsmat_status> rc;
+  std::vector<std::string> msg;
+  std::vector<int32_t> nv;          // variables per valid query
+  std::vector<TpStat> stats;        // per pattern, flat over the batch
+  std::vector<int> req_of;          // lookup of each pattern (-1: none)
+  std::vector<LookupRes> res;
+};
+void plan_prepare(const gsmat_store* st, const gsmat_pattern* pats, const int32_t* n_pats,
+                  int32_t nq, int32_t mode, hipStream_t s, PlanPrep* pp);
+gsmat_status plan_build(const gsmat_store* st, const gsmat_pattern* pats, const int32_t* n_pats,
+                        int32_t mode, PlanPrep& pp, int64_t i, gsmat_query_plan* pl);
+
+// The fused batch (plans built on the host straight into the device upload,
+// no plan objects): out[i] as above for the valid queries; status[i] is the
+// planning status (out[i] untouched where it is not GSMAT_OK); fallback[i]
+// holds a plan for each query that left the batch.
+void run_batch_device_bgp(gsmat_store* st, const gsmat_pattern* pats, const int32_t* n_pats,
+                          int32_t nq, int32_t mode, int64_t budget, int64_t max_rows,
+                          hipStream_t s, std::vector<DevQueryOut>& out,
+                          std::vector<gsmat_status>& status, std::vector<std::string>& msg,
+                          std::vector<std::unique_ptr<gsmat_query_plan>>& fallback);
 
 void launch_lookup_many(const LookupReq* req, int32_t n, const PredDesc* dout, const PredDesc* din,
                         OriPtrs out, OriPtrs in, LookupRes* res, hipStream_t s);

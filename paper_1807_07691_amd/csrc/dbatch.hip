@@ -52,6 +52,7 @@
 #include "batch_tiles.hpp"
 #include "device.hpp"
 #include "exec.hpp"
+#include "host_pool.hpp"
 
 namespace gsmat {
 
@@ -1404,18 +1405,24 @@ void launch_count(int items, int strategy, hipStream_t s, const DArgs& A, int nq
 
 }  // namespace
 
-void run_batch_device(gsmat_store* st, const gsmat_query_plan* const* plans, int32_t nq,
-                      int64_t budget, int64_t max_rows, hipStream_t s,
-                      std::vector<DevQueryOut>& out) {
+// The host side of a device-driven batch: the upload's row widths, each
+// query's variables and steps, and the filler of its upload rows (queries
+// [lo, hi): pq[i], pats and lookups [i * mp, (i + 1) * mp), steps
+// [i * ms, (i + 1) * ms)).  n_vars and n_steps are read after fill.
+struct PackedBatch {
+  int32_t nq = 0;
+  int mp = 1, ms = 1, mv = 1;
+  std::vector<int32_t> n_vars, n_steps;
+  std::function<void(DPlanQ*, DPat*, DStep*, DLk*)> fill;
+};
+
+void run_batch_packed(gsmat_store* st, PackedBatch& pb, int64_t budget, int64_t max_rows,
+                      hipStream_t s, std::vector<DevQueryOut>& out) {
+  const int32_t nq = pb.nq;
   out.assign(nq, DevQueryOut{nullptr, kDevDone, GSMAT_OK});
   if (nq == 0) return;
   DeviceMem* mem = st->mem.get();
-  int mp = 1, ms = 1, mv = 1;
-  for (int i = 0; i < nq; ++i) {
-    mp = std::max(mp, (int)plans[i]->pats.size());
-    ms = std::max(ms, (int)plans[i]->steps.size());
-    mv = std::max(mv, (int)plans[i]->n_vars);
-  }
+  const int mp = pb.mp, ms = pb.ms, mv = pb.mv;
   const size_t n = (size_t)nq;
   // ---- device layout: uploaded inputs first, then the state
   Lay L;
@@ -1450,49 +1457,13 @@ void run_batch_device(gsmat_store* st, const gsmat_query_plan* const* plans, int
   slabs.push_back(std::make_shared<Arena>(mem, (size_t)out_cap, s));
   std::unique_ptr<Arena> scr(new Arena(mem, (size_t)scr_cap, s));
 
-  // ---- pack the plans
+  // ---- the upload: every query's plan rows, then the control block
   char* h = (char*)pin_in().get(up_bytes);
   DPlanQ* hpq = (DPlanQ*)(h + o_pq);
   DPat* hpats = (DPat*)(h + o_pats);
   DStep* hsteps = (DStep*)(h + o_steps);
   DLk* hlk = (DLk*)(h + o_lkin);
-  for (int i = 0; i < nq; ++i) {
-    const gsmat_query_plan* pl = plans[i];
-    const int np = (int)pl->pats.size();
-    const bool have = pl->lk_store == st->uid && pl->lk.size() == pl->pats.size();
-    DPlanQ& q = hpq[i];
-    q.np = np;
-    q.nsteps = (int)pl->steps.size();
-    q.nv = pl->n_vars;
-    q.mode = pl->mode;
-    q.absent = 0;
-    q.pad = 0;
-    for (int j = 0; j < mp; ++j) {
-      DPat& d = hpats[(size_t)i * mp + j];
-      DLk& l = hlk[(size_t)i * mp + j];
-      if (j < np) {
-        const gsmat_pattern& p = pl->pats[j];
-        d = DPat{p.s, p.p, p.o};
-        if (p.p >= st->P || (p.s >= 0 && p.s >= st->V) || (p.o >= 0 && p.o >= st->V))
-          q.absent = 1;
-        l = have && pl->lk[j].valid
-                ? DLk{pl->lk[j].start, pl->lk[j].len, pl->lk[j].found, 1}
-                : DLk{0, 0, 0, 0};
-      } else {
-        d = DPat{0, 0, 0};
-        l = DLk{0, 0, 0, 0};
-      }
-    }
-    for (int j = 0; j < ms; ++j) {
-      DStep& d = hsteps[(size_t)i * ms + j];
-      if (j < q.nsteps) {
-        const gsmat_step_info& sp = pl->steps[j];
-        d = DStep{(int8_t)sp.kind, (int8_t)sp.tp, (int8_t)sp.orient, (int8_t)sp.var, sp.members};
-      } else {
-        d = DStep{0, 0, 0, 0, 0u};
-      }
-    }
-  }
+  pb.fill(hpq, hpats, hsteps, hlk);
   DCtl* hctl = (DCtl*)(h + o_ctl);
   std::memset(hctl, 0, sizeof(DCtl));
   hctl->out_base = (char*)slabs[0]->p;
@@ -1603,8 +1574,8 @@ void run_batch_device(gsmat_store* st, const gsmat_query_plan* const* plans, int
         made[i].reset(r);
         r->st = st;
         r->stream = s;
-        r->n_vars = plans[i]->n_vars;
-        r->reset_steps(plans[i]->steps.size());
+        r->n_vars = pb.n_vars[i];
+        r->reset_steps(pb.n_steps[i]);
         r->segs.reserve(1);
       }
     }
@@ -1660,16 +1631,15 @@ void run_batch_device(gsmat_store* st, const gsmat_query_plan* const* plans, int
       o.state = kDevFallback;
       continue;
     }
-    const gsmat_query_plan* pl = plans[i];
     std::unique_ptr<gsmat_result>& res = made[i];
-    for (size_t j = 0; j < pl->steps.size(); ++j) {
+    for (int j = 0; j < pb.n_steps[i]; ++j) {
       res->step_in[j] = hsin[(size_t)i * ms + j];
       res->step_out[j] = hsout[(size_t)i * ms + j];
     }
     if (r.rows > 0) {
       Segment seg;
       seg.rows = r.rows;
-      for (int v = 0; v < pl->n_vars; ++v) seg.col[v] = hcol[(size_t)i * mv + v];
+      for (int v = 0; v < pb.n_vars[i]; ++v) seg.col[v] = hcol[(size_t)i * mv + v];
       if (r.slab >= 0) {
         if (r.slab >= (int)slabs.size())
           throw StatusFail{GSMAT_EHIP, "internal: result in an unknown slab"};
@@ -1681,6 +1651,134 @@ void run_batch_device(gsmat_store* st, const gsmat_query_plan* const* plans, int
     o.res = res.release();
     o.state = kDevDone;
   }
+}
+
+
+// One query's upload rows from its plan.
+void pack_plan(const gsmat_store* st, const gsmat_query_plan* pl, int mp, int ms, DPlanQ& q,
+               DPat* pats, DStep* steps, DLk* lk) {
+  const int np = (int)pl->pats.size();
+  const bool have = pl->lk_store == st->uid && pl->lk.size() == pl->pats.size();
+  q.np = np;
+  q.nsteps = (int)pl->steps.size();
+  q.nv = pl->n_vars;
+  q.mode = pl->mode;
+  q.absent = 0;
+  q.pad = 0;
+  for (int j = 0; j < mp; ++j) {
+    DPat& d = pats[j];
+    DLk& l = lk[j];
+    if (j < np) {
+      const gsmat_pattern& p = pl->pats[j];
+      d = DPat{p.s, p.p, p.o};
+      if (p.p >= st->P || (p.s >= 0 && p.s >= st->V) || (p.o >= 0 && p.o >= st->V))
+        q.absent = 1;
+      l = have && pl->lk[j].valid ? DLk{pl->lk[j].start, pl->lk[j].len, pl->lk[j].found, 1}
+                                  : DLk{0, 0, 0, 0};
+    } else {
+      d = DPat{0, 0, 0};
+      l = DLk{0, 0, 0, 0};
+    }
+  }
+  for (int j = 0; j < ms; ++j) {
+    DStep& d = steps[j];
+    if (j < q.nsteps) {
+      const gsmat_step_info& sp = pl->steps[j];
+      d = DStep{(int8_t)sp.kind, (int8_t)sp.tp, (int8_t)sp.orient, (int8_t)sp.var, sp.members};
+    } else {
+      d = DStep{0, 0, 0, 0, 0u};
+    }
+  }
+}
+
+void run_batch_device(gsmat_store* st, const gsmat_query_plan* const* plans, int32_t nq,
+                      int64_t budget, int64_t max_rows, hipStream_t s,
+                      std::vector<DevQueryOut>& out) {
+  PackedBatch pb;
+  pb.nq = nq;
+  pb.n_vars.resize(nq);
+  pb.n_steps.resize(nq);
+  for (int i = 0; i < nq; ++i) {
+    pb.mp = std::max(pb.mp, (int)plans[i]->pats.size());
+    pb.ms = std::max(pb.ms, (int)plans[i]->steps.size());
+    pb.mv = std::max(pb.mv, (int)plans[i]->n_vars);
+    pb.n_vars[i] = plans[i]->n_vars;
+    pb.n_steps[i] = (int32_t)plans[i]->steps.size();
+  }
+  pb.fill = [&](DPlanQ* pq, DPat* pats, DStep* steps, DLk* lk) {
+    for (int i = 0; i < nq; ++i)
+      pack_plan(st, plans[i], pb.mp, pb.ms, pq[i], pats + (size_t)i * pb.mp,
+                steps + (size_t)i * pb.ms, lk + (size_t)i * pb.mp);
+  };
+  run_batch_packed(st, pb, budget, max_rows, s, out);
+}
+
+void run_batch_device_bgp(gsmat_store* st, const gsmat_pattern* pats, const int32_t* n_pats,
+                          int32_t nq, int32_t mode, int64_t budget, int64_t max_rows,
+                          hipStream_t s, std::vector<DevQueryOut>& out,
+                          std::vector<gsmat_status>& status, std::vector<std::string>& msg,
+                          std::vector<std::unique_ptr<gsmat_query_plan>>& fallback) {
+  PlanPrep P;
+  plan_prepare(st, pats, n_pats, nq, mode, s, &P);
+  // the valid queries form the batch, in order
+  std::vector<int32_t> vi;
+  vi.reserve(nq);
+  PackedBatch pb;
+  for (int i = 0; i < nq; ++i) {
+    if (P.rc[i] != GSMAT_OK) continue;
+    vi.push_back(i);
+    pb.mp = std::max(pb.mp, n_pats[i]);
+    pb.mv = std::max(pb.mv, P.nv[i]);
+  }
+  pb.nq = (int32_t)vi.size();
+  pb.ms = pb.mp + 1;  // at most one step per pattern, plus an intersection
+  pb.n_vars.assign(pb.nq, 0);
+  pb.n_steps.assign(pb.nq, 0);
+  // each plan is built in a per-thread scratch plan and packed at once
+  pb.fill = [&](DPlanQ* pq, DPat* up, DStep* us, DLk* ul) {
+    host_parallel_for(pb.nq, 256, [&](int64_t lo, int64_t hi) {
+      gsmat_query_plan pl;
+      for (int64_t k = lo; k < hi; ++k) {
+        const int i = vi[k];
+        try {
+          P.rc[i] = plan_build(st, pats, n_pats, mode, P, i, &pl);
+        } catch (...) {
+          P.rc[i] = GSMAT_ENOMEM;
+          P.msg[i] = "host memory exhausted while planning";
+        }
+        if (P.rc[i] != GSMAT_OK) {  // cannot happen after validation: an empty query
+          pl = gsmat_query_plan();
+          pl.n_vars = P.nv[i];
+        }
+        pack_plan(st, &pl, pb.mp, pb.ms, pq[k], up + (size_t)k * pb.mp,
+                  us + (size_t)k * pb.ms, ul + (size_t)k * pb.mp);
+        if (P.rc[i] != GSMAT_OK) pq[k].absent = 1;
+        pb.n_vars[k] = pl.n_vars;
+        pb.n_steps[k] = (int32_t)pl.steps.size();
+      }
+    });
+  };
+  std::vector<DevQueryOut> dq;
+  run_batch_packed(st, pb, budget, max_rows, s, dq);
+  out.assign(nq, DevQueryOut{nullptr, kDevFailed, GSMAT_OK});
+  fallback.clear();
+  fallback.resize(nq);
+  for (int32_t k = 0; k < pb.nq; ++k) {
+    const int i = vi[k];
+    out[i] = dq[k];
+    if (P.rc[i] != GSMAT_OK) {  // planning failed after all: drop any result
+      if (out[i].res) gsmat_result_free(out[i].res);
+      out[i] = DevQueryOut{nullptr, kDevFailed, P.rc[i]};
+      continue;
+    }
+    if (dq[k].state == kDevFallback) {  // runs alone: it needs its plan object
+      fallback[i].reset(new gsmat_query_plan);
+      const gsmat_status rc = plan_build(st, pats, n_pats, mode, P, i, fallback[i].get());
+      if (rc != GSMAT_OK) throw StatusFail{rc, P.msg[i]};
+    }
+  }
+  status = P.rc;
+  msg = P.msg;
 }
 
 }  // namespace gsmat

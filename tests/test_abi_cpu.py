@@ -255,3 +255,13 @@ def test_join_ext_validates_the_query_before_the_store(G):
     # another branch may reuse the variable freely; filters may name any variable
     assert rc(req + [[-2, 1, -3, 0, 1], [-3, 1, -1, 1, 0]], [[G.F_BOUND, -3, 0, 0]]) == G.GSMAT_EINVAL
     assert "store" in lib.gsmat_last_error().decode()
+
+
+def test_fused_batch_validates_before_device_work(G):
+    lib = G.lib()
+    out = (ctypes.c_void_p * 1)()
+    n = (ctypes.c_int32 * 1)(1)
+    pats = (ctypes.c_int32 * 3)(-1, 0, -2)
+    assert lib.gsmat_join_batch_bgp(None, pats, n, 1, 2, 0, -1, None, out, None) == G.GSMAT_EINVAL
+    assert lib.gsmat_join_batch_bgp(None, pats, n, -1, 2, 0, -1, None, out, None) == G.GSMAT_EINVAL
+    assert lib.gsmat_join_batch_bgp(None, None, n, 1, 2, 0, -1, None, out, None) == G.GSMAT_EINVAL

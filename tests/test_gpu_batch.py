@@ -478,3 +478,62 @@ def test_batch_wide_tables(G, O, sparse):
     for mode in (0, 2):
         _check_batch(G, st, queries, mode, oracle_rows=want)
     st.close()
+
+
+# ------------------------------------------------------------------ fused plan + join
+def _check_fused(G, st, queries, mode, budget=0, oracle_rows=None):
+    """gsmat_join_batch_bgp against gsmat_plan_batch + gsmat_join_batch (the
+    device-driven rounds): the same rows in the same order and the same
+    per-step counters; the oracle's sorted rows where given."""
+    G.gsmat_set_batch_engine(st, 1)
+    plans, _ = G.gsmat_plan_batch(st, queries, mode)
+    want, _ = G.gsmat_join_batch(st, plans, budget)
+    got, stat = G.gsmat_join_batch_bgp(st, queries, mode, budget)
+    assert stat == [0] * len(queries)
+    for i, (a, b) in enumerate(zip(got, want)):
+        ra, rb = G.gsmat_fetch_bindings(a), G.gsmat_fetch_bindings(b)
+        assert np.array_equal(ra, rb), (i, queries[i])
+        assert G.gsmat_result_info(a) == G.gsmat_result_info(b), i
+        if oracle_rows is not None:
+            assert np.array_equal(_sorted(ra), oracle_rows[i]), i
+        a.close()
+        b.close()
+    for pl in plans:
+        pl.close()
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_fused_tiny_and_shapes(G, O, tiny, mode):
+    spec, s, p, o, qs, st, want = tiny
+    print(f"[gpu] fused plan + join, tiny and shapes, mode={mode}", flush=True)
+    _check_fused(G, st, [q.tps for q in qs] * 2, mode, oracle_rows=want * 2)
+    rng = np.random.default_rng(7)
+    s2, p2, o2 = (rng.integers(0, 12, 150).astype(np.int32),
+                  rng.integers(0, 3, 150).astype(np.int32),
+                  rng.integers(0, 12, 150).astype(np.int32))
+    st2 = _store(G, s2, p2, o2, 100, 8)
+    w2 = [O.join(s2, p2, o2, t, nv) for t, nv in SHAPES]
+    _check_fused(G, st2, [t for t, _ in SHAPES], mode, oracle_rows=w2)
+    st2.close()
+
+
+def test_fused_errors_budget_and_large_batch(G, tiny):
+    """Invalid queries fail alone with their planning status; a small budget
+    sends queries to the chunked single path with their plans built on the
+    way; a batch above 4096 queries."""
+    spec, s, p, o, qs, st, want = tiny
+    queries = [qs[0].tps, [[-1, 0, -3]], qs[1].tps, [[-1, -1, -2]]]
+    res, stat = G.gsmat_join_batch_bgp(st, queries, G.PLAN_ADAPTIVE, raise_on_error=False)
+    assert stat == [0, G.GSMAT_EINVAL, 0, G.GSMAT_EUNSUPPORTED]
+    assert res[1] is None and res[3] is None
+    for i, w in ((0, want[0]), (2, want[1])):
+        assert np.array_equal(_sorted(G.gsmat_fetch_bindings(res[i])), w)
+        res[i].close()
+    with pytest.raises(G.GsmatError):
+        G.gsmat_join_batch_bgp(st, queries, G.PLAN_ADAPTIVE)
+    _check_fused(G, st, [q.tps for q in qs], G.PLAN_ADAPTIVE, budget=4 * 4 * 50_000,
+                 oracle_rows=want)
+    small = [q.tps for q in qs if q.count <= 5000] or [qs[0].tps]
+    reps = 4200 // len(small) + 1
+    print(f"[gpu] fused batch of {len(small) * reps} queries", flush=True)
+    _check_fused(G, st, small * reps, G.PLAN_ADAPTIVE)
