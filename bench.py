@@ -147,9 +147,9 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); this build has no "
-              "multi-GPU path. The query-sharded design is described in DESIGN.md.",
-              file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the library has no "
+              "multi-GPU path (the design would replicate the store on every GPU and shard "
+              "the queries).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -121,7 +121,7 @@ class QuerySpec:
 KIND_CHAIN, KIND_SSTAR, KIND_OSTAR, KIND_SNOW = 0, 1, 2, 3
 KIND_NAMES = {0: "chain", 1: "subject-star", 2: "object-star", 3: "snowflake"}
 
-# Configurations (sizes as the workloads are specified).
+# Configurations: each workload's graph and query specification.
 CONFIGS = {
     "tiny": (GraphSpec("tiny", V=10_000, P=16, T=100_000, zipf_s=1.1, out_cap=2000,
                        in_cap=2000, seed=0x18070769 ^ 1),
