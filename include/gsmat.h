@@ -276,14 +276,16 @@ gsmat_status gsmat_set_batch_engine(gsmat_store* st, int32_t engine);
 gsmat_status gsmat_set_batch_regions(gsmat_store* st, int64_t out_bytes, int64_t scratch_bytes);
 
 /* gsmat_plan_batch and gsmat_join_batch in one call, with the device-driven
- * rounds: the queries' patterns as for gsmat_plan_batch (pats holds the
- * n_pats[i] patterns of query i after those of queries 0..i-1), planned in
- * mode on the host and packed straight into the batch's upload, with no plan
- * objects.  Every query yields exactly the rows, in the same order, and the
- * per-step counters it yields through gsmat_plan_batch + gsmat_join_batch.
- * out[i] and status[i] as for gsmat_join_batch; a query that fails planning
- * has its planning status and no result.  The store's batch engine setting is
- * not consulted. */
+ * rounds (the plan of Sec. 6.2 and the join of Sec. 6-7): the queries'
+ * patterns as for gsmat_plan_batch (pats holds the n_pats[i] patterns of
+ * query i after those of queries 0..i-1), planned in mode on the host and
+ * packed straight into the batch's upload, with no plan objects.  Every query
+ * yields exactly the rows, in the same order, and the per-step counters it
+ * yields through gsmat_plan_batch + gsmat_join_batch.  out[i] and status[i]
+ * as for gsmat_join_batch; a query that fails planning has its planning
+ * status and no result.  EINVAL (nothing run) for a NULL store, array or
+ * out, a negative count or an unknown mode; the store's batch engine setting
+ * is not consulted. */
 gsmat_status gsmat_join_batch_bgp(gsmat_store* st, const gsmat_pattern* pats,
                                   const int32_t* n_pats, int32_t n_queries, int32_t mode,
                                   int64_t budget_bytes, int64_t max_rows, void* stream,
